@@ -1,0 +1,655 @@
+/*
+ * Plain FP64 CPU oracle for Nested Slice Sampling (NSS).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, obviously-correct reference that the GPU
+ * library is checked against.  Only the test suite, the smoke check and the CPU-baseline leg
+ * of the benchmark load it.  It shares no code, header, table or constant with the GPU
+ * library (paper_2601_23252_amd/csrc); the only thing both sides share is the seeded problem
+ * generator, which holds none of the method's arithmetic.
+ *
+ * What it computes (paper references are section / equation / algorithm / table):
+ *   - the batched NS outer kernel: delete the k worst, resample parents uniformly among the
+ *     survivors, mutate each parent with a constrained kernel, replace
+ *     (Sec. 3.1 "Parallel Nested Sampling"; Alg. "Nested Sampling outer kernel");
+ *   - the constrained kernel, Hit-and-Run Slice Sampling: random direction in the Mahalanobis
+ *     metric of the live-set covariance, randomised initial bracket of width w, linear
+ *     stepping-out capped at 10 expansions per side, shrinkage capped at 100 proposals with a
+ *     null move on the cap (Sec. 3.2; App. A.6 "Hit-and-Run Slice Sampling Implementation");
+ *   - evidence by the rectangle rule Z = sum L_i dX_i (Sec. 2.1, eq. marginal) with each batch
+ *     of k deaths unrolled into single deaths at live counts m, m-1, ..., m-k+1
+ *     (Sec. 2.1; App. D.2.1), using the deterministic log-volume decrement -1/n per death
+ *     (the expectation of log t for t ~ Beta(n,1), App. D.2.2);
+ *   - termination when an upper bound on the live set's remaining contribution is below a
+ *     tolerance (Sec. 2.1), and the final live-set contribution.
+ *
+ * Readings where the paper is silent are listed in the design notes: Mahalanobis-normalised
+ * direction; survivors' covariance with 1e-12 trace jitter; parents drawn from survivors with
+ * logL strictly above L* in ascending (logL, index) order; literal 10-per-side step-out cap;
+ * shrink side chosen by the sign of t'; normalised likelihood densities.
+ *
+ * Random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy
+ * as 1, 2, 3", SC'11), written here from that definition.  Counter = (purpose<<24 | index,
+ * iteration, step, draw), key = (seed_lo, seed_hi ^ run_id).  A 64-bit word x gives the uniform
+ * (2*(x>>12)+1) * 2^-53 in (0,1); normals by the Box-Muller transform.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define OR_PI 3.14159265358979323846
+
+enum { P_INIT = 1, P_RESAMPLE = 2, P_DIR = 3, P_STEP = 4, P_SHRINK = 5 };
+enum { PRIOR_BOX = 0, PRIOR_GAUSS = 1 };
+enum { LIK_MIXTURE = 1, LIK_FUNNEL = 2 };
+
+/* ------------------------------------------------------------------------------------------ */
+/* Philox4x32-10                                                                               */
+/* ------------------------------------------------------------------------------------------ */
+void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+        uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0, n1 = lo1, n2 = hi0 ^ c3 ^ k1, n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+static double u53(uint32_t lo, uint32_t hi)
+{
+    uint64_t x = ((uint64_t)hi << 32) | (uint64_t)lo;
+    return (double)(2u * (x >> 12) + 1u) * 0x1p-53;
+}
+
+typedef struct { uint32_t k[2]; } okey;
+
+/* Two FP64 uniforms from one Philox call at counter (purpose<<24|index, c1, c2, c3). */
+static void draw2(okey key, uint32_t purpose, uint32_t index, uint32_t c1, uint32_t c2,
+                  uint32_t c3, double *ua, double *ub)
+{
+    uint32_t ctr[4] = { (purpose << 24) | (index & 0xFFFFFFu), c1, c2, c3 }, r[4];
+    or_philox4x32_10(ctr, key.k, r);
+    *ua = u53(r[0], r[1]);
+    *ub = u53(r[2], r[3]);
+}
+
+void or_uniform_pair(uint64_t seed, uint32_t run_id, uint32_t purpose, uint32_t index,
+                     uint32_t c1, uint32_t c2, uint32_t c3, double out[2])
+{
+    okey key = { { (uint32_t)seed, (uint32_t)(seed >> 32) ^ run_id } };
+    draw2(key, purpose, index, c1, c2, c3, &out[0], &out[1]);
+}
+
+/* Box-Muller: one pair of uniforms -> two independent standard normals. */
+static void box_muller(double ua, double ub, double *z0, double *z1)
+{
+    double rad = sqrt(-2.0 * log(ua));
+    double th = 2.0 * OR_PI * ub;
+    *z0 = rad * cos(th);
+    *z1 = rad * sin(th);
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Problem: prior Pi and energy E = -log L                                                     */
+/* ------------------------------------------------------------------------------------------ */
+typedef struct {
+    int d;
+    int prior_kind;
+    double *pa, *pb;          /* box: lower, upper; gauss: mean, std (per coordinate) */
+    int lik_kind;
+    int K;                    /* mixture components */
+    double *logw;             /* K log weights */
+    double *mu;               /* K x d means */
+    double *chol;             /* K x d x d lower Cholesky factors of the covariances */
+    double *logdet_half;      /* K: sum log diag(chol) = 0.5 log det C */
+} oprob;
+
+static int cholesky_lower(const double *A, double *L, int n)
+{
+    memset(L, 0, sizeof(double) * (size_t)n * n);
+    for (int i = 0; i < n; ++i) {
+        for (int j = 0; j <= i; ++j) {
+            double s = A[i * n + j];
+            for (int t = 0; t < j; ++t) s -= L[i * n + t] * L[j * n + t];
+            if (i == j) {
+                if (!(s > 0.0)) return -1;
+                L[i * n + i] = sqrt(s);
+            } else {
+                L[i * n + j] = s / L[j * n + j];
+            }
+        }
+    }
+    return 0;
+}
+
+void or_problem_free(void *pp)
+{
+    oprob *p = (oprob *)pp;
+    if (!p) return;
+    free(p->pa); free(p->pb); free(p->logw); free(p->mu); free(p->chol); free(p->logdet_half);
+    free(p);
+}
+
+/* Returns NULL on invalid input (non-positive-definite covariance, bad sizes). */
+void *or_problem_new(int d, int prior_kind, const double *pa, const double *pb, int lik_kind,
+                     int K, const double *logw, const double *mu, const double *cov)
+{
+    if (d < 1) return NULL;
+    oprob *p = (oprob *)calloc(1, sizeof(oprob));
+    p->d = d;
+    p->prior_kind = prior_kind;
+    p->pa = (double *)malloc(sizeof(double) * d);
+    p->pb = (double *)malloc(sizeof(double) * d);
+    memcpy(p->pa, pa, sizeof(double) * d);
+    memcpy(p->pb, pb, sizeof(double) * d);
+    p->lik_kind = lik_kind;
+    if (lik_kind == LIK_MIXTURE) {
+        if (K < 1) { or_problem_free(p); return NULL; }
+        p->K = K;
+        p->logw = (double *)malloc(sizeof(double) * K);
+        p->mu = (double *)malloc(sizeof(double) * (size_t)K * d);
+        p->chol = (double *)malloc(sizeof(double) * (size_t)K * d * d);
+        p->logdet_half = (double *)malloc(sizeof(double) * K);
+        memcpy(p->logw, logw, sizeof(double) * K);
+        memcpy(p->mu, mu, sizeof(double) * (size_t)K * d);
+        for (int i = 0; i < K; ++i) {
+            double *L = p->chol + (size_t)i * d * d;
+            if (cholesky_lower(cov + (size_t)i * d * d, L, d) != 0) { or_problem_free(p); return NULL; }
+            double s = 0.0;
+            for (int j = 0; j < d; ++j) s += log(L[j * d + j]);
+            p->logdet_half[i] = s;
+        }
+    } else if (lik_kind != LIK_FUNNEL) {
+        or_problem_free(p);
+        return NULL;
+    }
+    return p;
+}
+
+/* Prior support test. */
+static int prior_in_support(const oprob *p, const double *x)
+{
+    if (p->prior_kind == PRIOR_BOX) {
+        for (int j = 0; j < p->d; ++j)
+            if (!(x[j] >= p->pa[j] && x[j] <= p->pb[j])) return 0;
+    }
+    return 1;
+}
+
+/* log Pi(x): normalised density; -inf outside the support. */
+double or_logprior(const void *pp, const double *x)
+{
+    const oprob *p = (const oprob *)pp;
+    if (!prior_in_support(p, x)) return -INFINITY;
+    double s = 0.0;
+    if (p->prior_kind == PRIOR_BOX) {
+        for (int j = 0; j < p->d; ++j) s -= log(p->pb[j] - p->pa[j]);
+    } else {
+        for (int j = 0; j < p->d; ++j) {
+            double z = (x[j] - p->pa[j]) / p->pb[j];
+            s += -0.5 * z * z - log(p->pb[j]) - 0.5 * log(2.0 * OR_PI);
+        }
+    }
+    return s;
+}
+
+/* log N(x; mu, C) with C = L L^T: solve L z = x - mu by forward substitution. */
+static double log_gauss_chol(const double *x, const double *mu, const double *L,
+                             double logdet_half, int d)
+{
+    double z[512];
+    double q = 0.0;
+    for (int a = 0; a < d; ++a) {
+        double s = x[a] - mu[a];
+        for (int b = 0; b < a; ++b) s -= L[a * d + b] * z[b];
+        z[a] = s / L[a * d + a];
+        q += z[a] * z[a];
+    }
+    return -0.5 * q - logdet_half - 0.5 * d * log(2.0 * OR_PI);
+}
+
+/* log L(x) = -E(x).  Mixture: log sum_i w_i N(x; mu_i, C_i).  Funnel: v = x_0 ~ N(0, 9),
+ * x_j | v ~ N(0, e^v) for j >= 1. */
+double or_loglik(const void *pp, const double *x)
+{
+    const oprob *p = (const oprob *)pp;
+    int d = p->d;
+    if (p->lik_kind == LIK_MIXTURE) {
+        double terms[256];
+        double mx = -INFINITY;
+        for (int i = 0; i < p->K; ++i) {
+            terms[i] = p->logw[i] + log_gauss_chol(x, p->mu + (size_t)i * d,
+                                                   p->chol + (size_t)i * d * d,
+                                                   p->logdet_half[i], d);
+            if (terms[i] > mx) mx = terms[i];
+        }
+        if (mx == -INFINITY) return -INFINITY;
+        double s = 0.0;
+        for (int i = 0; i < p->K; ++i) s += exp(terms[i] - mx);
+        return mx + log(s);
+    } else {
+        double v = x[0];
+        double r = -0.5 * v * v / 9.0 - 0.5 * log(2.0 * OR_PI * 9.0);
+        for (int j = 1; j < d; ++j)
+            r += -0.5 * x[j] * x[j] * exp(-v) - 0.5 * v - 0.5 * log(2.0 * OR_PI);
+        return r;
+    }
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Hit-and-Run Slice Sampling chain                                                            */
+/* ------------------------------------------------------------------------------------------ */
+typedef struct {
+    int64_t evals;          /* likelihood computations (candidate passed the prior checks) */
+    int64_t tests;          /* all inside-tests, including prior rejections */
+    int64_t prior_rejects;  /* candidates outside the prior support or below the height */
+    int64_t stepout_caps;   /* sides that stopped at the expansion cap */
+    int64_t shrink_caps;    /* null moves from the shrink cap */
+    int64_t nonfinite;      /* NaN / +inf log-likelihoods, treated as -inf */
+} octr;
+
+typedef struct {
+    const oprob *p;
+    const double *x0, *v;
+    double Lstar, logy;
+    int uniform_prior;
+    double *y;              /* scratch, d */
+    octr *c;
+    double last_logL;
+} inside_ctx;
+
+/* The slice predicate along the line: x0 + t v inside the prior support, above the prior
+ * height (non-uniform priors only) and strictly above the likelihood threshold. */
+static int inside(inside_ctx *s, double t)
+{
+    const int d = s->p->d;
+    for (int a = 0; a < d; ++a) s->y[a] = s->x0[a] + t * s->v[a];
+    s->c->tests++;
+    if (!prior_in_support(s->p, s->y)) { s->c->prior_rejects++; return 0; }
+    if (!s->uniform_prior && !(or_logprior(s->p, s->y) > s->logy)) { s->c->prior_rejects++; return 0; }
+    double L = or_loglik(s->p, s->y);
+    s->c->evals++;
+    if (isnan(L) || L == INFINITY) { s->c->nonfinite++; L = -INFINITY; }
+    s->last_logL = L;
+    return L > s->Lstar;
+}
+
+/*
+ * One chain of p HRSS steps from (x, logL) under the hard constraint logL > Lstar.
+ * Lsig: d x d lower-triangular factor of the direction covariance (row-major).
+ * trace (optional, 4 ints per step): left expansions, right expansions, shrink proposals,
+ * accepted (1) or null move (0).
+ * x and *logL are updated in place.
+ */
+void or_hrss_chain(const void *pp, double *x, double *logL, double Lstar, const double *Lsig,
+                   double w, int p_steps, int stepout_cap, int shrink_cap, uint64_t seed,
+                   uint32_t run_id, uint32_t iter, uint32_t chain, int64_t *counters,
+                   int32_t *trace)
+{
+    const oprob *p = (const oprob *)pp;
+    const int d = p->d;
+    okey key = { { (uint32_t)seed, (uint32_t)(seed >> 32) ^ run_id } };
+    double *z = (double *)malloc(sizeof(double) * d * 3);
+    double *v = z + d, *y = z + 2 * d;
+    octr c; memset(&c, 0, sizeof c);
+    inside_ctx s;
+    s.p = p; s.x0 = x; s.v = v; s.Lstar = Lstar; s.y = y; s.c = &c;
+    s.uniform_prior = (p->prior_kind == PRIOR_BOX);
+    for (int st = 0; st < p_steps; ++st) {
+        /* direction: z ~ N(0, I), v = Lsig z / |z| (unit length in the Mahalanobis metric) */
+        for (int q = 0; 2 * q < d; ++q) {
+            double ua, ub, z0, z1;
+            draw2(key, P_DIR, chain, iter, (uint32_t)st, (uint32_t)q, &ua, &ub);
+            box_muller(ua, ub, &z0, &z1);
+            z[2 * q] = z0;
+            if (2 * q + 1 < d) z[2 * q + 1] = z1;
+        }
+        double nz = 0.0;
+        for (int a = 0; a < d; ++a) nz += z[a] * z[a];
+        nz = sqrt(nz);
+        for (int a = 0; a < d; ++a) {
+            double s2 = 0.0;
+            for (int b = 0; b <= a; ++b) s2 += Lsig[a * d + b] * z[b];
+            v[a] = s2 / nz;
+        }
+        /* initial bracket position and slice height */
+        double U, uh;
+        draw2(key, P_STEP, chain, iter, (uint32_t)st, 0u, &U, &uh);
+        s.logy = s.uniform_prior ? -INFINITY : or_logprior(p, x) + log(uh);
+        double tL = -w * U, tR = tL + w;
+        /* linear stepping-out, at most stepout_cap expansions per side */
+        int nl = 0, nr = 0;
+        while (nl < stepout_cap && inside(&s, tL)) { tL -= w; ++nl; }
+        if (nl == stepout_cap) c.stepout_caps++;
+        while (nr < stepout_cap && inside(&s, tR)) { tR += w; ++nr; }
+        if (nr == stepout_cap) c.stepout_caps++;
+        /* shrinkage */
+        int ns = 0, acc = 0;
+        for (; ns < shrink_cap; ++ns) {
+            double us, unused;
+            draw2(key, P_SHRINK, chain, iter, (uint32_t)st, (uint32_t)ns, &us, &unused);
+            double t = tL + us * (tR - tL);
+            if (inside(&s, t)) {
+                for (int a = 0; a < d; ++a) x[a] = x[a] + t * v[a];
+                *logL = s.last_logL;
+                acc = 1;
+                ++ns;
+                break;
+            }
+            if (t < 0.0) tL = t; else tR = t;
+        }
+        if (!acc) c.shrink_caps++;
+        if (trace) {
+            trace[4 * st + 0] = nl; trace[4 * st + 1] = nr;
+            trace[4 * st + 2] = ns; trace[4 * st + 3] = acc;
+        }
+    }
+    free(z);
+    if (counters) {
+        counters[0] += c.evals; counters[1] += c.tests; counters[2] += c.prior_rejects;
+        counters[3] += c.stepout_caps; counters[4] += c.shrink_caps; counters[5] += c.nonfinite;
+    }
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* NS outer loop                                                                               */
+/* ------------------------------------------------------------------------------------------ */
+typedef struct {
+    const oprob *p;
+    int m, k, p_steps, stepout_cap, shrink_cap;
+    double width, term_frac;
+    uint64_t seed;
+    uint32_t run_id;
+    /* state */
+    double *x;        /* m x d, row per particle */
+    double *logL;     /* m */
+    int *perm;        /* m: ascending (logL, index) */
+    double Lstar;
+    double logZ, logX, M;   /* M = posterior mean of logL so far, H = M - logZ */
+    int64_t iter;
+    int64_t counters[6];
+    double *Lsig;     /* d x d, last whitening factor */
+    int *parents;     /* k, last resample */
+    double *dead;     /* dead logL record */
+    int64_t n_dead, cap_dead;
+    int whiten_fallbacks;
+} orun;
+
+void or_run_free(void *rr)
+{
+    orun *r = (orun *)rr;
+    if (!r) return;
+    free(r->x); free(r->logL); free(r->perm); free(r->Lsig); free(r->parents); free(r->dead);
+    free(r);
+}
+
+void *or_run_new(const void *pp, int m, int k, int p_steps, double width, int stepout_cap,
+                 int shrink_cap, double term_frac, uint64_t seed, uint32_t run_id)
+{
+    const oprob *p = (const oprob *)pp;
+    if (!p || m < 2 || k < 1 || k > m - 1 || p_steps < 1 || !(width > 0.0)) return NULL;
+    orun *r = (orun *)calloc(1, sizeof(orun));
+    int d = p->d;
+    r->p = p; r->m = m; r->k = k; r->p_steps = p_steps; r->width = width;
+    r->stepout_cap = stepout_cap; r->shrink_cap = shrink_cap; r->term_frac = term_frac;
+    r->seed = seed; r->run_id = run_id;
+    r->x = (double *)malloc(sizeof(double) * (size_t)m * d);
+    r->logL = (double *)malloc(sizeof(double) * m);
+    r->perm = (int *)malloc(sizeof(int) * m);
+    r->Lsig = (double *)calloc((size_t)d * d, sizeof(double));
+    r->parents = (int *)calloc(k, sizeof(int));
+    r->cap_dead = 1 << 16;
+    r->dead = (double *)malloc(sizeof(double) * r->cap_dead);
+    return r;
+}
+
+static const double *g_sort_logL;
+static int cmp_logL_index(const void *a, const void *b)
+{
+    int i = *(const int *)a, j = *(const int *)b;
+    double li = g_sort_logL[i], lj = g_sort_logL[j];
+    if (li < lj) return -1;
+    if (li > lj) return 1;
+    return (i > j) - (i < j);
+}
+
+static double lse2(double a, double b)
+{
+    if (a == -INFINITY) return b;
+    if (b == -INFINITY) return a;
+    double mx = a > b ? a : b;
+    return mx + log(exp(a - mx) + exp(b - mx));
+}
+
+/* Delete-k: sort by (logL, index); the first k are the deaths; L* is the k-th worst.  Then
+ * account the k deaths one at a time at live counts m, m-1, ..., m-k+1. */
+static void select_and_account(orun *r)
+{
+    const int m = r->m, k = r->k;
+    for (int i = 0; i < m; ++i) r->perm[i] = i;
+    g_sort_logL = r->logL;
+    qsort(r->perm, (size_t)m, sizeof(int), cmp_logL_index);
+    r->Lstar = r->logL[r->perm[k - 1]];
+    for (int j = 1; j <= k; ++j) {
+        double n = (double)(m - j + 1);
+        double L = r->logL[r->perm[j - 1]];
+        double logdX = r->logX + log(-expm1(-1.0 / n));   /* log(X_{j-1} - X_j) */
+        r->logX -= 1.0 / n;
+        double lw = L + logdX;
+        double zn = lse2(r->logZ, lw);
+        double Mn = (r->logZ == -INFINITY ? 0.0 : exp(r->logZ - zn) * r->M);
+        if (lw != -INFINITY) Mn += exp(lw - zn) * L;
+        r->M = Mn;
+        r->logZ = zn;
+        if (r->n_dead == r->cap_dead) {
+            r->cap_dead *= 2;
+            r->dead = (double *)realloc(r->dead, sizeof(double) * r->cap_dead);
+        }
+        r->dead[r->n_dead++] = L;
+    }
+}
+
+static int termination_reached(const orun *r)
+{
+    if (!(r->term_frac > 0.0)) return 0;
+    double maxL = r->logL[r->perm[r->m - 1]];
+    return (r->logX + maxL - r->logZ) < log(r->term_frac);
+}
+
+/* Draw m points from the prior, evaluate them, then the first delete-k.  Returns 1 if the
+ * termination test already holds, 0 otherwise. */
+int or_init(void *rr)
+{
+    orun *r = (orun *)rr;
+    const oprob *p = r->p;
+    const int d = p->d, m = r->m;
+    okey key = { { (uint32_t)r->seed, (uint32_t)(r->seed >> 32) ^ r->run_id } };
+    for (int i = 0; i < m; ++i) {
+        double *xi = r->x + (size_t)i * d;
+        for (int q = 0; 2 * q < d; ++q) {
+            double ua, ub, a0, a1;
+            draw2(key, P_INIT, (uint32_t)i, 0u, 0u, (uint32_t)q, &ua, &ub);
+            if (p->prior_kind == PRIOR_BOX) {
+                a0 = ua; a1 = ub;
+                xi[2 * q] = p->pa[2 * q] + (p->pb[2 * q] - p->pa[2 * q]) * a0;
+                if (2 * q + 1 < d)
+                    xi[2 * q + 1] = p->pa[2 * q + 1] + (p->pb[2 * q + 1] - p->pa[2 * q + 1]) * a1;
+            } else {
+                box_muller(ua, ub, &a0, &a1);
+                xi[2 * q] = p->pa[2 * q] + p->pb[2 * q] * a0;
+                if (2 * q + 1 < d) xi[2 * q + 1] = p->pa[2 * q + 1] + p->pb[2 * q + 1] * a1;
+            }
+        }
+        double L = or_loglik(p, xi);
+        if (isnan(L) || L == INFINITY) { r->counters[5]++; L = -INFINITY; }
+        r->logL[i] = L;
+    }
+    r->logZ = -INFINITY; r->logX = 0.0; r->M = 0.0; r->iter = 0; r->n_dead = 0;
+    select_and_account(r);
+    return termination_reached(r);
+}
+
+/* Whitening: covariance (divided by n) of the m-k survivors plus 1e-12 tr/d jitter, and its
+ * lower Cholesky factor; diagonal fallback if the factorisation fails. */
+static void whiten(orun *r)
+{
+    const int d = r->p->d, m = r->m, k = r->k, n = m - k;
+    double *mean = (double *)calloc(d, sizeof(double));
+    double *C = (double *)calloc((size_t)d * d, sizeof(double));
+    for (int t = k; t < m; ++t) {
+        const double *xi = r->x + (size_t)r->perm[t] * d;
+        for (int a = 0; a < d; ++a) mean[a] += xi[a];
+    }
+    for (int a = 0; a < d; ++a) mean[a] /= n;
+    for (int t = k; t < m; ++t) {
+        const double *xi = r->x + (size_t)r->perm[t] * d;
+        for (int a = 0; a < d; ++a)
+            for (int b = 0; b <= a; ++b) C[a * d + b] += (xi[a] - mean[a]) * (xi[b] - mean[b]);
+    }
+    double tr = 0.0;
+    for (int a = 0; a < d; ++a) {
+        for (int b = 0; b <= a; ++b) { C[a * d + b] /= n; C[b * d + a] = C[a * d + b]; }
+        tr += C[a * d + a];
+    }
+    for (int a = 0; a < d; ++a) C[a * d + a] += 1e-12 * tr / d;
+    if (cholesky_lower(C, r->Lsig, d) != 0) {
+        r->whiten_fallbacks++;
+        memset(r->Lsig, 0, sizeof(double) * (size_t)d * d);
+        for (int a = 0; a < d; ++a) r->Lsig[a * d + a] = sqrt(C[a * d + a] > 0 ? C[a * d + a] : 1.0);
+    }
+    free(mean); free(C);
+}
+
+/* One outer iteration: whiten, resample, mutate, replace, delete-k, account, terminate?
+ * Returns 1 when terminated, 0 otherwise, -4 if no survivor lies strictly above L*. */
+int or_step(void *rr, int n_threads)
+{
+    orun *r = (orun *)rr;
+    const oprob *p = r->p;
+    const int d = p->d, m = r->m, k = r->k;
+    const uint32_t it = (uint32_t)(r->iter + 1);
+    okey key = { { (uint32_t)r->seed, (uint32_t)(r->seed >> 32) ^ r->run_id } };
+    whiten(r);
+    /* resample: uniform over survivors with logL > L*, in ascending (logL, index) order */
+    int t0 = k;
+    while (t0 < m && !(r->logL[r->perm[t0]] > r->Lstar)) ++t0;
+    const int ns = m - t0;
+    if (ns == 0) return -4;
+    for (int j = 0; j < k; ++j) {
+        double u, unused;
+        draw2(key, P_RESAMPLE, (uint32_t)j, it, 0u, 0u, &u, &unused);
+        int q = (int)floor(u * ns);
+        if (q > ns - 1) q = ns - 1;
+        r->parents[j] = r->perm[t0 + q];
+    }
+    /* mutate: k independent chains */
+    double *xn = (double *)malloc(sizeof(double) * (size_t)k * d);
+    double *ln = (double *)malloc(sizeof(double) * k);
+    int64_t c0 = 0, c1 = 0, c2 = 0, c3 = 0, c4 = 0, c5 = 0;
+#ifdef _OPENMP
+    if (n_threads < 1) n_threads = 1;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(n_threads) reduction(+:c0,c1,c2,c3,c4,c5)
+#endif
+    for (int j = 0; j < k; ++j) {
+        int64_t cc[6] = { 0, 0, 0, 0, 0, 0 };
+        memcpy(xn + (size_t)j * d, r->x + (size_t)r->parents[j] * d, sizeof(double) * d);
+        ln[j] = r->logL[r->parents[j]];
+        or_hrss_chain(p, xn + (size_t)j * d, &ln[j], r->Lstar, r->Lsig, r->width, r->p_steps,
+                      r->stepout_cap, r->shrink_cap, r->seed, r->run_id, it, (uint32_t)j, cc, NULL);
+        c0 += cc[0]; c1 += cc[1]; c2 += cc[2]; c3 += cc[3]; c4 += cc[4]; c5 += cc[5];
+    }
+    (void)n_threads;
+    r->counters[0] += c0; r->counters[1] += c1; r->counters[2] += c2;
+    r->counters[3] += c3; r->counters[4] += c4; r->counters[5] += c5;
+    /* replace: the j-th new point takes the slot of the j-th deleted point */
+    for (int j = 0; j < k; ++j) {
+        int slot = r->perm[j];
+        memcpy(r->x + (size_t)slot * d, xn + (size_t)j * d, sizeof(double) * d);
+        r->logL[slot] = ln[j];
+    }
+    free(xn); free(ln);
+    r->iter = it;
+    select_and_account(r);
+    return termination_reached(r);
+}
+
+/* Evidence with the live set's remaining contribution added (non-destructive):
+ * out = {logZ, sqrt(H/m), H}. */
+void or_logz(const void *rr, double out[3])
+{
+    const orun *r = (const orun *)rr;
+    const int m = r->m, k = r->k, n = m - k;
+    double mx = -INFINITY;
+    for (int t = k; t < m; ++t) if (r->logL[r->perm[t]] > mx) mx = r->logL[r->perm[t]];
+    double s = 0.0;
+    for (int t = k; t < m; ++t) s += exp(r->logL[r->perm[t]] - mx);
+    double lme = mx + log(s) - log((double)n);
+    double zf = lse2(r->logZ, r->logX + lme);
+    double Mf = (r->logZ == -INFINITY ? 0.0 : exp(r->logZ - zf) * r->M);
+    for (int t = k; t < m; ++t) {
+        double L = r->logL[r->perm[t]];
+        double lw = r->logX - log((double)n) + L;
+        if (lw != -INFINITY) Mf += exp(lw - zf) * L;
+    }
+    double H = Mf - zf;
+    out[0] = zf;
+    out[1] = sqrt(H > 0 ? H / m : 0.0);
+    out[2] = H;
+}
+
+/* State access for parity tests. */
+void or_get_state(const void *rr, double *x, double *logL, int *perm, double scalars[4],
+                  int64_t *iter, int64_t counters[6])
+{
+    const orun *r = (const orun *)rr;
+    const int d = r->p->d, m = r->m;
+    if (x) memcpy(x, r->x, sizeof(double) * (size_t)m * d);
+    if (logL) memcpy(logL, r->logL, sizeof(double) * m);
+    if (perm) memcpy(perm, r->perm, sizeof(int) * m);
+    if (scalars) { scalars[0] = r->Lstar; scalars[1] = r->logZ; scalars[2] = r->logX; scalars[3] = r->M; }
+    if (iter) *iter = r->iter;
+    if (counters) memcpy(counters, r->counters, sizeof(int64_t) * 6);
+}
+
+/* Overwrite the live set and evidence scalars, then recompute the delete-k order (without
+ * re-accounting the deaths). */
+void or_set_state(void *rr, const double *x, const double *logL, const double scalars3[3],
+                  int64_t iter)
+{
+    orun *r = (orun *)rr;
+    const int d = r->p->d, m = r->m;
+    memcpy(r->x, x, sizeof(double) * (size_t)m * d);
+    memcpy(r->logL, logL, sizeof(double) * m);
+    r->logZ = scalars3[0]; r->logX = scalars3[1]; r->M = scalars3[2];
+    r->iter = iter;
+    for (int i = 0; i < m; ++i) r->perm[i] = i;
+    g_sort_logL = r->logL;
+    qsort(r->perm, (size_t)m, sizeof(int), cmp_logL_index);
+    r->Lstar = r->logL[r->perm[r->k - 1]];
+}
+
+void or_get_aux(const void *rr, double *Lsig, int *parents)
+{
+    const orun *r = (const orun *)rr;
+    const int d = r->p->d;
+    if (Lsig) memcpy(Lsig, r->Lsig, sizeof(double) * (size_t)d * d);
+    if (parents) memcpy(parents, r->parents, sizeof(int) * r->k);
+}
+
+int64_t or_get_dead(const void *rr, double *out, int64_t cap)
+{
+    const orun *r = (const orun *)rr;
+    int64_t n = r->n_dead < cap ? r->n_dead : cap;
+    if (out && n > 0) memcpy(out, r->dead, sizeof(double) * n);
+    return r->n_dead;
+}

@@ -1,0 +1,214 @@
+"""ctypes wrapper of the plain FP64 C oracle (``oracle/nss_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: imported by the test suite, the smoke check and the CPU-baseline
+leg of the benchmark, never by the GPU library.  It takes problems as plain arrays (the
+seeded generator's output) and imports nothing from the GPU package.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "nss_oracle.c")
+LIB = os.path.join(HERE, "libnss_oracle.so")
+
+PRIOR_BOX, PRIOR_GAUSS = 0, 1
+LIK_MIXTURE, LIK_FUNNEL = 1, 2
+P_INIT, P_RESAMPLE, P_DIR, P_STEP, P_SHRINK = 1, 2, 3, 4, 5
+
+_dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+_ip = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+_lp = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
+_up = np.ctypeslib.ndpointer(dtype=np.uint32, flags="C_CONTIGUOUS")
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (-O2, OpenMP).  Plain C, no GPU code."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fopenmp",
+                               "-o", tmp, SRC, "-lm"])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        L = C.CDLL(LIB)
+        L.or_philox4x32_10.argtypes = [_up, _up, _up]
+        L.or_uniform_pair.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32,
+                                      C.c_uint32, C.c_uint32, C.c_uint32, _dp]
+        L.or_problem_new.restype = C.c_void_p
+        L.or_problem_new.argtypes = [C.c_int, C.c_int, _dp, _dp, C.c_int, C.c_int,
+                                     C.c_void_p, C.c_void_p, C.c_void_p]
+        L.or_problem_free.argtypes = [C.c_void_p]
+        L.or_loglik.restype = C.c_double
+        L.or_loglik.argtypes = [C.c_void_p, _dp]
+        L.or_logprior.restype = C.c_double
+        L.or_logprior.argtypes = [C.c_void_p, _dp]
+        L.or_hrss_chain.argtypes = [C.c_void_p, _dp, _dp, C.c_double, _dp, C.c_double,
+                                    C.c_int, C.c_int, C.c_int, C.c_uint64, C.c_uint32,
+                                    C.c_uint32, C.c_uint32, _lp, C.c_void_p]
+        L.or_run_new.restype = C.c_void_p
+        L.or_run_new.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_double, C.c_int,
+                                 C.c_int, C.c_double, C.c_uint64, C.c_uint32]
+        L.or_run_free.argtypes = [C.c_void_p]
+        L.or_init.restype = C.c_int
+        L.or_init.argtypes = [C.c_void_p]
+        L.or_step.restype = C.c_int
+        L.or_step.argtypes = [C.c_void_p, C.c_int]
+        L.or_logz.argtypes = [C.c_void_p, _dp]
+        L.or_get_state.argtypes = [C.c_void_p, _dp, _dp, _ip, _dp, _lp, _lp]
+        L.or_set_state.argtypes = [C.c_void_p, _dp, _dp, _dp, C.c_int64]
+        L.or_get_aux.argtypes = [C.c_void_p, _dp, _ip]
+        L.or_get_dead.restype = C.c_int64
+        L.or_get_dead.argtypes = [C.c_void_p, C.c_void_p, C.c_int64]
+        _lib = L
+    return _lib
+
+
+def philox(ctr, key) -> np.ndarray:
+    out = np.zeros(4, np.uint32)
+    lib().or_philox4x32_10(np.asarray(ctr, np.uint32), np.asarray(key, np.uint32), out)
+    return out
+
+
+def uniform_pair(seed, run_id, purpose, index, c1, c2, c3) -> np.ndarray:
+    out = np.zeros(2)
+    lib().or_uniform_pair(seed, run_id, purpose, index, c1, c2, c3, out)
+    return out
+
+
+class Problem:
+    """Prior Pi and energy E = -log L, given as the generator's arrays."""
+
+    def __init__(self, prob: dict):
+        self.prob = prob
+        d = int(prob["d"])
+        self.d = d
+        pa = np.ascontiguousarray(prob["prior_a"], np.float64)
+        pb = np.ascontiguousarray(prob["prior_b"], np.float64)
+        pk = PRIOR_BOX if prob["prior"] == "box" else PRIOR_GAUSS
+        if prob["lik"] == "mixture":
+            K = int(prob["K"])
+            self._keep = [np.ascontiguousarray(prob["logw"], np.float64),
+                          np.ascontiguousarray(prob["mu"], np.float64).reshape(K, d),
+                          np.ascontiguousarray(prob["cov"], np.float64).reshape(K, d, d)]
+            ptrs = [a.ctypes.data for a in self._keep]
+            self.h = lib().or_problem_new(d, pk, pa, pb, LIK_MIXTURE, K, *ptrs)
+        elif prob["lik"] == "funnel":
+            self.h = lib().or_problem_new(d, pk, pa, pb, LIK_FUNNEL, 0, None, None, None)
+        else:
+            raise ValueError(prob["lik"])
+        if not self.h:
+            raise ValueError("oracle rejected the problem")
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().or_problem_free(self.h)
+            self.h = None
+
+    def loglik(self, x) -> np.ndarray:
+        x = np.ascontiguousarray(np.atleast_2d(x), np.float64)
+        return np.array([lib().or_loglik(self.h, xi) for xi in x])
+
+    def logprior(self, x) -> np.ndarray:
+        x = np.ascontiguousarray(np.atleast_2d(x), np.float64)
+        return np.array([lib().or_logprior(self.h, xi) for xi in x])
+
+    def hrss_chain(self, x, logL, Lstar, Lsig, width, p, seed, run_id, it, chain,
+                   stepout_cap=10, shrink_cap=100, trace=False):
+        """One chain of p HRSS steps; returns (x, logL, counters[6], trace or None)."""
+        x = np.array(x, np.float64, copy=True)
+        lv = np.array([logL], np.float64)
+        ctr = np.zeros(6, np.int64)
+        tr = np.zeros((p, 4), np.int32) if trace else None
+        lib().or_hrss_chain(self.h, x, lv, float(Lstar),
+                            np.ascontiguousarray(Lsig, np.float64), float(width), int(p),
+                            int(stepout_cap), int(shrink_cap), int(seed), int(run_id), int(it),
+                            int(chain), ctr, tr.ctypes.data if trace else None)
+        return x, float(lv[0]), ctr, tr
+
+
+class Run:
+    """One NS run of the oracle: init, step until done, logz."""
+
+    def __init__(self, problem: Problem, m, k, p, width, seed, run_id=0, term_frac=1e-3,
+                 stepout_cap=10, shrink_cap=100, threads=1):
+        self.P = problem
+        self.m, self.k, self.p, self.d = m, k, p, problem.d
+        self.threads = threads
+        self.h = lib().or_run_new(problem.h, m, k, p, float(width), stepout_cap, shrink_cap,
+                                  float(term_frac), int(seed), int(run_id))
+        if not self.h:
+            raise ValueError("oracle rejected the run configuration")
+        self.done = False
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().or_run_free(self.h)
+            self.h = None
+
+    def init(self) -> bool:
+        self.done = bool(lib().or_init(self.h))
+        return self.done
+
+    def step(self) -> bool:
+        r = lib().or_step(self.h, int(self.threads))
+        if r < 0:
+            raise RuntimeError("no survivor strictly above the threshold")
+        self.done = bool(r)
+        return self.done
+
+    def run(self, max_iter=100000) -> int:
+        if not self.done:
+            it = 0
+            while not self.done and it < max_iter:
+                self.step()
+                it += 1
+        return self.iter
+
+    def logz(self):
+        out = np.zeros(3)
+        lib().or_logz(self.h, out)
+        return float(out[0]), float(out[1]), float(out[2])
+
+    def state(self) -> dict:
+        m, d = self.m, self.d
+        x = np.zeros((m, d)); logL = np.zeros(m); perm = np.zeros(m, np.int32)
+        sc = np.zeros(4); it = np.zeros(1, np.int64); ctr = np.zeros(6, np.int64)
+        lib().or_get_state(self.h, x, logL, perm, sc, it, ctr)
+        return dict(x=x, logL=logL, perm=perm, Lstar=sc[0], logZ=sc[1], logX=sc[2], M=sc[3],
+                    iter=int(it[0]), evals=int(ctr[0]), tests=int(ctr[1]),
+                    prior_rejects=int(ctr[2]), stepout_caps=int(ctr[3]),
+                    shrink_caps=int(ctr[4]), nonfinite=int(ctr[5]))
+
+    def set_state(self, x, logL, logZ, logX, M, iter_):
+        lib().or_set_state(self.h, np.ascontiguousarray(x, np.float64),
+                           np.ascontiguousarray(logL, np.float64),
+                           np.array([logZ, logX, M], np.float64), int(iter_))
+
+    def aux(self):
+        Ls = np.zeros((self.d, self.d)); par = np.zeros(self.k, np.int32)
+        lib().or_get_aux(self.h, Ls, par)
+        return Ls, par
+
+    def dead(self) -> np.ndarray:
+        n = lib().or_get_dead(self.h, None, 0)
+        out = np.zeros(n)
+        lib().or_get_dead(self.h, out.ctypes.data, n)
+        return out
+
+    @property
+    def iter(self) -> int:
+        return self.state()["iter"]
