@@ -1,0 +1,160 @@
+"""Benchmark: slice-step likelihood evaluations per second of Nested Slice Sampling on the
+d=64, 8-component Gaussian mixture (uniform prior [-10,10]^64, n_live=2000, k=1000), mixed
+precision vs FP64, with every timed run checked against the closed-form evidence
+ln Z = -64 ln 20 (|d ln Z| < 3 sigma, sigma = sqrt(H / n_live)).
+
+One step = one complete run of the hot path on the GPU: prior draws and the first delete-k,
+then iterations of whitening, direction generation, k parallel HRSS chains, replacement,
+delete-k and evidence accumulation until the remaining-evidence bound is below 1e-3 of Z, then
+the final live-set contribution.  The problem is uploaded once, before the timed region.
+
+Prints one JSON line (see the keys below).  --gpus N > 1 is not supported (one GPU).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FLOP_PER_EVAL_MIX = None  # set from the problem: K d (d+1) + 3 K d
+
+
+def algorithmic_flop_per_eval(K: int, d: int) -> int:
+    """Triangular quadratic form per component (d(d+1) flop), residual, square and scaling
+    (3d), per component: the work the likelihood must do per evaluation."""
+    return K * d * (d + 1) + 3 * K * d
+
+
+def run_gpu(N, prob, precision, seeds, p, warmup, timing=True):
+    """Runs len(seeds) full NS runs on one context; returns per-run records and totals."""
+    import torch
+    R = N.NSRun(prob, p=p, seed=seeds[0], precision=precision, timing=timing)
+    for w in range(warmup):
+        R.reset(10_000 + w)
+        R.run()
+    recs = []
+    torch.cuda.synchronize()
+    t_all = time.perf_counter()
+    for s in seeds:
+        t0 = time.perf_counter()
+        R.reset(s)
+        it = R.run()
+        z, err, H = R.logz()
+        dt = time.perf_counter() - t0
+        st = R.stats()
+        recs.append(dict(seed=s, iters=it, wall_s=dt, evals=st["evals"], logz=z, err=err, H=H,
+                         hrss_ms=st["hrss_ms"], hrss_launches=st["hrss_launches"],
+                         rechecks=st["rechecks"], band_violations=st["band_violations"],
+                         tests=st["tests"]))
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t_all
+    R.close()
+    return recs, total
+
+
+def cpu_baseline(prob, p, seconds_budget=20.0):
+    """The FP64 oracle on the host cores: init + iterations of the same workload until the
+    time budget; evals/s over the timed iterations."""
+    from oracle import oracle as O, theory as T
+    threads = min(os.cpu_count() or 1, 16)
+    P = O.Problem(prob)
+    run = O.Run(P, prob["m"], prob["k"], p, T.width_whitened(prob["d"]), 0, threads=threads)
+    run.init()
+    e0 = run.state()["evals"]
+    t0 = time.perf_counter()
+    iters = 0
+    while time.perf_counter() - t0 < seconds_budget and iters < 50:
+        run.step()
+        iters += 1
+    dt = time.perf_counter() - t0
+    ev = run.state()["evals"] - e0
+    return dict(value=ev / dt, unit="evals/s", cores=threads, kind="oracle",
+                sample=f"first {iters} iterations after init of the same workload "
+                       f"(p={p}), {ev} evaluations in {dt:.1f} s, OpenMP over chains")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3, help="timed full runs (seeds 0..K-1)")
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", default="bf16x3",
+                    choices=["bf16", "fp16", "bf16x3", "fp16x3", "fp64"])
+    ap.add_argument("--chain-factor", type=int, default=20,
+                    help="chain length p = factor * d (20 is the shortest that meets the 3 sigma "
+                         "check on this mixture; 5 is biased)")
+    ap.add_argument("--fp64-steps", type=int, default=1, help="FP64 comparison runs (0 = skip)")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+
+    from paper_2601_23252_amd import nss as N, problems as G
+    N.load()
+    prob = G.config3()
+    d, K = prob["d"], prob["K"]
+    p = args.chain_factor * d
+    truth = -d * math.log(20.0)
+    fpe = algorithmic_flop_per_eval(K, d)
+
+    seeds = list(range(args.steps))
+    recs, total = run_gpu(N, prob, args.precision, seeds, p, args.warmup)
+    evals = sum(r["evals"] for r in recs)
+    value = evals / total
+    hrss_s = sum(r["hrss_ms"] for r in recs) / 1e3
+    launches = sum(r["hrss_launches"] for r in recs)
+    z_scores = [(r["logz"] - truth) / r["err"] for r in recs]
+    within = all(abs(z) < 3.0 for z in z_scores)
+    mixed = args.precision != "fp64"
+    peak = 2.5e15 if mixed else 78.6e12
+    achieved = evals * fpe / hrss_s if hrss_s > 0 else 0.0
+
+    out = {
+        "metric": "slice-step likelihood evals/s (d=64 mixture), mixed vs FP64, at |dlogZ|<3sigma",
+        "value": value,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * total / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"bf16": "bf16", "bf16x3": "bf16", "fp16": "fp16", "fp16x3": "fp16",
+                  "fp64": "f64"}[args.precision],
+        "data": "synthetic",
+        "config": {"workload": "mixture8_d64_uniform10_nlive2000_k1000", "d": d, "n_comp": K,
+                   "n_live": prob["m"], "k": prob["k"], "chain_len": p,
+                   "precision": args.precision, "term_frac": 1e-3, "seeds": seeds},
+        "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                     "kernel": "k_hrss", "flop_per_eval": fpe,
+                     "avg_launch_ms": 1e3 * hrss_s / max(1, launches)},
+        "lnz": {"truth": truth, "z_scores": z_scores, "all_within_3sigma": within,
+                "logz": [r["logz"] for r in recs], "sigma": [r["err"] for r in recs]},
+        "rechecks_per_eval": sum(r["rechecks"] for r in recs) / max(1, evals),
+        "band_violations": sum(r["band_violations"] for r in recs),
+        "iterations": [r["iters"] for r in recs],
+    }
+    if args.fp64_steps > 0 and mixed:
+        r64, t64 = run_gpu(N, prob, "fp64", list(range(args.fp64_steps)), p, 0)
+        ev64 = sum(r["evals"] for r in r64)
+        out["fp64"] = {"value": ev64 / t64, "unit": "evals/s",
+                       "z_scores": [(r["logz"] - truth) / r["err"] for r in r64],
+                       "hrss_frac_of_fp64_peak": ev64 * fpe / (sum(r["hrss_ms"] for r in r64) / 1e3) / 78.6e12}
+        out["speedup_vs_fp64"] = value / out["fp64"]["value"]
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(prob, p, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,213 @@
+/*
+ * nss.h -- C ABI of the MI355X (gfx950) Nested Slice Sampling library (libnss.so).
+ *
+ * The library runs the data-parallel hot path of Nested Slice Sampling (NSS, arXiv 2601.23252)
+ * on one GPU: batched delete-k nested sampling whose k replacements are produced in parallel by
+ * Hit-and-Run Slice Sampling (HRSS) chains under the hard constraint logL(x) > L*, with batched
+ * likelihood evaluation inside each chain step and log-sum-exp evidence accumulation.
+ *
+ * Problem statement (Sec. 1, eq. target / integral_Z): a prior (reference density) Pi and an
+ * energy E = -log L; the evidence is Z = integral of L(x) Pi(x) dx.  Run shape (Sec. 3.1,
+ * Alg. "Nested Sampling outer kernel"; Sec. 3.2): n_live = m live points, k deletions per
+ * iteration (1 <= k <= m-1), chain length p HRSS steps per replacement.
+ *
+ * Conventions for every call:
+ *  - Ownership: all array arguments are HOST pointers.  ns_init copies everything it needs; the
+ *    caller may free its arrays on return.  The context owns all device memory until ns_free.
+ *  - Layout: points are row-major host arrays, x[i*d + j] = coordinate j of point i.
+ *    Matrices are row-major, cov[(c*d + r)*d + s] = entry (r, s) of component c.
+ *  - Streams: work is enqueued on the hipStream_t passed to ns_init (NULL = the library's own
+ *    stream).  Calls returning host values (ns_step's done flag, ns_run, ns_logz, ns_stats,
+ *    state access) synchronise that stream.
+ *  - Errors: a call returns an ns_status; nothing throws across the ABI.  On failure,
+ *    ns_last_error(ctx) describes it (ns_init failures: ns_last_error(NULL)).  A failed call
+ *    leaves the context usable unless it returned NS_EDEVICE.
+ *  - Threading: calls on one context are not thread-safe; separate contexts are independent.
+ *  - Numerics: a NaN or +inf log-likelihood is treated as -inf (the candidate is rejected) and
+ *    counted in ns_stats_t.nonfinite.
+ */
+#ifndef NSS_H
+#define NSS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ns_ctx ns_ctx;
+
+typedef enum {
+    NS_OK = 0,
+    NS_DONE = 1,            /* ns_step: the run had already terminated; nothing was done */
+    NS_EINVAL = -1,         /* invalid argument */
+    NS_ENOMEM = -2,         /* device or host allocation failed */
+    NS_EDEVICE = -3,        /* a HIP call failed; the context should be freed */
+    NS_ESTATE = -4,         /* no survivor lies strictly above L* (likelihood plateau) */
+    NS_EUNSUPPORTED = -5    /* valid but outside what this build supports (sizes, kinds) */
+} ns_status;
+
+/* Prior Pi, one factor per coordinate (Sec. 1, the reference density). */
+typedef enum {
+    NS_PRIOR_BOX = 0,        /* uniform on [a_j, b_j] */
+    NS_PRIOR_GAUSS_DIAG = 1  /* normal with mean a_j and standard deviation b_j > 0 */
+} ns_prior_kind;
+
+/* Likelihood families L = exp(-E). */
+typedef enum {
+    /* log L(x) = log sum_c exp(logw_c) N(x; mean_c, cov_c): normalised Gaussian mixture,
+     * n_comp >= 1 components (n_comp = 1: a single, possibly correlated, Gaussian). */
+    NS_LIK_MIXTURE = 1,
+    /* Neal's funnel: v = x_0 ~ N(0, 9), x_j | v ~ N(0, e^v) for j = 1..d-1, normalised. */
+    NS_LIK_FUNNEL = 2
+} ns_lik_kind;
+
+/* Arithmetic of the likelihood evaluations inside the chains. */
+typedef enum {
+    NS_FP64 = 0,       /* everything in FP64 (the plain form) */
+    NS_MIXED_BF16 = 1, /* mixture quadratic forms as BF16 MFMA products with FP32 accumulation
+                        * and FP32 log-sum-exp; a candidate whose estimate falls within a guard
+                        * band of L* is re-evaluated in FP64 before the decision; stored logL,
+                        * L*, and the evidence are FP64 (App. A.6 "Reduced-precision
+                        * execution": HRSS only compares log densities) */
+    NS_MIXED_FP16 = 2, /* as NS_MIXED_BF16 with FP16 operands (8x smaller rounding error) */
+    NS_MIXED_BF16X3 = 3, /* split precision: W and the residual are each a 16-bit value plus a
+                          * 16-bit remainder; W_hi r_hi + W_hi r_lo + W_lo r_hi on three BF16
+                          * MFMAs (~600x smaller error than NS_MIXED_BF16, so FP64 re-checks
+                          * near L* become rare) */
+    NS_MIXED_FP16X3 = 4  /* as NS_MIXED_BF16X3 with FP16 parts */
+} ns_precision;
+
+typedef struct {
+    int32_t kind;       /* ns_prior_kind */
+    int32_t d;          /* dimension, 1 <= d <= 128 */
+    const double *a;    /* [d] box lower bound | Gaussian mean */
+    const double *b;    /* [d] box upper bound | Gaussian standard deviation */
+} ns_prior;
+
+typedef struct {
+    int32_t kind;       /* ns_lik_kind */
+    int32_t d;          /* must equal the prior's d */
+    int32_t n_comp;     /* NS_LIK_MIXTURE: number of components, 1 <= n_comp <= 64 */
+    const double *logw; /* [n_comp] log weights (normalised by the caller if Z must be) */
+    const double *mean; /* [n_comp * d] component means */
+    const double *cov;  /* [n_comp * d * d] symmetric positive-definite covariances */
+} ns_energy;
+
+typedef struct {
+    int32_t n_live;       /* m, 2 <= m <= 8192 */
+    int32_t k;            /* deletions per iteration, 1 <= k <= m-1 (Sec. 3.1) */
+    int32_t chain_len;    /* p >= 1 HRSS steps per replacement (Sec. 3.2) */
+    double width;         /* slice width in whitened units; <= 0 selects the tuning rule
+                           * w = 4 kappa R sqrt(2/(pi d)) for the unit-covariance ball,
+                           * R = sqrt(d+2), kappa = 1.3035 (Sec. 3.3; App. E ball corollary) */
+    int32_t stepout_cap;  /* expansions per side, default 10 (App. A.6) */
+    int32_t shrink_cap;   /* shrink proposals before a null move, default 100 (App. A.6) */
+    double term_frac;     /* stop when logX + max logL_live - logZ < ln(term_frac) (Sec. 2.1);
+                           * <= 0 never stops */
+    uint64_t seed;        /* Philox key: (seed_lo, seed_hi ^ run_id) */
+    uint32_t run_id;
+    int32_t precision;    /* ns_precision */
+    int32_t max_iter;     /* capacity of the dead-point record in iterations (>= 1) */
+    int32_t flags;        /* NS_FLAG_* */
+} ns_config;
+
+#define NS_FLAG_TRACE  1  /* record per-chain, per-step (left, right, shrinks, accepted) */
+#define NS_FLAG_TIMING 2  /* time every HRSS kernel with HIP events on the context's stream */
+#define NS_FLAG_INLINE_DIRECTIONS 4  /* chains draw their directions themselves instead of a
+                                      * per-iteration direction buffer of k*p*d doubles (the
+                                      * buffer is also skipped when it would exceed 4 GiB) */
+
+typedef struct {
+    int64_t iterations;     /* completed ns_step iterations */
+    int64_t evals;          /* likelihood evaluations inside chains (candidates that passed the
+                             * prior support and height tests); speculative / padded rows and
+                             * FP64 re-checks are not counted */
+    int64_t tests;          /* all slice-membership tests, including prior rejections */
+    int64_t prior_rejects;
+    int64_t stepout_caps;   /* sides that stopped at the expansion cap */
+    int64_t shrink_caps;    /* null moves from the shrink cap */
+    int64_t nonfinite;      /* NaN/+inf log-likelihoods treated as -inf */
+    int64_t rechecks;       /* mixed precision: candidates re-evaluated in FP64 near L* */
+    int64_t band_violations;/* mixed precision: accepted points whose FP64 logL <= L* */
+    int64_t whiten_fallbacks; /* iterations whose covariance factorisation failed (diagonal used) */
+    int64_t n_dead;         /* dead points recorded */
+    double hrss_ms;         /* NS_FLAG_TIMING: summed HRSS kernel time (HIP events) */
+    int64_t hrss_launches;
+    double width;           /* slice width in use */
+} ns_stats_t;
+
+/* Host arrays for state access (any pointer may be NULL to skip it). */
+typedef struct {
+    double *x;        /* [m*d] live points, row-major */
+    double *logL;     /* [m] */
+    int32_t *perm;    /* [m] live indices in ascending (logL, index) order; first k = deleted */
+    double *Lsig;     /* [d*d] lower Cholesky factor of the last direction covariance */
+    int32_t *parents; /* [k] live indices resampled as parents in the last iteration */
+    double Lstar;     /* threshold: logL of the k-th worst live point */
+    double logZ;      /* evidence of the dead points so far */
+    double logX;      /* log prior volume after the recorded deaths */
+    double M;         /* posterior mean of logL over the dead points; H = M - logZ */
+    int64_t iter;
+    int32_t done;
+} ns_state_view;
+
+/* Create a run: copy the problem to the device, draw m points from the prior (Philox purpose
+ * INIT), evaluate them in FP64, delete the k worst and account their evidence (Alg. outer
+ * kernel, first evaluate-sort-record).  Returns NS_EINVAL for inconsistent arguments,
+ * NS_EUNSUPPORTED for sizes beyond this build. */
+ns_status ns_init(const ns_prior *prior, const ns_energy *energy, const ns_config *cfg,
+                  void *hip_stream, ns_ctx **out);
+
+/* Restart the run on an existing context with a new Philox key (seed, run_id): the problem
+ * stays on the device; the live set is redrawn from the prior and evaluated, the evidence,
+ * counters, dead record and timing are cleared, and the first delete-k is accounted, exactly
+ * as ns_init does.  Lets a caller time runs without the problem upload. */
+ns_status ns_reset(ns_ctx *ctx, uint64_t seed, uint32_t run_id);
+
+/* One outer iteration (Sec. 3.1 (ii)-(iv) then (i)): whiten (survivor covariance, Sec. 3.2
+ * "Direction metric"), resample k parents uniformly among survivors with logL > L*, run the k
+ * HRSS chains of p steps, replace the deleted points, delete the next k worst, accumulate the
+ * evidence (Sec. 2.1, App. D.2.1), test termination.  *done = 1 once terminated.
+ * Returns NS_DONE (and does nothing) if the run had already terminated. */
+ns_status ns_step(ns_ctx *ctx, int32_t *done);
+
+/* Iterate until termination or max_iter further iterations; *iters = iterations done in this
+ * call.  The stop iteration is the same as with repeated ns_step calls. */
+ns_status ns_run(ns_ctx *ctx, int32_t max_iter, int32_t *iters);
+
+/* Evidence including the live set's remaining contribution X * mean(L_live) (non-destructive):
+ * ln Z, its error sqrt(H/m) and the information H (Sec. 2.1). */
+ns_status ns_logz(ns_ctx *ctx, double *logz, double *logz_err, double *H);
+
+ns_status ns_stats(ns_ctx *ctx, ns_stats_t *out);
+
+/* Copy the state to host arrays / overwrite it from host arrays.  ns_set_state takes x, logL,
+ * logZ, logX, M and iter; it recomputes the delete-k order and L* without re-accounting. */
+ns_status ns_get_state(ns_ctx *ctx, ns_state_view *view);
+ns_status ns_set_state(ns_ctx *ctx, const ns_state_view *view);
+
+/* Copy the dead-point log-likelihoods (ascending death order) to out[0..cap); *n = total. */
+ns_status ns_get_dead(ns_ctx *ctx, double *out, int64_t cap, int64_t *n);
+
+/* NS_FLAG_TRACE: copy the last iteration's trace, out[(j*p + s)*4 + {0,1,2,3}] = left
+ * expansions, right expansions, shrink proposals, accepted, for chain j and step s. */
+ns_status ns_get_trace(ns_ctx *ctx, int32_t *out);
+
+/* Evaluate the likelihood at n host points x[n*d] with the given precision (NS_FP64 or a mixed
+ * mode), writing out[n].  Runs the same device evaluators as the chains; for tests. */
+ns_status ns_eval_loglik(ns_ctx *ctx, const double *x, int32_t n, int32_t precision,
+                         double *out);
+
+void ns_free(ns_ctx *ctx);
+
+const char *ns_last_error(const ns_ctx *ctx);
+
+/* Default configuration values (caps 10/100, term_frac 1e-3, width rule, FP64). */
+void ns_config_default(ns_config *cfg);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NSS_H */

@@ -1,0 +1,1471 @@
+// gfx950 kernels of the Nested Slice Sampling hot path.
+//
+//  k_init_draw   prior draws of the m initial live points (Philox purpose INIT)
+//  k_eval        batched likelihood of n points, 16 rows per workgroup (init, tests)
+//  k_select      delete-k: sort (logL, index), threshold L*, unrolled evidence update of the
+//                k deaths, dead record, termination flag (Sec. 2.1; App. D.2.1)
+//  k_cov/k_chol  whitening: survivors' covariance + jitter, lower Cholesky factor (Sec. 3.2)
+//  k_hrss        the k HRSS chains (App. A.6): one wave runs one chain's finite-state machine
+//                (direction, bracket, step-out, shrink), the four waves of a workgroup
+//                evaluate the tile of up to 16 candidate rows together on MFMA
+//  k_logz        final live-set contribution to the evidence (Sec. 2.1)
+#include "nss_internal.hpp"
+#include "nss_rng.hpp"
+
+#include <math.h>
+
+namespace nss {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+
+#define LOG_2PI 1.8378770664093454836
+
+// ------------------------------------------------------------------------------------------
+// wave helpers
+// ------------------------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int o = 32; o; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ float wave_sumf(float v)
+{
+#pragma unroll
+    for (int o = 32; o; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ float wave_maxf(float v)
+{
+#pragma unroll
+    for (int o = 32; o; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+// Make this wave's LDS writes visible to its own other lanes.
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+// Reductions over the 16 lanes of a DPP row with VALU data movement (quad swaps, half-row and
+// row mirrors); every lane of the row ends with the same result.
+template <int CTRL>
+__device__ __forceinline__ float dppf(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
+                                                                 CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dppd(double v)
+{
+    int2 p = __builtin_bit_cast(int2, v);
+    p.x = __builtin_amdgcn_update_dpp(0, p.x, CTRL, 0xF, 0xF, false);
+    p.y = __builtin_amdgcn_update_dpp(0, p.y, CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, p);
+}
+#define DPP_XOR1 0xB1   /* quad_perm [1,0,3,2] */
+#define DPP_XOR2 0x4E   /* quad_perm [2,3,0,1] */
+#define DPP_HMIR 0x141  /* row_half_mirror */
+#define DPP_RMIR 0x140  /* row_mirror */
+__device__ __forceinline__ float row_sum16(float v)
+{
+    v += dppf<DPP_XOR1>(v); v += dppf<DPP_XOR2>(v); v += dppf<DPP_HMIR>(v); v += dppf<DPP_RMIR>(v);
+    return v;
+}
+__device__ __forceinline__ float row_max16(float v)
+{
+    v = fmaxf(v, dppf<DPP_XOR1>(v)); v = fmaxf(v, dppf<DPP_XOR2>(v));
+    v = fmaxf(v, dppf<DPP_HMIR>(v)); v = fmaxf(v, dppf<DPP_RMIR>(v));
+    return v;
+}
+__device__ __forceinline__ double row_sum16(double v)
+{
+    v += dppd<DPP_XOR1>(v); v += dppd<DPP_XOR2>(v); v += dppd<DPP_HMIR>(v); v += dppd<DPP_RMIR>(v);
+    return v;
+}
+__device__ __forceinline__ double row_max16(double v)
+{
+    v = fmax(v, dppd<DPP_XOR1>(v)); v = fmax(v, dppd<DPP_XOR2>(v));
+    v = fmax(v, dppd<DPP_HMIR>(v)); v = fmax(v, dppd<DPP_RMIR>(v));
+    return v;
+}
+__device__ __forceinline__ double readlane_d(double v, int lane)
+{
+    int2 p = __builtin_bit_cast(int2, v);
+    p.x = __builtin_amdgcn_readlane(p.x, lane);
+    p.y = __builtin_amdgcn_readlane(p.y, lane);
+    return __builtin_bit_cast(double, p);
+}
+// Sum over the wave: row sums, then the four row results combined (uniform result).
+__device__ __forceinline__ double wave_sum_fast(double v)
+{
+    v = row_sum16(v);
+    return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
+}
+
+__device__ __forceinline__ double sanitize(double L, unsigned long long &nonfinite)
+{
+    if (L != L || L == INFINITY) { ++nonfinite; return -INFINITY; }
+    return L;
+}
+
+// ------------------------------------------------------------------------------------------
+// LDS layout of the chain / evaluation workgroups (byte offsets; identical on host)
+// ------------------------------------------------------------------------------------------
+struct HLayout {
+    int z, cand, cand32, mu64, mu32, cst, cst32, pa, pb, L, L32, mask, rc, q, q32, lsig,
+        total;
+};
+__host__ __device__ inline int al16(int b) { return (b + 15) & ~15; }
+// direction factor in LDS: dense rows of stride D+1 (conflict-free column reads) up to D = 64,
+// packed lower triangle for D = 128
+__host__ __device__ inline int lsig_doubles(int D) { return D <= 64 ? D * (D + 1) : D * (D + 1) / 2; }
+// partial quadratic forms of a tile: q[row * q_stride + (c * D/16 + jb) * 4 + g], one value per
+// (candidate row, component, column block, lane group g); the row stride is padded by 4
+__host__ __device__ inline int q_stride(int D, int K) { return (K > 0 ? K : 1) * (D / 16) * 4 + 4; }
+__host__ __device__ inline HLayout hrss_layout(int D, int K)
+{
+    const int Kc = K > 0 ? K : 1;
+    HLayout o;
+    int off = 0;
+    o.z = off; off += al16(4 * D * 8);
+    o.cand = off; off += al16(kRows * (D + 1) * 8);
+    o.cand32 = off; off += al16(kRows * (D + 4) * 4);
+    o.mu64 = off; off += al16(Kc * D * 8);
+    o.mu32 = off; off += al16(Kc * D * 4);
+    o.cst = off; off += al16(Kc * 8);
+    o.cst32 = off; off += al16(Kc * 4);
+    o.pa = off; off += al16(D * 8);
+    o.pb = off; off += al16(D * 8);
+    o.L = off; off += al16(kRows * 8);
+    o.L32 = off; off += al16(kRows * 4);
+    o.mask = off; off += al16(kRows * 4);
+    o.rc = off; off += al16(kRows * 4);
+    o.q = off; off += al16(kRows * q_stride(D, K) * 8);
+    o.q32 = off; off += al16(kRows * q_stride(D, K) * 4);
+    o.lsig = off; off += al16(lsig_doubles(D) * 8);
+    o.total = off;
+    return o;
+}
+
+// LDS views of one workgroup's evaluation tile and the problem constants it stages.
+struct Tile {
+    double *cand;        // [16][D+1] candidate rows, FP64
+    float *cand32;       // [16][D+4] candidate rows, FP32 (mixed precision)
+    double *mu64;        // [K][D]
+    float *mu32;         // [K][D]
+    double *cst;         // [K] log w_c - d/2 log(2 pi) + log det W_c
+    float *cst32;
+    double *pa, *pb;     // prior parameters, [D]
+    double *L;           // [16] FP64 results
+    float *L32;          // [16] FP32 results
+    int *mask;           // [16] rows to evaluate
+    int *rc;             // [16] rows to re-check in FP64
+    double *q;           // [16][q_stride] partial quadratic forms
+    float *q32;
+};
+__device__ __forceinline__ Tile tile_of(unsigned char *smem, const HLayout &lay)
+{
+    Tile t;
+    t.cand = (double *)(smem + lay.cand);
+    t.cand32 = (float *)(smem + lay.cand32);
+    t.mu64 = (double *)(smem + lay.mu64);
+    t.mu32 = (float *)(smem + lay.mu32);
+    t.cst = (double *)(smem + lay.cst);
+    t.cst32 = (float *)(smem + lay.cst32);
+    t.pa = (double *)(smem + lay.pa);
+    t.pb = (double *)(smem + lay.pb);
+    t.L = (double *)(smem + lay.L);
+    t.L32 = (float *)(smem + lay.L32);
+    t.mask = (int *)(smem + lay.mask);
+    t.rc = (int *)(smem + lay.rc);
+    t.q = (double *)(smem + lay.q);
+    t.q32 = (float *)(smem + lay.q32);
+    return t;
+}
+// Copy the problem constants into LDS (caller synchronises).
+template <int D>
+__device__ __forceinline__ void stage_problem(const DevProblem &P, const Tile &T)
+{
+    const int tid = threadIdx.x;
+    for (int i = tid; i < P.K * D; i += blockDim.x) { T.mu64[i] = P.mu[i]; T.mu32[i] = P.mu32[i]; }
+    for (int i = tid; i < P.K; i += blockDim.x) { T.cst[i] = P.cst[i]; T.cst32[i] = P.cst32[i]; }
+    for (int i = tid; i < D; i += blockDim.x) { T.pa[i] = P.pa[i]; T.pb[i] = P.pb[i]; }
+}
+
+// ------------------------------------------------------------------------------------------
+// Likelihood tiles.  16 candidate rows live in LDS; mask[r] != 0 marks rows to evaluate.
+// All 256 threads call these; they end with a barrier, after which out[r] holds log L of
+// every masked row.
+//
+// Mixture work unit = (component c, 16-column block jb of W_c^T), W_c the inverse of the lower
+// Cholesky factor of cov_c, so the quadratic form is |W_c (x - mu_c)|^2 and W_c is lower
+// triangular: block jb needs k <= 16 jb + 15 only.  Units are dealt to the four waves so that
+// each wave gets the same mix of short and long blocks: wave w's uu-th unit is
+//   D/16 = 2: u = w + 4 uu (c = u/2, jb = u%2);
+//   D/16 = 4: c = uu, jb = (w - uu) mod 4;
+//   D/16 = 8: c = uu/2, jb = kk or 7 - kk with kk = (w - c) mod 4.
+// ------------------------------------------------------------------------------------------
+template <int NJB>
+__device__ __forceinline__ void unit_of(int w, int uu, int &c, int &jb)
+{
+    if constexpr (NJB == 2) {
+        const int u = w + 4 * uu;
+        c = u >> 1;
+        jb = u & 1;
+    } else if constexpr (NJB == 4) {
+        c = uu;
+        jb = (w - uu) & 3;
+    } else {
+        c = uu >> 1;
+        const int kk = (w - c) & 3;
+        jb = (uu & 1) ? 7 - kk : kk;
+    }
+}
+
+// log L = LSE_c (cst_c - q_c / 2) from the partials.  Wave w handles rows 4w..4w+3: the lanes
+// of DPP row rr take row 4w+rr, lane c of the row takes components c, c+16, ...
+template <int D, typename F>
+__device__ __forceinline__ F lse_rows(const DevProblem &P, const F *q, const F *cst, int r, int c)
+{
+    constexpr int NJB = D / 16;
+    const int QS = q_stride(D, P.K);
+    F mx = -INFINITY, se = 0;
+    for (int c0 = 0; c0 < P.K; c0 += 16) {
+        const int cc = c0 + c;
+        F t = -INFINITY;
+        if (cc < P.K) {
+            const F *src = q + r * QS + cc * NJB * 4;
+            F s = 0;
+#pragma unroll
+            for (int i = 0; i < NJB * 4; ++i) s += src[i];
+            t = cst[cc] - (F)0.5 * s;
+        }
+        const F m = row_max16(t);
+        F e;
+        if constexpr (sizeof(F) == 8) e = (cc < P.K && m != -INFINITY) ? exp(t - m) : 0.0;
+        else e = (cc < P.K && m != -INFINITY) ? __expf(t - m) : 0.f;
+        e = row_sum16(e);
+        if (m > mx) {
+            if constexpr (sizeof(F) == 8) se = se * exp(mx - m) + e;
+            else se = se * __expf(mx - m) + e;
+            mx = m;
+        } else if (m != -INFINITY) {
+            if constexpr (sizeof(F) == 8) se += e * exp(m - mx);
+            else se += e * __expf(m - mx);
+        }
+    }
+    if (mx == -INFINITY) return -INFINITY;
+    if constexpr (sizeof(F) == 8) return mx + log(se);
+    else return mx + __logf(se);
+}
+
+// FP64 mixture tile on v_mfma_f64_16x16x4 with W as the A operand and the residuals as B:
+// D[j][n] = sum_k W_c[16 jb + j][k] (x_n - mu_c)[k], so lane l, register i holds
+// y[n = l & 15][16 jb + (l >> 4) + 4 i]; its four squares sum to one partial per lane group.
+// The unit's B fragments (pre-swizzled, 512 contiguous bytes per k-step) are requested
+// before the first product so their L2 latencies overlap.
+template <int D>
+__device__ void mix_eval64(const DevProblem &P, const Tile &T, const int *mask, double *out)
+{
+    constexpr int NJB = D / 16, NKS = D / 4, LDC = D + 1;
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int row = l & 15, kq = l >> 4;
+    const int QS = q_stride(D, P.K);
+    const bool on = mask[row] != 0;
+    const double *cr = T.cand + row * LDC;
+    for (int uu = 0;; ++uu) {
+        int c, jb;
+        unit_of<NJB>(w, uu, c, jb);
+        if (c >= P.K) break;
+        const int u = c * NJB + jb;
+        const int ke = (4 * jb + 4 < NKS) ? 4 * jb + 4 : NKS;
+        const double *wf = P.wf64 + (size_t)u * NKS * 64 + l;
+        double bfr[NKS];
+#pragma unroll
+        for (int ks = 0; ks < NKS; ++ks) bfr[ks] = (ks < ke) ? wf[ks * 64] : 0.0;
+        const double *mu = T.mu64 + c * D;
+        d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int ks = 0; ks < NKS; ++ks) {
+            if (ks < ke) {
+                const int kk = 4 * ks + kq;
+                const double b = on ? cr[kk] - mu[kk] : 0.0;
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(bfr[ks], b, acc, 0, 0, 0);
+            }
+        }
+        T.q[row * QS + u * 4 + kq] = (acc[0] * acc[0] + acc[1] * acc[1]) + (acc[2] * acc[2] + acc[3] * acc[3]);
+    }
+    __syncthreads();
+    {
+        const int r = 4 * w + (l >> 4), c = l & 15;
+        const double L = lse_rows<D, double>(P, T.q, T.cst, r, c);
+        if (c == 0) out[r] = L;
+    }
+    __syncthreads();
+}
+
+template <int MODE> struct MixTraits;
+template <> struct MixTraits<MODE_BF16> { typedef __bf16 H; typedef bf8 V8; static constexpr int NP = 1; };
+template <> struct MixTraits<MODE_FP16> { typedef _Float16 H; typedef h8 V8; static constexpr int NP = 1; };
+template <> struct MixTraits<MODE_BF16X3> { typedef __bf16 H; typedef bf8 V8; static constexpr int NP = 2; };
+template <> struct MixTraits<MODE_FP16X3> { typedef _Float16 H; typedef h8 V8; static constexpr int NP = 2; };
+
+__device__ __forceinline__ f4 mfma16(bf8 a, bf8 b, f4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4 mfma16(h8 a, h8 b, f4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+}
+
+// Register-resident 16-bit W fragments of one wave: v[0] = rounded W, v[1] = W - v[0] rounded
+// (split-precision modes only).
+template <int D, int UPW, int NP>
+struct WFrag { uint4 v[NP][UPW][D / 32]; };
+
+// Mixed-precision mixture tile: residuals x - mu_c in FP32 rounded to 16 bits (split into a
+// rounded part and the rounded remainder in the split modes), times the 16-bit W_c fragments on
+// v_mfma_f32_16x16x32_{bf16,f16} with FP32 accumulation (W as A, residuals as B, lane l,
+// register i = y[n = l & 15][16 jb + 4 (l >> 4) + i]); the split modes form
+// W_hi r_hi + W_hi r_lo + W_lo r_hi.  FP32 squares and log-sum-exp.
+template <int D, int UPW, int MODE>
+__device__ void mix_eval16(const DevProblem &P, const WFrag<D, UPW, MixTraits<MODE>::NP> &wr,
+                           const Tile &T, const int *mask, float *out)
+{
+    typedef typename MixTraits<MODE>::H H;
+    typedef typename MixTraits<MODE>::V8 V8;
+    constexpr int NP = MixTraits<MODE>::NP;
+    constexpr int NJB = D / 16, NKS = D / 32, LDC = D + 4;
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int row = l & 15, kq = l >> 4;
+    const int QS = q_stride(D, P.K);
+    const bool on = mask[row] != 0;
+    const float *cr = T.cand32 + row * LDC;
+#pragma unroll
+    for (int uu = 0; uu < UPW; ++uu) {
+        int c, jb;
+        unit_of<NJB>(w, uu, c, jb);
+        if (c < P.K) {
+            const int u = c * NJB + jb;
+            const int ke = (16 * jb + 16 + 31) / 32;
+            const float *mu = T.mu32 + c * D;
+            f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int ks = 0; ks < NKS; ++ks) {
+                if (ks < ke) {
+                    const int k0 = 32 * ks + 8 * kq;
+                    float rr[8];
+                    if (on) {
+                        const float4 c0 = *(const float4 *)(cr + k0);
+                        const float4 c1 = *(const float4 *)(cr + k0 + 4);
+                        const float4 m0 = *(const float4 *)(mu + k0);
+                        const float4 m1 = *(const float4 *)(mu + k0 + 4);
+                        rr[0] = c0.x - m0.x; rr[1] = c0.y - m0.y; rr[2] = c0.z - m0.z; rr[3] = c0.w - m0.w;
+                        rr[4] = c1.x - m1.x; rr[5] = c1.y - m1.y; rr[6] = c1.z - m1.z; rr[7] = c1.w - m1.w;
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < 8; ++e) rr[e] = 0.f;
+                    }
+                    V8 hi;
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) hi[e] = (H)rr[e];
+                    const V8 w0 = __builtin_bit_cast(V8, wr.v[0][uu][ks]);
+                    acc = mfma16(w0, hi, acc);
+                    if constexpr (NP == 2) {
+                        V8 lo;
+#pragma unroll
+                        for (int e = 0; e < 8; ++e) lo[e] = (H)(rr[e] - (float)hi[e]);
+                        acc = mfma16(w0, lo, acc);
+                        acc = mfma16(__builtin_bit_cast(V8, wr.v[1][uu][ks]), hi, acc);
+                    }
+                }
+            }
+            T.q32[row * QS + u * 4 + kq] = (acc[0] * acc[0] + acc[1] * acc[1]) + (acc[2] * acc[2] + acc[3] * acc[3]);
+        }
+    }
+    __syncthreads();
+    {
+        const int r = 4 * w + (l >> 4), c = l & 15;
+        const float L = lse_rows<D, float>(P, T.q32, T.cst32, r, c);
+        if (c == 0) out[r] = L;
+    }
+    __syncthreads();
+}
+
+// Neal's funnel, FP64: log N(v; 0, 9) + sum_{j>=1} log N(x_j; 0, e^v), v = x_0.
+template <int D>
+__device__ void funnel_eval64(const DevProblem &P, const Tile &T, const int *mask, double *out)
+{
+    constexpr int LDC = D + 1;
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    __syncthreads();
+    for (int rr = 0; rr < 4; ++rr) {
+        const int r = 4 * w + rr;
+        if (!mask[r]) continue;
+        const double v = T.cand[r * LDC];
+        double s = 0.0;
+        for (int a = l; a < P.d; a += 64)
+            if (a >= 1) { const double x = T.cand[r * LDC + a]; s += x * x; }
+        s = wave_sum_fast(s);
+        if (l == 0)
+            out[r] = -v * v / 18.0 - 0.5 * (LOG_2PI + log(9.0)) - 0.5 * exp(-v) * s
+                     - (double)(P.d - 1) * 0.5 * (v + LOG_2PI);
+    }
+    __syncthreads();
+}
+
+template <int D, int LIK>
+__device__ __forceinline__ void eval64(const DevProblem &P, const Tile &T, const int *mask,
+                                       double *out)
+{
+    if constexpr (LIK == LIK_MIXTURE) mix_eval64<D>(P, T, mask, out);
+    else funnel_eval64<D>(P, T, mask, out);
+}
+
+// Loads this wave's register-resident 16-bit W fragments (same unit order as mix_eval16).
+template <int D, int UPW, int NP>
+__device__ __forceinline__ void load_wfrag(const DevProblem &P, WFrag<D, UPW, NP> &wr)
+{
+    constexpr int NJB = D / 16, NKS = D / 32;
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+#pragma unroll
+    for (int uu = 0; uu < UPW; ++uu) {
+        int c, jb;
+        unit_of<NJB>(w, uu, c, jb);
+        const int u = c * NJB + jb;
+#pragma unroll
+        for (int ks = 0; ks < NKS; ++ks) {
+            const size_t o = ((size_t)u * NKS + ks) * 64 + l;
+            wr.v[0][uu][ks] = (c < P.K) ? P.wf16[o] : make_uint4(0, 0, 0, 0);
+            if constexpr (NP == 2) wr.v[1][uu][ks] = (c < P.K) ? P.wf16lo[o] : make_uint4(0, 0, 0, 0);
+        }
+    }
+}
+
+// Evaluates the masked rows of the tile in the kernel's precision: FP64 results in T.L, 16-bit
+// mode results in T.L32.
+template <int D, int MODE, int LIK, int UPW, int NP>
+__device__ __forceinline__ void eval_tile(const DevProblem &P, const WFrag<D, UPW, NP> &wr,
+                                          const Tile &T, const int *mask)
+{
+    if constexpr (MODE == MODE_FP64) eval64<D, LIK>(P, T, mask, T.L);
+    else mix_eval16<D, UPW, MODE>(P, wr, T, mask, T.L32);
+}
+
+template <int MODE> struct NPOf { static constexpr int v = 1; };
+template <> struct NPOf<MODE_BF16X3> { static constexpr int v = 2; };
+template <> struct NPOf<MODE_FP16X3> { static constexpr int v = 2; };
+
+// ------------------------------------------------------------------------------------------
+// init: m prior draws
+// ------------------------------------------------------------------------------------------
+__global__ void k_init_draw(DevProblem P, DevRun R)
+{
+    const int nq = (P.d + 1) >> 1;
+    const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= (long long)R.m * nq) return;
+    const int i = (int)(gid / nq), q = (int)(gid - (long long)i * nq);
+    double ua, ub;
+    draw2(R.key0, R.key1, PUR_INIT, (uint32_t)i, 0u, 0u, (uint32_t)q, ua, ub);
+    const int a0 = 2 * q, a1 = 2 * q + 1;
+    double x0, x1;
+    if (P.prior_kind == PRIOR_BOX) {
+        x0 = P.pa[a0] + (P.pb[a0] - P.pa[a0]) * ua;
+        x1 = (a1 < P.d) ? P.pa[a1] + (P.pb[a1] - P.pa[a1]) * ub : 0.0;
+    } else {
+        double z0, z1;
+        box_muller(ua, ub, z0, z1);
+        x0 = P.pa[a0] + P.pb[a0] * z0;
+        x1 = (a1 < P.d) ? P.pa[a1] + P.pb[a1] * z1 : 0.0;
+    }
+    R.X[(size_t)a0 * R.m_pad + i] = x0;
+    if (a1 < P.d) R.X[(size_t)a1 * R.m_pad + i] = x1;
+}
+
+// ------------------------------------------------------------------------------------------
+// batched evaluation of n points stored coordinate-major X[a*ld + i]
+// ------------------------------------------------------------------------------------------
+template <int D, int MODE, int LIK, int UPW>
+__global__ __launch_bounds__(256) void k_eval(DevProblem P, const double *X, int ld, int n,
+                                              double *out, unsigned long long *nonfinite)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const HLayout lay = hrss_layout(D, P.K);
+    const Tile T = tile_of(smem, lay);
+    const int tid = threadIdx.x;
+    const int p0 = blockIdx.x * kRows;
+    for (int i = tid; i < kRows * D; i += 256) {
+        const int r = i / D, a = i - r * D;
+        const int p = p0 + r;
+        const double x = (p < n && a < P.d) ? X[(size_t)a * ld + p] : 0.0;
+        T.cand[r * (D + 1) + a] = x;
+        T.cand32[r * (D + 4) + a] = (float)x;
+    }
+    if (tid < kRows) T.mask[tid] = (p0 + tid < n);
+    stage_problem<D>(P, T);
+    __syncthreads();
+    WFrag<D, UPW, NPOf<MODE>::v> wr;
+    if constexpr (MODE != MODE_FP64) load_wfrag<D, UPW, NPOf<MODE>::v>(P, wr);
+    eval_tile<D, MODE, LIK, UPW, NPOf<MODE>::v>(P, wr, T, T.mask);
+    if (tid < kRows && p0 + tid < n) {
+        unsigned long long nf = 0;
+        const double L = (MODE == MODE_FP64) ? T.L[tid] : (double)T.L32[tid];
+        out[p0 + tid] = sanitize(L, nf);
+        if (nf && nonfinite) atomicAdd(nonfinite, nf);
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// delete-k, threshold, unrolled evidence, termination (one workgroup of 1024 threads)
+// ------------------------------------------------------------------------------------------
+__device__ __forceinline__ unsigned long long key_of(double x)
+{
+    if (x == 0.0) x = 0.0;  // -0 -> +0
+    const unsigned long long b = __double_as_longlong(x);
+    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+__device__ __forceinline__ double val_of(unsigned long long k)
+{
+    const unsigned long long b = (k >> 63) ? (k & 0x7FFFFFFFFFFFFFFFull) : ~k;
+    return __longlong_as_double(b);
+}
+
+// Block reductions over 1024 threads (16 waves); red has >= 16 doubles.
+__device__ __forceinline__ double block_sum(double v, double *red)
+{
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    v = wave_sum(v);
+    __syncthreads();
+    if (l == 0) red[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += red[i];
+    return s;
+}
+__device__ __forceinline__ double block_max(double v, double *red)
+{
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    v = wave_max(v);
+    __syncthreads();
+    if (l == 0) red[w] = v;
+    __syncthreads();
+    double s = -INFINITY;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s = fmax(s, red[i]);
+    return s;
+}
+// Exclusive prefix sum over the block.
+__device__ __forceinline__ double block_exscan(double v, double *red)
+{
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    double inc = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const double t = __shfl_up(inc, o, 64);
+        if (l >= o) inc += t;
+    }
+    __syncthreads();
+    if (l == 63) red[w] = inc;
+    __syncthreads();
+    double pre = 0.0;
+    for (int i = 0; i < w; ++i) pre += red[i];
+    return pre + inc - v;
+}
+
+// packed lower-triangular index e = a(a+1)/2 + b  ->  (a, b)
+__device__ __forceinline__ void unpack_tri(int e, int &a, int &b)
+{
+    a = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
+    while (a * (a + 1) / 2 > e) --a;
+    while ((a + 1) * (a + 2) / 2 <= e) ++a;
+    b = e - a * (a + 1) / 2;
+}
+
+__device__ __forceinline__ double lse2(double a, double b)
+{
+    if (a == -INFINITY) return b;
+    if (b == -INFINITY) return a;
+    const double mx = fmax(a, b);
+    return mx + log(exp(a - mx) + exp(b - mx));
+}
+
+__global__ __launch_bounds__(1024) void k_select(DevRun R, int op)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    if (R.iscal[0]) return;
+    const int m = R.m, k = R.k, tid = threadIdx.x;
+    int NP = 1;
+    while (NP < m) NP <<= 1;
+    unsigned long long *key = (unsigned long long *)smem;
+    int *idx = (int *)(key + NP);
+    double *red = (double *)(idx + NP + (NP & 1));
+    int *st0 = (int *)(red + 32);
+    for (int t = tid; t < NP; t += blockDim.x) {
+        if (t < m) { key[t] = key_of(R.logL[t]); idx[t] = t; }
+        else { key[t] = ~0ull; idx[t] = 0x7FFFFFFF; }
+    }
+    if (tid == 0) *st0 = m;
+    __syncthreads();
+    // bitonic sort of (key, idx) ascending
+    for (int size = 2; size <= NP; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int t = tid; t < (NP >> 1); t += blockDim.x) {
+                const int i = 2 * t - (t & (stride - 1));
+                const int j = i + stride;
+                const bool asc = ((i & size) == 0);
+                const unsigned long long ki = key[i], kj = key[j];
+                const int ii = idx[i], ij = idx[j];
+                const bool gt = (ki > kj) || (ki == kj && ii > ij);
+                if (gt == asc) { key[i] = kj; key[j] = ki; idx[i] = ij; idx[j] = ii; }
+            }
+            __syncthreads();
+        }
+    }
+    for (int t = tid; t < m; t += blockDim.x) R.perm[t] = idx[t];
+    const double Lstar = val_of(key[k - 1]);
+    for (int t = k + tid; t < m; t += blockDim.x)
+        if (val_of(key[t]) > Lstar) atomicMin(st0, t);
+    if (op == 2) {
+        __syncthreads();
+        if (tid == 0) {
+            R.scal[0] = Lstar;
+            R.iscal[1] = *st0;
+            R.iscal[2] = m - *st0;
+        }
+        return;
+    }
+    // unrolled deaths j = 1..k at live counts n_j = m - j + 1
+    const double logZ0 = R.scal[1], logX0 = R.scal[2], M0 = R.scal[3];
+    const int E = (k + (int)blockDim.x - 1) / (int)blockDim.x;
+    const int j0 = tid * E;
+    double ssum = 0.0;
+    for (int e = 0; e < E; ++e) {
+        const int jj = j0 + e + 1;
+        if (jj <= k) ssum += 1.0 / (double)(m - jj + 1);
+    }
+    const double pre = block_exscan(ssum, red);
+    double lwv[8], Lv[8];
+    double lmax = -INFINITY, run = pre;
+    for (int e = 0; e < E; ++e) {
+        const int jj = j0 + e + 1;
+        lwv[e] = -INFINITY; Lv[e] = 0.0;
+        if (jj <= k) {
+            const double inv = 1.0 / (double)(m - jj + 1);
+            const double L = val_of(key[jj - 1]);
+            const double lw = L + (logX0 - run) + log(-expm1(-inv));
+            run += inv;
+            lwv[e] = lw; Lv[e] = L;
+            lmax = fmax(lmax, lw);
+        }
+    }
+    const double S_k = block_sum(ssum, red);
+    const double mx = block_max(lmax, red);
+    double es = 0.0;
+    for (int e = 0; e < E; ++e) if (lwv[e] != -INFINITY) es += exp(lwv[e] - mx);
+    const double esum = block_sum(es, red);
+    const double lse_new = (mx == -INFINITY) ? -INFINITY : mx + log(esum);
+    const double logZ1 = lse2(logZ0, lse_new);
+    double mt = 0.0;
+    for (int e = 0; e < E; ++e) if (lwv[e] != -INFINITY) mt += exp(lwv[e] - logZ1) * Lv[e];
+    const double msum = block_sum(mt, red);
+    const double M1 = (logZ0 == -INFINITY ? 0.0 : exp(logZ0 - logZ1) * M0) + msum;
+    const double logX1 = logX0 - S_k;
+    // dead record
+    const long long nd0 = (long long)R.ctr[9];
+    for (int t = tid; t < k; t += blockDim.x)
+        if (nd0 + t < R.dead_cap) R.dead[nd0 + t] = val_of(key[t]);
+    __syncthreads();
+    if (tid == 0) {
+        const int t0 = *st0;
+        const double maxL = val_of(key[m - 1]);
+        int done = (R.term_on && (logX1 + maxL - logZ1 < R.log_term)) ? 1 : 0;
+        R.scal[0] = Lstar; R.scal[1] = logZ1; R.scal[2] = logX1; R.scal[3] = M1;
+        R.iscal[1] = t0;
+        R.iscal[2] = m - t0;
+        if (!done && m - t0 <= 0) { R.iscal[4] = 1; done = 1; }
+        R.iscal[0] = done;
+        if (op == 1) R.iscal[3] += 1;
+        R.ctr[9] = (unsigned long long)(nd0 + k);
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// whitening: survivors' covariance (one-pass about a fixed shift c = the best live point),
+// partial sums over groups of survivors, then a single-workgroup reduction + Cholesky
+// ------------------------------------------------------------------------------------------
+// grid (tile, group); tile = lower 16x16 block (ta >= tb).  part2[g][tile][256], part1[g][D]
+__global__ __launch_bounds__(256) void k_cov(DevProblem P, DevRun R, double *part1,
+                                             double *part2, int G)
+{
+    if (R.iscal[0]) return;
+    const int d = P.d;
+    const int tile = blockIdx.x, g = blockIdx.y, tid = threadIdx.x;
+    int ta, tb;
+    unpack_tri(tile, ta, tb);
+    const int n = R.m - R.k;
+    const int s0 = (int)((long long)n * g / G), s1 = (int)((long long)n * (g + 1) / G);
+    const int cidx = R.perm[R.m - 1];
+    __shared__ double ca[32][17], cb[32][17];
+    __shared__ double shift[32];
+    if (tid < 16) {
+        const int aa = ta * 16 + tid, bb = tb * 16 + tid;
+        shift[tid] = (aa < d) ? R.X[(size_t)aa * R.m_pad + cidx] : 0.0;
+        shift[16 + tid] = (bb < d) ? R.X[(size_t)bb * R.m_pad + cidx] : 0.0;
+    }
+    __syncthreads();
+    double acc = 0.0, acc1 = 0.0;
+    for (int sb = s0; sb < s1; sb += 32) {
+        // stage up to 32 survivors: columns of tile a and tile b
+        for (int i = tid; i < 32 * 32; i += 256) {
+            const int s = i >> 5, c = i & 31;
+            const int ss = sb + s;
+            double v = 0.0;
+            if (ss < s1) {
+                const int pi = R.perm[R.k + ss];
+                const int coord = (c < 16) ? ta * 16 + c : tb * 16 + (c - 16);
+                if (coord < d) v = R.X[(size_t)coord * R.m_pad + pi] - shift[c];
+            }
+            if (c < 16) ca[s][c] = v; else cb[s][c - 16] = v;
+        }
+        __syncthreads();
+        const int ns = (s1 - sb < 32) ? s1 - sb : 32;
+        for (int s = 0; s < ns; ++s) acc += ca[s][tid & 15] * cb[s][tid >> 4];
+        if (ta == tb && tid < 16)
+            for (int s = 0; s < ns; ++s) acc1 += ca[s][tid];
+        __syncthreads();
+    }
+    part2[((size_t)g * gridDim.x + tile) * 256 + tid] = acc;
+    if (ta == tb && tid < 16) part1[(size_t)g * P.D + ta * 16 + tid] = acc1;
+}
+
+__global__ __launch_bounds__(1024) void k_chol(DevProblem P, DevRun R, const double *part1,
+                                               const double *part2, int G, int ntile)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    if (R.iscal[0]) return;
+    const int D = P.D, d = P.d, tid = threadIdx.x;
+    double *A = (double *)smem;              // packed lower, D(D+1)/2
+    double *mc = A + D * (D + 1) / 2;        // mean - shift, [D]
+    double *red = mc + D;                    // [32]
+    int *fail = (int *)(red + 32);
+    const int n = R.m - R.k;
+    for (int a = tid; a < D; a += blockDim.x) {
+        double s = 0.0;
+        if (a < d) for (int g = 0; g < G; ++g) s += part1[(size_t)g * D + a];
+        mc[a] = s / n;
+    }
+    if (tid == 0) *fail = 0;
+    __syncthreads();
+    const int np = D * (D + 1) / 2;
+    for (int e = tid; e < np; e += blockDim.x) {
+        int a, b;  // a >= b
+        unpack_tri(e, a, b);
+        double v = 0.0;
+        if (a < d && b < d) {
+            const int ta = a >> 4, tb = b >> 4;
+            const int tile = ta * (ta + 1) / 2 + tb;
+            const int off = (b & 15) * 16 + (a & 15);
+            double s = 0.0;
+            for (int g = 0; g < G; ++g) s += part2[((size_t)g * ntile + tile) * 256 + off];
+            v = s / n - mc[a] * mc[b];
+        } else if (a == b) {
+            v = 1.0;  // padded coordinates: identity (never used, keeps the factor regular)
+        }
+        A[e] = v;
+    }
+    __syncthreads();
+    // jitter: 1e-12 * tr / d on the diagonal
+    double tr = 0.0;
+    for (int a = tid; a < d; a += blockDim.x) tr += A[a * (a + 1) / 2 + a];
+    tr = block_sum(tr, red);
+    for (int a = tid; a < d; a += blockDim.x) A[a * (a + 1) / 2 + a] += 1e-12 * tr / d;
+    __syncthreads();
+    // right-looking Cholesky on the packed lower triangle
+    for (int j = 0; j < d; ++j) {
+        const double ajj = A[j * (j + 1) / 2 + j];
+        if (!(ajj > 0.0)) { if (tid == 0) *fail = 1; break; }
+        const double ljj = sqrt(ajj);
+        __syncthreads();
+        for (int i = j + 1 + tid; i < d; i += blockDim.x) A[i * (i + 1) / 2 + j] /= ljj;
+        __syncthreads();
+        if (tid == 0) A[j * (j + 1) / 2 + j] = ljj;
+        const int rem = d - j - 1;
+        for (int e = tid; e < rem * rem; e += blockDim.x) {
+            const int ii = e / rem, r2 = e - ii * rem;
+            if (r2 > ii) continue;
+            const int i = j + 1 + ii, l2 = j + 1 + r2;
+            A[i * (i + 1) / 2 + l2] -= A[i * (i + 1) / 2 + j] * A[l2 * (l2 + 1) / 2 + j];
+        }
+        __syncthreads();
+    }
+    __syncthreads();
+    const int failed = *fail;
+    if (failed) {
+        // diagonal fallback: sqrt of the (jittered) variances, recomputed from the partials
+        for (int e = tid; e < np; e += blockDim.x) A[e] = 0.0;
+        __syncthreads();
+        for (int a = tid; a < d; a += blockDim.x) {
+            const int ta = a >> 4;
+            const int tile = ta * (ta + 1) / 2 + ta;
+            const int off = (a & 15) * 16 + (a & 15);
+            double s = 0.0;
+            for (int g = 0; g < G; ++g) s += part2[((size_t)g * ntile + tile) * 256 + off];
+            const double v = s / n - mc[a] * mc[a];
+            A[a * (a + 1) / 2 + a] = (v > 0.0) ? sqrt(v) : 1.0;
+        }
+        if (tid == 0) atomicAdd(&R.ctr[8], 1ull);
+    }
+    __syncthreads();
+    for (int a = d; a < D; ++a)
+        if (tid == 0) A[a * (a + 1) / 2 + a] = 0.0;  // padded coordinates never move
+    for (int e = tid; e < np; e += blockDim.x) {
+        int a, b;
+        unpack_tri(e, a, b);
+        R.Lpk[e] = (a < d && b < d) ? A[e] : 0.0;
+    }
+    for (int e = tid; e < D * D; e += blockDim.x) {
+        const int a = e / D, b = e - a * D;
+        R.Lsig[e] = (b <= a && a < d) ? A[a * (a + 1) / 2 + b] : 0.0;
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// directions of every chain and step of the iteration (they do not depend on the chains'
+// outcomes): z ~ N(0, I_d) from Philox purpose DIR, v = L z / |z| (unit Mahalanobis length),
+// dirbuf[(j p + s) D + a], zero for a >= d.  64 directions per workgroup.
+// ------------------------------------------------------------------------------------------
+constexpr int kDirRows = 64;
+__host__ __device__ inline int dirs_lds_bytes(int D)
+{
+    return al16(lsig_doubles(D) * 8) + al16(kDirRows * (D + 1) * 8) + kDirRows * 8;
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_dirs(DevProblem P, DevRun R)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    if (R.iscal[0] || R.iscal[2] <= 0) return;
+    double *Ls = (double *)smem;
+    double *zs = (double *)(smem + al16(lsig_doubles(D) * 8));
+    double *nz = zs + kDirRows * (D + 1);
+    const int tid = threadIdx.x, d = P.d, p = R.p;
+    const long long total = (long long)R.k * p;
+    const long long base = (long long)blockIdx.x * kDirRows;
+    const uint32_t it = (uint32_t)R.iscal[3] + 1u;
+    if constexpr (D <= 64) {
+        for (int i = tid; i < D * D; i += 256) {
+            const int a = i / D, b = i - a * D;
+            Ls[a * (D + 1) + b] = R.Lsig[i];
+        }
+    } else {
+        for (int i = tid; i < D * (D + 1) / 2; i += 256) Ls[i] = R.Lpk[i];
+    }
+    const int nq = (d + 1) >> 1;
+    for (int i = tid; i < kDirRows * nq; i += 256) {
+        const int r = i / nq, q = i - r * nq;
+        const long long idx = base + r;
+        if (idx >= total) continue;
+        const int j = (int)(idx / p), st = (int)(idx - (long long)j * p);
+        double ua, ub, z0, z1;
+        draw2(R.key0, R.key1, PUR_DIR, (uint32_t)j, it, (uint32_t)st, (uint32_t)q, ua, ub);
+        box_muller(ua, ub, z0, z1);
+        zs[r * (D + 1) + 2 * q] = z0;
+        if (2 * q + 1 < d) zs[r * (D + 1) + 2 * q + 1] = z1;
+    }
+    __syncthreads();
+    if (tid < kDirRows) {
+        double s2 = 0.0;
+        for (int a = 0; a < d; ++a) s2 += zs[tid * (D + 1) + a] * zs[tid * (D + 1) + a];
+        nz[tid] = sqrt(s2);
+    }
+    __syncthreads();
+    for (int i = tid; i < kDirRows * D; i += 256) {
+        const int r = i / D, a = i - r * D;
+        const long long idx = base + r;
+        if (idx >= total) continue;
+        double v = 0.0;
+        if (a < d) {
+            const double *Lr = (D <= 64) ? Ls + a * (D + 1) : Ls + a * (a + 1) / 2;
+            const double *z = zs + r * (D + 1);
+            double s2 = 0.0;
+            for (int b = 0; b <= a; ++b) s2 += Lr[b] * z[b];
+            v = s2 / nz[r];
+        }
+        R.dirbuf[idx * D + a] = v;
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// the k HRSS chains
+// ------------------------------------------------------------------------------------------
+enum Phase { PH_NEWSTEP = 0, PH_STEPOUT = 1, PH_SHRINK = 2, PH_DONE = 3 };
+
+// One workgroup = four waves = up to four chains (chain c <-> wave c).  Each wave runs its
+// chain's finite-state machine with wave-uniform state; lane l owns coordinates l and l + 64 of
+// the chain's point and direction in registers.  A round: every active chain emits up to two
+// candidates (the two bracket ends while stepping out, one proposal while shrinking), the four
+// waves evaluate the 16-row tile together, each chain consumes its results.  Mixed precision:
+// a candidate whose FP32 estimate lies within the guard band of L* is re-evaluated in FP64
+// before the decision, so decisions equal the FP64 ones; the stored logL is FP64.
+template <int D, int MODE, int LIK, int UPW>
+__global__ __launch_bounds__(256) void k_hrss(DevProblem P, DevRun R, int C)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    if (R.iscal[0]) return;
+    if (R.iscal[2] <= 0) return;
+    constexpr int LDC = D + 1, LDC32 = D + 4;
+    constexpr int NA = (D + 63) / 64;        // coordinates per lane
+    constexpr int NP = NPOf<MODE>::v;
+    const HLayout lay = hrss_layout(D, P.K);
+    const Tile T = tile_of(smem, lay);
+    double *sz = (double *)(smem + lay.z);
+    double *sLs = (double *)(smem + lay.lsig);
+    double *scand = T.cand;
+    float *scand32 = T.cand32;
+    int *smask = T.mask;
+    int *src = T.rc;
+
+    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+    const int d = P.d;
+    const double Lstar = R.scal[0];
+    const int t0 = R.iscal[1], nsurv = R.iscal[2];
+    const uint32_t it = (uint32_t)R.iscal[3] + 1u;
+    const double width = R.width;
+    const int p = R.p, cap_out = R.stepout_cap, cap_sh = R.shrink_cap;
+    const bool box = (P.prior_kind == PRIOR_BOX);
+    const bool pre = (R.dirbuf != nullptr);
+
+    if (!pre) {
+        if constexpr (D <= 64) {
+            for (int i = tid; i < D * D; i += 256) {
+                const int a = i / D, b = i - a * D;
+                sLs[a * (D + 1) + b] = R.Lsig[i];
+            }
+        } else {
+            for (int i = tid; i < D * (D + 1) / 2; i += 256) sLs[i] = R.Lpk[i];
+        }
+    }
+    stage_problem<D>(P, T);
+    if (tid < kRows) { smask[tid] = 0; src[tid] = 0; }
+    for (int i = tid; i < kRows * LDC; i += 256) scand[i] = 0.0;
+    for (int i = tid; i < kRows * LDC32; i += 256) scand32[i] = 0.f;
+    WFrag<D, UPW, NP> wr;
+    if constexpr (MODE != MODE_FP64) load_wfrag<D, UPW, NP>(P, wr);
+#ifdef NSS_PHASE_TIMING
+    unsigned long long pt[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    unsigned long long tmark = __builtin_amdgcn_s_memtime();
+#define PT(slot)                                                                             \
+    do {                                                                                     \
+        const unsigned long long t_ = __builtin_amdgcn_s_memtime();                          \
+        pt[slot] += t_ - tmark;                                                              \
+        tmark = t_;                                                                          \
+    } while (0)
+#else
+#define PT(slot) do {} while (0)
+#endif
+
+    const int j = blockIdx.x * C + w;
+    const bool has_chain = (w < C) && (j < R.k);
+    double *zz = sz + w * D;
+
+    // lane-owned coordinates a = l + 64 i of the point, direction and prior parameters
+    double x0r[NA], vr[NA], par[NA], pbr[NA];
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+        const int a = l + 64 * i;
+        x0r[i] = 0.0; vr[i] = 0.0;
+        par[i] = (a < D) ? P.pa[a] : 0.0;
+        pbr[i] = (a < D) ? P.pb[a] : 1.0;
+    }
+
+    // per-chain state (wave-uniform, replicated in every lane of the chain's wave)
+    int phase = PH_DONE, step = 0, nl = 0, nr = 0, ns = 0;
+    bool la = false, ra = false;
+    double tL = 0.0, tR = 0.0, tsh = 0.0, logy = -INFINITY, logL0 = -INFINITY;
+    unsigned long long c_evals = 0, c_tests = 0, c_prej = 0, c_outcap = 0, c_shcap = 0,
+                       c_nonfin = 0, c_rc = 0, c_viol = 0;
+
+    if (has_chain) {
+        double u, unused;
+        draw2(R.key0, R.key1, PUR_RESAMPLE, (uint32_t)j, it, 0u, 0u, u, unused);
+        int qi = (int)floor(u * (double)nsurv);
+        if (qi > nsurv - 1) qi = nsurv - 1;
+        const int parent = R.perm[t0 + qi];
+        if (l == 0) R.parents[j] = parent;
+#pragma unroll
+        for (int i = 0; i < NA; ++i) {
+            const int a = l + 64 * i;
+            if (a < d) x0r[i] = R.X[(size_t)a * R.m_pad + parent];
+        }
+        if (!pre)
+            for (int a = l; a < D; a += 64) zz[a] = 0.0;
+        logL0 = R.logL[parent];
+        phase = (p > 0) ? PH_NEWSTEP : PH_DONE;
+    }
+    __syncthreads();
+
+    // next step's direction, prefetched into registers one step ahead
+    double pv[NA];
+#pragma unroll
+    for (int i = 0; i < NA; ++i) pv[i] = 0.0;
+    auto prefetch_dir = [&](int st) {
+        if (has_chain && st < p) {
+            const double *srcv = R.dirbuf + ((size_t)j * p + st) * D;
+#pragma unroll
+            for (int i = 0; i < NA; ++i) if (l + 64 * i < D) pv[i] = srcv[l + 64 * i];
+        }
+    };
+    if (pre) prefetch_dir(0);
+
+    // log prior density at the lane-owned point (Gaussian prior only)
+    auto logprior_x0 = [&]() -> double {
+        double lp = 0.0;
+#pragma unroll
+        for (int i = 0; i < NA; ++i) {
+            const int a = l + 64 * i;
+            if (a < d) { const double zt = (x0r[i] - par[i]) / pbr[i]; lp += -0.5 * zt * zt; }
+        }
+        return wave_sum_fast(lp) + P.logprior_norm;
+    };
+
+    // candidate row r = x0 + t v; returns whether it passes the prior tests
+    auto build = [&](int r, double t) -> bool {
+        bool inb = true;
+        double lp = 0.0;
+#pragma unroll
+        for (int i = 0; i < NA; ++i) {
+            const int a = l + 64 * i;
+            if (a < D) {
+                const double y = x0r[i] + t * vr[i];
+                scand[r * LDC + a] = y;
+                if constexpr (MODE != MODE_FP64) scand32[r * LDC32 + a] = (float)y;
+                if (a < d) {
+                    if (box) inb = inb && (y >= par[i] && y <= pbr[i]);
+                    else { const double zt = (y - par[i]) / pbr[i]; lp += -0.5 * zt * zt; }
+                }
+            }
+        }
+        if (box) return __all(inb) != 0;
+        lp = wave_sum_fast(lp) + P.logprior_norm;
+        return lp > logy;
+    };
+
+    auto finish_step = [&](int acc, int nsh) {
+        if (R.trace && l == 0) {
+            int *tr = R.trace + ((size_t)j * p + step) * 4;
+            tr[0] = nl; tr[1] = nr; tr[2] = nsh; tr[3] = acc;
+        }
+        if (!acc) ++c_shcap;
+        ++step;
+        phase = (step >= p) ? PH_DONE : PH_NEWSTEP;
+    };
+
+    auto enter_shrink = [&]() {
+        phase = PH_SHRINK;
+        ns = 0;
+        if (cap_sh <= 0) finish_step(0, 0);
+    };
+
+    for (;;) {
+        const bool act = has_chain && phase != PH_DONE;
+        int em0 = 0, em1 = 0, ok0 = 0, ok1 = 0;
+        if (act) {
+            PT(6);
+            if (phase == PH_NEWSTEP) {
+                if (pre) {
+#pragma unroll
+                    for (int i = 0; i < NA; ++i) vr[i] = pv[i];
+                    prefetch_dir(step + 1);
+                } else {
+                    // direction z ~ N(0, I_d), v = L z / |z|, drawn by the chain itself
+                    const int nq = (d + 1) >> 1;
+                    for (int q = l; q < nq; q += 64) {
+                        double ua, ub, z0, z1;
+                        draw2(R.key0, R.key1, PUR_DIR, (uint32_t)j, it, (uint32_t)step,
+                              (uint32_t)q, ua, ub);
+                        box_muller(ua, ub, z0, z1);
+                        zz[2 * q] = z0;
+                        if (2 * q + 1 < d) zz[2 * q + 1] = z1;
+                    }
+                    wave_sync();
+                    double s2 = 0.0;
+                    for (int a = l; a < d; a += 64) s2 += zz[a] * zz[a];
+                    const double nz = sqrt(wave_sum_fast(s2));
+#pragma unroll
+                    for (int i = 0; i < NA; ++i) {
+                        const int a = l + 64 * i;
+                        double v = 0.0;
+                        if (a < d) {
+                            const double *Lr = (D <= 64) ? sLs + a * (D + 1) : sLs + a * (a + 1) / 2;
+                            double s0 = 0.0;
+                            for (int b = 0; b <= a; ++b) s0 += Lr[b] * zz[b];
+                            v = s0 / nz;
+                        }
+                        vr[i] = v;
+                    }
+                }
+                double U, uh;
+                draw2(R.key0, R.key1, PUR_STEP, (uint32_t)j, it, (uint32_t)step, 0u, U, uh);
+                logy = box ? -INFINITY : logprior_x0() + log(uh);
+                tL = -width * U;
+                tR = tL + width;
+                nl = nr = 0;
+                la = ra = (cap_out > 0);
+                if (cap_out <= 0) c_outcap += 2;
+                phase = PH_STEPOUT;
+                if (!la && !ra) enter_shrink();
+#ifdef NSS_PHASE_TIMING
+                pt[9] += 1;
+#endif
+                PT(0);
+            }
+            if (phase == PH_STEPOUT) {
+                if (la) { em0 = 1; ok0 = build(w * kSlots + 0, tL); }
+                if (ra) { em1 = 1; ok1 = build(w * kSlots + 1, tR); }
+            } else if (phase == PH_SHRINK) {
+                double us, unused;
+                draw2(R.key0, R.key1, PUR_SHRINK, (uint32_t)j, it, (uint32_t)step, (uint32_t)ns,
+                      us, unused);
+                tsh = tL + us * (tR - tL);
+                em0 = 1;
+                ok0 = build(w * kSlots + 0, tsh);
+            }
+            c_tests += em0 + em1;
+            c_prej += (em0 && !ok0) + (em1 && !ok1);
+            PT(1);
+        }
+        if (l == 0) {
+            smask[w * kSlots + 0] = em0 && ok0;
+            smask[w * kSlots + 1] = em1 && ok1;
+            src[w * kSlots + 0] = 0;
+            src[w * kSlots + 1] = 0;
+        }
+        if (!__syncthreads_or(act)) break;
+        PT(2);
+#ifdef NSS_PHASE_TIMING
+        pt[8] += 1;
+#endif
+
+        // ---- batched likelihood of the tile ----
+        double Lr0 = -INFINITY, Lr1 = -INFINITY;
+        eval_tile<D, MODE, LIK, UPW, NP>(P, wr, T, smask);
+        PT(3);
+        if constexpr (MODE == MODE_FP64) {
+            if (act) {
+                if (em0 && ok0) Lr0 = sanitize(T.L[w * kSlots + 0], c_nonfin);
+                if (em1 && ok1) Lr1 = sanitize(T.L[w * kSlots + 1], c_nonfin);
+            }
+        } else {
+            int need = 0;
+            float m0 = -INFINITY, m1 = -INFINITY;
+            if (act) {
+                if (em0 && ok0) m0 = T.L32[w * kSlots + 0];
+                if (em1 && ok1) m1 = T.L32[w * kSlots + 1];
+                auto near = [&](float Lm) -> bool {
+                    if (Lm != Lm) return true;
+                    const float band = P.guard_rel * fmaxf(0.f, P.cmax32 - Lm) + P.guard_abs +
+                                       1e-6f * fabsf(Lm);
+                    return fabs((double)Lm - Lstar) <= (double)band;
+                };
+                const int r0 = em0 && ok0 && near(m0), r1 = em1 && ok1 && near(m1);
+                if (l == 0) { src[w * kSlots + 0] = r0; src[w * kSlots + 1] = r1; }
+                need = r0 | r1;
+                c_rc += r0 + r1;
+            }
+            const int any_rc = __syncthreads_or(need);
+            PT(4);
+            if (any_rc) {
+                eval64<D, LIK>(P, T, src, T.L);
+#ifdef NSS_PHASE_TIMING
+                pt[10] += 1;
+#endif
+                PT(5);
+            }
+            if (act) {
+                if (em0 && ok0) Lr0 = src[w * kSlots + 0] ? sanitize(T.L[w * kSlots + 0], c_nonfin)
+                                                          : sanitize((double)m0, c_nonfin);
+                if (em1 && ok1) Lr1 = src[w * kSlots + 1] ? sanitize(T.L[w * kSlots + 1], c_nonfin)
+                                                          : sanitize((double)m1, c_nonfin);
+            }
+        }
+
+        // ---- per-chain state update ----
+        if (act) {
+            c_evals += (em0 && ok0) + (em1 && ok1);
+            const bool in0 = em0 && ok0 && (Lr0 > Lstar);
+            const bool in1 = em1 && ok1 && (Lr1 > Lstar);
+            if (phase == PH_STEPOUT) {
+                if (em0) {
+                    if (in0) { tL -= width; ++nl; if (nl >= cap_out) { la = false; ++c_outcap; } }
+                    else la = false;
+                }
+                if (em1) {
+                    if (in1) { tR += width; ++nr; if (nr >= cap_out) { ra = false; ++c_outcap; } }
+                    else ra = false;
+                }
+                if (!la && !ra) enter_shrink();
+            } else if (phase == PH_SHRINK && em0) {
+                if (in0) {
+                    // the accepted point is the evaluated candidate row, bit for bit
+                    const int r = w * kSlots + 0;
+#pragma unroll
+                    for (int i = 0; i < NA; ++i)
+                        if (l + 64 * i < D) x0r[i] = scand[r * LDC + l + 64 * i];
+                    logL0 = Lr0;
+                    finish_step(1, ns + 1);
+                } else {
+                    if (tsh < 0.0) tL = tsh; else tR = tsh;
+                    ++ns;
+                    if (ns >= cap_sh) finish_step(0, ns);
+                }
+            }
+            PT(7);
+        }
+    }
+#ifdef NSS_PHASE_TIMING
+    if (tid == 0 && R.prof) for (int i = 0; i < 12; ++i) atomicAdd(&R.prof[i], pt[i]);
+#endif
+#undef PT
+
+    if constexpr (MODE != MODE_FP64) {
+        // stored log-likelihoods are FP64: re-evaluate each chain's final point
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < NA; ++i)
+            if (l + 64 * i < D) scand[w * LDC + l + 64 * i] = has_chain ? x0r[i] : 0.0;
+        if (tid < kRows) smask[tid] = (tid < kMaxChainsPerWG) && (tid < C) &&
+                                      (blockIdx.x * C + tid < R.k);
+        __syncthreads();
+        eval64<D, LIK>(P, T, smask, T.L);
+        if (has_chain) {
+            unsigned long long dummy = 0;
+            logL0 = sanitize(T.L[w], dummy);
+            if (!(logL0 > Lstar)) ++c_viol;
+        }
+    }
+
+    if (has_chain) {
+        const int slot = R.perm[j];
+#pragma unroll
+        for (int i = 0; i < NA; ++i) {
+            const int a = l + 64 * i;
+            if (a < d) R.X[(size_t)a * R.m_pad + slot] = x0r[i];
+        }
+        if (l == 0) {
+            R.logL[slot] = logL0;
+            atomicAdd(&R.ctr[0], c_evals);
+            atomicAdd(&R.ctr[1], c_tests);
+            atomicAdd(&R.ctr[2], c_prej);
+            atomicAdd(&R.ctr[3], c_outcap);
+            atomicAdd(&R.ctr[4], c_shcap);
+            atomicAdd(&R.ctr[5], c_nonfin);
+            atomicAdd(&R.ctr[6], c_rc);
+            atomicAdd(&R.ctr[7], c_viol);
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// final live-set contribution (non-destructive): scal[4..6] = ln Z, sqrt(H/m), H
+// ------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_logz(DevRun R)
+{
+    __shared__ double red[32];
+    const int m = R.m, k = R.k, n = m - k, tid = threadIdx.x;
+    double mx = -INFINITY;
+    for (int t = k + tid; t < m; t += blockDim.x) mx = fmax(mx, R.logL[R.perm[t]]);
+    mx = block_max(mx, red);
+    double s = 0.0;
+    for (int t = k + tid; t < m; t += blockDim.x) s += exp(R.logL[R.perm[t]] - mx);
+    s = block_sum(s, red);
+    const double logZ = R.scal[1], logX = R.scal[2], M = R.scal[3];
+    const double lme = mx + log(s) - log((double)n);
+    const double zf = lse2(logZ, logX + lme);
+    double mt = 0.0;
+    for (int t = k + tid; t < m; t += blockDim.x) {
+        const double L = R.logL[R.perm[t]];
+        const double lw = logX - log((double)n) + L;
+        if (lw != -INFINITY) mt += exp(lw - zf) * L;
+    }
+    mt = block_sum(mt, red);
+    if (tid == 0) {
+        const double Mf = (logZ == -INFINITY ? 0.0 : exp(logZ - zf) * M) + mt;
+        const double H = Mf - zf;
+        R.scal[4] = zf;
+        R.scal[5] = sqrt(H > 0.0 ? H / m : 0.0);
+        R.scal[6] = H;
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// launchers
+// ------------------------------------------------------------------------------------------
+static int upw_for(const DevProblem &P) { return (P.K * (P.D / 16) + 3) / 4; }
+
+int mode_supported(const DevProblem &P, int mode)
+{
+    if (hrss_layout(P.D, P.K).total > 160 * 1024) return 0;  // one workgroup's LDS
+    if (mode == MODE_FP64) return 1;
+    if (P.lik_kind != LIK_MIXTURE) return 0;
+    const int upw = upw_for(P);
+    if (P.D == 32) return upw <= 16;
+    if (P.D == 64) return upw <= 8;
+    return upw <= 4;
+}
+
+static size_t hrss_lds(const DevProblem &P) { return (size_t)hrss_layout(P.D, P.K).total; }
+
+template <typename F>
+static hipError_t set_lds(F *f, size_t bytes)
+{
+    return hipFuncSetAttribute((const void *)f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)bytes);
+}
+
+hipError_t launch_init_draw(const DevProblem &P, const DevRun &R, hipStream_t s)
+{
+    const long long n = (long long)R.m * ((P.d + 1) / 2);
+    const int blocks = (int)((n + 255) / 256);
+    hipLaunchKernelGGL(k_init_draw, dim3(blocks), dim3(256), 0, s, P, R);
+    return hipGetLastError();
+}
+
+template <int D, int MODE, int LIK, int UPW>
+static hipError_t eval_t(const DevProblem &P, const double *X, int ld, int n, double *out,
+                         unsigned long long *nf, hipStream_t s)
+{
+    const size_t lds = hrss_lds(P);
+    auto f = k_eval<D, MODE, LIK, UPW>;
+    hipError_t e = set_lds(f, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(f, dim3((n + kRows - 1) / kRows), dim3(256), lds, s, P, X, ld, n, out, nf);
+    return hipGetLastError();
+}
+
+template <int D, int MODE, int LIK, int UPW>
+static hipError_t hrss_t(const DevProblem &P, const DevRun &R, hipStream_t s)
+{
+    const size_t lds = hrss_lds(P);
+    auto f = k_hrss<D, MODE, LIK, UPW>;
+    hipError_t e = set_lds(f, lds);
+    if (e != hipSuccess) return e;
+    int C = (R.k + 255) / 256;
+    if (C < 1) C = 1;
+    if (C > kMaxChainsPerWG) C = kMaxChainsPerWG;
+    const int blocks = (R.k + C - 1) / C;
+    hipLaunchKernelGGL(f, dim3(blocks), dim3(256), lds, s, P, R, C);
+    return hipGetLastError();
+}
+
+// dispatch over (D, mode, likelihood); UPW = register fragment units per wave (mixed only)
+// dispatch over (D, mode, likelihood); UPW = register fragment units per wave (mixed only)
+#define NSS_MIXED_D(FN, MODE_, ...)                                                           \
+    do {                                                                                      \
+        if (P.D == 32) {                                                                      \
+            if (upw <= 4) return FN<32, MODE_, LIK_MIXTURE, 4>(__VA_ARGS__);                  \
+            return FN<32, MODE_, LIK_MIXTURE, 16>(__VA_ARGS__);                               \
+        }                                                                                     \
+        if (P.D == 64) {                                                                      \
+            if (upw <= 2) return FN<64, MODE_, LIK_MIXTURE, 2>(__VA_ARGS__);                  \
+            return FN<64, MODE_, LIK_MIXTURE, 8>(__VA_ARGS__);                                \
+        }                                                                                     \
+        return FN<128, MODE_, LIK_MIXTURE, 4>(__VA_ARGS__);                                   \
+    } while (0)
+#define NSS_DISPATCH(FN, ...)                                                                 \
+    do {                                                                                      \
+        if (P.lik_kind == LIK_FUNNEL) {                                                       \
+            if (mode != MODE_FP64) return hipErrorNotSupported;                               \
+            if (P.D == 32) return FN<32, MODE_FP64, LIK_FUNNEL, 1>(__VA_ARGS__);              \
+            if (P.D == 64) return FN<64, MODE_FP64, LIK_FUNNEL, 1>(__VA_ARGS__);              \
+            return FN<128, MODE_FP64, LIK_FUNNEL, 1>(__VA_ARGS__);                            \
+        }                                                                                     \
+        if (mode == MODE_FP64) {                                                              \
+            if (P.D == 32) return FN<32, MODE_FP64, LIK_MIXTURE, 1>(__VA_ARGS__);             \
+            if (P.D == 64) return FN<64, MODE_FP64, LIK_MIXTURE, 1>(__VA_ARGS__);             \
+            return FN<128, MODE_FP64, LIK_MIXTURE, 1>(__VA_ARGS__);                           \
+        }                                                                                     \
+        if (!mode_supported(P, mode)) return hipErrorNotSupported;                            \
+        const int upw = upw_for(P);                                                           \
+        if (mode == MODE_BF16) NSS_MIXED_D(FN, MODE_BF16, __VA_ARGS__);                       \
+        if (mode == MODE_FP16) NSS_MIXED_D(FN, MODE_FP16, __VA_ARGS__);                       \
+        if (mode == MODE_BF16X3) NSS_MIXED_D(FN, MODE_BF16X3, __VA_ARGS__);                   \
+        NSS_MIXED_D(FN, MODE_FP16X3, __VA_ARGS__);                                            \
+    } while (0)
+
+hipError_t launch_eval_points(const DevProblem &P, const double *X, int ld, int n, double *out,
+                              unsigned long long *nonfinite, int mode, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    NSS_DISPATCH(eval_t, P, X, ld, n, out, nonfinite, s);
+}
+
+hipError_t launch_hrss(const DevProblem &P, const DevRun &R, int mode, hipStream_t s)
+{
+    NSS_DISPATCH(hrss_t, P, R, s);
+}
+
+hipError_t launch_select(const DevProblem &P, const DevRun &R, int op, hipStream_t s)
+{
+    (void)P;
+    int NP = 1;
+    while (NP < R.m) NP <<= 1;
+    const size_t lds = (size_t)NP * 8 + (size_t)(NP + (NP & 1)) * 4 + 32 * 8 + 16;
+    hipError_t e = set_lds(k_select, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_select, dim3(1), dim3(kSelectThreads), lds, s, R, op);
+    return hipGetLastError();
+}
+
+hipError_t launch_cov(const DevProblem &P, const DevRun &R, double *part1, double *part2, int G,
+                      hipStream_t s)
+{
+    const int nt = P.D / 16;
+    const int ntile = nt * (nt + 1) / 2;
+    hipLaunchKernelGGL(k_cov, dim3(ntile, G), dim3(256), 0, s, P, R, part1, part2, G);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const size_t lds = (size_t)(P.D * (P.D + 1) / 2 + P.D + 32) * 8 + 16;
+    e = set_lds(k_chol, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_chol, dim3(1), dim3(1024), lds, s, P, R, part1, part2, G, ntile);
+    return hipGetLastError();
+}
+
+template <int D>
+static hipError_t dirs_t(const DevProblem &P, const DevRun &R, hipStream_t s)
+{
+    const size_t lds = (size_t)dirs_lds_bytes(D);
+    hipError_t e = set_lds(k_dirs<D>, lds);
+    if (e != hipSuccess) return e;
+    const long long total = (long long)R.k * R.p;
+    hipLaunchKernelGGL(k_dirs<D>, dim3((unsigned)((total + kDirRows - 1) / kDirRows)), dim3(256),
+                       lds, s, P, R);
+    return hipGetLastError();
+}
+
+hipError_t launch_dirs(const DevProblem &P, const DevRun &R, hipStream_t s)
+{
+    if (!R.dirbuf) return hipSuccess;
+    if (P.D == 32) return dirs_t<32>(P, R, s);
+    if (P.D == 64) return dirs_t<64>(P, R, s);
+    return dirs_t<128>(P, R, s);
+}
+
+hipError_t launch_logz(const DevProblem &P, const DevRun &R, hipStream_t s)
+{
+    (void)P;
+    hipLaunchKernelGGL(k_logz, dim3(1), dim3(1024), 0, s, R);
+    return hipGetLastError();
+}
+}  // namespace nss

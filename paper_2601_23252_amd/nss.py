@@ -1,0 +1,322 @@
+"""Python binding of libnss.so (include/nss.h): argument marshalling only.
+
+Every step of the sampler runs in the HIP kernels behind the C ABI; this module converts
+numpy arrays and problem dictionaries to the ABI's structs and back.  The functions carry the
+ABI's names (ns_init, ns_step, ns_run, ns_logz, ...); ``NSRun`` bundles them for convenience.
+If the library is missing it is built with hipcc; if it cannot be loaded an ImportError is
+raised: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libnss.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "nss.h")
+
+NS_OK, NS_DONE, NS_EINVAL, NS_ENOMEM, NS_EDEVICE, NS_ESTATE, NS_EUNSUPPORTED = 0, 1, -1, -2, -3, -4, -5
+NS_PRIOR_BOX, NS_PRIOR_GAUSS_DIAG = 0, 1
+NS_LIK_MIXTURE, NS_LIK_FUNNEL = 1, 2
+NS_FP64, NS_MIXED_BF16, NS_MIXED_FP16, NS_MIXED_BF16X3, NS_MIXED_FP16X3 = 0, 1, 2, 3, 4
+NS_FLAG_TRACE, NS_FLAG_TIMING, NS_FLAG_INLINE_DIRECTIONS = 1, 2, 4
+PRECISIONS = {"fp64": NS_FP64, "bf16": NS_MIXED_BF16, "fp16": NS_MIXED_FP16,
+              "bf16x3": NS_MIXED_BF16X3, "fp16x3": NS_MIXED_FP16X3}
+# guard band of each mixed mode: (rel, abs) as set by the library
+GUARD = {"bf16": (0.025, 2e-3), "fp16": (0.0032, 2e-3), "bf16x3": (4e-5, 2e-4),
+         "fp16x3": (6e-6, 2e-4)}
+
+_d = C.POINTER(C.c_double)
+_i32 = C.POINTER(C.c_int32)
+
+
+class ns_prior(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("d", C.c_int32), ("a", _d), ("b", _d)]
+
+
+class ns_energy(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("d", C.c_int32), ("n_comp", C.c_int32), ("logw", _d),
+                ("mean", _d), ("cov", _d)]
+
+
+class ns_config(C.Structure):
+    _fields_ = [("n_live", C.c_int32), ("k", C.c_int32), ("chain_len", C.c_int32),
+                ("width", C.c_double), ("stepout_cap", C.c_int32), ("shrink_cap", C.c_int32),
+                ("term_frac", C.c_double), ("seed", C.c_uint64), ("run_id", C.c_uint32),
+                ("precision", C.c_int32), ("max_iter", C.c_int32), ("flags", C.c_int32)]
+
+
+class ns_stats_t(C.Structure):
+    _fields_ = [("iterations", C.c_int64), ("evals", C.c_int64), ("tests", C.c_int64),
+                ("prior_rejects", C.c_int64), ("stepout_caps", C.c_int64),
+                ("shrink_caps", C.c_int64), ("nonfinite", C.c_int64), ("rechecks", C.c_int64),
+                ("band_violations", C.c_int64), ("whiten_fallbacks", C.c_int64),
+                ("n_dead", C.c_int64), ("hrss_ms", C.c_double), ("hrss_launches", C.c_int64),
+                ("width", C.c_double)]
+
+
+class ns_state_view(C.Structure):
+    _fields_ = [("x", _d), ("logL", _d), ("perm", _i32), ("Lsig", _d), ("parents", _i32),
+                ("Lstar", C.c_double), ("logZ", C.c_double), ("logX", C.c_double),
+                ("M", C.c_double), ("iter", C.c_int64), ("done", C.c_int32)]
+
+
+def header_functions() -> list[str]:
+    """Names of the functions include/nss.h declares."""
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(ns_[a-z_]+)\s*\(", txt)))
+
+
+_lib = None
+
+
+def load(build_if_missing: bool = True):
+    global _lib
+    if _lib is not None:
+        return _lib
+    # One HIP runtime per process: torch ships its own libamdhip64 whose dependents ask for
+    # the unversioned name, so loading /opt/rocm's copy first would put two runtimes in the
+    # process.  Importing torch first makes libnss.so bind to the copy torch already loaded.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    if not os.path.exists(LIB_PATH):
+        if not build_if_missing:
+            raise ImportError(f"{LIB_PATH} is not built")
+        from . import build as _b
+        _b.build()
+    L = C.CDLL(LIB_PATH)
+    vp = C.c_void_p
+    L.ns_init.restype = C.c_int
+    L.ns_init.argtypes = [C.POINTER(ns_prior), C.POINTER(ns_energy), C.POINTER(ns_config), vp,
+                          C.POINTER(vp)]
+    L.ns_reset.restype = C.c_int
+    L.ns_reset.argtypes = [vp, C.c_uint64, C.c_uint32]
+    L.ns_step.restype = C.c_int
+    L.ns_step.argtypes = [vp, _i32]
+    L.ns_run.restype = C.c_int
+    L.ns_run.argtypes = [vp, C.c_int32, _i32]
+    L.ns_logz.restype = C.c_int
+    L.ns_logz.argtypes = [vp, _d, _d, _d]
+    L.ns_stats.restype = C.c_int
+    L.ns_stats.argtypes = [vp, C.POINTER(ns_stats_t)]
+    L.ns_get_state.restype = C.c_int
+    L.ns_get_state.argtypes = [vp, C.POINTER(ns_state_view)]
+    L.ns_set_state.restype = C.c_int
+    L.ns_set_state.argtypes = [vp, C.POINTER(ns_state_view)]
+    L.ns_get_dead.restype = C.c_int
+    L.ns_get_dead.argtypes = [vp, _d, C.c_int64, C.POINTER(C.c_int64)]
+    L.ns_get_trace.restype = C.c_int
+    L.ns_get_trace.argtypes = [vp, _i32]
+    L.ns_eval_loglik.restype = C.c_int
+    L.ns_eval_loglik.argtypes = [vp, _d, C.c_int32, C.c_int32, _d]
+    L.ns_free.restype = None
+    L.ns_free.argtypes = [vp]
+    L.ns_last_error.restype = C.c_char_p
+    L.ns_last_error.argtypes = [vp]
+    L.ns_config_default.restype = None
+    L.ns_config_default.argtypes = [C.POINTER(ns_config)]
+    _lib = L
+    return L
+
+
+class NSError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"status {status}: {msg}")
+        self.status = status
+
+
+def _ptr(a, t=_d):
+    return a.ctypes.data_as(t) if a is not None else None
+
+
+def _check(st, ctx=None, ok=(NS_OK,)):
+    if st not in ok:
+        raise NSError(st, load().ns_last_error(ctx).decode())
+    return st
+
+
+# ---- the ABI's calls -------------------------------------------------------------------------
+def ns_config_default() -> ns_config:
+    c = ns_config()
+    load().ns_config_default(C.byref(c))
+    return c
+
+
+def ns_init(prior: ns_prior, energy: ns_energy, cfg: ns_config, stream=None):
+    """Returns (status, ctx); ctx is None unless status is NS_OK."""
+    ctx = C.c_void_p()
+    ref = lambda o: C.byref(o) if o is not None else None
+    st = load().ns_init(ref(prior), ref(energy), ref(cfg), stream, C.byref(ctx))
+    return st, (ctx.value if st == NS_OK else None)
+
+
+def ns_reset(ctx, seed, run_id=0):
+    return load().ns_reset(ctx, int(seed), int(run_id))
+
+
+def ns_step(ctx):
+    done = C.c_int32(0)
+    st = load().ns_step(ctx, C.byref(done))
+    return st, int(done.value)
+
+
+def ns_run(ctx, max_iter):
+    it = C.c_int32(0)
+    st = load().ns_run(ctx, int(max_iter), C.byref(it))
+    return st, int(it.value)
+
+
+def ns_logz(ctx):
+    z, e, h = C.c_double(), C.c_double(), C.c_double()
+    st = load().ns_logz(ctx, C.byref(z), C.byref(e), C.byref(h))
+    return st, z.value, e.value, h.value
+
+
+def ns_stats(ctx):
+    s = ns_stats_t()
+    st = load().ns_stats(ctx, C.byref(s))
+    return st, {f: getattr(s, f) for f, _ in ns_stats_t._fields_}
+
+
+def ns_free(ctx):
+    if ctx:
+        load().ns_free(ctx)
+
+
+def ns_last_error(ctx=None) -> str:
+    return load().ns_last_error(ctx).decode()
+
+
+# ---- problem marshalling ---------------------------------------------------------------------
+def make_structs(prob: dict):
+    """(ns_prior, ns_energy, keep-alive arrays) from a problem dictionary."""
+    d = int(prob["d"])
+    pa = np.ascontiguousarray(prob["prior_a"], np.float64)
+    pb = np.ascontiguousarray(prob["prior_b"], np.float64)
+    pr = ns_prior(NS_PRIOR_BOX if prob["prior"] == "box" else NS_PRIOR_GAUSS_DIAG, d, _ptr(pa),
+                  _ptr(pb))
+    keep = [pa, pb]
+    if prob["lik"] == "mixture":
+        K = int(prob["K"])
+        lw = np.ascontiguousarray(prob["logw"], np.float64)
+        mu = np.ascontiguousarray(prob["mu"], np.float64).reshape(K, d)
+        cov = np.ascontiguousarray(prob["cov"], np.float64).reshape(K, d, d)
+        keep += [lw, mu, cov]
+        en = ns_energy(NS_LIK_MIXTURE, d, K, _ptr(lw), _ptr(mu), _ptr(cov))
+    elif prob["lik"] == "funnel":
+        en = ns_energy(NS_LIK_FUNNEL, d, 0, None, None, None)
+    else:
+        raise ValueError(prob["lik"])
+    return pr, en, keep
+
+
+def current_stream():
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    except Exception:
+        pass
+    return None
+
+
+class NSRun:
+    """One nested-sampling run on the GPU (wraps one ns_ctx)."""
+
+    def __init__(self, prob: dict, m=None, k=None, p=None, width=0.0, seed=0, run_id=0,
+                 precision="fp64", term_frac=1e-3, stepout_cap=10, shrink_cap=100,
+                 max_iter=100000, trace=False, timing=False, inline_directions=False,
+                 stream="torch"):
+        self.prob = prob
+        self.d = int(prob["d"])
+        self.m = int(m or prob["m"])
+        self.k = int(k or prob["k"])
+        self.p = int(p or prob["p"])
+        pr, en, self._keep = make_structs(prob)
+        cfg = ns_config_default()
+        cfg.n_live, cfg.k, cfg.chain_len = self.m, self.k, self.p
+        cfg.width = float(width)
+        cfg.stepout_cap, cfg.shrink_cap = int(stepout_cap), int(shrink_cap)
+        cfg.term_frac = float(term_frac)
+        cfg.seed, cfg.run_id = int(seed), int(run_id)
+        cfg.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        cfg.max_iter = int(max_iter)
+        cfg.flags = ((NS_FLAG_TRACE if trace else 0) | (NS_FLAG_TIMING if timing else 0)
+                     | (NS_FLAG_INLINE_DIRECTIONS if inline_directions else 0))
+        self.cfg = cfg
+        s = current_stream() if stream == "torch" else stream
+        st, self.ctx = ns_init(pr, en, cfg, s)
+        _check(st)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            ns_free(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        self.close()
+
+    def reset(self, seed, run_id=0):
+        _check(ns_reset(self.ctx, seed, run_id), self.ctx)
+
+    def step(self) -> bool:
+        st, done = ns_step(self.ctx)
+        _check(st, self.ctx, ok=(NS_OK, NS_DONE))
+        return bool(done)
+
+    def run(self, max_iter=100000) -> int:
+        st, it = ns_run(self.ctx, max_iter)
+        _check(st, self.ctx)
+        return it
+
+    def logz(self):
+        st, z, e, h = ns_logz(self.ctx)
+        _check(st, self.ctx)
+        return z, e, h
+
+    def stats(self) -> dict:
+        st, s = ns_stats(self.ctx)
+        _check(st, self.ctx)
+        return s
+
+    def state(self) -> dict:
+        m, d, k = self.m, self.d, self.k
+        x = np.zeros((m, d)); logL = np.zeros(m); perm = np.zeros(m, np.int32)
+        Ls = np.zeros((d, d)); par = np.zeros(k, np.int32)
+        v = ns_state_view(_ptr(x), _ptr(logL), _ptr(perm, _i32), _ptr(Ls), _ptr(par, _i32),
+                          0.0, 0.0, 0.0, 0.0, 0, 0)
+        _check(load().ns_get_state(self.ctx, C.byref(v)), self.ctx)
+        return dict(x=x, logL=logL, perm=perm, Lsig=Ls, parents=par, Lstar=v.Lstar, logZ=v.logZ,
+                    logX=v.logX, M=v.M, iter=int(v.iter), done=int(v.done))
+
+    def set_state(self, x, logL, logZ, logX, M, iter_, done=0):
+        x = np.ascontiguousarray(x, np.float64)
+        logL = np.ascontiguousarray(logL, np.float64)
+        v = ns_state_view(_ptr(x), _ptr(logL), None, None, None, 0.0, float(logZ), float(logX),
+                          float(M), int(iter_), int(done))
+        _check(load().ns_set_state(self.ctx, C.byref(v)), self.ctx)
+
+    def dead(self) -> np.ndarray:
+        n = C.c_int64(0)
+        _check(load().ns_get_dead(self.ctx, None, 0, C.byref(n)), self.ctx)
+        out = np.zeros(n.value)
+        _check(load().ns_get_dead(self.ctx, _ptr(out), n.value, C.byref(n)), self.ctx)
+        return out
+
+    def trace(self) -> np.ndarray:
+        out = np.zeros((self.k, self.p, 4), np.int32)
+        _check(load().ns_get_trace(self.ctx, _ptr(out, _i32)), self.ctx)
+        return out
+
+    def eval_loglik(self, x, precision="fp64") -> np.ndarray:
+        x = np.ascontiguousarray(np.atleast_2d(x), np.float64)
+        out = np.zeros(x.shape[0])
+        prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        _check(load().ns_eval_loglik(self.ctx, _ptr(x), x.shape[0], prec, _ptr(out)), self.ctx)
+        return out

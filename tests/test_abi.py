@@ -1,0 +1,72 @@
+"""C ABI checks that need no GPU: the library loads, exports every function include/nss.h
+declares, and rejects invalid arguments before touching a device."""
+import numpy as np
+import pytest
+
+
+@pytest.fixture(scope="module")
+def N():
+    from paper_2601_23252_amd import nss
+    nss.load()
+    return nss
+
+
+def test_exports_every_declared_function(N):
+    L = N.load()
+    names = N.header_functions()
+    for required in ("ns_init", "ns_step", "ns_run", "ns_logz", "ns_reset", "ns_free",
+                     "ns_stats", "ns_get_state", "ns_set_state", "ns_eval_loglik"):
+        assert required in names
+    for f in names:
+        assert hasattr(L, f), f
+
+
+def test_config_defaults(N):
+    c = N.ns_config_default()
+    assert (c.stepout_cap, c.shrink_cap) == (10, 100)
+    assert abs(c.term_frac - 1e-3) < 1e-15 and c.precision == N.NS_FP64
+
+
+def _structs(N, prob):
+    return N.make_structs(prob)
+
+
+@pytest.mark.parametrize("m,k,p", [(10, 10, 5), (10, 0, 5), (1, 1, 5), (10, 3, 0), (9000, 10, 5)])
+def test_invalid_run_shape(N, m, k, p):
+    from paper_2601_23252_amd import problems as G
+    pr, en, keep = _structs(N, G.config1())
+    cfg = N.ns_config_default()
+    cfg.n_live, cfg.k, cfg.chain_len = m, k, p
+    st, ctx = N.ns_init(pr, en, cfg, None)
+    assert ctx is None
+    assert st == (N.NS_EUNSUPPORTED if m > 8192 else N.NS_EINVAL)
+    assert N.ns_last_error(None)
+
+
+def test_invalid_problem(N):
+    from paper_2601_23252_amd import problems as G
+    cfg = N.ns_config_default()
+    cfg.n_live, cfg.k, cfg.chain_len = 50, 10, 5
+    pr, en, keep = _structs(N, G.funnel(200))
+    assert N.ns_init(pr, en, cfg, None)[0] == N.NS_EUNSUPPORTED   # d > 128
+    pr, en, keep = _structs(N, G.funnel(1 + 1))
+    en.d = 3
+    assert N.ns_init(pr, en, cfg, None)[0] == N.NS_EINVAL          # dimension mismatch
+    pr, en, keep = _structs(N, G.config1())
+    en.n_comp = 0
+    assert N.ns_init(pr, en, cfg, None)[0] == N.NS_EINVAL
+    pr, en, keep = _structs(N, G.config1())
+    cfg.precision = 9
+    assert N.ns_init(pr, en, cfg, None)[0] == N.NS_EINVAL
+    pr, en, keep = _structs(N, G.funnel(8))
+    cfg.precision = N.NS_MIXED_BF16
+    assert N.ns_init(pr, en, cfg, None)[0] == N.NS_EUNSUPPORTED    # mixed: mixtures only
+    assert N.ns_init(None, en, cfg, None)[0] == N.NS_EINVAL
+
+
+def test_null_context_calls(N):
+    assert N.ns_step(None)[0] == N.NS_EINVAL
+    assert N.ns_run(None, 1)[0] == N.NS_EINVAL
+    assert N.ns_logz(None)[0] == N.NS_EINVAL
+    assert N.ns_reset(None, 0) == N.NS_EINVAL
+    N.ns_free(None)
