@@ -48,6 +48,9 @@ def run_gpu(N, prob, precision, seeds, p, warmup, timing=True):
         z, err, H = R.logz()
         dt = time.perf_counter() - t0
         st = R.stats()
+        print(f"[bench] {precision} seed {s}: {it} iterations, {dt:.2f} s, "
+              f"{st['evals'] / dt:.3e} evals/s, ln Z {z:.3f} +- {err:.3f}", file=sys.stderr,
+              flush=True)
         recs.append(dict(seed=s, iters=it, wall_s=dt, evals=st["evals"], logz=z, err=err, H=H,
                          hrss_ms=st["hrss_ms"], hrss_launches=st["hrss_launches"],
                          rechecks=st["rechecks"], band_violations=st["band_violations"],
