@@ -115,9 +115,10 @@ typedef struct {
 
 #define NS_FLAG_TRACE  1  /* record per-chain, per-step (left, right, shrinks, accepted) */
 #define NS_FLAG_TIMING 2  /* time every HRSS kernel with HIP events on the context's stream */
-#define NS_FLAG_INLINE_DIRECTIONS 4  /* chains draw their directions themselves instead of a
-                                      * per-iteration direction buffer of k*p*d doubles (the
-                                      * buffer is also skipped when it would exceed 4 GiB) */
+#define NS_FLAG_INLINE_DIRECTIONS 4  /* chains draw their directions and step uniforms
+                                      * themselves instead of reading a per-iteration buffer
+                                      * of k*p*(d+8) doubles (the buffer is also skipped when
+                                      * it would exceed 4 GiB) */
 
 typedef struct {
     int64_t iterations;     /* completed ns_step iterations */
@@ -129,7 +130,8 @@ typedef struct {
     int64_t stepout_caps;   /* sides that stopped at the expansion cap */
     int64_t shrink_caps;    /* null moves from the shrink cap */
     int64_t nonfinite;      /* NaN/+inf log-likelihoods treated as -inf */
-    int64_t rechecks;       /* mixed precision: candidates re-evaluated in FP64 near L* */
+    int64_t rechecks;       /* mixed precision: decisions taken on an FP64 re-evaluation
+                             * because the 16-bit estimate was within the guard band of L* */
     int64_t band_violations;/* mixed precision: accepted points whose FP64 logL <= L* */
     int64_t whiten_fallbacks; /* iterations whose covariance factorisation failed (diagonal used) */
     int64_t n_dead;         /* dead points recorded */
@@ -199,6 +201,36 @@ ns_status ns_get_trace(ns_ctx *ctx, int32_t *out);
  * mode), writing out[n].  Runs the same device evaluators as the chains; for tests. */
 ns_status ns_eval_loglik(ns_ctx *ctx, const double *x, int32_t n, int32_t precision,
                          double *out);
+
+/* Batched serving of independent runs (many runs of uneven dimension and likelihood on one
+ * GPU).  Run r has its own prior priors[r], energy energies[r] and configuration cfgs[r]
+ * (dimension, n_live, k, chain length, precision, seed, run_id, flags; NS_FLAG_TIMING on any
+ * run times the whole batch).  Every kernel of an outer iteration is one launch over all
+ * unfinished runs that share its compiled shape (padded dimension, likelihood, precision);
+ * runs that have terminated drop out of the launches.  Each run follows exactly the trajectory
+ * it has alone (ns_init with the same arguments): chains draw from counters keyed by their
+ * own run's (seed, run_id) and runs share no state.
+ * On a batch context: ns_step and ns_run advance every unfinished run (ns_step's *done = 1 and
+ * NS_DONE once all have terminated; ns_run's *iters = the most iterations any run advanced);
+ * ns_reset restarts run r with (seed, run_id + r); NS_ESTATE from ns_step or ns_run means
+ * some run stopped on a plateau (it is finished; the others continue).  ns_logz, ns_stats,
+ * ns_get_state, ns_set_state, ns_get_dead, ns_get_trace and ns_eval_loglik address run 0.
+ * Arrays have n_runs entries; all pointers are host pointers copied as by ns_init.
+ * Errors: NS_EINVAL if n_runs < 1 or any run's arguments are invalid (ns_last_error(NULL)
+ * names the run), NS_EUNSUPPORTED for n_runs > 65536 or a run beyond this build. */
+ns_status ns_init_batch(int32_t n_runs, const ns_prior *priors, const ns_energy *energies,
+                        const ns_config *cfgs, void *hip_stream, ns_ctx **out);
+
+/* Number of runs of a context (0 for NULL). */
+int32_t ns_num_runs(const ns_ctx *ctx);
+
+/* ns_logz for every run: logz[r], logz_err[r], H[r] (any array may be NULL). */
+ns_status ns_logz_batch(ns_ctx *ctx, double *logz, double *logz_err, double *H);
+
+/* ns_stats / ns_get_state of run `run` (0 <= run < n_runs, else NS_EINVAL); hrss_ms and
+ * hrss_launches are the batch's. */
+ns_status ns_stats_run(ns_ctx *ctx, int32_t run, ns_stats_t *out);
+ns_status ns_get_state_run(ns_ctx *ctx, int32_t run, ns_state_view *view);
 
 void ns_free(ns_ctx *ctx);
 

@@ -12,19 +12,49 @@
 
 using namespace nss;
 
+// One run of a context: its configuration, the device descriptors (host copies holding device
+// pointers) and the run's launch shape.
+struct RunHost {
+    ns_config cfg;
+    int d = 0, D = 0, m = 0, m_pad = 0, k = 0, p = 0, mode = 0, lik = 0, K = 0, upw = 1;
+    DevProblem P;   // descriptor in the run's own precision
+    DevRun R;
+    // 16-bit W fragments per format, and the rounded remainders for the split modes
+    const uint4 *wf_bf16 = nullptr, *wf_fp16 = nullptr, *wf_bf16_lo = nullptr,
+                *wf_fp16_lo = nullptr;
+    int done = 0;
+};
+
+// Runs that share one compiled HRSS kernel: (padded dimension, likelihood, precision, fragment
+// capacity).
+struct Group {
+    int D, lik, mode, upwT;
+    std::vector<int> runs;
+};
+
 struct ns_ctx {
     hipStream_t stream = nullptr;
     bool own_stream = false;
-    ns_config cfg;
-    int d = 0, D = 0, m = 0, m_pad = 0, k = 0, p = 0, mode = 0;
-    DevProblem P;
-    DevRun R;
-    double *part1 = nullptr, *part2 = nullptr;
-    // 16-bit W fragments per format, and the rounded remainders for the split modes
-    const uint4 *wf_bf16 = nullptr, *wf_fp16 = nullptr, *wf_bf16_lo = nullptr, *wf_fp16_lo = nullptr;
-    int covG = 1;
-    int *h_iscal = nullptr;   // pinned mirror of iscal[0..7]
-    int done = 0;
+    int n = 0;                       // runs
+    int timing = 0;
+    std::vector<RunHost> runs;
+    std::vector<Group> groups;
+    DevProblem *dP = nullptr;        // [n + 1] device descriptors; slot n is ns_eval_loglik's
+    DevRun *dR = nullptr;            // [n + 1]
+    int *d_iscal = nullptr;          // [n][8] run flags, contiguous so one copy reads them all
+    double *d_scal = nullptr;        // [n][8]
+    unsigned long long *d_ctr = nullptr;  // [n][16]
+    int *h_iscal = nullptr;          // pinned mirror of d_iscal
+    int2 *d_map1 = nullptr;          // [n + 1]: (r, 0), a one-block launch of run r
+    int2 *d_map = nullptr;           // block maps of the current launches
+    size_t map_cap = 0;
+    std::vector<int2> h_map;
+    // launches over the unfinished runs (rebuilt when the set changes)
+    Launch L_init, L_one, L_cov, L_dirs[3];
+    std::vector<Launch> L_eval;      // per group (FP64 initial evaluation)
+    std::vector<Launch> L_hrss;      // per group
+    int Dmax = 32;
+    std::vector<char> mapped_active;
     std::vector<void *> allocs;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
     double hrss_ms = 0.0;
@@ -138,10 +168,12 @@ static uint16_t to_fp16(float f)
     return u;
 }
 
-static ns_status prepare_problem(ns_ctx *ctx, const ns_prior *prior, const ns_energy *en)
+
+static ns_status prepare_problem(ns_ctx *ctx, RunHost &rh, const ns_prior *prior,
+                                 const ns_energy *en)
 {
-    const int d = ctx->d, D = ctx->D;
-    DevProblem &P = ctx->P;
+    const int d = rh.d, D = rh.D;
+    DevProblem &P = rh.P;
     memset(&P, 0, sizeof(P));
     P.d = d;
     P.D = D;
@@ -169,8 +201,6 @@ static ns_status prepare_problem(ns_ctx *ctx, const ns_prior *prior, const ns_en
     P.pa = dpa;
     P.pb = dpb;
     P.lik_kind = en->kind == NS_LIK_MIXTURE ? LIK_MIXTURE : LIK_FUNNEL;
-    P.guard_rel = 0.f;
-    P.guard_abs = 0.f;
     if (P.lik_kind == LIK_FUNNEL) {
         P.K = 0;
         return NS_OK;
@@ -222,10 +252,9 @@ static ns_status prepare_problem(ns_ctx *ctx, const ns_prior *prior, const ns_en
     }
     double *dmu, *dcst, *dwf64;
     float *dmu32, *dcst32;
-    uint4 *dwf16;
     if ((st = dalloc(ctx, &dmu, mu.size())) || (st = dalloc(ctx, &dcst, K)) ||
         (st = dalloc(ctx, &dwf64, wf64.size())) || (st = dalloc(ctx, &dmu32, mu32.size())) ||
-        (st = dalloc(ctx, &dcst32, K)) || (st = dalloc(ctx, &dwf16, wbf.size() / 8)))
+        (st = dalloc(ctx, &dcst32, K)))
         return st;
     CK(hipMemcpy(dmu, mu.data(), mu.size() * 8, hipMemcpyHostToDevice));
     CK(hipMemcpy(dcst, cst.data(), K * 8, hipMemcpyHostToDevice));
@@ -235,19 +264,18 @@ static ns_status prepare_problem(ns_ctx *ctx, const ns_prior *prior, const ns_en
     P.mu = dmu; P.cst = dcst; P.wf64 = dwf64; P.mu32 = dmu32; P.cst32 = dcst32;
     P.cmax32 = cmax;
     // both 16-bit formats are kept so that any precision can be evaluated (ns_eval_loglik)
-    uint4 *dwfh, *dwfbl, *dwfhl;
-    if ((st = dalloc(ctx, &dwfh, nf16 / 8)) || (st = dalloc(ctx, &dwfbl, nf16 / 8)) ||
-        (st = dalloc(ctx, &dwfhl, nf16 / 8)))
+    uint4 *dwfb, *dwfh, *dwfbl, *dwfhl;
+    if ((st = dalloc(ctx, &dwfb, nf16 / 8)) || (st = dalloc(ctx, &dwfh, nf16 / 8)) ||
+        (st = dalloc(ctx, &dwfbl, nf16 / 8)) || (st = dalloc(ctx, &dwfhl, nf16 / 8)))
         return st;
-    CK(hipMemcpy(dwf16, wbf.data(), nf16 * 2, hipMemcpyHostToDevice));
+    CK(hipMemcpy(dwfb, wbf.data(), nf16 * 2, hipMemcpyHostToDevice));
     CK(hipMemcpy(dwfh, wh.data(), nf16 * 2, hipMemcpyHostToDevice));
     CK(hipMemcpy(dwfbl, wbf_lo.data(), nf16 * 2, hipMemcpyHostToDevice));
     CK(hipMemcpy(dwfhl, wh_lo.data(), nf16 * 2, hipMemcpyHostToDevice));
-    ctx->wf_bf16 = dwf16;
-    ctx->wf_fp16 = dwfh;
-    ctx->wf_bf16_lo = dwfbl;
-    ctx->wf_fp16_lo = dwfhl;
-    P.wf16 = dwf16;
+    rh.wf_bf16 = dwfb;
+    rh.wf_fp16 = dwfh;
+    rh.wf_bf16_lo = dwfbl;
+    rh.wf_fp16_lo = dwfhl;
     return NS_OK;
 }
 
@@ -259,57 +287,181 @@ static int pad_dim(int d) { return d <= 32 ? 32 : (d <= 64 ? 64 : 128); }
 // ~4.5x the worst relative error of the quadratic forms measured on the synthetic mixtures
 // (bf16 5.5e-3, fp16 7e-4, split bf16 8.9e-6, split fp16 6.4e-7 with FP32 accumulation) and
 // abs covers FP32 rounding of the log-sum-exp.
-static void run_dev_mode(const ns_ctx *ctx, int mode, DevProblem &P)
+static DevProblem problem_for_mode(const RunHost &rh, int mode)
 {
-    P = ctx->P;
+    DevProblem P = rh.P;
+    P.wf16 = nullptr;
+    P.wf16lo = nullptr;
     float rel = 0.f, ab = 0.f;
     switch (mode) {
-    case NS_MIXED_BF16: P.wf16 = ctx->wf_bf16; rel = 0.025f; ab = 2e-3f; break;
-    case NS_MIXED_FP16: P.wf16 = ctx->wf_fp16; rel = 0.0032f; ab = 2e-3f; break;
+    case NS_MIXED_BF16: P.wf16 = rh.wf_bf16; rel = 0.025f; ab = 2e-3f; break;
+    case NS_MIXED_FP16: P.wf16 = rh.wf_fp16; rel = 0.0032f; ab = 2e-3f; break;
     case NS_MIXED_BF16X3:
-        P.wf16 = ctx->wf_bf16; P.wf16lo = ctx->wf_bf16_lo; rel = 4e-5f; ab = 2e-4f; break;
+        P.wf16 = rh.wf_bf16; P.wf16lo = rh.wf_bf16_lo; rel = 4e-5f; ab = 2e-4f; break;
     case NS_MIXED_FP16X3:
-        P.wf16 = ctx->wf_fp16; P.wf16lo = ctx->wf_fp16_lo; rel = 6e-6f; ab = 2e-4f; break;
+        P.wf16 = rh.wf_fp16; P.wf16lo = rh.wf_fp16_lo; rel = 6e-6f; ab = 2e-4f; break;
     default: break;
     }
     P.guard_rel = rel;
     P.guard_abs = ab + rel * (P.K > 1 ? logf((float)P.K) : 0.f);
+    return P;
 }
 
-static int kmode(int precision) { return precision; }  // ns_precision values equal nss::Mode
 static bool precision_valid(int p) { return p >= NS_FP64 && p <= NS_MIXED_FP16X3; }
+static int d_index(int D) { return D == 32 ? 0 : (D == 64 ? 1 : 2); }
+
+// ---- block maps of the launches over the unfinished runs ----
+static int init_blocks(const RunHost &r) { return (r.m * ((r.d + 1) / 2) + 255) / 256; }
+static int eval_blocks(const RunHost &r) { return (r.m + kRows - 1) / kRows; }
+static int cov_blocks(const RunHost &r)
+{
+    const int nt = r.D / 16;
+    return nt * (nt + 1) / 2 * r.R.covG;
+}
+static int dirs_blocks(const RunHost &r)
+{
+    if (!r.R.dirbuf) return 0;
+    const long long t = (long long)r.k * r.p;
+    return (int)((t + dirs_rows() - 1) / dirs_rows());
+}
+static int hrss_blocks(const RunHost &r) { return (r.k + r.R.C - 1) / r.R.C; }
+
+struct MapBuilder {
+    std::vector<int2> &h;
+    std::vector<std::pair<Launch *, size_t>> fix;
+    template <typename F>
+    void add(ns_ctx *ctx, Launch &L, const std::vector<int> &rs, const std::vector<char> &act,
+             F blocks)
+    {
+        const size_t off = h.size();
+        L = Launch{ctx->dP, ctx->dR, nullptr, 0, 0, 0};
+        for (int r : rs) {
+            if (!act[r]) continue;
+            const RunHost &rh = ctx->runs[r];
+            const int nb = blocks(rh);
+            for (int b = 0; b < nb; ++b) h.push_back(make_int2(r, b));
+            if (nb > 0) {
+                if (rh.m > L.max_m) L.max_m = rh.m;
+                if (rh.K > L.max_K) L.max_K = rh.K;
+            }
+        }
+        L.nblocks = (int)(h.size() - off);
+        fix.emplace_back(&L, off);
+    }
+};
+
+// (Re)build every launch for the runs in act; uploads the maps (synchronously).
+static ns_status build_maps(ns_ctx *ctx, const std::vector<char> &act)
+{
+    ctx->h_map.clear();
+    MapBuilder mb{ctx->h_map, {}};
+    std::vector<int> all(ctx->n);
+    for (int r = 0; r < ctx->n; ++r) all[r] = r;
+    mb.add(ctx, ctx->L_init, all, act, init_blocks);
+    mb.add(ctx, ctx->L_one, all, act, [](const RunHost &) { return 1; });
+    mb.add(ctx, ctx->L_cov, all, act, cov_blocks);
+    for (int di = 0; di < 3; ++di) {
+        const int D = 32 << di;
+        std::vector<int> rs;
+        for (int r = 0; r < ctx->n; ++r)
+            if (ctx->runs[r].D == D) rs.push_back(r);
+        mb.add(ctx, ctx->L_dirs[di], rs, act, dirs_blocks);
+    }
+    ctx->L_eval.resize(ctx->groups.size());
+    ctx->L_hrss.resize(ctx->groups.size());
+    for (size_t g = 0; g < ctx->groups.size(); ++g) {
+        mb.add(ctx, ctx->L_eval[g], ctx->groups[g].runs, act, eval_blocks);
+        mb.add(ctx, ctx->L_hrss[g], ctx->groups[g].runs, act, hrss_blocks);
+    }
+    ctx->Dmax = 32;
+    for (int r = 0; r < ctx->n; ++r)
+        if (act[r] && ctx->runs[r].D > ctx->Dmax) ctx->Dmax = ctx->runs[r].D;
+    if (ctx->h_map.size() > ctx->map_cap) {
+        ctx->err = "internal: block map larger than its allocation";
+        return NS_EDEVICE;
+    }
+    for (auto &f : mb.fix) f.first->map = ctx->d_map + f.second;
+    if (!ctx->h_map.empty()) {
+        CK(hipStreamSynchronize(ctx->stream));
+        CK(hipMemcpy(ctx->d_map, ctx->h_map.data(), ctx->h_map.size() * sizeof(int2),
+                     hipMemcpyHostToDevice));
+    }
+    ctx->mapped_active = act;
+    return NS_OK;
+}
+
+static Launch launch_one(const ns_ctx *ctx, int slot)
+{
+    const RunHost &rh = ctx->runs[slot < ctx->n ? slot : 0];
+    return Launch{ctx->dP, ctx->dR, ctx->d_map1 + slot, 1, rh.m, rh.K};
+}
 
 static ns_status sync_flags(ns_ctx *ctx)
 {
-    CK(hipMemcpyAsync(ctx->h_iscal, ctx->R.iscal, 8 * sizeof(int), hipMemcpyDeviceToHost,
-                      ctx->stream));
+    CK(hipMemcpyAsync(ctx->h_iscal, ctx->d_iscal, (size_t)ctx->n * 8 * sizeof(int),
+                      hipMemcpyDeviceToHost, ctx->stream));
     CK(hipStreamSynchronize(ctx->stream));
-    ctx->done = ctx->h_iscal[0];
+    for (int r = 0; r < ctx->n; ++r) ctx->runs[r].done = ctx->h_iscal[8 * r];
     return NS_OK;
+}
+
+static bool all_done(const ns_ctx *ctx)
+{
+    for (const RunHost &r : ctx->runs)
+        if (!r.done) return false;
+    return true;
+}
+
+static bool any_error(const ns_ctx *ctx)
+{
+    for (int r = 0; r < ctx->n; ++r)
+        if (ctx->h_iscal[8 * r + 4]) return true;
+    return false;
+}
+
+// drop finished runs from the launches once they are known to be finished
+static ns_status refresh_maps(ns_ctx *ctx)
+{
+    std::vector<char> act(ctx->n);
+    bool changed = false;
+    for (int r = 0; r < ctx->n; ++r) {
+        act[r] = !ctx->runs[r].done;
+        if (act[r] != ctx->mapped_active[r]) changed = true;
+    }
+    return changed ? build_maps(ctx, act) : NS_OK;
+}
+
+static ns_status device_error(ns_ctx *ctx, const char *what, hipError_t e)
+{
+    ctx->err = std::string(what) + ": " + hipGetErrorString(e);
+    return e == hipErrorNotSupported ? NS_EUNSUPPORTED : NS_EDEVICE;
 }
 
 static ns_status enqueue_iteration(ns_ctx *ctx)
 {
-    DevProblem P;
-    run_dev_mode(ctx, ctx->mode, P);
-    CK(launch_cov(P, ctx->R, ctx->part1, ctx->part2, ctx->covG, ctx->stream));
-    CK(launch_dirs(P, ctx->R, ctx->stream));
+    hipError_t e = launch_cov(ctx->L_cov, ctx->L_one, ctx->Dmax, ctx->stream);
+    if (e != hipSuccess) return device_error(ctx, "whitening launch", e);
+    for (int di = 0; di < 3; ++di) {
+        e = launch_dirs(ctx->L_dirs[di], 32 << di, ctx->stream);
+        if (e != hipSuccess) return device_error(ctx, "direction launch", e);
+    }
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (ctx->cfg.flags & NS_FLAG_TIMING) {
+    if (ctx->timing) {
         CK(hipEventCreate(&e0));
         CK(hipEventCreate(&e1));
         CK(hipEventRecord(e0, ctx->stream));
     }
-    hipError_t e = launch_hrss(P, ctx->R, kmode(ctx->mode), ctx->stream);
-    if (e != hipSuccess) {
-        ctx->err = std::string("HRSS launch: ") + hipGetErrorString(e);
-        return e == hipErrorNotSupported ? NS_EUNSUPPORTED : NS_EDEVICE;
+    for (size_t g = 0; g < ctx->groups.size(); ++g) {
+        const Group &G = ctx->groups[g];
+        e = launch_hrss(ctx->L_hrss[g], G.D, G.lik, G.mode, G.upwT, ctx->stream);
+        if (e != hipSuccess) return device_error(ctx, "HRSS launch", e);
     }
     if (e1) {
         CK(hipEventRecord(e1, ctx->stream));
         ctx->events.emplace_back(e0, e1);
     }
-    CK(launch_select(P, ctx->R, 1, ctx->stream));
+    e = launch_select(ctx->L_one, 1, ctx->stream);
+    if (e != hipSuccess) return device_error(ctx, "select launch", e);
     return NS_OK;
 }
 
@@ -329,33 +481,41 @@ static ns_status collect_events(ns_ctx *ctx)
     return NS_OK;
 }
 
-// Prior draws, FP64 evaluation, first delete-k; resets every run counter.
-static ns_status start_run(ns_ctx *ctx)
+// Prior draws, FP64 evaluation and first delete-k of every run; resets every run counter.
+static ns_status start_runs(ns_ctx *ctx)
 {
-    DevRun &R = ctx->R;
-    const int D = ctx->D, k = ctx->k, p = ctx->p;
-    CK(hipMemsetAsync(R.X, 0, (size_t)D * ctx->m_pad * 8, ctx->stream));
-    CK(hipMemsetAsync(R.iscal, 0, 8 * sizeof(int), ctx->stream));
-    CK(hipMemsetAsync(R.ctr, 0, 16 * 8, ctx->stream));
-    CK(hipMemsetAsync(R.Lsig, 0, (size_t)D * D * 8, ctx->stream));
-    CK(hipMemsetAsync(R.Lpk, 0, (size_t)D * (D + 1) / 2 * 8, ctx->stream));
-    if (R.trace) CK(hipMemsetAsync(R.trace, 0, (size_t)k * p * 16, ctx->stream));
-    if (R.prof) CK(hipMemsetAsync(R.prof, 0, 16 * 8, ctx->stream));
-    static const double sc0[8] = {0.0, -INFINITY, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    CK(hipMemcpyAsync(R.scal, sc0, sizeof(sc0), hipMemcpyHostToDevice, ctx->stream));
-    CK(launch_init_draw(ctx->P, R, ctx->stream));
-    hipError_t e = launch_eval_points(ctx->P, R.X, ctx->m_pad, ctx->m, R.logL, R.ctr + 5,
-                                      MODE_FP64, ctx->stream);
-    if (e != hipSuccess) {
-        ctx->err = std::string("init evaluation: ") + hipGetErrorString(e);
-        return NS_EDEVICE;
+    const int n = ctx->n;
+    for (RunHost &rh : ctx->runs) {
+        DevRun &R = rh.R;
+        CK(hipMemsetAsync(R.X, 0, (size_t)rh.D * rh.m_pad * 8, ctx->stream));
+        CK(hipMemsetAsync(R.Lsig, 0, (size_t)rh.D * rh.D * 8, ctx->stream));
+        CK(hipMemsetAsync(R.Lpk, 0, (size_t)rh.D * (rh.D + 1) / 2 * 8, ctx->stream));
+        if (R.trace) CK(hipMemsetAsync(R.trace, 0, (size_t)rh.k * rh.p * 16, ctx->stream));
+        if (R.prof) CK(hipMemsetAsync(R.prof, 0, 16 * 8, ctx->stream));
+        rh.done = 0;
     }
-    CK(launch_select(ctx->P, R, 0, ctx->stream));
+    CK(hipMemsetAsync(ctx->d_iscal, 0, (size_t)n * 8 * sizeof(int), ctx->stream));
+    CK(hipMemsetAsync(ctx->d_ctr, 0, (size_t)n * 16 * 8, ctx->stream));
+    std::vector<double> sc((size_t)n * 8, 0.0);
+    for (int r = 0; r < n; ++r) sc[(size_t)8 * r + 1] = -INFINITY;  // logZ
+    CK(hipMemcpyAsync(ctx->d_scal, sc.data(), sc.size() * 8, hipMemcpyHostToDevice, ctx->stream));
+    CK(hipStreamSynchronize(ctx->stream));  // sc is pageable host memory
+    ns_status st = build_maps(ctx, std::vector<char>(n, 1));
+    if (st != NS_OK) return st;
+    hipError_t e = launch_init_draw(ctx->L_init, ctx->stream);
+    if (e != hipSuccess) return device_error(ctx, "prior draw launch", e);
+    for (size_t g = 0; g < ctx->groups.size(); ++g) {
+        e = launch_eval_init(ctx->L_eval[g], ctx->groups[g].D, ctx->groups[g].lik, ctx->stream);
+        if (e != hipSuccess) return device_error(ctx, "initial evaluation", e);
+    }
+    e = launch_select(ctx->L_one, 0, ctx->stream);
+    if (e != hipSuccess) return device_error(ctx, "select launch", e);
     for (auto &pr : ctx->events) { (void)hipEventDestroy(pr.first); (void)hipEventDestroy(pr.second); }
     ctx->events.clear();
     ctx->hrss_ms = 0.0;
     ctx->hrss_launches = 0;
-    return sync_flags(ctx);
+    if ((st = sync_flags(ctx)) != NS_OK) return st;
+    return refresh_maps(ctx);
 }
 
 extern "C" const char *ns_last_error(const ns_ctx *ctx)
@@ -374,47 +534,121 @@ extern "C" void ns_free(ns_ctx *ctx)
     delete ctx;
 }
 
-extern "C" ns_status ns_init(const ns_prior *prior, const ns_energy *energy, const ns_config *cfg,
-                             void *hip_stream, ns_ctx **out)
+// Argument checks of one run (no allocation).
+static ns_status validate_run(const ns_prior *prior, const ns_energy *energy, const ns_config *cfg,
+                              std::string &msg)
+{
+    if (!prior || !energy || !cfg || !prior->a || !prior->b) { msg = "NULL argument"; return NS_EINVAL; }
+    const int d = prior->d;
+    if (d < 1 || energy->d != d) { msg = "dimension mismatch or d < 1"; return NS_EINVAL; }
+    if (d > 128) { msg = "d > 128"; return NS_EUNSUPPORTED; }
+    if (prior->kind != NS_PRIOR_BOX && prior->kind != NS_PRIOR_GAUSS_DIAG) {
+        msg = "unknown prior kind";
+        return NS_EINVAL;
+    }
+    if (energy->kind == NS_LIK_MIXTURE) {
+        if (energy->n_comp < 1 || !energy->logw || !energy->mean || !energy->cov) {
+            msg = "mixture needs n_comp >= 1, logw, mean, cov";
+            return NS_EINVAL;
+        }
+        if (energy->n_comp > 64) { msg = "n_comp > 64"; return NS_EUNSUPPORTED; }
+    } else if (energy->kind != NS_LIK_FUNNEL) {
+        msg = "unknown likelihood kind";
+        return NS_EINVAL;
+    } else if (d < 2) {
+        msg = "funnel needs d >= 2";
+        return NS_EINVAL;
+    }
+    const int m = cfg->n_live, k = cfg->k, p = cfg->chain_len;
+    if (m < 2 || k < 1 || k > m - 1 || p < 1) {
+        msg = "need 2 <= n_live, 1 <= k <= n_live-1, chain_len >= 1";
+        return NS_EINVAL;
+    }
+    if (m > kMaxLive) { msg = "n_live > 8192"; return NS_EUNSUPPORTED; }
+    if (cfg->stepout_cap < 0 || cfg->shrink_cap < 0 || cfg->max_iter < 1) {
+        msg = "negative cap or max_iter < 1";
+        return NS_EINVAL;
+    }
+    if (!precision_valid(cfg->precision)) { msg = "unknown precision"; return NS_EINVAL; }
+    if (cfg->precision != NS_FP64 && energy->kind != NS_LIK_MIXTURE) {
+        msg = "mixed precision is implemented for mixtures only";
+        return NS_EUNSUPPORTED;
+    }
+    return NS_OK;
+}
+
+static void set_key(DevRun &R, uint64_t seed, uint32_t run_id)
+{
+    R.key0 = (uint32_t)seed;
+    R.key1 = (uint32_t)(seed >> 32) ^ run_id;
+}
+
+// Device buffers of one run (the scalar blocks come from the context's contiguous arrays).
+static ns_status alloc_run(ns_ctx *ctx, int r)
+{
+    RunHost &rh = ctx->runs[r];
+    const ns_config *cfg = &rh.cfg;
+    DevRun &R = rh.R;
+    memset(&R, 0, sizeof(R));
+    const int d = rh.d, D = rh.D, m = rh.m, k = rh.k, p = rh.p;
+    R.m = m; R.m_pad = rh.m_pad; R.k = k; R.p = p;
+    const double kappa = 1.3035;
+    R.width = cfg->width > 0.0 ? cfg->width
+                               : 4.0 * kappa * sqrt((double)d + 2.0) * sqrt(2.0 / (M_PI * d));
+    R.stepout_cap = cfg->stepout_cap;
+    R.shrink_cap = cfg->shrink_cap;
+    R.term_on = cfg->term_frac > 0.0;
+    R.log_term = cfg->term_frac > 0.0 ? log(cfg->term_frac) : 0.0;
+    set_key(R, cfg->seed, cfg->run_id);
+    R.dead_cap = (long long)(cfg->max_iter + 1) * k;
+    R.iscal = ctx->d_iscal + 8 * r;
+    R.scal = ctx->d_scal + 8 * r;
+    R.ctr = ctx->d_ctr + 16 * r;
+    ns_status st;
+    if ((st = dalloc(ctx, &R.X, (size_t)D * rh.m_pad)) || (st = dalloc(ctx, &R.logL, m)) ||
+        (st = dalloc(ctx, &R.perm, m)) || (st = dalloc(ctx, &R.Lsig, (size_t)D * D)) ||
+        (st = dalloc(ctx, &R.Lpk, (size_t)D * (D + 1) / 2)) || (st = dalloc(ctx, &R.parents, k)) ||
+        (st = dalloc(ctx, &R.dead, (size_t)R.dead_cap)))
+        return st;
+    if (cfg->flags & NS_FLAG_TRACE)
+        if ((st = dalloc(ctx, &R.trace, (size_t)k * p * 4))) return st;
+#ifdef NSS_PHASE_TIMING
+    if ((st = dalloc(ctx, &R.prof, 16))) return st;
+#endif
+    // per-iteration direction buffer (k p D doubles) unless it would exceed 4 GiB; without it
+    // the chains generate their directions inline
+    const size_t bytes = (size_t)k * p * (D + 8) * 8;
+    if (bytes <= ((size_t)4 << 30) && !(cfg->flags & NS_FLAG_INLINE_DIRECTIONS)) {
+        if ((st = dalloc(ctx, &R.dirbuf, (size_t)k * p * D))) return st;
+        if ((st = dalloc(ctx, &R.ubuf, (size_t)k * p * 8))) return st;
+    }
+    const int n = m - k;
+    R.covG = n / 64 < 1 ? 1 : (n / 64 > 32 ? 32 : n / 64);
+    const int nt = D / 16, ntile = nt * (nt + 1) / 2;
+    if ((st = dalloc(ctx, &R.part1, (size_t)R.covG * D)) ||
+        (st = dalloc(ctx, &R.part2, (size_t)R.covG * ntile * 256)))
+        return st;
+    return NS_OK;
+}
+
+extern "C" ns_status ns_init_batch(int32_t n_runs, const ns_prior *priors,
+                                   const ns_energy *energies, const ns_config *cfgs,
+                                   void *hip_stream, ns_ctx **out)
 {
     g_init_err.clear();
     if (!out) return fail(nullptr, NS_EINVAL, "out is NULL");
     *out = nullptr;
-    if (!prior || !energy || !cfg || !prior->a || !prior->b)
-        return fail(nullptr, NS_EINVAL, "NULL argument");
-    const int d = prior->d;
-    if (d < 1 || energy->d != d) return fail(nullptr, NS_EINVAL, "dimension mismatch or d < 1");
-    if (d > 128) return fail(nullptr, NS_EUNSUPPORTED, "d > 128");
-    if (prior->kind != NS_PRIOR_BOX && prior->kind != NS_PRIOR_GAUSS_DIAG)
-        return fail(nullptr, NS_EINVAL, "unknown prior kind");
-    if (energy->kind == NS_LIK_MIXTURE) {
-        if (energy->n_comp < 1 || !energy->logw || !energy->mean || !energy->cov)
-            return fail(nullptr, NS_EINVAL, "mixture needs n_comp >= 1, logw, mean, cov");
-        if (energy->n_comp > 64) return fail(nullptr, NS_EUNSUPPORTED, "n_comp > 64");
-    } else if (energy->kind != NS_LIK_FUNNEL) {
-        return fail(nullptr, NS_EINVAL, "unknown likelihood kind");
-    } else if (d < 2) {
-        return fail(nullptr, NS_EINVAL, "funnel needs d >= 2");
+    if (n_runs < 1 || !priors || !energies || !cfgs)
+        return fail(nullptr, NS_EINVAL, "need n_runs >= 1 and non-NULL arrays");
+    if (n_runs > 65536) return fail(nullptr, NS_EUNSUPPORTED, "n_runs > 65536");
+    for (int r = 0; r < n_runs; ++r) {
+        std::string msg;
+        const ns_status s = validate_run(priors + r, energies + r, cfgs + r, msg);
+        if (s != NS_OK)
+            return fail(nullptr, s, n_runs > 1 ? "run " + std::to_string(r) + ": " + msg : msg);
     }
-    const int m = cfg->n_live, k = cfg->k, p = cfg->chain_len;
-    if (m < 2 || k < 1 || k > m - 1 || p < 1)
-        return fail(nullptr, NS_EINVAL, "need 2 <= n_live, 1 <= k <= n_live-1, chain_len >= 1");
-    if (m > kMaxLive) return fail(nullptr, NS_EUNSUPPORTED, "n_live > 8192");
-    if (cfg->stepout_cap < 0 || cfg->shrink_cap < 0 || cfg->max_iter < 1)
-        return fail(nullptr, NS_EINVAL, "negative cap or max_iter < 1");
-    if (!precision_valid(cfg->precision)) return fail(nullptr, NS_EINVAL, "unknown precision");
-    if (cfg->precision != NS_FP64 && energy->kind != NS_LIK_MIXTURE)
-        return fail(nullptr, NS_EUNSUPPORTED, "mixed precision is implemented for mixtures only");
-
     ns_ctx *ctx = new ns_ctx();
-    ctx->cfg = *cfg;
-    ctx->d = d;
-    ctx->D = pad_dim(d);
-    ctx->m = m;
-    ctx->m_pad = (m + 63) & ~63;
-    ctx->k = k;
-    ctx->p = p;
-    ctx->mode = cfg->precision;
+    ctx->n = n_runs;
     ns_status st;
     auto bail = [&](ns_status s) {
         g_init_err = ctx->err;
@@ -430,56 +664,89 @@ extern "C" ns_status ns_init(const ns_prior *prior, const ns_energy *energy, con
         }
         ctx->own_stream = true;
     }
-    if ((st = prepare_problem(ctx, prior, energy)) != NS_OK) return bail(st);
-    if (!mode_supported(ctx->P, kmode(ctx->mode))) {
-        ctx->err = "mixed precision: n_comp too large for this dimension";
-        return bail(NS_EUNSUPPORTED);
-    }
-    DevRun &R = ctx->R;
-    memset(&R, 0, sizeof(R));
-    R.m = m; R.m_pad = ctx->m_pad; R.k = k; R.p = p;
-    const double kappa = 1.3035;
-    R.width = cfg->width > 0.0 ? cfg->width
-                               : 4.0 * kappa * sqrt((double)d + 2.0) * sqrt(2.0 / (M_PI * d));
-    R.stepout_cap = cfg->stepout_cap;
-    R.shrink_cap = cfg->shrink_cap;
-    R.term_on = cfg->term_frac > 0.0;
-    R.log_term = cfg->term_frac > 0.0 ? log(cfg->term_frac) : 0.0;
-    R.key0 = (uint32_t)cfg->seed;
-    R.key1 = (uint32_t)(cfg->seed >> 32) ^ cfg->run_id;
-    const int D = ctx->D;
-    R.dead_cap = (long long)(cfg->max_iter + 1) * k;
-    if ((st = dalloc(ctx, &R.X, (size_t)D * ctx->m_pad)) || (st = dalloc(ctx, &R.logL, m)) ||
-        (st = dalloc(ctx, &R.perm, m)) || (st = dalloc(ctx, &R.scal, 8)) ||
-        (st = dalloc(ctx, &R.iscal, 8)) || (st = dalloc(ctx, &R.ctr, 16)) ||
-        (st = dalloc(ctx, &R.Lsig, (size_t)D * D)) ||
-        (st = dalloc(ctx, &R.Lpk, (size_t)D * (D + 1) / 2)) || (st = dalloc(ctx, &R.parents, k)) ||
-        (st = dalloc(ctx, &R.dead, (size_t)R.dead_cap)))
+    const int n = n_runs;
+    if ((st = dalloc(ctx, &ctx->d_iscal, (size_t)n * 8)) ||
+        (st = dalloc(ctx, &ctx->d_scal, (size_t)n * 8)) ||
+        (st = dalloc(ctx, &ctx->d_ctr, (size_t)n * 16)) ||
+        (st = dalloc(ctx, &ctx->dP, (size_t)n + 1)) || (st = dalloc(ctx, &ctx->dR, (size_t)n + 1)) ||
+        (st = dalloc(ctx, &ctx->d_map1, (size_t)n + 1)))
         return bail(st);
-    if (cfg->flags & NS_FLAG_TRACE)
-        if ((st = dalloc(ctx, &R.trace, (size_t)k * p * 4))) return bail(st);
-#ifdef NSS_PHASE_TIMING
-    if ((st = dalloc(ctx, &R.prof, 16))) return bail(st);
-#endif
-    // per-iteration direction buffer (k p D doubles) unless it would exceed 4 GiB; without it
-    // the chains generate their directions inline
-    {
-        const size_t bytes = (size_t)k * p * D * 8;
-        if (bytes <= ((size_t)4 << 30) && !(cfg->flags & NS_FLAG_INLINE_DIRECTIONS))
-            if ((st = dalloc(ctx, &R.dirbuf, (size_t)k * p * D))) return bail(st);
-    }
-    const int n = m - k;
-    ctx->covG = n / 64 < 1 ? 1 : (n / 64 > 32 ? 32 : n / 64);
-    const int nt = D / 16, ntile = nt * (nt + 1) / 2;
-    if ((st = dalloc(ctx, &ctx->part1, (size_t)ctx->covG * D)) ||
-        (st = dalloc(ctx, &ctx->part2, (size_t)ctx->covG * ntile * 256)))
-        return bail(st);
-    if (hipHostMalloc((void **)&ctx->h_iscal, 8 * sizeof(int), hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc((void **)&ctx->h_iscal, (size_t)n * 8 * sizeof(int), hipHostMallocDefault) !=
+        hipSuccess) {
         ctx->err = "hipHostMalloc failed";
         return bail(NS_ENOMEM);
     }
-    if ((st = start_run(ctx)) != NS_OK) return bail(st);
-    if (ctx->h_iscal[4]) {
+    ctx->runs.resize(n);
+    for (int r = 0; r < n; ++r) {
+        RunHost &rh = ctx->runs[r];
+        rh.cfg = cfgs[r];
+        rh.d = priors[r].d;
+        rh.D = pad_dim(rh.d);
+        rh.m = cfgs[r].n_live;
+        rh.m_pad = (rh.m + 63) & ~63;
+        rh.k = cfgs[r].k;
+        rh.p = cfgs[r].chain_len;
+        rh.mode = cfgs[r].precision;
+        if (cfgs[r].flags & NS_FLAG_TIMING) ctx->timing = 1;
+        if ((st = prepare_problem(ctx, rh, priors + r, energies + r)) != NS_OK) return bail(st);
+        rh.lik = rh.P.lik_kind;
+        rh.K = rh.P.K;
+        if (!mode_supported(rh.P, rh.mode)) {
+            ctx->err = "mixed precision: n_comp too large for this dimension";
+            if (n > 1) ctx->err = "run " + std::to_string(r) + ": " + ctx->err;
+            return bail(NS_EUNSUPPORTED);
+        }
+        rh.upw = rh.mode == NS_FP64 ? 1 : upw_template(rh.D, upw_for(rh.P));
+        rh.P = problem_for_mode(rh, rh.mode);
+        if ((st = alloc_run(ctx, r)) != NS_OK) return bail(st);
+        // group by compiled HRSS kernel
+        int g = -1;
+        for (size_t i = 0; i < ctx->groups.size(); ++i) {
+            const Group &G = ctx->groups[i];
+            if (G.D == rh.D && G.lik == rh.lik && G.mode == rh.mode && G.upwT == rh.upw) g = (int)i;
+        }
+        if (g < 0) {
+            ctx->groups.push_back(Group{rh.D, rh.lik, rh.mode, rh.upw, {}});
+            g = (int)ctx->groups.size() - 1;
+        }
+        ctx->groups[g].runs.push_back(r);
+    }
+    // chains per HRSS workgroup: enough workgroups to cover the CUs, full 16-row tiles beyond
+    for (const Group &G : ctx->groups) {
+        long long chains = 0;
+        for (int r : G.runs) chains += ctx->runs[r].k;
+        int C = (int)((chains + 255) / 256);
+        C = C < 1 ? 1 : (C > kMaxChainsPerWG ? kMaxChainsPerWG : C);
+        for (int r : G.runs) ctx->runs[r].R.C = C;
+    }
+    std::vector<DevProblem> hp(n + 1);
+    std::vector<DevRun> hr(n + 1);
+    std::vector<int2> m1(n + 1);
+    size_t cap = 0;
+    for (int r = 0; r < n; ++r) {
+        const RunHost &rh = ctx->runs[r];
+        hp[r] = rh.P;
+        hr[r] = rh.R;
+        m1[r] = make_int2(r, 0);
+        cap += (size_t)init_blocks(rh) + 1 + cov_blocks(rh) + dirs_blocks(rh) + eval_blocks(rh) +
+               hrss_blocks(rh);
+    }
+    hp[n] = hp[0];
+    hr[n] = hr[0];
+    m1[n] = make_int2(n, 0);
+    if ((st = dalloc(ctx, &ctx->d_map, cap))) return bail(st);
+    ctx->map_cap = cap;
+    if (hipMemcpy(ctx->dP, hp.data(), hp.size() * sizeof(DevProblem), hipMemcpyHostToDevice) !=
+            hipSuccess ||
+        hipMemcpy(ctx->dR, hr.data(), hr.size() * sizeof(DevRun), hipMemcpyHostToDevice) !=
+            hipSuccess ||
+        hipMemcpy(ctx->d_map1, m1.data(), m1.size() * sizeof(int2), hipMemcpyHostToDevice) !=
+            hipSuccess) {
+        ctx->err = "descriptor upload failed";
+        return bail(NS_EDEVICE);
+    }
+    if ((st = start_runs(ctx)) != NS_OK) return bail(st);
+    if (any_error(ctx)) {
         ctx->err = "no live point lies strictly above L* after the first deletion";
         return bail(NS_ESTATE);
     }
@@ -487,24 +754,43 @@ extern "C" ns_status ns_init(const ns_prior *prior, const ns_energy *energy, con
     return NS_OK;
 }
 
+extern "C" ns_status ns_init(const ns_prior *prior, const ns_energy *energy, const ns_config *cfg,
+                             void *hip_stream, ns_ctx **out)
+{
+    if (!prior || !energy || !cfg) {
+        g_init_err = "NULL argument";
+        if (out) *out = nullptr;
+        return NS_EINVAL;
+    }
+    return ns_init_batch(1, prior, energy, cfg, hip_stream, out);
+}
+
+extern "C" int32_t ns_num_runs(const ns_ctx *ctx) { return ctx ? ctx->n : 0; }
+
 extern "C" ns_status ns_reset(ns_ctx *ctx, uint64_t seed, uint32_t run_id)
 {
     if (!ctx) return NS_EINVAL;
     CK(hipStreamSynchronize(ctx->stream));
-    ctx->R.key0 = (uint32_t)seed;
-    ctx->R.key1 = (uint32_t)(seed >> 32) ^ run_id;
-    ctx->cfg.seed = seed;
-    ctx->cfg.run_id = run_id;
-    ns_status st = start_run(ctx);
+    std::vector<DevRun> hr(ctx->n + 1);
+    for (int r = 0; r < ctx->n; ++r) {
+        RunHost &rh = ctx->runs[r];
+        rh.cfg.seed = seed;
+        rh.cfg.run_id = run_id + (uint32_t)r;
+        set_key(rh.R, seed, rh.cfg.run_id);
+        hr[r] = rh.R;
+    }
+    hr[ctx->n] = hr[0];
+    CK(hipMemcpy(ctx->dR, hr.data(), hr.size() * sizeof(DevRun), hipMemcpyHostToDevice));
+    ns_status st = start_runs(ctx);
     if (st != NS_OK) return st;
-    if (ctx->h_iscal[4]) return fail(ctx, NS_ESTATE, "no live point lies strictly above L*");
+    if (any_error(ctx)) return fail(ctx, NS_ESTATE, "no live point lies strictly above L*");
     return NS_OK;
 }
 
 extern "C" ns_status ns_step(ns_ctx *ctx, int32_t *done)
 {
     if (!ctx) return NS_EINVAL;
-    if (ctx->done) {
+    if (all_done(ctx)) {
         if (done) *done = 1;
         return NS_DONE;
     }
@@ -512,8 +798,9 @@ extern "C" ns_status ns_step(ns_ctx *ctx, int32_t *done)
     if (st != NS_OK) return st;
     if ((st = sync_flags(ctx)) != NS_OK) return st;
     if ((st = collect_events(ctx)) != NS_OK) return st;
-    if (done) *done = ctx->done;
-    if (ctx->h_iscal[4]) return fail(ctx, NS_ESTATE, "no live point lies strictly above L*");
+    if ((st = refresh_maps(ctx)) != NS_OK) return st;
+    if (done) *done = all_done(ctx) ? 1 : 0;
+    if (any_error(ctx)) return fail(ctx, NS_ESTATE, "no live point lies strictly above L*");
     return NS_OK;
 }
 
@@ -522,28 +809,55 @@ extern "C" ns_status ns_run(ns_ctx *ctx, int32_t max_iter, int32_t *iters)
     if (!ctx || max_iter < 0) return NS_EINVAL;
     ns_status st;
     if ((st = sync_flags(ctx)) != NS_OK) return st;
-    const int start = ctx->h_iscal[3];
+    std::vector<int> start(ctx->n);
+    for (int r = 0; r < ctx->n; ++r) start[r] = ctx->h_iscal[8 * r + 3];
     int issued = 0;
-    while (!ctx->done && issued < max_iter) {
+    while (!all_done(ctx) && issued < max_iter) {
+        if ((st = refresh_maps(ctx)) != NS_OK) return st;
         const int batch = (max_iter - issued) < 16 ? (max_iter - issued) : 16;
         for (int b = 0; b < batch; ++b)
             if ((st = enqueue_iteration(ctx)) != NS_OK) return st;
         issued += batch;
         if ((st = sync_flags(ctx)) != NS_OK) return st;
-        if (ctx->h_iscal[4]) break;
     }
     if ((st = collect_events(ctx)) != NS_OK) return st;
-    if (iters) *iters = ctx->h_iscal[3] - start;
-    if (ctx->h_iscal[4]) return fail(ctx, NS_ESTATE, "no live point lies strictly above L*");
+    int adv = 0;
+    for (int r = 0; r < ctx->n; ++r) {
+        const int a = ctx->h_iscal[8 * r + 3] - start[r];
+        if (a > adv) adv = a;
+    }
+    if (iters) *iters = adv;
+    if (any_error(ctx)) return fail(ctx, NS_ESTATE, "no live point lies strictly above L*");
+    return NS_OK;
+}
+
+extern "C" ns_status ns_logz_batch(ns_ctx *ctx, double *logz, double *logz_err, double *H)
+{
+    if (!ctx) return NS_EINVAL;
+    // every run, finished or not (the finalisation does not change the run's state)
+    Launch L{ctx->dP, ctx->dR, ctx->d_map1, ctx->n, 0, 0};
+    hipError_t e = launch_logz(L, ctx->stream);
+    if (e != hipSuccess) return device_error(ctx, "ns_logz", e);
+    std::vector<double> sc((size_t)ctx->n * 8);
+    CK(hipMemcpyAsync(sc.data(), ctx->d_scal, sc.size() * 8, hipMemcpyDeviceToHost, ctx->stream));
+    CK(hipStreamSynchronize(ctx->stream));
+    for (int r = 0; r < ctx->n; ++r) {
+        if (logz) logz[r] = sc[(size_t)8 * r + 4];
+        if (logz_err) logz_err[r] = sc[(size_t)8 * r + 5];
+        if (H) H[r] = sc[(size_t)8 * r + 6];
+    }
     return NS_OK;
 }
 
 extern "C" ns_status ns_logz(ns_ctx *ctx, double *logz, double *logz_err, double *H)
 {
     if (!ctx) return NS_EINVAL;
-    CK(launch_logz(ctx->P, ctx->R, ctx->stream));
+    const Launch L = launch_one(ctx, 0);
+    hipError_t e = launch_logz(L, ctx->stream);
+    if (e != hipSuccess) return device_error(ctx, "ns_logz", e);
     double out[3];
-    CK(hipMemcpyAsync(out, ctx->R.scal + 4, 3 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    CK(hipMemcpyAsync(out, ctx->d_scal + 4, 3 * sizeof(double), hipMemcpyDeviceToHost,
+                      ctx->stream));
     CK(hipStreamSynchronize(ctx->stream));
     if (logz) *logz = out[0];
     if (logz_err) *logz_err = out[1];
@@ -551,16 +865,18 @@ extern "C" ns_status ns_logz(ns_ctx *ctx, double *logz, double *logz_err, double
     return NS_OK;
 }
 
-extern "C" ns_status ns_stats(ns_ctx *ctx, ns_stats_t *o)
+static bool run_ok(const ns_ctx *ctx, int r) { return ctx && r >= 0 && r < ctx->n; }
+
+extern "C" ns_status ns_stats_run(ns_ctx *ctx, int32_t run, ns_stats_t *o)
 {
-    if (!ctx || !o) return NS_EINVAL;
+    if (!run_ok(ctx, run) || !o) return NS_EINVAL;
     ns_status st;
     if ((st = collect_events(ctx)) != NS_OK) return st;
     unsigned long long c[16];
-    CK(hipMemcpyAsync(c, ctx->R.ctr, sizeof(c), hipMemcpyDeviceToHost, ctx->stream));
+    CK(hipMemcpyAsync(c, ctx->d_ctr + 16 * run, sizeof(c), hipMemcpyDeviceToHost, ctx->stream));
     if ((st = sync_flags(ctx)) != NS_OK) return st;
     memset(o, 0, sizeof(*o));
-    o->iterations = ctx->h_iscal[3];
+    o->iterations = ctx->h_iscal[8 * run + 3];
     o->evals = (int64_t)c[0];
     o->tests = (int64_t)c[1];
     o->prior_rejects = (int64_t)c[2];
@@ -573,76 +889,89 @@ extern "C" ns_status ns_stats(ns_ctx *ctx, ns_stats_t *o)
     o->n_dead = (int64_t)c[9];
     o->hrss_ms = ctx->hrss_ms;
     o->hrss_launches = ctx->hrss_launches;
-    o->width = ctx->R.width;
+    o->width = ctx->runs[run].R.width;
     return NS_OK;
 }
 
-extern "C" ns_status ns_get_state(ns_ctx *ctx, ns_state_view *v)
+extern "C" ns_status ns_stats(ns_ctx *ctx, ns_stats_t *o) { return ns_stats_run(ctx, 0, o); }
+
+extern "C" ns_status ns_get_state_run(ns_ctx *ctx, int32_t run, ns_state_view *v)
 {
-    if (!ctx || !v) return NS_EINVAL;
-    const int d = ctx->d, D = ctx->D, m = ctx->m, mp = ctx->m_pad;
+    if (!run_ok(ctx, run) || !v) return NS_EINVAL;
+    const RunHost &rh = ctx->runs[run];
+    const DevRun &R = rh.R;
+    const int d = rh.d, D = rh.D, m = rh.m, mp = rh.m_pad;
     CK(hipStreamSynchronize(ctx->stream));
     if (v->x) {
         std::vector<double> t((size_t)D * mp);
-        CK(hipMemcpy(t.data(), ctx->R.X, t.size() * 8, hipMemcpyDeviceToHost));
+        CK(hipMemcpy(t.data(), R.X, t.size() * 8, hipMemcpyDeviceToHost));
         for (int i = 0; i < m; ++i)
             for (int a = 0; a < d; ++a) v->x[(size_t)i * d + a] = t[(size_t)a * mp + i];
     }
-    if (v->logL) CK(hipMemcpy(v->logL, ctx->R.logL, m * 8, hipMemcpyDeviceToHost));
-    if (v->perm) CK(hipMemcpy(v->perm, ctx->R.perm, m * 4, hipMemcpyDeviceToHost));
+    if (v->logL) CK(hipMemcpy(v->logL, R.logL, m * 8, hipMemcpyDeviceToHost));
+    if (v->perm) CK(hipMemcpy(v->perm, R.perm, m * 4, hipMemcpyDeviceToHost));
     if (v->Lsig) {
         std::vector<double> t((size_t)D * D);
-        CK(hipMemcpy(t.data(), ctx->R.Lsig, t.size() * 8, hipMemcpyDeviceToHost));
+        CK(hipMemcpy(t.data(), R.Lsig, t.size() * 8, hipMemcpyDeviceToHost));
         for (int a = 0; a < d; ++a)
             for (int b = 0; b < d; ++b) v->Lsig[a * d + b] = t[a * D + b];
     }
-    if (v->parents) CK(hipMemcpy(v->parents, ctx->R.parents, ctx->k * 4, hipMemcpyDeviceToHost));
+    if (v->parents) CK(hipMemcpy(v->parents, R.parents, rh.k * 4, hipMemcpyDeviceToHost));
     double sc[4];
     int is[8];
-    CK(hipMemcpy(sc, ctx->R.scal, sizeof(sc), hipMemcpyDeviceToHost));
-    CK(hipMemcpy(is, ctx->R.iscal, sizeof(is), hipMemcpyDeviceToHost));
+    CK(hipMemcpy(sc, R.scal, sizeof(sc), hipMemcpyDeviceToHost));
+    CK(hipMemcpy(is, R.iscal, sizeof(is), hipMemcpyDeviceToHost));
     v->Lstar = sc[0]; v->logZ = sc[1]; v->logX = sc[2]; v->M = sc[3];
     v->iter = is[3];
     v->done = is[0];
     return NS_OK;
 }
 
+extern "C" ns_status ns_get_state(ns_ctx *ctx, ns_state_view *v)
+{
+    return ns_get_state_run(ctx, 0, v);
+}
+
 extern "C" ns_status ns_set_state(ns_ctx *ctx, const ns_state_view *v)
 {
     if (!ctx || !v || !v->x || !v->logL) return NS_EINVAL;
-    const int d = ctx->d, D = ctx->D, m = ctx->m, mp = ctx->m_pad;
+    RunHost &rh = ctx->runs[0];
+    const DevRun &R = rh.R;
+    const int d = rh.d, D = rh.D, m = rh.m, mp = rh.m_pad;
     std::vector<double> t((size_t)D * mp, 0.0);
     for (int i = 0; i < m; ++i)
         for (int a = 0; a < d; ++a) t[(size_t)a * mp + i] = v->x[(size_t)i * d + a];
     CK(hipStreamSynchronize(ctx->stream));
-    CK(hipMemcpy(ctx->R.X, t.data(), t.size() * 8, hipMemcpyHostToDevice));
-    CK(hipMemcpy(ctx->R.logL, v->logL, m * 8, hipMemcpyHostToDevice));
+    CK(hipMemcpy(R.X, t.data(), t.size() * 8, hipMemcpyHostToDevice));
+    CK(hipMemcpy(R.logL, v->logL, m * 8, hipMemcpyHostToDevice));
     double sc[4] = {0.0, v->logZ, v->logX, v->M};
-    CK(hipMemcpy(ctx->R.scal, sc, sizeof(sc), hipMemcpyHostToDevice));
+    CK(hipMemcpy(R.scal, sc, sizeof(sc), hipMemcpyHostToDevice));
     int is[8];
-    CK(hipMemcpy(is, ctx->R.iscal, sizeof(is), hipMemcpyDeviceToHost));
+    CK(hipMemcpy(is, R.iscal, sizeof(is), hipMemcpyDeviceToHost));
     is[0] = 0; is[3] = (int)v->iter; is[4] = 0;
-    CK(hipMemcpy(ctx->R.iscal, is, sizeof(is), hipMemcpyHostToDevice));
-    CK(launch_select(ctx->P, ctx->R, 2, ctx->stream));
+    CK(hipMemcpy(R.iscal, is, sizeof(is), hipMemcpyHostToDevice));
+    hipError_t e = launch_select(launch_one(ctx, 0), 2, ctx->stream);
+    if (e != hipSuccess) return device_error(ctx, "select launch", e);
     ns_status st;
     if ((st = sync_flags(ctx)) != NS_OK) return st;
     is[0] = v->done ? 1 : 0;
-    CK(hipMemcpy(ctx->R.iscal, is, sizeof(int), hipMemcpyHostToDevice));
-    ctx->done = is[0];
-    return NS_OK;
+    CK(hipMemcpy(R.iscal, is, sizeof(int), hipMemcpyHostToDevice));
+    rh.done = is[0];
+    return refresh_maps(ctx);
 }
 
 extern "C" ns_status ns_get_dead(ns_ctx *ctx, double *out, int64_t cap, int64_t *n)
 {
     if (!ctx) return NS_EINVAL;
+    const DevRun &R = ctx->runs[0].R;
     unsigned long long nd = 0;
     CK(hipStreamSynchronize(ctx->stream));
-    CK(hipMemcpy(&nd, ctx->R.ctr + 9, 8, hipMemcpyDeviceToHost));
-    long long stored = (long long)nd < ctx->R.dead_cap ? (long long)nd : ctx->R.dead_cap;
+    CK(hipMemcpy(&nd, R.ctr + 9, 8, hipMemcpyDeviceToHost));
+    long long stored = (long long)nd < R.dead_cap ? (long long)nd : R.dead_cap;
     if (n) *n = (int64_t)nd;
     if (out && cap > 0) {
         const long long c = stored < cap ? stored : cap;
-        if (c > 0) CK(hipMemcpy(out, ctx->R.dead, c * 8, hipMemcpyDeviceToHost));
+        if (c > 0) CK(hipMemcpy(out, R.dead, c * 8, hipMemcpyDeviceToHost));
     }
     return NS_OK;
 }
@@ -650,9 +979,10 @@ extern "C" ns_status ns_get_dead(ns_ctx *ctx, double *out, int64_t cap, int64_t 
 extern "C" ns_status ns_get_trace(ns_ctx *ctx, int32_t *out)
 {
     if (!ctx || !out) return NS_EINVAL;
-    if (!ctx->R.trace) return fail(ctx, NS_EINVAL, "context was created without NS_FLAG_TRACE");
+    const RunHost &rh = ctx->runs[0];
+    if (!rh.R.trace) return fail(ctx, NS_EINVAL, "context was created without NS_FLAG_TRACE");
     CK(hipStreamSynchronize(ctx->stream));
-    CK(hipMemcpy(out, ctx->R.trace, (size_t)ctx->k * ctx->p * 16, hipMemcpyDeviceToHost));
+    CK(hipMemcpy(out, rh.R.trace, (size_t)rh.k * rh.p * 16, hipMemcpyDeviceToHost));
     return NS_OK;
 }
 
@@ -662,32 +992,48 @@ extern "C" ns_status ns_eval_loglik(ns_ctx *ctx, const double *x, int32_t n, int
     if (!ctx || (!x && n > 0) || (!out && n > 0) || n < 0) return NS_EINVAL;
     if (n == 0) return NS_OK;
     if (!precision_valid(precision)) return fail(ctx, NS_EINVAL, "unknown precision");
-    DevProblem P;
-    run_dev_mode(ctx, precision, P);
-    if (!mode_supported(P, kmode(precision)))
+    const RunHost &rh = ctx->runs[0];
+    if (!mode_supported(rh.P, precision))
         return fail(ctx, NS_EUNSUPPORTED, "precision not supported for this problem");
-    const int d = ctx->d, D = ctx->D;
+    const DevProblem P = problem_for_mode(rh, precision);
+    const int upw = precision == NS_FP64 ? 1 : upw_template(rh.D, upw_for(P));
+    const int d = rh.d, D = rh.D;
     const int np = (n + 63) & ~63;
+    const int nb = (n + kRows - 1) / kRows;
     std::vector<double> t((size_t)D * np, 0.0);
     for (int i = 0; i < n; ++i)
         for (int a = 0; a < d; ++a) t[(size_t)a * np + i] = x[(size_t)i * d + a];
+    std::vector<int2> mp(nb);
+    for (int b = 0; b < nb; ++b) mp[b] = make_int2(ctx->n, b);  // the scratch descriptor slot
+    CK(hipStreamSynchronize(ctx->stream));
+    CK(hipMemcpy(ctx->dP + ctx->n, &P, sizeof(P), hipMemcpyHostToDevice));
     double *dx = nullptr, *dout = nullptr;
-    CK(hipMalloc(&dx, t.size() * 8));
-    hipError_t e = hipMalloc(&dout, (size_t)n * 8);
-    if (e != hipSuccess) { (void)hipFree(dx); return fail(ctx, NS_ENOMEM, "hipMalloc failed"); }
+    int2 *dmap = nullptr;
+    hipError_t e = hipMalloc(&dx, t.size() * 8);
+    if (e == hipSuccess) e = hipMalloc(&dout, (size_t)n * 8);
+    if (e == hipSuccess) e = hipMalloc(&dmap, (size_t)nb * sizeof(int2));
+    if (e != hipSuccess) {
+        (void)hipFree(dx);
+        (void)hipFree(dout);
+        return fail(ctx, NS_ENOMEM, "hipMalloc failed");
+    }
     ns_status st = NS_OK;
-    e = hipMemcpyAsync(dx, t.data(), t.size() * 8, hipMemcpyHostToDevice, ctx->stream);
-    if (e == hipSuccess)
-        e = launch_eval_points(P, dx, np, n, dout, nullptr, kmode(precision), ctx->stream);
+    e = hipMemcpy(dx, t.data(), t.size() * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(dmap, mp.data(), mp.size() * sizeof(int2), hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+        const Launch L{ctx->dP, ctx->dR, dmap, nb, rh.m, rh.K};
+        e = launch_eval_points(L, D, rh.lik, precision, upw, dx, np, n, dout, ctx->stream);
+    }
     if (e == hipSuccess)
         e = hipMemcpyAsync(out, dout, (size_t)n * 8, hipMemcpyDeviceToHost, ctx->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     if (e != hipSuccess) {
         ctx->err = std::string("ns_eval_loglik: ") + hipGetErrorString(e);
-        st = NS_EDEVICE;
+        st = e == hipErrorNotSupported ? NS_EUNSUPPORTED : NS_EDEVICE;
     }
     (void)hipFree(dx);
     (void)hipFree(dout);
+    (void)hipFree(dmap);
     return st;
 }
 
@@ -697,9 +1043,9 @@ extern "C" ns_status ns_eval_loglik(ns_ctx *ctx, const double *x, int32_t n, int
 // 5 FP64 re-check, 6 round top, 7 state update, 8 rounds, 9 steps, 10 re-check rounds).
 extern "C" ns_status nss_debug_phase_times(ns_ctx *ctx, unsigned long long *out)
 {
-    if (!ctx || !out || !ctx->R.prof) return NS_EINVAL;
+    if (!ctx || !out || !ctx->runs[0].R.prof) return NS_EINVAL;
     CK(hipStreamSynchronize(ctx->stream));
-    CK(hipMemcpy(out, ctx->R.prof, 12 * 8, hipMemcpyDeviceToHost));
+    CK(hipMemcpy(out, ctx->runs[0].R.prof, 12 * 8, hipMemcpyDeviceToHost));
     return NS_OK;
 }
 #endif

@@ -8,7 +8,7 @@ namespace nss {
 
 constexpr int kWG = 256;         // threads per chain workgroup (4 waves of 64)
 constexpr int kRows = 16;        // candidate rows per evaluation tile (one 16-row MFMA block)
-constexpr int kSlots = 2;        // candidate slots per chain per round (left / right end)
+constexpr int kSlots = 4;        // candidate rows per chain per round (4 chains x 4 = 16 rows)
 constexpr int kMaxChainsPerWG = 4;
 constexpr int kSelectThreads = 1024;
 constexpr int kMaxLive = 8192;
@@ -64,20 +64,42 @@ struct DevRun {
     int *trace;            // [k][p][4] or null
     unsigned long long *prof;  // per-phase cycle counters of the HRSS kernel (timing builds)
     double *dirbuf;        // [k][p][D] directions of the current iteration, or null (inline)
+    double *ubuf;          // [k][p][8] per-step default plan (tL0, uh, 6 shrink), with dirbuf
+    int C;                 // chains per HRSS workgroup
+    int covG;              // survivor groups of the covariance partial sums
+    double *part1, *part2; // covariance partials [covG][D], [covG][ntile][256]
 };
 
-// ---- launchers (nss_kernels.hip) ----
-hipError_t launch_init_draw(const DevProblem &P, const DevRun &R, hipStream_t s);
-hipError_t launch_eval_points(const DevProblem &P, const double *X, int ld, int n, double *out,
-                              unsigned long long *nonfinite, int mode, hipStream_t s);
+// One kernel launch over a group of runs: block b works on run map[b].x, local block map[b].y.
+// P and R are device arrays of the batch's runs.
+struct Launch {
+    const DevProblem *P;
+    const DevRun *R;
+    const int2 *map;
+    int nblocks;
+    int max_m;   // largest n_live among the launch's runs (select workspace)
+    int max_K;   // largest component count among the launch's runs (HRSS workspace)
+};
+
+// ---- launchers (nss_kernels.hip); D, likelihood and mode are the group's template values ----
+hipError_t launch_init_draw(const Launch &L, hipStream_t s);
+// FP64 evaluation of each run's live set into its logL (after launch_init_draw)
+hipError_t launch_eval_init(const Launch &L, int D, int lik, hipStream_t s);
+// evaluation of n points X[a * ld + i] of the map's run(s) into out (tests)
+hipError_t launch_eval_points(const Launch &L, int D, int lik, int mode, int upw, const double *X,
+                              int ld, int n, double *out, hipStream_t s);
 // op: 0 = initial delete-k (accounted), 1 = delete-k of an iteration (accounted, iter + 1),
-//     2 = re-sort only (no accounting; after an external state overwrite)
-hipError_t launch_select(const DevProblem &P, const DevRun &R, int op, hipStream_t s);
-hipError_t launch_cov(const DevProblem &P, const DevRun &R, double *part1, double *part2, int G,
-                      hipStream_t s);
-hipError_t launch_dirs(const DevProblem &P, const DevRun &R, hipStream_t s);
-hipError_t launch_hrss(const DevProblem &P, const DevRun &R, int mode, hipStream_t s);
-hipError_t launch_logz(const DevProblem &P, const DevRun &R, hipStream_t s);
+//     2 = re-sort only (no accounting; after an external state overwrite); one block per run
+hipError_t launch_select(const Launch &L, int op, hipStream_t s);
+// survivors' covariance (cov map: (run, tile + ntile * group)) and factorisation (one per run)
+hipError_t launch_cov(const Launch &cov, const Launch &one, int D, hipStream_t s);
+hipError_t launch_dirs(const Launch &L, int D, hipStream_t s);
+hipError_t launch_hrss(const Launch &L, int D, int lik, int mode, int upw, hipStream_t s);
+hipError_t launch_logz(const Launch &L, hipStream_t s);
 int mode_supported(const DevProblem &P, int mode);
+int upw_for(const DevProblem &P);
+int upw_template(int D, int upw);         // the compiled UPW that covers upw (0 if none)
+size_t hrss_lds_bytes(int D, int K);
+int dirs_rows();                          // directions per k_dirs block
 
 }  // namespace nss

@@ -106,6 +106,9 @@ __device__ __forceinline__ double readlane_d(double v, int lane)
     p.y = __builtin_amdgcn_readlane(p.y, lane);
     return __builtin_bit_cast(double, p);
 }
+__device__ __forceinline__ int uniform_i(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ double uniform_d(double v) { return readlane_d(v, 0); }
+
 // Sum over the wave: row sums, then the four row results combined (uniform result).
 __device__ __forceinline__ double wave_sum_fast(double v)
 {
@@ -216,6 +219,18 @@ __device__ __forceinline__ void stage_problem(const DevProblem &P, const Tile &T
 //   D/16 = 4: c = uu, jb = (w - uu) mod 4;
 //   D/16 = 8: c = uu/2, jb = kk or 7 - kk with kk = (w - c) mod 4.
 // ------------------------------------------------------------------------------------------
+// With K >= 4 components, wave w instead takes whole components c = w, w+4, ... (all their
+// column blocks): the residual of a component is then converted once per wave and shared by its
+// blocks, and every wave still gets the same triangular work.  uu = (c - w)/4 * D/16 + jb.
+__device__ __forceinline__ bool comp_major(int K) { return K >= 4; }
+
+template <int NJB>
+__device__ __forceinline__ void unit_of_cm(int w, int uu, int &c, int &jb)
+{
+    c = w + 4 * (uu / NJB);
+    jb = uu % NJB;
+}
+
 template <int NJB>
 __device__ __forceinline__ void unit_of(int w, int uu, int &c, int &jb)
 {
@@ -284,6 +299,40 @@ __device__ void mix_eval64(const DevProblem &P, const Tile &T, const int *mask, 
     const int QS = q_stride(D, P.K);
     const bool on = mask[row] != 0;
     const double *cr = T.cand + row * LDC;
+    if constexpr (D <= 64) {
+        if (comp_major(P.K)) {
+            for (int c = w; c < P.K; c += 4) {
+                const double *wf = P.wf64 + (size_t)c * NJB * NKS * 64 + l;
+                const double *mu = T.mu64 + c * D;
+                d4 acc[NJB];
+#pragma unroll
+                for (int jb = 0; jb < NJB; ++jb) acc[jb] = (d4){0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int ks = 0; ks < NKS; ++ks) {
+                    const int kk = 4 * ks + kq;
+                    const double b = on ? cr[kk] - mu[kk] : 0.0;
+#pragma unroll
+                    for (int jb = 0; jb < NJB; ++jb)
+                        if (ks < 4 * jb + 4)
+                            acc[jb] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                                wf[((size_t)jb * NKS + ks) * 64], b, acc[jb], 0, 0, 0);
+                }
+#pragma unroll
+                for (int jb = 0; jb < NJB; ++jb)
+                    T.q[row * QS + (c * NJB + jb) * 4 + kq] =
+                        (acc[jb][0] * acc[jb][0] + acc[jb][1] * acc[jb][1]) +
+                        (acc[jb][2] * acc[jb][2] + acc[jb][3] * acc[jb][3]);
+            }
+            __syncthreads();
+            {
+                const int r = 4 * w + (l >> 4), c = l & 15;
+                const double L = lse_rows<D, double>(P, T.q, T.cst, r, c);
+                if (c == 0) out[r] = L;
+            }
+            __syncthreads();
+            return;
+        }
+    }
     for (int uu = 0;; ++uu) {
         int c, jb;
         unit_of<NJB>(w, uu, c, jb);
@@ -335,14 +384,30 @@ __device__ __forceinline__ f4 mfma16(h8 a, h8 b, f4 c)
 template <int D, int UPW, int NP>
 struct WFrag { uint4 v[NP][UPW][D / 32]; };
 
+// Guard band of the mixed modes: a row whose FP32 estimate L has
+// |L - L*| <= rel * max(0, cmax - L) + abs + 1e-6 |L| is re-evaluated in FP64.
+struct Guard {
+    double Lstar;
+    float rel, abs, cmax;
+};
+__device__ __forceinline__ bool near_threshold(const Guard &g, float L)
+{
+    if (L != L) return true;
+    const float band = g.rel * fmaxf(0.f, g.cmax - L) + g.abs + 1e-6f * fabsf(L);
+    return fabs((double)L - g.Lstar) <= (double)band;
+}
+
 // Mixed-precision mixture tile: residuals x - mu_c in FP32 rounded to 16 bits (split into a
 // rounded part and the rounded remainder in the split modes), times the 16-bit W_c fragments on
 // v_mfma_f32_16x16x32_{bf16,f16} with FP32 accumulation (W as A, residuals as B, lane l,
 // register i = y[n = l & 15][16 jb + 4 (l >> 4) + i]); the split modes form
-// W_hi r_hi + W_hi r_lo + W_lo r_hi.  FP32 squares and log-sum-exp.
+// W_hi r_hi + W_hi r_lo + W_lo r_hi.  FP32 squares and log-sum-exp.  Every row is computed
+// (rows outside the mask hold stale finite data and are never read).  Rows inside the mask
+// whose estimate is near L* get rc[r] = 1; returns whether any row did (the vote is the
+// tile's final barrier).
 template <int D, int UPW, int MODE>
-__device__ void mix_eval16(const DevProblem &P, const WFrag<D, UPW, MixTraits<MODE>::NP> &wr,
-                           const Tile &T, const int *mask, float *out)
+__device__ int mix_eval16(const DevProblem &P, const WFrag<D, UPW, MixTraits<MODE>::NP> &wr,
+                          const Tile &T, const int *mask, float *out, const Guard &g)
 {
     typedef typename MixTraits<MODE>::H H;
     typedef typename MixTraits<MODE>::V8 V8;
@@ -351,8 +416,62 @@ __device__ void mix_eval16(const DevProblem &P, const WFrag<D, UPW, MixTraits<MO
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     const int row = l & 15, kq = l >> 4;
     const int QS = q_stride(D, P.K);
-    const bool on = mask[row] != 0;
-    const float *cr = T.cand32 + row * LDC;
+    // this lane's candidate coordinates, read once for all units
+    float cx[NKS][8];
+    {
+        const float *cr = T.cand32 + row * LDC;
+#pragma unroll
+        for (int ks = 0; ks < NKS; ++ks) {
+            const float4 c0 = *(const float4 *)(cr + 32 * ks + 8 * kq);
+            const float4 c1 = *(const float4 *)(cr + 32 * ks + 8 * kq + 4);
+            cx[ks][0] = c0.x; cx[ks][1] = c0.y; cx[ks][2] = c0.z; cx[ks][3] = c0.w;
+            cx[ks][4] = c1.x; cx[ks][5] = c1.y; cx[ks][6] = c1.z; cx[ks][7] = c1.w;
+        }
+    }
+    if (comp_major(P.K)) {
+        constexpr int CW = (UPW + NJB - 1) / NJB;
+#pragma unroll
+        for (int cw = 0; cw < CW; ++cw) {
+            const int c = w + 4 * cw;
+            if (c < P.K) {
+                const float *mu = T.mu32 + c * D + 8 * kq;
+                f4 acc[NJB];
+#pragma unroll
+                for (int jb = 0; jb < NJB; ++jb) acc[jb] = (f4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int ks = 0; ks < NKS; ++ks) {
+                    const float4 m0 = *(const float4 *)(mu + 32 * ks);
+                    const float4 m1 = *(const float4 *)(mu + 32 * ks + 4);
+                    const float mm[8] = {m0.x, m0.y, m0.z, m0.w, m1.x, m1.y, m1.z, m1.w};
+                    float rr[8];
+                    V8 hi, lo;
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) { rr[e] = cx[ks][e] - mm[e]; hi[e] = (H)rr[e]; }
+                    if constexpr (NP == 2) {
+#pragma unroll
+                        for (int e = 0; e < 8; ++e) lo[e] = (H)(rr[e] - (float)hi[e]);
+                    }
+#pragma unroll
+                    for (int jb = 0; jb < NJB; ++jb) {
+                        if (ks < (16 * jb + 16 + 31) / 32 && cw * NJB + jb < UPW) {
+                            const V8 w0 = __builtin_bit_cast(V8, wr.v[0][cw * NJB + jb][ks]);
+                            acc[jb] = mfma16(w0, hi, acc[jb]);
+                            if constexpr (NP == 2) {
+                                acc[jb] = mfma16(w0, lo, acc[jb]);
+                                acc[jb] = mfma16(__builtin_bit_cast(V8, wr.v[1][cw * NJB + jb][ks]),
+                                                 hi, acc[jb]);
+                            }
+                        }
+                    }
+                }
+#pragma unroll
+                for (int jb = 0; jb < NJB; ++jb)
+                    T.q32[row * QS + (c * NJB + jb) * 4 + kq] =
+                        (acc[jb][0] * acc[jb][0] + acc[jb][1] * acc[jb][1]) +
+                        (acc[jb][2] * acc[jb][2] + acc[jb][3] * acc[jb][3]);
+            }
+        }
+    } else {
 #pragma unroll
     for (int uu = 0; uu < UPW; ++uu) {
         int c, jb;
@@ -360,27 +479,18 @@ __device__ void mix_eval16(const DevProblem &P, const WFrag<D, UPW, MixTraits<MO
         if (c < P.K) {
             const int u = c * NJB + jb;
             const int ke = (16 * jb + 16 + 31) / 32;
-            const float *mu = T.mu32 + c * D;
+            const float *mu = T.mu32 + c * D + 8 * kq;
             f4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int ks = 0; ks < NKS; ++ks) {
                 if (ks < ke) {
-                    const int k0 = 32 * ks + 8 * kq;
+                    const float4 m0 = *(const float4 *)(mu + 32 * ks);
+                    const float4 m1 = *(const float4 *)(mu + 32 * ks + 4);
+                    const float mm[8] = {m0.x, m0.y, m0.z, m0.w, m1.x, m1.y, m1.z, m1.w};
                     float rr[8];
-                    if (on) {
-                        const float4 c0 = *(const float4 *)(cr + k0);
-                        const float4 c1 = *(const float4 *)(cr + k0 + 4);
-                        const float4 m0 = *(const float4 *)(mu + k0);
-                        const float4 m1 = *(const float4 *)(mu + k0 + 4);
-                        rr[0] = c0.x - m0.x; rr[1] = c0.y - m0.y; rr[2] = c0.z - m0.z; rr[3] = c0.w - m0.w;
-                        rr[4] = c1.x - m1.x; rr[5] = c1.y - m1.y; rr[6] = c1.z - m1.z; rr[7] = c1.w - m1.w;
-                    } else {
-#pragma unroll
-                        for (int e = 0; e < 8; ++e) rr[e] = 0.f;
-                    }
                     V8 hi;
 #pragma unroll
-                    for (int e = 0; e < 8; ++e) hi[e] = (H)rr[e];
+                    for (int e = 0; e < 8; ++e) { rr[e] = cx[ks][e] - mm[e]; hi[e] = (H)rr[e]; }
                     const V8 w0 = __builtin_bit_cast(V8, wr.v[0][uu][ks]);
                     acc = mfma16(w0, hi, acc);
                     if constexpr (NP == 2) {
@@ -395,13 +505,19 @@ __device__ void mix_eval16(const DevProblem &P, const WFrag<D, UPW, MixTraits<MO
             T.q32[row * QS + u * 4 + kq] = (acc[0] * acc[0] + acc[1] * acc[1]) + (acc[2] * acc[2] + acc[3] * acc[3]);
         }
     }
+    }
     __syncthreads();
+    int flag = 0;
     {
         const int r = 4 * w + (l >> 4), c = l & 15;
         const float L = lse_rows<D, float>(P, T.q32, T.cst32, r, c);
-        if (c == 0) out[r] = L;
+        if (c == 0) {
+            out[r] = L;
+            flag = (mask[r] != 0) && near_threshold(g, L);
+            T.rc[r] = flag;
+        }
     }
-    __syncthreads();
+    return __syncthreads_or(flag);
 }
 
 // Neal's funnel, FP64: log N(v; 0, 9) + sum_{j>=1} log N(x_j; 0, e^v), v = x_0.
@@ -443,7 +559,8 @@ __device__ __forceinline__ void load_wfrag(const DevProblem &P, WFrag<D, UPW, NP
 #pragma unroll
     for (int uu = 0; uu < UPW; ++uu) {
         int c, jb;
-        unit_of<NJB>(w, uu, c, jb);
+        if (comp_major(P.K)) unit_of_cm<NJB>(w, uu, c, jb);
+        else unit_of<NJB>(w, uu, c, jb);
         const int u = c * NJB + jb;
 #pragma unroll
         for (int ks = 0; ks < NKS; ++ks) {
@@ -455,13 +572,18 @@ __device__ __forceinline__ void load_wfrag(const DevProblem &P, WFrag<D, UPW, NP
 }
 
 // Evaluates the masked rows of the tile in the kernel's precision: FP64 results in T.L, 16-bit
-// mode results in T.L32.
+// mode results in T.L32 with the re-check flags in T.rc; returns whether any row needs an FP64
+// re-check (always 0 in FP64 mode).
 template <int D, int MODE, int LIK, int UPW, int NP>
-__device__ __forceinline__ void eval_tile(const DevProblem &P, const WFrag<D, UPW, NP> &wr,
-                                          const Tile &T, const int *mask)
+__device__ __forceinline__ int eval_tile(const DevProblem &P, const WFrag<D, UPW, NP> &wr,
+                                         const Tile &T, const int *mask, const Guard &g)
 {
-    if constexpr (MODE == MODE_FP64) eval64<D, LIK>(P, T, mask, T.L);
-    else mix_eval16<D, UPW, MODE>(P, wr, T, mask, T.L32);
+    if constexpr (MODE == MODE_FP64) {
+        eval64<D, LIK>(P, T, mask, T.L);
+        return 0;
+    } else {
+        return mix_eval16<D, UPW, MODE>(P, wr, T, mask, T.L32, g);
+    }
 }
 
 template <int MODE> struct NPOf { static constexpr int v = 1; };
@@ -471,10 +593,13 @@ template <> struct NPOf<MODE_FP16X3> { static constexpr int v = 2; };
 // ------------------------------------------------------------------------------------------
 // init: m prior draws
 // ------------------------------------------------------------------------------------------
-__global__ void k_init_draw(DevProblem P, DevRun R)
+__global__ void k_init_draw(Launch Lc)
 {
+    const int2 bm = Lc.map[blockIdx.x];
+    const DevProblem P = Lc.P[bm.x];
+    const DevRun R = Lc.R[bm.x];
     const int nq = (P.d + 1) >> 1;
-    const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long gid = (long long)bm.y * blockDim.x + threadIdx.x;
     if (gid >= (long long)R.m * nq) return;
     const int i = (int)(gid / nq), q = (int)(gid - (long long)i * nq);
     double ua, ub;
@@ -497,15 +622,21 @@ __global__ void k_init_draw(DevProblem P, DevRun R)
 // ------------------------------------------------------------------------------------------
 // batched evaluation of n points stored coordinate-major X[a*ld + i]
 // ------------------------------------------------------------------------------------------
+// from_run: evaluate the run's own live set X -> logL (init); else the given points
 template <int D, int MODE, int LIK, int UPW>
-__global__ __launch_bounds__(256) void k_eval(DevProblem P, const double *X, int ld, int n,
-                                              double *out, unsigned long long *nonfinite)
+__global__ __launch_bounds__(256) void k_eval(Launch Lc, const double *X, int ld, int n,
+                                              double *out, int from_run)
 {
     extern __shared__ __align__(16) unsigned char smem[];
+    const int2 bm = Lc.map[blockIdx.x];
+    const DevProblem P = Lc.P[bm.x];
+    const DevRun R = Lc.R[bm.x];
+    unsigned long long *nonfinite = nullptr;
+    if (from_run) { X = R.X; ld = R.m_pad; n = R.m; out = R.logL; nonfinite = R.ctr + 5; }
     const HLayout lay = hrss_layout(D, P.K);
     const Tile T = tile_of(smem, lay);
     const int tid = threadIdx.x;
-    const int p0 = blockIdx.x * kRows;
+    const int p0 = bm.y * kRows;
     for (int i = tid; i < kRows * D; i += 256) {
         const int r = i / D, a = i - r * D;
         const int p = p0 + r;
@@ -518,7 +649,8 @@ __global__ __launch_bounds__(256) void k_eval(DevProblem P, const double *X, int
     __syncthreads();
     WFrag<D, UPW, NPOf<MODE>::v> wr;
     if constexpr (MODE != MODE_FP64) load_wfrag<D, UPW, NPOf<MODE>::v>(P, wr);
-    eval_tile<D, MODE, LIK, UPW, NPOf<MODE>::v>(P, wr, T, T.mask);
+    const Guard g = {0.0, 0.f, 0.f, 0.f};
+    eval_tile<D, MODE, LIK, UPW, NPOf<MODE>::v>(P, wr, T, T.mask, g);
     if (tid < kRows && p0 + tid < n) {
         unsigned long long nf = 0;
         const double L = (MODE == MODE_FP64) ? T.L[tid] : (double)T.L32[tid];
@@ -600,9 +732,10 @@ __device__ __forceinline__ double lse2(double a, double b)
     return mx + log(exp(a - mx) + exp(b - mx));
 }
 
-__global__ __launch_bounds__(1024) void k_select(DevRun R, int op)
+__global__ __launch_bounds__(1024) void k_select(Launch Lc, int op)
 {
     extern __shared__ __align__(16) unsigned char smem[];
+    const DevRun R = Lc.R[Lc.map[blockIdx.x].x];
     if (R.iscal[0]) return;
     const int m = R.m, k = R.k, tid = threadIdx.x;
     int NP = 1;
@@ -705,12 +838,17 @@ __global__ __launch_bounds__(1024) void k_select(DevRun R, int op)
 // partial sums over groups of survivors, then a single-workgroup reduction + Cholesky
 // ------------------------------------------------------------------------------------------
 // grid (tile, group); tile = lower 16x16 block (ta >= tb).  part2[g][tile][256], part1[g][D]
-__global__ __launch_bounds__(256) void k_cov(DevProblem P, DevRun R, double *part1,
-                                             double *part2, int G)
+__global__ __launch_bounds__(256) void k_cov(Launch Lc)
 {
+    const int2 bm = Lc.map[blockIdx.x];
+    const DevProblem P = Lc.P[bm.x];
+    const DevRun R = Lc.R[bm.x];
     if (R.iscal[0]) return;
     const int d = P.d;
-    const int tile = blockIdx.x, g = blockIdx.y, tid = threadIdx.x;
+    const int nt = P.D / 16, ntile = nt * (nt + 1) / 2;
+    const int G = R.covG;
+    double *part1 = R.part1, *part2 = R.part2;
+    const int tile = bm.y % ntile, g = bm.y / ntile, tid = threadIdx.x;
     int ta, tb;
     unpack_tri(tile, ta, tb);
     const int n = R.m - R.k;
@@ -745,15 +883,19 @@ __global__ __launch_bounds__(256) void k_cov(DevProblem P, DevRun R, double *par
             for (int s = 0; s < ns; ++s) acc1 += ca[s][tid];
         __syncthreads();
     }
-    part2[((size_t)g * gridDim.x + tile) * 256 + tid] = acc;
+    part2[((size_t)g * ntile + tile) * 256 + tid] = acc;
     if (ta == tb && tid < 16) part1[(size_t)g * P.D + ta * 16 + tid] = acc1;
 }
 
-__global__ __launch_bounds__(1024) void k_chol(DevProblem P, DevRun R, const double *part1,
-                                               const double *part2, int G, int ntile)
+__global__ __launch_bounds__(1024) void k_chol(Launch Lc)
 {
     extern __shared__ __align__(16) unsigned char smem[];
+    const int2 bm = Lc.map[blockIdx.x];
+    const DevProblem P = Lc.P[bm.x];
+    const DevRun R = Lc.R[bm.x];
     if (R.iscal[0]) return;
+    const int G = R.covG, ntile = (P.D / 16) * (P.D / 16 + 1) / 2;
+    const double *part1 = R.part1, *part2 = R.part2;
     const int D = P.D, d = P.d, tid = threadIdx.x;
     double *A = (double *)smem;              // packed lower, D(D+1)/2
     double *mc = A + D * (D + 1) / 2;        // mean - shift, [D]
@@ -846,22 +988,28 @@ __global__ __launch_bounds__(1024) void k_chol(DevProblem P, DevRun R, const dou
 // dirbuf[(j p + s) D + a], zero for a >= d.  64 directions per workgroup.
 // ------------------------------------------------------------------------------------------
 constexpr int kDirRows = 64;
+constexpr int kStepU = 8;                 // per step: tL0, uh, default shrink proposals 0..5
+constexpr int kStepShrinkU = kStepU - 2;
 __host__ __device__ inline int dirs_lds_bytes(int D)
 {
-    return al16(lsig_doubles(D) * 8) + al16(kDirRows * (D + 1) * 8) + kDirRows * 8;
+    return al16(lsig_doubles(D) * 8) + al16(kDirRows * (D + 1) * 8) + kDirRows * 8 +
+           kDirRows * kStepU * 8;
 }
 
 template <int D>
-__global__ __launch_bounds__(256) void k_dirs(DevProblem P, DevRun R)
+__global__ __launch_bounds__(256) void k_dirs(Launch Lc)
 {
     extern __shared__ __align__(16) unsigned char smem[];
+    const int2 bm = Lc.map[blockIdx.x];
+    const DevProblem P = Lc.P[bm.x];
+    const DevRun R = Lc.R[bm.x];
     if (R.iscal[0] || R.iscal[2] <= 0) return;
     double *Ls = (double *)smem;
     double *zs = (double *)(smem + al16(lsig_doubles(D) * 8));
     double *nz = zs + kDirRows * (D + 1);
     const int tid = threadIdx.x, d = P.d, p = R.p;
     const long long total = (long long)R.k * p;
-    const long long base = (long long)blockIdx.x * kDirRows;
+    const long long base = (long long)bm.y * kDirRows;
     const uint32_t it = (uint32_t)R.iscal[3] + 1u;
     if constexpr (D <= 64) {
         for (int i = tid; i < D * D; i += 256) {
@@ -882,6 +1030,40 @@ __global__ __launch_bounds__(256) void k_dirs(DevProblem P, DevRun R)
         box_muller(ua, ub, z0, z1);
         zs[r * (D + 1) + 2 * q] = z0;
         if (2 * q + 1 < d) zs[r * (D + 1) + 2 * q + 1] = z1;
+    }
+    // The step's default plan (what the chain proposes while no bracket end has expanded):
+    // ubuf[0] = tL0 = -w U, ubuf[1] = the height uniform uh (purpose STEP), ubuf[2 + i] = the
+    // i-th shrink proposal of the bracket [tL0, tL0 + w] after i rejections (purpose SHRINK,
+    // draws 0, 1, ...), with the same arithmetic as the chain's own proposals.
+    double *udraw = nz + kDirRows;   // [kDirRows][kStepU] raw uniforms
+    for (int i = tid; i < kDirRows * kStepU; i += 256) {
+        const int r = i / kStepU, q = i - r * kStepU;
+        const long long idx = base + r;
+        if (idx >= total) continue;
+        const int j = (int)(idx / p), st = (int)(idx - (long long)j * p);
+        double ua, ub;
+        if (q < 2) {
+            draw2(R.key0, R.key1, PUR_STEP, (uint32_t)j, it, (uint32_t)st, 0u, ua, ub);
+            udraw[r * kStepU + q] = (q == 0) ? ua : ub;
+        } else {
+            draw2(R.key0, R.key1, PUR_SHRINK, (uint32_t)j, it, (uint32_t)st, (uint32_t)(q - 2), ua, ub);
+            udraw[r * kStepU + q] = ua;
+        }
+    }
+    __syncthreads();
+    if (tid < kDirRows && base + tid < total) {
+        const double *u = udraw + tid * kStepU;
+        double *o = R.ubuf + (base + tid) * kStepU;
+        const double width = R.width;
+        double sL = -width * u[0];
+        double sR = sL + width;
+        o[0] = sL;
+        o[1] = u[1];
+        for (int q = 0; q < kStepShrinkU; ++q) {
+            const double t = sL + u[2 + q] * (sR - sL);
+            o[2 + q] = t;
+            if (t < 0.0) sL = t; else sR = t;
+        }
     }
     __syncthreads();
     if (tid < kDirRows) {
@@ -919,9 +1101,13 @@ enum Phase { PH_NEWSTEP = 0, PH_STEPOUT = 1, PH_SHRINK = 2, PH_DONE = 3 };
 // a candidate whose FP32 estimate lies within the guard band of L* is re-evaluated in FP64
 // before the decision, so decisions equal the FP64 ones; the stored logL is FP64.
 template <int D, int MODE, int LIK, int UPW>
-__global__ __launch_bounds__(256) void k_hrss(DevProblem P, DevRun R, int C)
+__global__ __launch_bounds__(256) void k_hrss(Launch Lc)
 {
     extern __shared__ __align__(16) unsigned char smem[];
+    const int2 bm = Lc.map[blockIdx.x];
+    const DevProblem P = Lc.P[bm.x];
+    const DevRun R = Lc.R[bm.x];
+    const int C = R.C;
     if (R.iscal[0]) return;
     if (R.iscal[2] <= 0) return;
     constexpr int LDC = D + 1, LDC32 = D + 4;
@@ -936,7 +1122,7 @@ __global__ __launch_bounds__(256) void k_hrss(DevProblem P, DevRun R, int C)
     int *smask = T.mask;
     int *src = T.rc;
 
-    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+    const int tid = threadIdx.x, w = uniform_i(tid >> 6), l = tid & 63;
     const int d = P.d;
     const double Lstar = R.scal[0];
     const int t0 = R.iscal[1], nsurv = R.iscal[2];
@@ -975,7 +1161,7 @@ __global__ __launch_bounds__(256) void k_hrss(DevProblem P, DevRun R, int C)
 #define PT(slot) do {} while (0)
 #endif
 
-    const int j = blockIdx.x * C + w;
+    const int j = bm.y * C + w;
     const bool has_chain = (w < C) && (j < R.k);
     double *zz = sz + w * D;
 
@@ -992,7 +1178,7 @@ __global__ __launch_bounds__(256) void k_hrss(DevProblem P, DevRun R, int C)
     // per-chain state (wave-uniform, replicated in every lane of the chain's wave)
     int phase = PH_DONE, step = 0, nl = 0, nr = 0, ns = 0;
     bool la = false, ra = false;
-    double tL = 0.0, tR = 0.0, tsh = 0.0, logy = -INFINITY, logL0 = -INFINITY;
+    double tL = 0.0, tR = 0.0, logy = -INFINITY, logL0 = -INFINITY;
     unsigned long long c_evals = 0, c_tests = 0, c_prej = 0, c_outcap = 0, c_shcap = 0,
                        c_nonfin = 0, c_rc = 0, c_viol = 0;
 
@@ -1015,8 +1201,9 @@ __global__ __launch_bounds__(256) void k_hrss(DevProblem P, DevRun R, int C)
     }
     __syncthreads();
 
-    // next step's direction, prefetched into registers one step ahead
-    double pv[NA];
+    // next step's direction and uniforms, prefetched into registers one step ahead (the
+    // uniforms sit in lanes 0..7: U, uh, then shrink uniforms 0..5)
+    double pv[NA], pu = 0.0, cu = 0.0;
 #pragma unroll
     for (int i = 0; i < NA; ++i) pv[i] = 0.0;
     auto prefetch_dir = [&](int st) {
@@ -1024,9 +1211,17 @@ __global__ __launch_bounds__(256) void k_hrss(DevProblem P, DevRun R, int C)
             const double *srcv = R.dirbuf + ((size_t)j * p + st) * D;
 #pragma unroll
             for (int i = 0; i < NA; ++i) if (l + 64 * i < D) pv[i] = srcv[l + 64 * i];
+            if (l < kStepU) pu = R.ubuf[((size_t)j * p + st) * kStepU + l];
         }
     };
     if (pre) prefetch_dir(0);
+    // shrink uniform number sn of the current step
+    auto shrink_u = [&](int sn) -> double {
+        double us, unused;
+        draw2(R.key0, R.key1, PUR_SHRINK, (uint32_t)j, it, (uint32_t)step, (uint32_t)sn, us, unused);
+        return us;
+    };
+    bool dflt = false;   // no bracket end has expanded this step: the default plan applies
 
     // log prior density at the lane-owned point (Gaussian prior only)
     auto logprior_x0 = [&]() -> double {
@@ -1037,28 +1232,6 @@ __global__ __launch_bounds__(256) void k_hrss(DevProblem P, DevRun R, int C)
             if (a < d) { const double zt = (x0r[i] - par[i]) / pbr[i]; lp += -0.5 * zt * zt; }
         }
         return wave_sum_fast(lp) + P.logprior_norm;
-    };
-
-    // candidate row r = x0 + t v; returns whether it passes the prior tests
-    auto build = [&](int r, double t) -> bool {
-        bool inb = true;
-        double lp = 0.0;
-#pragma unroll
-        for (int i = 0; i < NA; ++i) {
-            const int a = l + 64 * i;
-            if (a < D) {
-                const double y = x0r[i] + t * vr[i];
-                scand[r * LDC + a] = y;
-                if constexpr (MODE != MODE_FP64) scand32[r * LDC32 + a] = (float)y;
-                if (a < d) {
-                    if (box) inb = inb && (y >= par[i] && y <= pbr[i]);
-                    else { const double zt = (y - par[i]) / pbr[i]; lp += -0.5 * zt * zt; }
-                }
-            }
-        }
-        if (box) return __all(inb) != 0;
-        lp = wave_sum_fast(lp) + P.logprior_norm;
-        return lp > logy;
     };
 
     auto finish_step = [&](int acc, int nsh) {
@@ -1077,15 +1250,29 @@ __global__ __launch_bounds__(256) void k_hrss(DevProblem P, DevRun R, int C)
         if (cap_sh <= 0) finish_step(0, 0);
     };
 
+    const Guard guard = {Lstar, P.guard_rel, P.guard_abs, P.cmax32};
+
+    // A round's plan: up to kSlots tests in the order the sequential algorithm would make them
+    // if every stepping-out test fell outside and every shrink proposal were rejected.  Each
+    // proposal after a rejection is fully determined (the bracket end that moves depends only
+    // on the sign of t'), so the plan is exact up to its first surprise; the rest is discarded
+    // and neither counted nor used.
+    enum { S_NONE = 0, S_LEFT = 1, S_RIGHT = 2, S_SHRINK = 3 };
     for (;;) {
         const bool act = has_chain && phase != PH_DONE;
-        int em0 = 0, em1 = 0, ok0 = 0, ok1 = 0;
+        int kind[kSlots], ok[kSlots];
+        double tv[kSlots], bLa[kSlots], bRa[kSlots];   // t per slot; bracket after rejecting it
+#pragma unroll
+        for (int sl = 0; sl < kSlots; ++sl) {
+            kind[sl] = S_NONE; ok[sl] = 0; tv[sl] = 0.0; bLa[sl] = 0.0; bRa[sl] = 0.0;
+        }
         if (act) {
             PT(6);
             if (phase == PH_NEWSTEP) {
                 if (pre) {
 #pragma unroll
                     for (int i = 0; i < NA; ++i) vr[i] = pv[i];
+                    cu = pu;
                     prefetch_dir(step + 1);
                 } else {
                     // direction z ~ N(0, I_d), v = L z / |z|, drawn by the chain itself
@@ -1115,10 +1302,17 @@ __global__ __launch_bounds__(256) void k_hrss(DevProblem P, DevRun R, int C)
                         vr[i] = v;
                     }
                 }
-                double U, uh;
-                draw2(R.key0, R.key1, PUR_STEP, (uint32_t)j, it, (uint32_t)step, 0u, U, uh);
+                double uh;
+                if (pre) {
+                    tL = readlane_d(cu, 0);
+                    uh = readlane_d(cu, 1);
+                } else {
+                    double U;
+                    draw2(R.key0, R.key1, PUR_STEP, (uint32_t)j, it, (uint32_t)step, 0u, U, uh);
+                    tL = -width * U;
+                }
+                dflt = pre;
                 logy = box ? -INFINITY : logprior_x0() + log(uh);
-                tL = -width * U;
                 tR = tL + width;
                 nl = nr = 0;
                 la = ra = (cap_out > 0);
@@ -1130,26 +1324,69 @@ __global__ __launch_bounds__(256) void k_hrss(DevProblem P, DevRun R, int C)
 #endif
                 PT(0);
             }
+            // the plan
+            int ns_plan = 0;
+            double sL = tL, sR = tR;
+            int sn = ns;
             if (phase == PH_STEPOUT) {
-                if (la) { em0 = 1; ok0 = build(w * kSlots + 0, tL); }
-                if (ra) { em1 = 1; ok1 = build(w * kSlots + 1, tR); }
-            } else if (phase == PH_SHRINK) {
-                double us, unused;
-                draw2(R.key0, R.key1, PUR_SHRINK, (uint32_t)j, it, (uint32_t)step, (uint32_t)ns,
-                      us, unused);
-                tsh = tL + us * (tR - tL);
-                em0 = 1;
-                ok0 = build(w * kSlots + 0, tsh);
+                if (la) { kind[ns_plan] = S_LEFT; tv[ns_plan] = tL; ++ns_plan; }
+                if (ra) { kind[ns_plan] = S_RIGHT; tv[ns_plan] = tR; ++ns_plan; }
+                sn = 0;
             }
-            c_tests += em0 + em1;
-            c_prej += (em0 && !ok0) + (em1 && !ok1);
-            PT(1);
+            if (phase == PH_STEPOUT || phase == PH_SHRINK) {
+#pragma unroll
+                for (int sl = 0; sl < kSlots; ++sl) {
+                    if (sl >= ns_plan && sn < cap_sh) {
+                        const double t = (dflt && sn < kStepShrinkU)
+                                             ? readlane_d(cu, 2 + sn)
+                                             : sL + shrink_u(sn) * (sR - sL);
+                        kind[sl] = S_SHRINK;
+                        tv[sl] = t;
+                        ++sn;
+                        if (t < 0.0) sL = t; else sR = t;
+                    }
+                    bLa[sl] = sL;
+                    bRa[sl] = sR;
+                }
+            }
+            PT(4);
+            {
+                // all planned candidates in one pass over the lane's coordinates
+                bool inb[kSlots];
+                double lp[kSlots];
+#pragma unroll
+                for (int sl = 0; sl < kSlots; ++sl) { inb[sl] = true; lp[sl] = 0.0; }
+#pragma unroll
+                for (int i = 0; i < NA; ++i) {
+                    const int a = l + 64 * i;
+                    if (a < D) {
+#pragma unroll
+                        for (int sl = 0; sl < kSlots; ++sl) {
+                            if (kind[sl] == S_NONE) continue;
+                            const int r = w * kSlots + sl;
+                            const double y = x0r[i] + tv[sl] * vr[i];
+                            scand[r * LDC + a] = y;
+                            if constexpr (MODE != MODE_FP64) scand32[r * LDC32 + a] = (float)y;
+                            if (a < d) {
+                                if (box) inb[sl] = inb[sl] && (y >= par[i] && y <= pbr[i]);
+                                else { const double zt = (y - par[i]) / pbr[i]; lp[sl] += -0.5 * zt * zt; }
+                            }
+                        }
+                    }
+                }
+                PT(1);
+#pragma unroll
+                for (int sl = 0; sl < kSlots; ++sl) {
+                    if (kind[sl] == S_NONE) continue;
+                    if (box) ok[sl] = __all(inb[sl]) != 0;
+                    else ok[sl] = (wave_sum_fast(lp[sl]) + P.logprior_norm) > logy;
+                }
+            }
+            PT(11);
         }
         if (l == 0) {
-            smask[w * kSlots + 0] = em0 && ok0;
-            smask[w * kSlots + 1] = em1 && ok1;
-            src[w * kSlots + 0] = 0;
-            src[w * kSlots + 1] = 0;
+#pragma unroll
+            for (int sl = 0; sl < kSlots; ++sl) smask[w * kSlots + sl] = (kind[sl] != S_NONE) && ok[sl];
         }
         if (!__syncthreads_or(act)) break;
         PT(2);
@@ -1157,77 +1394,97 @@ __global__ __launch_bounds__(256) void k_hrss(DevProblem P, DevRun R, int C)
         pt[8] += 1;
 #endif
 
-        // ---- batched likelihood of the tile ----
-        double Lr0 = -INFINITY, Lr1 = -INFINITY;
-        eval_tile<D, MODE, LIK, UPW, NP>(P, wr, T, smask);
+        // ---- batched likelihood of the tile (+ FP64 re-check of near-threshold rows) ----
+        const int any_rc = eval_tile<D, MODE, LIK, UPW, NP>(P, wr, T, smask, guard);
         PT(3);
-        if constexpr (MODE == MODE_FP64) {
-            if (act) {
-                if (em0 && ok0) Lr0 = sanitize(T.L[w * kSlots + 0], c_nonfin);
-                if (em1 && ok1) Lr1 = sanitize(T.L[w * kSlots + 1], c_nonfin);
-            }
-        } else {
-            int need = 0;
-            float m0 = -INFINITY, m1 = -INFINITY;
-            if (act) {
-                if (em0 && ok0) m0 = T.L32[w * kSlots + 0];
-                if (em1 && ok1) m1 = T.L32[w * kSlots + 1];
-                auto near = [&](float Lm) -> bool {
-                    if (Lm != Lm) return true;
-                    const float band = P.guard_rel * fmaxf(0.f, P.cmax32 - Lm) + P.guard_abs +
-                                       1e-6f * fabsf(Lm);
-                    return fabs((double)Lm - Lstar) <= (double)band;
-                };
-                const int r0 = em0 && ok0 && near(m0), r1 = em1 && ok1 && near(m1);
-                if (l == 0) { src[w * kSlots + 0] = r0; src[w * kSlots + 1] = r1; }
-                need = r0 | r1;
-                c_rc += r0 + r1;
-            }
-            const int any_rc = __syncthreads_or(need);
-            PT(4);
+        if constexpr (MODE != MODE_FP64) {
             if (any_rc) {
-                eval64<D, LIK>(P, T, src, T.L);
+                eval64<D, LIK>(P, T, T.rc, T.L);
 #ifdef NSS_PHASE_TIMING
                 pt[10] += 1;
 #endif
                 PT(5);
             }
-            if (act) {
-                if (em0 && ok0) Lr0 = src[w * kSlots + 0] ? sanitize(T.L[w * kSlots + 0], c_nonfin)
-                                                          : sanitize((double)m0, c_nonfin);
-                if (em1 && ok1) Lr1 = src[w * kSlots + 1] ? sanitize(T.L[w * kSlots + 1], c_nonfin)
-                                                          : sanitize((double)m1, c_nonfin);
-            }
         }
 
-        // ---- per-chain state update ----
+        // ---- walk the plan ----
         if (act) {
-            c_evals += (em0 && ok0) + (em1 && ok1);
-            const bool in0 = em0 && ok0 && (Lr0 > Lstar);
-            const bool in1 = em1 && ok1 && (Lr1 > Lstar);
-            if (phase == PH_STEPOUT) {
-                if (em0) {
-                    if (in0) { tL -= width; ++nl; if (nl >= cap_out) { la = false; ++c_outcap; } }
-                    else la = false;
+            // every slot's outcome at once (FP64 where re-checked), as bit masks
+            unsigned okm = 0, inm = 0, rcm = 0, nfm = 0, shm = 0;
+            double Lv[kSlots];
+#pragma unroll
+            for (int sl = 0; sl < kSlots; ++sl) {
+                Lv[sl] = -INFINITY;
+                if (kind[sl] == S_SHRINK) shm |= 1u << sl;
+                if (kind[sl] != S_NONE && ok[sl]) {
+                    const int r = w * kSlots + sl;
+                    int rc = 0;
+                    double L;
+                    if constexpr (MODE == MODE_FP64) L = T.L[r];
+                    else { rc = T.rc[r]; L = rc ? T.L[r] : (double)T.L32[r]; }
+                    L = uniform_d(L);
+                    const bool nf = (L != L) || L == INFINITY;
+                    if (nf) L = -INFINITY;
+                    Lv[sl] = L;
+                    okm |= 1u << sl;
+                    if (L > Lstar) inm |= 1u << sl;
+                    if (rc) rcm |= 1u << sl;
+                    if (nf) nfm |= 1u << sl;
                 }
-                if (em1) {
-                    if (in1) { tR += width; ++nr; if (nr >= cap_out) { ra = false; ++c_outcap; } }
-                    else ra = false;
+            }
+            auto tally = [&](unsigned cons) {
+                c_tests += __builtin_popcount(cons);
+                c_evals += __builtin_popcount(cons & okm);
+                c_prej += __builtin_popcount(cons & ~okm);
+                c_rc += __builtin_popcount(cons & rcm);
+                c_nonfin += __builtin_popcount(cons & nfm);
+            };
+            bool moved = false;   // a bracket end moved during stepping-out this round
+#pragma unroll
+            for (int sl = 0; sl < 2; ++sl) {
+                if (kind[sl] == S_LEFT || kind[sl] == S_RIGHT) {
+                    tally(1u << sl);
+                    const bool in = (inm >> sl) & 1u;
+                    if (kind[sl] == S_LEFT) {
+                        if (in) { tL -= width; ++nl; moved = true; if (nl >= cap_out) { la = false; ++c_outcap; } }
+                        else la = false;
+                    } else {
+                        if (in) { tR += width; ++nr; moved = true; if (nr >= cap_out) { ra = false; ++c_outcap; } }
+                        else ra = false;
+                    }
                 }
-                if (!la && !ra) enter_shrink();
-            } else if (phase == PH_SHRINK && em0) {
-                if (in0) {
+            }
+            if (moved) dflt = false;
+            if (phase == PH_STEPOUT && !la && !ra) enter_shrink();
+            if (phase == PH_SHRINK && !moved && shm) {
+                const int s0 = __builtin_ctz(shm);
+                const unsigned acc = inm & shm;
+                const int last = acc ? __builtin_ctz(acc) : 31 - __builtin_clz(shm);
+                const unsigned cons = shm & ((2u << last) - 1u);
+                tally(cons);
+                const int nrej = __builtin_popcount(cons) - (acc ? 1 : 0);
+                // bracket after the last rejected slot (slots are contiguous from s0)
+                if (nrej > 0) {
+                    const int lr = s0 + nrej - 1;
+                    double bl = bLa[0], br = bRa[0];
+#pragma unroll
+                    for (int sl = 1; sl < kSlots; ++sl) if (sl == lr) { bl = bLa[sl]; br = bRa[sl]; }
+                    tL = bl; tR = br;
+                }
+                ns += nrej;
+                if (acc) {
                     // the accepted point is the evaluated candidate row, bit for bit
-                    const int r = w * kSlots + 0;
+                    const int r = w * kSlots + last;
 #pragma unroll
                     for (int i = 0; i < NA; ++i)
                         if (l + 64 * i < D) x0r[i] = scand[r * LDC + l + 64 * i];
-                    logL0 = Lr0;
+                    double La = Lv[0];
+#pragma unroll
+                    for (int sl = 1; sl < kSlots; ++sl) if (sl == last) La = Lv[sl];
+                    logL0 = La;
                     finish_step(1, ns + 1);
-                } else {
-                    if (tsh < 0.0) tL = tsh; else tR = tsh;
-                    ++ns;
-                    if (ns >= cap_sh) finish_step(0, ns);
+                } else if (ns >= cap_sh) {
+                    finish_step(0, ns);
                 }
             }
             PT(7);
@@ -1245,7 +1502,7 @@ __global__ __launch_bounds__(256) void k_hrss(DevProblem P, DevRun R, int C)
         for (int i = 0; i < NA; ++i)
             if (l + 64 * i < D) scand[w * LDC + l + 64 * i] = has_chain ? x0r[i] : 0.0;
         if (tid < kRows) smask[tid] = (tid < kMaxChainsPerWG) && (tid < C) &&
-                                      (blockIdx.x * C + tid < R.k);
+                                      (bm.y * C + tid < R.k);
         __syncthreads();
         eval64<D, LIK>(P, T, smask, T.L);
         if (has_chain) {
@@ -1279,8 +1536,9 @@ __global__ __launch_bounds__(256) void k_hrss(DevProblem P, DevRun R, int C)
 // ------------------------------------------------------------------------------------------
 // final live-set contribution (non-destructive): scal[4..6] = ln Z, sqrt(H/m), H
 // ------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_logz(DevRun R)
+__global__ __launch_bounds__(1024) void k_logz(Launch Lc)
 {
+    const DevRun R = Lc.R[Lc.map[blockIdx.x].x];
     __shared__ double red[32];
     const int m = R.m, k = R.k, n = m - k, tid = threadIdx.x;
     double mx = -INFINITY;
@@ -1311,20 +1569,32 @@ __global__ __launch_bounds__(1024) void k_logz(DevRun R)
 // ------------------------------------------------------------------------------------------
 // launchers
 // ------------------------------------------------------------------------------------------
-static int upw_for(const DevProblem &P) { return (P.K * (P.D / 16) + 3) / 4; }
+// register fragment units per wave: whole components (K >= 4) or spread blocks (K < 4)
+int upw_for(const DevProblem &P)
+{
+    const int NJB = P.D / 16;
+    return P.K >= 4 ? (P.K + 3) / 4 * NJB : (P.K * NJB + 3) / 4;
+}
+
+// compiled fragment capacities per padded dimension
+int upw_template(int D, int upw)
+{
+    if (D == 32) return upw <= 4 ? 4 : (upw <= 16 ? 16 : 0);
+    if (D == 64) return upw <= 2 ? 2 : (upw <= 8 ? 8 : 0);
+    if (D == 128) return upw <= 4 ? 4 : 0;
+    return 0;
+}
+
+size_t hrss_lds_bytes(int D, int K) { return (size_t)hrss_layout(D, K).total; }
+int dirs_rows() { return kDirRows; }
 
 int mode_supported(const DevProblem &P, int mode)
 {
-    if (hrss_layout(P.D, P.K).total > 160 * 1024) return 0;  // one workgroup's LDS
+    if (hrss_lds_bytes(P.D, P.K) > 160 * 1024) return 0;  // one workgroup's LDS
     if (mode == MODE_FP64) return 1;
     if (P.lik_kind != LIK_MIXTURE) return 0;
-    const int upw = upw_for(P);
-    if (P.D == 32) return upw <= 16;
-    if (P.D == 64) return upw <= 8;
-    return upw <= 4;
+    return upw_template(P.D, upw_for(P)) != 0;
 }
-
-static size_t hrss_lds(const DevProblem &P) { return (size_t)hrss_layout(P.D, P.K).total; }
 
 template <typename F>
 static hipError_t set_lds(F *f, size_t bytes)
@@ -1333,50 +1603,44 @@ static hipError_t set_lds(F *f, size_t bytes)
                                (int)bytes);
 }
 
-hipError_t launch_init_draw(const DevProblem &P, const DevRun &R, hipStream_t s)
+hipError_t launch_init_draw(const Launch &L, hipStream_t s)
 {
-    const long long n = (long long)R.m * ((P.d + 1) / 2);
-    const int blocks = (int)((n + 255) / 256);
-    hipLaunchKernelGGL(k_init_draw, dim3(blocks), dim3(256), 0, s, P, R);
+    if (L.nblocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_init_draw, dim3(L.nblocks), dim3(256), 0, s, L);
     return hipGetLastError();
 }
 
 template <int D, int MODE, int LIK, int UPW>
-static hipError_t eval_t(const DevProblem &P, const double *X, int ld, int n, double *out,
-                         unsigned long long *nf, hipStream_t s)
+static hipError_t eval_t(const Launch &L, const double *X, int ld, int n, double *out,
+                         int from_run, hipStream_t s)
 {
-    const size_t lds = hrss_lds(P);
+    const size_t lds = hrss_lds_bytes(D, L.max_K);
     auto f = k_eval<D, MODE, LIK, UPW>;
     hipError_t e = set_lds(f, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(f, dim3((n + kRows - 1) / kRows), dim3(256), lds, s, P, X, ld, n, out, nf);
+    hipLaunchKernelGGL(f, dim3(L.nblocks), dim3(256), lds, s, L, X, ld, n, out, from_run);
     return hipGetLastError();
 }
 
 template <int D, int MODE, int LIK, int UPW>
-static hipError_t hrss_t(const DevProblem &P, const DevRun &R, hipStream_t s)
+static hipError_t hrss_t(const Launch &L, hipStream_t s)
 {
-    const size_t lds = hrss_lds(P);
+    const size_t lds = hrss_lds_bytes(D, L.max_K);
     auto f = k_hrss<D, MODE, LIK, UPW>;
     hipError_t e = set_lds(f, lds);
     if (e != hipSuccess) return e;
-    int C = (R.k + 255) / 256;
-    if (C < 1) C = 1;
-    if (C > kMaxChainsPerWG) C = kMaxChainsPerWG;
-    const int blocks = (R.k + C - 1) / C;
-    hipLaunchKernelGGL(f, dim3(blocks), dim3(256), lds, s, P, R, C);
+    hipLaunchKernelGGL(f, dim3(L.nblocks), dim3(256), lds, s, L);
     return hipGetLastError();
 }
 
 // dispatch over (D, mode, likelihood); UPW = register fragment units per wave (mixed only)
-// dispatch over (D, mode, likelihood); UPW = register fragment units per wave (mixed only)
 #define NSS_MIXED_D(FN, MODE_, ...)                                                           \
     do {                                                                                      \
-        if (P.D == 32) {                                                                      \
+        if (D == 32) {                                                                        \
             if (upw <= 4) return FN<32, MODE_, LIK_MIXTURE, 4>(__VA_ARGS__);                  \
             return FN<32, MODE_, LIK_MIXTURE, 16>(__VA_ARGS__);                               \
         }                                                                                     \
-        if (P.D == 64) {                                                                      \
+        if (D == 64) {                                                                        \
             if (upw <= 2) return FN<64, MODE_, LIK_MIXTURE, 2>(__VA_ARGS__);                  \
             return FN<64, MODE_, LIK_MIXTURE, 8>(__VA_ARGS__);                                \
         }                                                                                     \
@@ -1384,88 +1648,95 @@ static hipError_t hrss_t(const DevProblem &P, const DevRun &R, hipStream_t s)
     } while (0)
 #define NSS_DISPATCH(FN, ...)                                                                 \
     do {                                                                                      \
-        if (P.lik_kind == LIK_FUNNEL) {                                                       \
+        if (D != 32 && D != 64 && D != 128) return hipErrorInvalidValue;                      \
+        if (lik == LIK_FUNNEL) {                                                              \
             if (mode != MODE_FP64) return hipErrorNotSupported;                               \
-            if (P.D == 32) return FN<32, MODE_FP64, LIK_FUNNEL, 1>(__VA_ARGS__);              \
-            if (P.D == 64) return FN<64, MODE_FP64, LIK_FUNNEL, 1>(__VA_ARGS__);              \
+            if (D == 32) return FN<32, MODE_FP64, LIK_FUNNEL, 1>(__VA_ARGS__);                \
+            if (D == 64) return FN<64, MODE_FP64, LIK_FUNNEL, 1>(__VA_ARGS__);                \
             return FN<128, MODE_FP64, LIK_FUNNEL, 1>(__VA_ARGS__);                            \
         }                                                                                     \
+        if (lik != LIK_MIXTURE) return hipErrorInvalidValue;                                  \
         if (mode == MODE_FP64) {                                                              \
-            if (P.D == 32) return FN<32, MODE_FP64, LIK_MIXTURE, 1>(__VA_ARGS__);             \
-            if (P.D == 64) return FN<64, MODE_FP64, LIK_MIXTURE, 1>(__VA_ARGS__);             \
+            if (D == 32) return FN<32, MODE_FP64, LIK_MIXTURE, 1>(__VA_ARGS__);               \
+            if (D == 64) return FN<64, MODE_FP64, LIK_MIXTURE, 1>(__VA_ARGS__);               \
             return FN<128, MODE_FP64, LIK_MIXTURE, 1>(__VA_ARGS__);                           \
         }                                                                                     \
-        if (!mode_supported(P, mode)) return hipErrorNotSupported;                            \
-        const int upw = upw_for(P);                                                           \
+        if (upw_template(D, upw) == 0) return hipErrorNotSupported;                           \
         if (mode == MODE_BF16) NSS_MIXED_D(FN, MODE_BF16, __VA_ARGS__);                       \
         if (mode == MODE_FP16) NSS_MIXED_D(FN, MODE_FP16, __VA_ARGS__);                       \
         if (mode == MODE_BF16X3) NSS_MIXED_D(FN, MODE_BF16X3, __VA_ARGS__);                   \
-        NSS_MIXED_D(FN, MODE_FP16X3, __VA_ARGS__);                                            \
+        if (mode == MODE_FP16X3) NSS_MIXED_D(FN, MODE_FP16X3, __VA_ARGS__);                   \
+        return hipErrorInvalidValue;                                                          \
     } while (0)
 
-hipError_t launch_eval_points(const DevProblem &P, const double *X, int ld, int n, double *out,
-                              unsigned long long *nonfinite, int mode, hipStream_t s)
+hipError_t launch_eval_init(const Launch &L, int D, int lik, hipStream_t s)
 {
-    if (n <= 0) return hipSuccess;
-    NSS_DISPATCH(eval_t, P, X, ld, n, out, nonfinite, s);
+    if (L.nblocks <= 0) return hipSuccess;
+    const int mode = MODE_FP64, upw = 1;
+    NSS_DISPATCH(eval_t, L, nullptr, 0, 0, nullptr, 1, s);
 }
 
-hipError_t launch_hrss(const DevProblem &P, const DevRun &R, int mode, hipStream_t s)
+hipError_t launch_eval_points(const Launch &L, int D, int lik, int mode, int upw, const double *X,
+                              int ld, int n, double *out, hipStream_t s)
 {
-    NSS_DISPATCH(hrss_t, P, R, s);
+    if (n <= 0 || L.nblocks <= 0) return hipSuccess;
+    NSS_DISPATCH(eval_t, L, X, ld, n, out, 0, s);
 }
 
-hipError_t launch_select(const DevProblem &P, const DevRun &R, int op, hipStream_t s)
+hipError_t launch_hrss(const Launch &L, int D, int lik, int mode, int upw, hipStream_t s)
 {
-    (void)P;
+    if (L.nblocks <= 0) return hipSuccess;
+    NSS_DISPATCH(hrss_t, L, s);
+}
+
+hipError_t launch_select(const Launch &L, int op, hipStream_t s)
+{
+    if (L.nblocks <= 0) return hipSuccess;
     int NP = 1;
-    while (NP < R.m) NP <<= 1;
+    while (NP < L.max_m) NP <<= 1;
     const size_t lds = (size_t)NP * 8 + (size_t)(NP + (NP & 1)) * 4 + 32 * 8 + 16;
     hipError_t e = set_lds(k_select, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_select, dim3(1), dim3(kSelectThreads), lds, s, R, op);
+    hipLaunchKernelGGL(k_select, dim3(L.nblocks), dim3(kSelectThreads), lds, s, L, op);
     return hipGetLastError();
 }
 
-hipError_t launch_cov(const DevProblem &P, const DevRun &R, double *part1, double *part2, int G,
-                      hipStream_t s)
+hipError_t launch_cov(const Launch &cov, const Launch &one, int D, hipStream_t s)
 {
-    const int nt = P.D / 16;
-    const int ntile = nt * (nt + 1) / 2;
-    hipLaunchKernelGGL(k_cov, dim3(ntile, G), dim3(256), 0, s, P, R, part1, part2, G);
+    if (one.nblocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cov, dim3(cov.nblocks), dim3(256), 0, s, cov);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const size_t lds = (size_t)(P.D * (P.D + 1) / 2 + P.D + 32) * 8 + 16;
+    const size_t lds = (size_t)(D * (D + 1) / 2 + D + 32) * 8 + 16;
     e = set_lds(k_chol, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_chol, dim3(1), dim3(1024), lds, s, P, R, part1, part2, G, ntile);
+    hipLaunchKernelGGL(k_chol, dim3(one.nblocks), dim3(1024), lds, s, one);
     return hipGetLastError();
 }
 
 template <int D>
-static hipError_t dirs_t(const DevProblem &P, const DevRun &R, hipStream_t s)
+static hipError_t dirs_t(const Launch &L, hipStream_t s)
 {
     const size_t lds = (size_t)dirs_lds_bytes(D);
     hipError_t e = set_lds(k_dirs<D>, lds);
     if (e != hipSuccess) return e;
-    const long long total = (long long)R.k * R.p;
-    hipLaunchKernelGGL(k_dirs<D>, dim3((unsigned)((total + kDirRows - 1) / kDirRows)), dim3(256),
-                       lds, s, P, R);
+    hipLaunchKernelGGL(k_dirs<D>, dim3(L.nblocks), dim3(256), lds, s, L);
     return hipGetLastError();
 }
 
-hipError_t launch_dirs(const DevProblem &P, const DevRun &R, hipStream_t s)
+hipError_t launch_dirs(const Launch &L, int D, hipStream_t s)
 {
-    if (!R.dirbuf) return hipSuccess;
-    if (P.D == 32) return dirs_t<32>(P, R, s);
-    if (P.D == 64) return dirs_t<64>(P, R, s);
-    return dirs_t<128>(P, R, s);
+    if (L.nblocks <= 0) return hipSuccess;
+    if (D == 32) return dirs_t<32>(L, s);
+    if (D == 64) return dirs_t<64>(L, s);
+    if (D == 128) return dirs_t<128>(L, s);
+    return hipErrorInvalidValue;
 }
 
-hipError_t launch_logz(const DevProblem &P, const DevRun &R, hipStream_t s)
+hipError_t launch_logz(const Launch &L, hipStream_t s)
 {
-    (void)P;
-    hipLaunchKernelGGL(k_logz, dim3(1), dim3(1024), 0, s, R);
+    if (L.nblocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_logz, dim3(L.nblocks), dim3(1024), 0, s, L);
     return hipGetLastError();
 }
 }  // namespace nss

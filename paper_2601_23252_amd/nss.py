@@ -121,6 +121,17 @@ def load(build_if_missing: bool = True):
     L.ns_last_error.argtypes = [vp]
     L.ns_config_default.restype = None
     L.ns_config_default.argtypes = [C.POINTER(ns_config)]
+    L.ns_init_batch.restype = C.c_int
+    L.ns_init_batch.argtypes = [C.c_int32, C.POINTER(ns_prior), C.POINTER(ns_energy),
+                                C.POINTER(ns_config), vp, C.POINTER(vp)]
+    L.ns_num_runs.restype = C.c_int32
+    L.ns_num_runs.argtypes = [vp]
+    L.ns_logz_batch.restype = C.c_int
+    L.ns_logz_batch.argtypes = [vp, _d, _d, _d]
+    L.ns_stats_run.restype = C.c_int
+    L.ns_stats_run.argtypes = [vp, C.c_int32, C.POINTER(ns_stats_t)]
+    L.ns_get_state_run.restype = C.c_int
+    L.ns_get_state_run.argtypes = [vp, C.c_int32, C.POINTER(ns_state_view)]
     _lib = L
     return L
 
@@ -184,6 +195,36 @@ def ns_stats(ctx):
     return st, {f: getattr(s, f) for f, _ in ns_stats_t._fields_}
 
 
+def ns_init_batch(priors, energies, cfgs, stream=None):
+    """priors, energies, cfgs: equal-length lists of structs.  Returns (status, ctx)."""
+    n = len(priors)
+    if not (len(energies) == n and len(cfgs) == n):
+        raise ValueError("priors, energies and cfgs must have equal length")
+    pa = (ns_prior * max(n, 1))(*priors)
+    ea = (ns_energy * max(n, 1))(*energies)
+    ca = (ns_config * max(n, 1))(*cfgs)
+    ctx = C.c_void_p()
+    st = load().ns_init_batch(n, pa, ea, ca, stream, C.byref(ctx))
+    return st, (ctx.value if st == NS_OK else None)
+
+
+def ns_num_runs(ctx) -> int:
+    return int(load().ns_num_runs(ctx))
+
+
+def ns_logz_batch(ctx):
+    n = ns_num_runs(ctx)
+    z, e, h = np.zeros(n), np.zeros(n), np.zeros(n)
+    st = load().ns_logz_batch(ctx, _ptr(z), _ptr(e), _ptr(h))
+    return st, z, e, h
+
+
+def ns_stats_run(ctx, run):
+    s = ns_stats_t()
+    st = load().ns_stats_run(ctx, int(run), C.byref(s))
+    return st, {f: getattr(s, f) for f, _ in ns_stats_t._fields_}
+
+
 def ns_free(ctx):
     if ctx:
         load().ns_free(ctx)
@@ -226,6 +267,32 @@ def current_stream():
     return None
 
 
+def make_config(m, k, p, width=0.0, seed=0, run_id=0, precision="fp64", term_frac=1e-3,
+                stepout_cap=10, shrink_cap=100, max_iter=100000, trace=False, timing=False,
+                inline_directions=False) -> ns_config:
+    cfg = ns_config_default()
+    cfg.n_live, cfg.k, cfg.chain_len = int(m), int(k), int(p)
+    cfg.width = float(width)
+    cfg.stepout_cap, cfg.shrink_cap = int(stepout_cap), int(shrink_cap)
+    cfg.term_frac = float(term_frac)
+    cfg.seed, cfg.run_id = int(seed), int(run_id)
+    cfg.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    cfg.max_iter = int(max_iter)
+    cfg.flags = ((NS_FLAG_TRACE if trace else 0) | (NS_FLAG_TIMING if timing else 0)
+                 | (NS_FLAG_INLINE_DIRECTIONS if inline_directions else 0))
+    return cfg
+
+
+def _state_of(ctx, run, m, d, k):
+    x = np.zeros((m, d)); logL = np.zeros(m); perm = np.zeros(m, np.int32)
+    Ls = np.zeros((d, d)); par = np.zeros(k, np.int32)
+    v = ns_state_view(_ptr(x), _ptr(logL), _ptr(perm, _i32), _ptr(Ls), _ptr(par, _i32),
+                      0.0, 0.0, 0.0, 0.0, 0, 0)
+    _check(load().ns_get_state_run(ctx, int(run), C.byref(v)), ctx)
+    return dict(x=x, logL=logL, perm=perm, Lsig=Ls, parents=par, Lstar=v.Lstar, logZ=v.logZ,
+                logX=v.logX, M=v.M, iter=int(v.iter), done=int(v.done))
+
+
 class NSRun:
     """One nested-sampling run on the GPU (wraps one ns_ctx)."""
 
@@ -239,16 +306,8 @@ class NSRun:
         self.k = int(k or prob["k"])
         self.p = int(p or prob["p"])
         pr, en, self._keep = make_structs(prob)
-        cfg = ns_config_default()
-        cfg.n_live, cfg.k, cfg.chain_len = self.m, self.k, self.p
-        cfg.width = float(width)
-        cfg.stepout_cap, cfg.shrink_cap = int(stepout_cap), int(shrink_cap)
-        cfg.term_frac = float(term_frac)
-        cfg.seed, cfg.run_id = int(seed), int(run_id)
-        cfg.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
-        cfg.max_iter = int(max_iter)
-        cfg.flags = ((NS_FLAG_TRACE if trace else 0) | (NS_FLAG_TIMING if timing else 0)
-                     | (NS_FLAG_INLINE_DIRECTIONS if inline_directions else 0))
+        cfg = make_config(self.m, self.k, self.p, width, seed, run_id, precision, term_frac,
+                          stepout_cap, shrink_cap, max_iter, trace, timing, inline_directions)
         self.cfg = cfg
         s = current_stream() if stream == "torch" else stream
         st, self.ctx = ns_init(pr, en, cfg, s)
@@ -286,14 +345,7 @@ class NSRun:
         return s
 
     def state(self) -> dict:
-        m, d, k = self.m, self.d, self.k
-        x = np.zeros((m, d)); logL = np.zeros(m); perm = np.zeros(m, np.int32)
-        Ls = np.zeros((d, d)); par = np.zeros(k, np.int32)
-        v = ns_state_view(_ptr(x), _ptr(logL), _ptr(perm, _i32), _ptr(Ls), _ptr(par, _i32),
-                          0.0, 0.0, 0.0, 0.0, 0, 0)
-        _check(load().ns_get_state(self.ctx, C.byref(v)), self.ctx)
-        return dict(x=x, logL=logL, perm=perm, Lsig=Ls, parents=par, Lstar=v.Lstar, logZ=v.logZ,
-                    logX=v.logX, M=v.M, iter=int(v.iter), done=int(v.done))
+        return _state_of(self.ctx, 0, self.m, self.d, self.k)
 
     def set_state(self, x, logL, logZ, logX, M, iter_, done=0):
         x = np.ascontiguousarray(x, np.float64)
@@ -320,3 +372,59 @@ class NSRun:
         prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         _check(load().ns_eval_loglik(self.ctx, _ptr(x), x.shape[0], prec, _ptr(out)), self.ctx)
         return out
+
+
+class NSBatch:
+    """Independent runs in one context (ns_init_batch): runs[r] = (problem dict, config kwargs
+    for make_config, with m, k, p defaulting to the problem's)."""
+
+    def __init__(self, runs, stream="torch"):
+        self._keep, prs, ens, cfgs, self.shapes = [], [], [], [], []
+        for prob, kw in runs:
+            kw = dict(kw)
+            m, k, p = (int(kw.pop(a, None) or prob[a]) for a in ("m", "k", "p"))
+            pr, en, keep = make_structs(prob)
+            self._keep.append(keep)
+            prs.append(pr)
+            ens.append(en)
+            cfgs.append(make_config(m, k, p, **kw))
+            self.shapes.append((m, int(prob["d"]), k))
+        s = current_stream() if stream == "torch" else stream
+        st, self.ctx = ns_init_batch(prs, ens, cfgs, s)
+        _check(st)
+        self.n = len(runs)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            ns_free(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        self.close()
+
+    def reset(self, seed, run_id=0):
+        _check(ns_reset(self.ctx, seed, run_id), self.ctx)
+
+    def step(self) -> bool:
+        st, done = ns_step(self.ctx)
+        _check(st, self.ctx, ok=(NS_OK, NS_DONE))
+        return bool(done)
+
+    def run(self, max_iter=100000) -> int:
+        st, it = ns_run(self.ctx, max_iter)
+        _check(st, self.ctx)
+        return it
+
+    def logz(self):
+        st, z, e, h = ns_logz_batch(self.ctx)
+        _check(st, self.ctx)
+        return z, e, h
+
+    def stats(self, run) -> dict:
+        st, s = ns_stats_run(self.ctx, run)
+        _check(st, self.ctx)
+        return s
+
+    def state(self, run) -> dict:
+        m, d, k = self.shapes[run]
+        return _state_of(self.ctx, run, m, d, k)

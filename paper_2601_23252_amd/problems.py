@@ -22,6 +22,9 @@ these shapes, see the design notes):
               [-10,10]^d; m=2000, k=1000, p=5d
     gaussian20  prior N(0, I), likelihood N(x; 1, 0.01 I), d=20 (the paper's overhead example)
     funnel    prior U[-20,20]^d, Neal's funnel likelihood
+    config5   batched serving: 256 independent runs, d uniform on {8, 16, ..., 128}; even runs
+              a correlated Gaussian drawn as config2 (prior N(0, 4 I)), odd runs the funnel
+              under U[-20,20]^d; m=500, k=250, p=5d each
 """
 from __future__ import annotations
 
@@ -98,6 +101,24 @@ def funnel(d: int, box: float = 20.0, m: int = 500, k: int = 250, p=None):
     return dict(name=f"funnel_d{d}", d=d, prior="box", prior_a=np.full(d, -box),
                 prior_b=np.full(d, box), lik="funnel", K=0, m=m, k=k,
                 p=5 * d if p is None else p)
+
+
+def config5(seed: int = 1005, n_runs: int = 256, m: int = 500, k: int = 250):
+    """List of n_runs problem dicts of uneven dimension (see the module docstring)."""
+    rng = np.random.default_rng(seed)
+    dims = 8 * rng.integers(1, 17, n_runs)
+    sub = rng.integers(0, 2**31 - 1, n_runs)
+    out = []
+    for r in range(n_runs):
+        d = int(dims[r])
+        if r % 2 == 0:
+            pr = config2(int(sub[r]), d=d, m=m, k=k)
+            pr["name"] = f"batch_gauss{d}_{r}"
+        else:
+            pr = funnel(d, m=m, k=k)
+            pr["name"] = f"batch_funnel{d}_{r}"
+        out.append(pr)
+    return out
 
 
 CONFIGS = {"config1": config1, "config2": config2, "config3": config3}
