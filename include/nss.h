@@ -60,7 +60,14 @@ typedef enum {
      * n_comp >= 1 components (n_comp = 1: a single, possibly correlated, Gaussian). */
     NS_LIK_MIXTURE = 1,
     /* Neal's funnel: v = x_0 ~ N(0, 9), x_j | v ~ N(0, e^v) for j = 1..d-1, normalised. */
-    NS_LIK_FUNNEL = 2
+    NS_LIK_FUNNEL = 2,
+    /* GP hyperparameter marginalisation (Sec. 5 GP experiments; App. "Gaussian Process
+     * Hyperparameter Marginalization"): d = 6 coordinates u = log theta,
+     * theta = (sigma_f, l_1, l_2, l_p, P, sigma_n); log L(u) = log N(y; 0, K + sigma_n^2 I)
+     * over n_obs observations (x_obs[i] in R^2, y_obs[i]) with the product kernel
+     * K_ab = sigma_f^2 exp(-1/2 sum_j (a_j - b_j)^2 / l_j^2 - 2 sum_j sin^2(pi (a_j - b_j)/P)
+     * / l_p^2), j = 1, 2.  A Cholesky factorisation that breaks down gives log L = -inf. */
+    NS_LIK_GP = 3
 } ns_lik_kind;
 
 /* Arithmetic of the likelihood evaluations inside the chains. */
@@ -76,7 +83,11 @@ typedef enum {
                           * 16-bit remainder; W_hi r_hi + W_hi r_lo + W_lo r_hi on three BF16
                           * MFMAs (~600x smaller error than NS_MIXED_BF16, so FP64 re-checks
                           * near L* become rare) */
-    NS_MIXED_FP16X3 = 4  /* as NS_MIXED_BF16X3 with FP16 parts */
+    NS_MIXED_FP16X3 = 4, /* as NS_MIXED_BF16X3 with FP16 parts */
+    NS_MIXED_FP32 = 5  /* NS_LIK_GP only: kernel matrix and Cholesky factorisation in FP32 on
+                        * MFMA (FP64 log-determinant and |z|^2 sums); a candidate whose
+                        * estimate falls within a guard band of L*, or whose FP32
+                        * factorisation breaks down, is re-evaluated in FP64 */
 } ns_precision;
 
 typedef struct {
@@ -88,11 +99,14 @@ typedef struct {
 
 typedef struct {
     int32_t kind;       /* ns_lik_kind */
-    int32_t d;          /* must equal the prior's d */
+    int32_t d;          /* must equal the prior's d (NS_LIK_GP: 6) */
     int32_t n_comp;     /* NS_LIK_MIXTURE: number of components, 1 <= n_comp <= 64 */
     const double *logw; /* [n_comp] log weights (normalised by the caller if Z must be) */
     const double *mean; /* [n_comp * d] component means */
     const double *cov;  /* [n_comp * d * d] symmetric positive-definite covariances */
+    int32_t n_obs;      /* NS_LIK_GP: observations, 1 <= n_obs <= 256 */
+    const double *x_obs;/* NS_LIK_GP: [n_obs * 2] inputs, row-major */
+    const double *y_obs;/* NS_LIK_GP: [n_obs] targets */
 } ns_energy;
 
 typedef struct {

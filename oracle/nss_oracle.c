@@ -44,7 +44,7 @@
 
 enum { P_INIT = 1, P_RESAMPLE = 2, P_DIR = 3, P_STEP = 4, P_SHRINK = 5 };
 enum { PRIOR_BOX = 0, PRIOR_GAUSS = 1 };
-enum { LIK_MIXTURE = 1, LIK_FUNNEL = 2 };
+enum { LIK_MIXTURE = 1, LIK_FUNNEL = 2, LIK_GP = 3 };
 
 /* ------------------------------------------------------------------------------------------ */
 /* Philox4x32-10                                                                               */
@@ -112,6 +112,9 @@ typedef struct {
     double *mu;               /* K x d means */
     double *chol;             /* K x d x d lower Cholesky factors of the covariances */
     double *logdet_half;      /* K: sum log diag(chol) = 0.5 log det C */
+    int gp_n;                 /* GP regression: n observations */
+    double *gp_x;             /* n x 2 inputs */
+    double *gp_y;             /* n targets */
 } oprob;
 
 static int cholesky_lower(const double *A, double *L, int n)
@@ -137,6 +140,7 @@ void or_problem_free(void *pp)
     oprob *p = (oprob *)pp;
     if (!p) return;
     free(p->pa); free(p->pb); free(p->logw); free(p->mu); free(p->chol); free(p->logdet_half);
+    free(p->gp_x); free(p->gp_y);
     free(p);
 }
 
@@ -173,6 +177,30 @@ void *or_problem_new(int d, int prior_kind, const double *pa, const double *pb, 
         or_problem_free(p);
         return NULL;
     }
+    return p;
+}
+
+/* GP hyperparameter marginalisation: d = 6 coordinates u = log theta with
+ * theta = (sigma_f, l_1, l_2, l_p, P, sigma_n), a box prior on u (log-uniform theta), data
+ * (X[n][2], y[n]).  Returns NULL on invalid input. */
+void *or_problem_new_gp(int n, const double *X, const double *y, const double *pa,
+                        const double *pb)
+{
+    if (n < 1) return NULL;
+    const int d = 6;
+    oprob *p = (oprob *)calloc(1, sizeof(oprob));
+    p->d = d;
+    p->prior_kind = PRIOR_BOX;
+    p->pa = (double *)malloc(sizeof(double) * d);
+    p->pb = (double *)malloc(sizeof(double) * d);
+    memcpy(p->pa, pa, sizeof(double) * d);
+    memcpy(p->pb, pb, sizeof(double) * d);
+    p->lik_kind = LIK_GP;
+    p->gp_n = n;
+    p->gp_x = (double *)malloc(sizeof(double) * 2 * (size_t)n);
+    p->gp_y = (double *)malloc(sizeof(double) * (size_t)n);
+    memcpy(p->gp_x, X, sizeof(double) * 2 * (size_t)n);
+    memcpy(p->gp_y, y, sizeof(double) * (size_t)n);
     return p;
 }
 
@@ -218,12 +246,57 @@ static double log_gauss_chol(const double *x, const double *mu, const double *L,
     return -0.5 * q - logdet_half - 0.5 * d * log(2.0 * OR_PI);
 }
 
+/* GP log marginal likelihood log N(y; 0, K + sigma_n^2 I) with the product kernel
+ *   k(a, b) = sigma_f^2 exp(-1/2 sum_j (a_j - b_j)^2 / l_j^2)
+ *                       exp(-2 sum_j sin^2(pi (a_j - b_j) / P) / l_p^2),   j = 1, 2,
+ * (a squared-exponential times a periodic kernel, each a product over the input dimensions),
+ * by a Cholesky factorisation K_y = L L^T: log L = -1/2 |L^{-1} y|^2 - sum log L_ii
+ * - n/2 log(2 pi).  A factorisation that breaks down gives -inf. */
+static double gp_loglik(const oprob *p, const double *u)
+{
+    const int n = p->gp_n;
+    const double sf2 = exp(2.0 * u[0]), l1 = exp(u[1]), l2 = exp(u[2]), lp = exp(u[3]);
+    const double per = exp(u[4]), sn2 = exp(2.0 * u[5]);
+    double *K = (double *)malloc(sizeof(double) * (size_t)n * n);
+    double *L = (double *)malloc(sizeof(double) * (size_t)n * n);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j <= i; ++j) {
+            const double d1 = p->gp_x[2 * i] - p->gp_x[2 * j];
+            const double d2 = p->gp_x[2 * i + 1] - p->gp_x[2 * j + 1];
+            const double s1 = sin(OR_PI * d1 / per), s2 = sin(OR_PI * d2 / per);
+            double k = sf2 * exp(-0.5 * (d1 * d1 / (l1 * l1) + d2 * d2 / (l2 * l2))) *
+                       exp(-2.0 * (s1 * s1 + s2 * s2) / (lp * lp));
+            if (i == j) k += sn2;
+            K[(size_t)i * n + j] = k;
+            K[(size_t)j * n + i] = k;
+        }
+    double r;
+    if (cholesky_lower(K, L, n) != 0) {
+        r = -INFINITY;
+    } else {
+        double q = 0.0, ld = 0.0;
+        double *z = K;  /* reuse: forward substitution L z = y */
+        for (int i = 0; i < n; ++i) {
+            double s = p->gp_y[i];
+            for (int t = 0; t < i; ++t) s -= L[(size_t)i * n + t] * z[t];
+            z[i] = s / L[(size_t)i * n + i];
+            q += z[i] * z[i];
+            ld += log(L[(size_t)i * n + i]);
+        }
+        r = -0.5 * q - ld - 0.5 * n * log(2.0 * OR_PI);
+    }
+    free(K);
+    free(L);
+    return r;
+}
+
 /* log L(x) = -E(x).  Mixture: log sum_i w_i N(x; mu_i, C_i).  Funnel: v = x_0 ~ N(0, 9),
- * x_j | v ~ N(0, e^v) for j >= 1. */
+ * x_j | v ~ N(0, e^v) for j >= 1.  GP: log marginal likelihood of the regression data. */
 double or_loglik(const void *pp, const double *x)
 {
     const oprob *p = (const oprob *)pp;
     int d = p->d;
+    if (p->lik_kind == LIK_GP) return gp_loglik(p, x);
     if (p->lik_kind == LIK_MIXTURE) {
         double terms[256];
         double mx = -INFINITY;

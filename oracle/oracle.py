@@ -17,7 +17,7 @@ SRC = os.path.join(HERE, "nss_oracle.c")
 LIB = os.path.join(HERE, "libnss_oracle.so")
 
 PRIOR_BOX, PRIOR_GAUSS = 0, 1
-LIK_MIXTURE, LIK_FUNNEL = 1, 2
+LIK_MIXTURE, LIK_FUNNEL, LIK_GP = 1, 2, 3
 P_INIT, P_RESAMPLE, P_DIR, P_STEP, P_SHRINK = 1, 2, 3, 4, 5
 
 _dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
@@ -51,6 +51,8 @@ def lib():
         L.or_problem_new.restype = C.c_void_p
         L.or_problem_new.argtypes = [C.c_int, C.c_int, _dp, _dp, C.c_int, C.c_int,
                                      C.c_void_p, C.c_void_p, C.c_void_p]
+        L.or_problem_new_gp.restype = C.c_void_p
+        L.or_problem_new_gp.argtypes = [C.c_int, _dp, _dp, _dp, _dp]
         L.or_problem_free.argtypes = [C.c_void_p]
         L.or_loglik.restype = C.c_double
         L.or_loglik.argtypes = [C.c_void_p, _dp]
@@ -108,14 +110,22 @@ class Problem:
             self.h = lib().or_problem_new(d, pk, pa, pb, LIK_MIXTURE, K, *ptrs)
         elif prob["lik"] == "funnel":
             self.h = lib().or_problem_new(d, pk, pa, pb, LIK_FUNNEL, 0, None, None, None)
+        elif prob["lik"] == "gp":
+            gx = np.ascontiguousarray(prob["gp_x"], np.float64)
+            gy = np.ascontiguousarray(prob["gp_y"], np.float64)
+            if d != 6 or prob["prior"] != "box" or gx.shape != (len(gy), 2):
+                raise ValueError("GP problem: d = 6, box prior on log theta, X of shape (n, 2)")
+            self._keep = [gx, gy]
+            self.h = lib().or_problem_new_gp(len(gy), gx, gy, pa, pb)
         else:
             raise ValueError(prob["lik"])
         if not self.h:
             raise ValueError("oracle rejected the problem")
 
     def __del__(self):
-        if getattr(self, "h", None):
-            lib().or_problem_free(self.h)
+        # at interpreter shutdown the module globals may already be gone
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.or_problem_free(self.h)
             self.h = None
 
     def loglik(self, x) -> np.ndarray:

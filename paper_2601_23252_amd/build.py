@@ -7,12 +7,12 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libnss.so")
-SOURCES = ["nss_kernels.hip", "nss_capi.hip"]
-HEADERS = ["nss_internal.hpp", "nss_rng.hpp"]
+SOURCES = ["nss_kernels.hip", "nss_gp.hip", "nss_capi.hip"]
+HEADERS = ["nss_internal.hpp", "nss_rng.hpp", "nss_wave.hpp"]
 ARCH = os.environ.get("NSS_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [
-    "-O3", "-std=c++17", "-fPIC", "-shared", f"--offload-arch={ARCH}",
+    "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     # no packed FP32 instructions anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function",
@@ -26,14 +26,30 @@ def build(force: bool = True, verbose: bool = False) -> str:
     if not force and os.path.exists(LIB) and all(
             os.path.getmtime(LIB) >= os.path.getmtime(p) for p in deps):
         return LIB
+    # one object per source, compiled concurrently, then linked
+    objs = [os.path.join(CSRC, os.path.splitext(s)[0] + ".o") for s in SOURCES]
+    procs = []
+    for src, obj in zip(srcs, objs):
+        cmd = ["hipcc", *FLAGS, "-c", "-o", obj, src]
+        if verbose:
+            print(" ".join(cmd))
+        procs.append((cmd, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE,
+                                            text=True)))
+    errors = []
+    for cmd, pr in procs:
+        _, err = pr.communicate()
+        if pr.returncode != 0:
+            errors.append(f"{' '.join(cmd)}\n{err[-6000:]}")
+    if errors:
+        raise RuntimeError("hipcc failed:\n" + "\n".join(errors))
     tmp = LIB + ".tmp"
-    cmd = ["hipcc", *FLAGS, "-o", tmp, *srcs]
-    if verbose:
-        print(" ".join(cmd))
+    cmd = ["hipcc", "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
-        raise RuntimeError(f"hipcc failed ({r.returncode}):\n{r.stderr[-8000:]}")
+        raise RuntimeError(f"link failed ({r.returncode}):\n{r.stderr[-8000:]}")
     os.replace(tmp, LIB)
+    for o in objs:
+        os.remove(o)
     return LIB
 
 

@@ -200,9 +200,22 @@ static ns_status prepare_problem(ns_ctx *ctx, RunHost &rh, const ns_prior *prior
     CK(hipMemcpy(dpb, pb.data(), D * 8, hipMemcpyHostToDevice));
     P.pa = dpa;
     P.pb = dpb;
-    P.lik_kind = en->kind == NS_LIK_MIXTURE ? LIK_MIXTURE : LIK_FUNNEL;
+    P.lik_kind = en->kind == NS_LIK_MIXTURE ? LIK_MIXTURE
+                                            : (en->kind == NS_LIK_GP ? LIK_GP : LIK_FUNNEL);
     if (P.lik_kind == LIK_FUNNEL) {
         P.K = 0;
+        return NS_OK;
+    }
+    if (P.lik_kind == LIK_GP) {
+        P.K = 0;
+        P.gp_n = en->n_obs;
+        double *gx, *gy;
+        if ((st = dalloc(ctx, &gx, (size_t)2 * en->n_obs)) || (st = dalloc(ctx, &gy, en->n_obs)))
+            return st;
+        CK(hipMemcpy(gx, en->x_obs, (size_t)2 * en->n_obs * 8, hipMemcpyHostToDevice));
+        CK(hipMemcpy(gy, en->y_obs, (size_t)en->n_obs * 8, hipMemcpyHostToDevice));
+        P.gp_x = gx;
+        P.gp_y = gy;
         return NS_OK;
     }
     const int K = en->n_comp;
@@ -300,6 +313,15 @@ static DevProblem problem_for_mode(const RunHost &rh, int mode)
         P.wf16 = rh.wf_bf16; P.wf16lo = rh.wf_bf16_lo; rel = 4e-5f; ab = 2e-4f; break;
     case NS_MIXED_FP16X3:
         P.wf16 = rh.wf_fp16; P.wf16lo = rh.wf_fp16_lo; rel = 6e-6f; ab = 2e-4f; break;
+    case NS_MIXED_FP32:
+        // GP: FP32 kernel matrix and factorisation.  Band = rel |L| + abs + c s sqrt(n) with
+        // s = (sigma_f^2 + sigma_n^2) / sigma_n^2: FP32-vs-FP64 differences on 16800 prior
+        // and posterior draws (n = 8..256) stayed below 2.6e-2 s sqrt(n) and 2.5e-5 |L| + 0.62;
+        // c is twice that (the tests check the 2x margin).
+        P.guard_rel = 5e-5f;
+        P.guard_abs = 1.25f;
+        P.guard_kappa = 5.2e-2f;
+        return P;
     default: break;
     }
     P.guard_rel = rel;
@@ -307,12 +329,15 @@ static DevProblem problem_for_mode(const RunHost &rh, int mode)
     return P;
 }
 
-static bool precision_valid(int p) { return p >= NS_FP64 && p <= NS_MIXED_FP16X3; }
+static bool precision_valid(int p) { return p >= NS_FP64 && p <= NS_MIXED_FP32; }
 static int d_index(int D) { return D == 32 ? 0 : (D == 64 ? 1 : 2); }
 
 // ---- block maps of the launches over the unfinished runs ----
 static int init_blocks(const RunHost &r) { return (r.m * ((r.d + 1) / 2) + 255) / 256; }
-static int eval_blocks(const RunHost &r) { return (r.m + kRows - 1) / kRows; }
+static int eval_blocks(const RunHost &r)
+{
+    return r.lik == LIK_GP ? r.m : (r.m + kRows - 1) / kRows;  // GP: one point per workgroup
+}
 static int cov_blocks(const RunHost &r)
 {
     const int nt = r.D / 16;
@@ -324,7 +349,7 @@ static int dirs_blocks(const RunHost &r)
     const long long t = (long long)r.k * r.p;
     return (int)((t + dirs_rows() - 1) / dirs_rows());
 }
-static int hrss_blocks(const RunHost &r) { return (r.k + r.R.C - 1) / r.R.C; }
+static int hrss_blocks(const RunHost &r) { return (r.k + r.R.C - 1) / r.R.C; }  // GP: C = 1
 
 struct MapBuilder {
     std::vector<int2> &h;
@@ -453,7 +478,8 @@ static ns_status enqueue_iteration(ns_ctx *ctx)
     }
     for (size_t g = 0; g < ctx->groups.size(); ++g) {
         const Group &G = ctx->groups[g];
-        e = launch_hrss(ctx->L_hrss[g], G.D, G.lik, G.mode, G.upwT, ctx->stream);
+        e = G.lik == LIK_GP ? launch_hrss_gp(ctx->L_hrss[g], G.mode, ctx->stream)
+                            : launch_hrss(ctx->L_hrss[g], G.D, G.lik, G.mode, G.upwT, ctx->stream);
         if (e != hipSuccess) return device_error(ctx, "HRSS launch", e);
     }
     if (e1) {
@@ -505,7 +531,10 @@ static ns_status start_runs(ns_ctx *ctx)
     hipError_t e = launch_init_draw(ctx->L_init, ctx->stream);
     if (e != hipSuccess) return device_error(ctx, "prior draw launch", e);
     for (size_t g = 0; g < ctx->groups.size(); ++g) {
-        e = launch_eval_init(ctx->L_eval[g], ctx->groups[g].D, ctx->groups[g].lik, ctx->stream);
+        const Group &G = ctx->groups[g];
+        e = G.lik == LIK_GP
+                ? launch_eval_gp(ctx->L_eval[g], MODE_FP64, nullptr, 0, 0, nullptr, 1, ctx->stream)
+                : launch_eval_init(ctx->L_eval[g], G.D, G.lik, ctx->stream);
         if (e != hipSuccess) return device_error(ctx, "initial evaluation", e);
     }
     e = launch_select(ctx->L_one, 0, ctx->stream);
@@ -552,6 +581,13 @@ static ns_status validate_run(const ns_prior *prior, const ns_energy *energy, co
             return NS_EINVAL;
         }
         if (energy->n_comp > 64) { msg = "n_comp > 64"; return NS_EUNSUPPORTED; }
+    } else if (energy->kind == NS_LIK_GP) {
+        if (d != 6) { msg = "GP likelihood needs d = 6 (log hyperparameters)"; return NS_EINVAL; }
+        if (energy->n_obs < 1 || !energy->x_obs || !energy->y_obs) {
+            msg = "GP likelihood needs n_obs >= 1, x_obs, y_obs";
+            return NS_EINVAL;
+        }
+        if (energy->n_obs > kGpMaxObs) { msg = "GP n_obs > 256"; return NS_EUNSUPPORTED; }
     } else if (energy->kind != NS_LIK_FUNNEL) {
         msg = "unknown likelihood kind";
         return NS_EINVAL;
@@ -570,7 +606,15 @@ static ns_status validate_run(const ns_prior *prior, const ns_energy *energy, co
         return NS_EINVAL;
     }
     if (!precision_valid(cfg->precision)) { msg = "unknown precision"; return NS_EINVAL; }
-    if (cfg->precision != NS_FP64 && energy->kind != NS_LIK_MIXTURE) {
+    if (energy->kind == NS_LIK_GP) {
+        if (cfg->precision != NS_FP64 && cfg->precision != NS_MIXED_FP32) {
+            msg = "GP likelihood: precision NS_FP64 or NS_MIXED_FP32";
+            return NS_EUNSUPPORTED;
+        }
+    } else if (cfg->precision == NS_MIXED_FP32) {
+        msg = "NS_MIXED_FP32 is implemented for the GP likelihood only";
+        return NS_EUNSUPPORTED;
+    } else if (cfg->precision != NS_FP64 && energy->kind != NS_LIK_MIXTURE) {
         msg = "mixed precision is implemented for mixtures only";
         return NS_EUNSUPPORTED;
     }
@@ -618,7 +662,8 @@ static ns_status alloc_run(ns_ctx *ctx, int r)
     // per-iteration direction buffer (k p D doubles) unless it would exceed 4 GiB; without it
     // the chains generate their directions inline
     const size_t bytes = (size_t)k * p * (D + 8) * 8;
-    if (bytes <= ((size_t)4 << 30) && !(cfg->flags & NS_FLAG_INLINE_DIRECTIONS)) {
+    if (bytes <= ((size_t)4 << 30) && !(cfg->flags & NS_FLAG_INLINE_DIRECTIONS) &&
+        rh.lik != LIK_GP) {  // GP chains draw their directions themselves
         if ((st = dalloc(ctx, &R.dirbuf, (size_t)k * p * D))) return st;
         if ((st = dalloc(ctx, &R.ubuf, (size_t)k * p * 8))) return st;
     }
@@ -691,12 +736,12 @@ extern "C" ns_status ns_init_batch(int32_t n_runs, const ns_prior *priors,
         if ((st = prepare_problem(ctx, rh, priors + r, energies + r)) != NS_OK) return bail(st);
         rh.lik = rh.P.lik_kind;
         rh.K = rh.P.K;
-        if (!mode_supported(rh.P, rh.mode)) {
+        if (rh.lik != LIK_GP && !mode_supported(rh.P, rh.mode)) {
             ctx->err = "mixed precision: n_comp too large for this dimension";
             if (n > 1) ctx->err = "run " + std::to_string(r) + ": " + ctx->err;
             return bail(NS_EUNSUPPORTED);
         }
-        rh.upw = rh.mode == NS_FP64 ? 1 : upw_template(rh.D, upw_for(rh.P));
+        rh.upw = (rh.mode == NS_FP64 || rh.lik == LIK_GP) ? 1 : upw_template(rh.D, upw_for(rh.P));
         rh.P = problem_for_mode(rh, rh.mode);
         if ((st = alloc_run(ctx, r)) != NS_OK) return bail(st);
         // group by compiled HRSS kernel
@@ -717,6 +762,7 @@ extern "C" ns_status ns_init_batch(int32_t n_runs, const ns_prior *priors,
         for (int r : G.runs) chains += ctx->runs[r].k;
         int C = (int)((chains + 255) / 256);
         C = C < 1 ? 1 : (C > kMaxChainsPerWG ? kMaxChainsPerWG : C);
+        if (G.lik == LIK_GP) C = 1;   // one chain per workgroup
         for (int r : G.runs) ctx->runs[r].R.C = C;
     }
     std::vector<DevProblem> hp(n + 1);
@@ -993,13 +1039,15 @@ extern "C" ns_status ns_eval_loglik(ns_ctx *ctx, const double *x, int32_t n, int
     if (n == 0) return NS_OK;
     if (!precision_valid(precision)) return fail(ctx, NS_EINVAL, "unknown precision");
     const RunHost &rh = ctx->runs[0];
-    if (!mode_supported(rh.P, precision))
+    const bool gp = rh.lik == LIK_GP;
+    if (gp ? (precision != NS_FP64 && precision != NS_MIXED_FP32)
+           : (precision == NS_MIXED_FP32 || !mode_supported(rh.P, precision)))
         return fail(ctx, NS_EUNSUPPORTED, "precision not supported for this problem");
     const DevProblem P = problem_for_mode(rh, precision);
-    const int upw = precision == NS_FP64 ? 1 : upw_template(rh.D, upw_for(P));
+    const int upw = (precision == NS_FP64 || gp) ? 1 : upw_template(rh.D, upw_for(P));
     const int d = rh.d, D = rh.D;
     const int np = (n + 63) & ~63;
-    const int nb = (n + kRows - 1) / kRows;
+    const int nb = gp ? n : (n + kRows - 1) / kRows;
     std::vector<double> t((size_t)D * np, 0.0);
     for (int i = 0; i < n; ++i)
         for (int a = 0; a < d; ++a) t[(size_t)a * np + i] = x[(size_t)i * d + a];
@@ -1022,7 +1070,8 @@ extern "C" ns_status ns_eval_loglik(ns_ctx *ctx, const double *x, int32_t n, int
     if (e == hipSuccess) e = hipMemcpy(dmap, mp.data(), mp.size() * sizeof(int2), hipMemcpyHostToDevice);
     if (e == hipSuccess) {
         const Launch L{ctx->dP, ctx->dR, dmap, nb, rh.m, rh.K};
-        e = launch_eval_points(L, D, rh.lik, precision, upw, dx, np, n, dout, ctx->stream);
+        e = gp ? launch_eval_gp(L, precision, dx, np, n, dout, 0, ctx->stream)
+               : launch_eval_points(L, D, rh.lik, precision, upw, dx, np, n, dout, ctx->stream);
     }
     if (e == hipSuccess)
         e = hipMemcpyAsync(out, dout, (size_t)n * 8, hipMemcpyDeviceToHost, ctx->stream);

@@ -1,0 +1,616 @@
+// GP hyperparameter marginalisation on gfx950 (Sec. 5 "Gaussian process" experiments; App.
+// "Gaussian Process Hyperparameter Marginalization"): the likelihood of a candidate
+// u = log theta, theta = (sigma_f, l_1, l_2, l_p, P, sigma_n), is the log marginal likelihood
+//   log N(y; 0, K + sigma_n^2 I),  K_ab = sigma_f^2 exp(-1/2 sum_j (a_j-b_j)^2 / l_j^2
+//                                               - 2 sum_j sin^2(pi (a_j-b_j)/P) / l_p^2)
+// over n <= 256 observations with 2-D inputs (a squared-exponential times a periodic kernel,
+// each a product over the input dimensions).
+//
+// One workgroup of 8 waves evaluates one candidate at a time.  The kernel matrix is built
+// directly in registers as 16x16 tiles of the lower triangle, in the accumulator layout of the
+// 16x16x4 MFMA (tile t lives in wave t mod 8), and factorised by a right-looking blocked
+// Cholesky: for each block column J one wave factors the diagonal tile and inverts the factor,
+// the panel tiles are multiplied by that inverse on MFMA, and every trailing tile takes its
+// rank-16 update on MFMA with operands from LDS.  The right-hand side y rides along, so the
+// forward solve z = L^{-1} y and the log-determinant come out of the same sweep:
+//   log L = -|z|^2 / 2 - sum_i log L_ii - n/2 log(2 pi).
+// A pivot that is not positive makes the factorisation fail (FP64: log L = -inf).
+//
+//  k_hrss_gp   one HRSS chain per workgroup (App. A.6), candidates evaluated one at a time
+//  k_eval_gp   one point per workgroup (initial live set, tests)
+#include "nss_internal.hpp"
+#include "nss_rng.hpp"
+#include "nss_wave.hpp"
+
+#include <math.h>
+
+namespace nss {
+
+namespace {
+
+constexpr int kGpWaves = 8;
+constexpr int kGpThreads = 64 * kGpWaves;
+constexpr int kGpMaxTiles = 136;                                      // 16 * 17 / 2
+constexpr int kGpSlots = (kGpMaxTiles + kGpWaves - 1) / kGpWaves;     // tiles per wave
+constexpr int kGpLd = 17;                                             // LDS tile row stride
+constexpr int kTile = 16 * kGpLd;
+constexpr int kGpD = 6;                                               // hyperparameters
+
+// LDS: inputs and targets (FP64), reduction slots, then the factorisation's tiles in T
+constexpr int kOffXs = 0;                                             // double [256][2]
+constexpr int kOffYs = kOffXs + 2 * kGpMaxObs * 8;                    // double [256]
+constexpr int kOffMisc = kOffYs + kGpMaxObs * 8;                      // double [16], int flag
+constexpr int kOffChain = kOffMisc + 256;                             // chain point, direction
+constexpr int kOffT = kOffChain + 128;
+template <typename T>
+constexpr int gp_lds_bytes()
+{
+    // 16 panel tiles, diagonal tile, inverse tile, right-hand side, z block
+    return kOffT + (int)sizeof(T) * (16 * kTile + 2 * kTile + kGpMaxObs + 32);
+}
+
+template <typename T> struct Mf;
+template <> struct Mf<double> {
+    typedef double v4 __attribute__((ext_vector_type(4)));
+    __device__ static v4 mma(double a, double b, v4 c)
+    {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    // accumulator row of register r in lane l (column l & 15)
+    __device__ static int row(int l, int r) { return (l >> 4) + 4 * r; }
+};
+template <> struct Mf<float> {
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    __device__ static v4 mma(float a, float b, v4 c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    __device__ static int row(int l, int r) { return 4 * (l >> 4) + r; }
+};
+
+__device__ __forceinline__ double readlane_t(double v, int lane) { return readlane_d(v, lane); }
+__device__ __forceinline__ float readlane_t(float v, int lane)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
+}
+
+// lower tile index t = I (I + 1) / 2 + K  ->  (I, K), K <= I
+__device__ __forceinline__ void tile_ik(int t, int &I, int &K)
+{
+    int i = (int)((sqrtf(8.f * (float)t + 1.f) - 1.f) * 0.5f);
+    while (i * (i + 1) / 2 > t) --i;
+    while ((i + 1) * (i + 2) / 2 <= t) ++i;
+    I = i;
+    K = t - i * (i + 1) / 2;
+}
+
+struct GpTheta {
+    double sf2, il1, il2, ilp2, iper, sn2;
+};
+
+__device__ __forceinline__ GpTheta gp_theta(const double *u)
+{
+    GpTheta h;
+    h.sf2 = exp(2.0 * u[0]);
+    h.il1 = exp(-u[1]);
+    h.il2 = exp(-u[2]);
+    h.ilp2 = exp(-2.0 * u[3]);
+    h.iper = exp(-u[4]);
+    h.sn2 = exp(2.0 * u[5]);
+    return h;
+}
+
+// Entry (row, col) of the padded covariance: identity outside the n observations, zero above
+// the diagonal (never read as data).
+template <typename T>
+__device__ __forceinline__ T gp_entry(const double *xs, int n, int row, int col, const GpTheta &h)
+{
+    if (row >= n || col >= n) return (row == col) ? T(1) : T(0);
+    if (col > row) return T(0);
+    const double d1 = xs[2 * row] - xs[2 * col], d2 = xs[2 * row + 1] - xs[2 * col + 1];
+    if constexpr (sizeof(T) == 8) {
+        const double s1 = sinpi(d1 * h.iper), s2 = sinpi(d2 * h.iper);
+        const double a1 = d1 * h.il1, a2 = d2 * h.il2;
+        double v = h.sf2 * exp(-0.5 * (a1 * a1 + a2 * a2) - 2.0 * (s1 * s1 + s2 * s2) * h.ilp2);
+        if (row == col) v += h.sn2;
+        return v;
+    } else {
+        const float s1 = sinpif((float)(d1 * h.iper)), s2 = sinpif((float)(d2 * h.iper));
+        const float a1 = (float)(d1 * h.il1), a2 = (float)(d2 * h.il2);
+        float v = (float)h.sf2 *
+                  expf(-0.5f * (a1 * a1 + a2 * a2) - 2.0f * (s1 * s1 + s2 * s2) * (float)h.ilp2);
+        if (row == col) v += (float)h.sn2;
+        return v;
+    }
+}
+
+template <typename T, typename V>
+__device__ __forceinline__ void store_tile(const V &acc, T *p, int l)
+{
+#pragma unroll
+    for (int r = 0; r < 4; ++r) p[Mf<T>::row(l, r) * kGpLd + (l & 15)] = acc[r];
+}
+
+// log N(y; 0, K_theta + sigma_n^2 I) at u = log theta with the factorisation in T.  Called by
+// every thread of the workgroup with the same u (the result is uniform); the inputs and
+// targets must be staged at kOffXs / kOffYs.  failed = a pivot was not positive.
+template <typename T>
+__device__ __forceinline__ double gp_eval(const double *u, int n, unsigned char *smem, bool &failed)
+{
+    typedef Mf<T> M;
+    typedef typename M::v4 v4;
+    const double *xs = (const double *)(smem + kOffXs);
+    const double *ys = (const double *)(smem + kOffYs);
+    double *red = (double *)(smem + kOffMisc);
+    int *flag = (int *)(red + 16);
+    T *pan = (T *)(smem + kOffT);
+    T *dg = pan + 16 * kTile;
+    T *li = dg + kTile;
+    T *yb = li + kTile;
+    T *zb = yb + kGpMaxObs;
+    T *dv = zb + 16;                 // reciprocal pivots of the diagonal tile
+    const int tid = threadIdx.x, lane0 = tid & 63, w = uniform_i(tid >> 6);
+    const int NT = (n + 15) >> 4, NTT = NT * (NT + 1) / 2;
+    const GpTheta h = gp_theta(u);
+
+    for (int i = tid; i < 16 * NT; i += kGpThreads) yb[i] = (i < n) ? (T)ys[i] : T(0);
+    if (tid == 0) *flag = 0;
+
+    int tI[kGpSlots], tK[kGpSlots];
+    v4 acc[kGpSlots];
+    {
+    const int l = lane0;
+#pragma unroll
+    for (int s = 0; s < kGpSlots; ++s) {
+        const int t = w + kGpWaves * s;
+        int I = -1, K = 0;
+        if (t < NTT) tile_ik(t, I, K);
+        tI[s] = I;
+        tK[s] = K;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[s][r] = T(0);
+    }
+    // entries of the wave's tiles: one tile per (not unrolled) iteration, then moved into its
+    // register slot by a uniform branch (keeps one copy of the transcendental code)
+#pragma unroll 1
+    for (int s = 0; s < kGpSlots; ++s) {
+        const int t = w + kGpWaves * s;
+        if (t >= NTT) break;
+        int I, K;
+        tile_ik(t, I, K);
+        const int col = 16 * K + (l & 15);
+        T e[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) e[r] = gp_entry<T>(xs, n, 16 * I + M::row(l, r), col, h);
+#pragma unroll
+        for (int S = 0; S < kGpSlots; ++S)
+            if (S == s) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) acc[S][r] = e[r];
+            }
+    }
+    }
+    __syncthreads();
+
+    double ldet = 0.0, quad = 0.0;   // wave 0, lane 0
+    for (int J = 0; J < NT; ++J) {
+        const int tJ = J * (J + 1) / 2 + J;
+        // the lane index, opaque to the compiler inside each iteration: keeps the many
+        // lane-derived masks and LDS addresses of the unrolled code below from being hoisted
+        // out of the loop, where they would hold registers across all of it
+        int l = lane0;
+        asm volatile("" : "+v"(l));
+#pragma unroll
+        for (int s = 0; s < kGpSlots; ++s)
+            if (w + kGpWaves * s == tJ) store_tile<T>(acc[s], dg, l);
+        __syncthreads();
+
+        if (w == 0) {
+            // factor the diagonal tile: lane i holds row i (every DPP row holds a copy)
+            const int i = l & 15;
+            T a[16];
+#pragma unroll
+            for (int c = 0; c < 16; ++c) a[c] = dg[i * kGpLd + c];
+            bool bad = false;
+            double prod = 1.0;
+#pragma unroll
+            for (int jj = 0; jj < 16; ++jj) {
+                const T piv = readlane_t(a[jj], jj);
+                const bool ok = piv > T(0);
+                bad = bad || !ok;
+                const T ljj = ok ? (T)sqrt(piv) : T(1);
+                const T inv = T(1) / ljj;
+                if (l == 0) dv[jj] = inv;
+                prod *= (double)ljj;
+                a[jj] = (i > jj) ? a[jj] * inv : ((i == jj) ? ljj : a[jj]);
+#pragma unroll
+                for (int c = jj + 1; c < 16; ++c) {
+                    const T lcj = readlane_t(a[jj], c);
+                    if (i > jj) a[c] -= a[jj] * lcj;
+                }
+            }
+            ldet += log(prod);
+            if (l < 16) {
+#pragma unroll
+                for (int c = 0; c < 16; ++c) dg[i * kGpLd + c] = a[c];
+            }
+            if (l == 0 && bad) *flag = 1;
+            wave_sync();
+            // inverse of the factor, one column per lane (lanes 0..15): x = L^{-1} e_c by
+            // forward substitution; L's rows are read from LDS (same address in every lane),
+            // the column is kept in LDS (each lane reads back only what it wrote)
+            const int c = l & 15;
+            if (l < 16) {
+#pragma unroll 1
+                for (int r = 0; r < 16; ++r) {
+                    T sacc = (r == c) ? T(1) : T(0);
+                    for (int t = c; t < r; ++t) sacc -= dg[r * kGpLd + t] * li[t * kGpLd + c];
+                    li[r * kGpLd + c] = (r < c) ? T(0) : sacc * dv[r];
+                }
+            }
+            wave_sync();
+            // z_J = L_JJ^{-1} y_J: lane r sums row r of the inverse against y_J
+            if (l < 16) {
+                T zr = T(0);
+#pragma unroll
+                for (int t = 0; t < 16; ++t) zr += li[l * kGpLd + t] * yb[16 * J + t];
+                zb[l] = zr;
+                const double zd = (double)zr;
+                double q2 = zd * zd;
+                q2 += __shfl_xor(q2, 1, 64);
+                q2 += __shfl_xor(q2, 2, 64);
+                q2 += __shfl_xor(q2, 4, 64);
+                q2 += __shfl_xor(q2, 8, 64);
+                if (l == 0) quad += q2;
+            }
+        }
+        __syncthreads();
+
+        // panel: L_IJ = A_IJ L_JJ^{-T}, and y_I -= L_IJ z_J
+#pragma unroll
+        for (int s = 0; s < kGpSlots; ++s) {
+            if (tK[s] == J && tI[s] > J) {
+                T *pI = pan + tI[s] * kTile;
+                store_tile<T>(acc[s], pI, l);
+                wave_sync();
+                v4 o;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) o[r] = T(0);
+#pragma unroll
+                for (int ks = 0; ks < 4; ++ks) {
+                    const int ko = (l & 15) * kGpLd + 4 * ks + (l >> 4);
+                    o = M::mma(pI[ko], li[ko], o);
+                }
+                wave_sync();
+                store_tile<T>(o, pI, l);
+                acc[s] = o;
+                const T zc = zb[l & 15];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const T sr = row_sum16(o[r] * zc);
+                    if ((l & 15) == 0) yb[16 * tI[s] + M::row(l, r)] -= sr;
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        __syncthreads();
+
+        // trailing update: A_IK -= L_IJ L_KJ^T for J < K <= I
+#pragma unroll
+        for (int s = 0; s < kGpSlots; ++s) {
+            if (tK[s] > J) {
+                const T *pI = pan + tI[s] * kTile, *pK = pan + tK[s] * kTile;
+#pragma unroll
+                for (int ks = 0; ks < 4; ++ks) {
+                    const int ko = (l & 15) * kGpLd + 4 * ks + (l >> 4);
+                    acc[s] = M::mma(-pI[ko], pK[ko], acc[s]);
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+    if (tid == 0) {
+        red[0] = ldet;
+        red[1] = quad;
+    }
+    __syncthreads();
+    const double ld = red[0], q = red[1];
+    failed = (*flag != 0);
+    __syncthreads();   // the LDS slots are reused by the next evaluation
+    return -0.5 * q - ld - 0.5 * (double)n * LOG_2PI;
+}
+
+__device__ __forceinline__ void gp_stage(const DevProblem &P, unsigned char *smem)
+{
+    double *xs = (double *)(smem + kOffXs);
+    double *ys = (double *)(smem + kOffYs);
+    for (int i = threadIdx.x; i < 2 * P.gp_n; i += blockDim.x) xs[i] = P.gp_x[i];
+    for (int i = threadIdx.x; i < P.gp_n; i += blockDim.x) ys[i] = P.gp_y[i];
+}
+
+// Mixed precision: the FP32 estimate decides unless it lies within this band of L*; then (and
+// when the FP32 factorisation breaks down) the FP64 value decides.  The FP32 error grows with
+// the signal-to-noise ratio s = (sigma_f^2 + sigma_n^2) / sigma_n^2 (the noise floor bounds
+// the smallest eigenvalue of the covariance, its trace the largest) and with sqrt(n).
+__device__ __forceinline__ bool gp_near(double L32, double Lstar, const DevProblem &P,
+                                        const double *u)
+{
+    const double sf2 = exp(2.0 * u[0]), sn2 = exp(2.0 * u[5]);
+    const double snr = (sf2 + sn2) / sn2;
+    const double band = (double)P.guard_rel * fabs(L32) + (double)P.guard_abs +
+                        (double)P.guard_kappa * snr * sqrt((double)P.gp_n);
+    return !(fabs(L32 - Lstar) > band);
+}
+
+}  // namespace
+
+template <int MODE>
+__global__ __launch_bounds__(kGpThreads) void k_eval_gp(Launch Lc, const double *X, int ld, int n,
+                                                        double *out, int from_run)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int2 bm = Lc.map[blockIdx.x];
+    const DevProblem P = Lc.P[bm.x];
+    const DevRun R = Lc.R[bm.x];
+    unsigned long long *nonfinite = nullptr;
+    if (from_run) { X = R.X; ld = R.m_pad; n = R.m; out = R.logL; nonfinite = R.ctr + 5; }
+    const int i = bm.y;
+    if (i >= n) return;
+    gp_stage(P, smem);
+    double u[kGpD];
+#pragma unroll
+    for (int a = 0; a < kGpD; ++a) u[a] = X[(size_t)a * ld + i];
+    __syncthreads();
+    bool failed = false;
+    double L;
+    if constexpr (MODE == MODE_FP64) L = gp_eval<double>(u, P.gp_n, smem, failed);
+    else L = gp_eval<float>(u, P.gp_n, smem, failed);
+    if (threadIdx.x == 0) {
+        unsigned long long nf = 0;
+        out[i] = failed ? -INFINITY : sanitize(L, nf);
+        if (nf && nonfinite) atomicAdd(nonfinite, nf);
+    }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kGpThreads) void k_hrss_gp(Launch Lc)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int2 bm = Lc.map[blockIdx.x];
+    const DevProblem P = Lc.P[bm.x];
+    const DevRun R = Lc.R[bm.x];
+    if (R.iscal[0] || R.iscal[2] <= 0) return;
+    const int j = bm.y;
+    if (j >= R.k) return;
+    const int tid = threadIdx.x, n = P.gp_n;
+    double *sx0 = (double *)(smem + kOffChain);   // current point of the chain
+    double *sv = sx0 + 8;                         // direction of the current step
+    gp_stage(P, smem);
+    const double Lstar = R.scal[0];
+    const int t0 = R.iscal[1], nsurv = R.iscal[2];
+    const uint32_t it = (uint32_t)R.iscal[3] + 1u;
+    const double width = R.width;
+    const int p = R.p, cap_out = R.stepout_cap, cap_sh = R.shrink_cap;
+    const bool box = (P.prior_kind == PRIOR_BOX);
+
+    double ur, unused;
+    draw2(R.key0, R.key1, PUR_RESAMPLE, (uint32_t)j, it, 0u, 0u, ur, unused);
+    int qi = (int)floor(ur * (double)nsurv);
+    if (qi > nsurv - 1) qi = nsurv - 1;
+    const int parent = R.perm[t0 + qi];
+    if (tid == 0) R.parents[j] = parent;
+    if (tid < kGpD) sx0[tid] = R.X[(size_t)tid * R.m_pad + parent];
+    double logL0 = R.logL[parent];
+    bool exact0 = true;
+    // counters (every thread keeps identical copies; thread 0 publishes them)
+    unsigned long long c_evals = 0, c_tests = 0, c_prej = 0, c_outcap = 0, c_shcap = 0,
+                       c_nonfin = 0, c_rc = 0, c_viol = 0;
+    __syncthreads();
+
+    // log prior density (Gaussian prior; the box prior is uniform on its support)
+    auto logprior = [&](const double *x) -> double {
+        double lp = 0.0;
+#pragma unroll
+        for (int a = 0; a < kGpD; ++a) {
+            const double zt = (x[a] - P.pa[a]) / P.pb[a];
+            lp += -0.5 * zt * zt;
+        }
+        return lp + P.logprior_norm;
+    };
+
+    // The chain as one loop with a single evaluation site (the evaluator is large and fully
+    // inlined): each pass picks the next test of the current phase, evaluates it and advances.
+    enum { PH_NEW = 0, PH_LEFT = 1, PH_RIGHT = 2, PH_SHRINK = 3, PH_FINAL = 4 };
+    int phase = PH_NEW, st = 0, nl = 0, nr = 0, ns = 0;
+    double tL = 0.0, tR = 0.0, logy = -INFINITY;
+    for (;;) {
+        if (phase == PH_NEW) {
+            if (st == p) {
+                if (MODE == MODE_FP64 || exact0) break;
+                phase = PH_FINAL;   // stored log-likelihoods are FP64
+                __syncthreads();    // the last accepted point is in sx0 for every wave
+            } else {
+                __syncthreads();   // every thread is done with the previous direction
+                if (tid == 0) {
+                    // direction z ~ N(0, I), v = Lsig z / |z|
+                    double z[kGpD];
+#pragma unroll
+                    for (int q = 0; q < kGpD / 2; ++q) {
+                        double ua, ub;
+                        draw2(R.key0, R.key1, PUR_DIR, (uint32_t)j, it, (uint32_t)st,
+                              (uint32_t)q, ua, ub);
+                        box_muller(ua, ub, z[2 * q], z[2 * q + 1]);
+                    }
+                    double nz = 0.0;
+#pragma unroll
+                    for (int a = 0; a < kGpD; ++a) nz += z[a] * z[a];
+                    nz = sqrt(nz);
+                    for (int a = 0; a < kGpD; ++a) {
+                        double s2 = 0.0;
+                        for (int b = 0; b <= a; ++b) s2 += R.Lsig[a * P.D + b] * z[b];
+                        sv[a] = s2 / nz;
+                    }
+                }
+                __syncthreads();
+                double U, uh;
+                draw2(R.key0, R.key1, PUR_STEP, (uint32_t)j, it, (uint32_t)st, 0u, U, uh);
+                logy = box ? -INFINITY : logprior(sx0) + log(uh);
+                tL = -width * U;
+                tR = tL + width;
+                nl = nr = ns = 0;
+                phase = PH_LEFT;
+                continue;
+            }
+        }
+        double t = 0.0;
+        if (phase == PH_LEFT) {
+            if (nl >= cap_out) { ++c_outcap; phase = PH_RIGHT; continue; }
+            t = tL;
+        } else if (phase == PH_RIGHT) {
+            if (nr >= cap_out) { ++c_outcap; phase = PH_SHRINK; continue; }
+            t = tR;
+        } else if (phase == PH_SHRINK) {
+            if (ns >= cap_sh) {
+                // null move
+                ++c_shcap;
+                if (R.trace && tid == 0) {
+                    int *tr = R.trace + ((size_t)j * p + st) * 4;
+                    tr[0] = nl; tr[1] = nr; tr[2] = ns; tr[3] = 0;
+                }
+                ++st;
+                phase = PH_NEW;
+                continue;
+            }
+            double us, un2;
+            draw2(R.key0, R.key1, PUR_SHRINK, (uint32_t)j, it, (uint32_t)st, (uint32_t)ns, us, un2);
+            t = tL + us * (tR - tL);
+        }
+        double y[kGpD];
+#pragma unroll
+        for (int a = 0; a < kGpD; ++a) y[a] = (phase == PH_FINAL) ? sx0[a] : sx0[a] + t * sv[a];
+        bool in = true;
+        if (phase != PH_FINAL) {
+            ++c_tests;
+            if (box) {
+#pragma unroll
+                for (int a = 0; a < kGpD; ++a) in = in && (y[a] >= P.pa[a] && y[a] <= P.pb[a]);
+            } else {
+                in = logprior(y) > logy;
+            }
+        }
+        bool r = false, exact = true;
+        double L = -INFINITY;
+        if (!in) {
+            ++c_prej;
+        } else {
+            // the single evaluation site
+            bool failed = false;
+            if constexpr (MODE == MODE_FP64) {
+                L = gp_eval<double>(y, n, smem, failed);
+            } else {
+                bool need64 = (phase == PH_FINAL);
+                if (!need64) {
+                    L = gp_eval<float>(y, n, smem, failed);
+                    need64 = failed || !(L == L) || gp_near(L, Lstar, P, y);
+                    if (need64) ++c_rc; else exact = false;
+                }
+                if (need64) L = gp_eval<double>(y, n, smem, failed);
+            }
+            if (failed) L = -INFINITY;
+            if (phase == PH_FINAL) {
+                logL0 = L;
+                if (!(logL0 > Lstar)) ++c_viol;
+                break;
+            }
+            ++c_evals;
+            L = sanitize(L, c_nonfin);
+            r = L > Lstar;
+        }
+        if (phase == PH_LEFT) {
+            if (r) { tL -= width; ++nl; } else phase = PH_RIGHT;
+        } else if (phase == PH_RIGHT) {
+            if (r) { tR += width; ++nr; } else phase = PH_SHRINK;
+        } else {
+            ++ns;
+            if (r) {
+                // every thread has passed the evaluation's barriers: sx0 is free to update
+                if (tid < kGpD) sx0[tid] = y[tid];
+                logL0 = L;
+                exact0 = exact;
+                if (R.trace && tid == 0) {
+                    int *tr = R.trace + ((size_t)j * p + st) * 4;
+                    tr[0] = nl; tr[1] = nr; tr[2] = ns; tr[3] = 1;
+                }
+                ++st;
+                phase = PH_NEW;
+            } else if (t < 0.0) {
+                tL = t;
+            } else {
+                tR = t;
+            }
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        const int slot = R.perm[j];
+#pragma unroll
+        for (int a = 0; a < kGpD; ++a) R.X[(size_t)a * R.m_pad + slot] = sx0[a];
+        R.logL[slot] = logL0;
+        atomicAdd(&R.ctr[0], c_evals);
+        atomicAdd(&R.ctr[1], c_tests);
+        atomicAdd(&R.ctr[2], c_prej);
+        atomicAdd(&R.ctr[3], c_outcap);
+        atomicAdd(&R.ctr[4], c_shcap);
+        atomicAdd(&R.ctr[5], c_nonfin);
+        atomicAdd(&R.ctr[6], c_rc);
+        atomicAdd(&R.ctr[7], c_viol);
+    }
+}
+
+template <typename F>
+static hipError_t gp_lds(F *f, size_t bytes)
+{
+    return hipFuncSetAttribute((const void *)f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)bytes);
+}
+
+hipError_t launch_hrss_gp(const Launch &L, int mode, hipStream_t s)
+{
+    if (L.nblocks <= 0) return hipSuccess;
+    const size_t lds = (size_t)gp_lds_bytes<double>();
+    if (mode == MODE_FP64) {
+        hipError_t e = gp_lds(k_hrss_gp<MODE_FP64>, lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_hrss_gp<MODE_FP64>, dim3(L.nblocks), dim3(kGpThreads), lds, s, L);
+    } else if (mode == MODE_FP32) {
+        hipError_t e = gp_lds(k_hrss_gp<MODE_FP32>, lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_hrss_gp<MODE_FP32>, dim3(L.nblocks), dim3(kGpThreads), lds, s, L);
+    } else {
+        return hipErrorNotSupported;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_eval_gp(const Launch &L, int mode, const double *X, int ld, int n, double *out,
+                          int from_run, hipStream_t s)
+{
+    if (L.nblocks <= 0) return hipSuccess;
+    const size_t lds = (size_t)gp_lds_bytes<double>();
+    if (mode == MODE_FP64) {
+        hipError_t e = gp_lds(k_eval_gp<MODE_FP64>, lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_eval_gp<MODE_FP64>, dim3(L.nblocks), dim3(kGpThreads), lds, s, L, X,
+                           ld, n, out, from_run);
+    } else if (mode == MODE_FP32) {
+        hipError_t e = gp_lds(k_eval_gp<MODE_FP32>, lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_eval_gp<MODE_FP32>, dim3(L.nblocks), dim3(kGpThreads), lds, s, L, X,
+                           ld, n, out, from_run);
+    } else {
+        return hipErrorNotSupported;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace nss

@@ -14,9 +14,11 @@ constexpr int kSelectThreads = 1024;
 constexpr int kMaxLive = 8192;
 
 // likelihood arithmetic inside the chains (values equal the C ABI's ns_precision)
-enum Mode { MODE_FP64 = 0, MODE_BF16 = 1, MODE_FP16 = 2, MODE_BF16X3 = 3, MODE_FP16X3 = 4 };
+enum Mode { MODE_FP64 = 0, MODE_BF16 = 1, MODE_FP16 = 2, MODE_BF16X3 = 3, MODE_FP16X3 = 4,
+            MODE_FP32 = 5 };
 enum PriorKind { PRIOR_BOX = 0, PRIOR_GAUSS = 1 };
-enum LikKind { LIK_MIXTURE = 1, LIK_FUNNEL = 2 };
+enum LikKind { LIK_MIXTURE = 1, LIK_FUNNEL = 2, LIK_GP = 3 };
+constexpr int kGpMaxObs = 256;   // GP observations per problem
 
 // Problem, resident on the device for the lifetime of a context.
 struct DevProblem {
@@ -37,7 +39,11 @@ struct DevProblem {
     const float *cst32;
     float cmax32;          // max_c cst32[c]
     float guard_rel;       // mixed precision guard band: rel * max(0, cmax - L) + abs
-    float guard_abs;
+    float guard_abs;       //   (GP: rel |L| + abs + kappa_coef kappa n / 256)
+    float guard_kappa;
+    int gp_n;              // GP: observations
+    const double *gp_x;    // GP: [n][2] inputs
+    const double *gp_y;    // GP: [n] targets
 };
 
 // Run state on the device.
@@ -96,6 +102,11 @@ hipError_t launch_cov(const Launch &cov, const Launch &one, int D, hipStream_t s
 hipError_t launch_dirs(const Launch &L, int D, hipStream_t s);
 hipError_t launch_hrss(const Launch &L, int D, int lik, int mode, int upw, hipStream_t s);
 hipError_t launch_logz(const Launch &L, hipStream_t s);
+// GP likelihood (nss_gp.hip): chains one per workgroup (map: (run, chain)); evaluation one
+// point per workgroup (map: (run, point)), from_run = 1 evaluates the run's live set
+hipError_t launch_hrss_gp(const Launch &L, int mode, hipStream_t s);
+hipError_t launch_eval_gp(const Launch &L, int mode, const double *X, int ld, int n, double *out,
+                          int from_run, hipStream_t s);
 int mode_supported(const DevProblem &P, int mode);
 int upw_for(const DevProblem &P);
 int upw_template(int D, int upw);         // the compiled UPW that covers upw (0 if none)

@@ -11,116 +11,11 @@
 //  k_logz        final live-set contribution to the evidence (Sec. 2.1)
 #include "nss_internal.hpp"
 #include "nss_rng.hpp"
+#include "nss_wave.hpp"
 
 #include <math.h>
 
 namespace nss {
-
-typedef double d4 __attribute__((ext_vector_type(4)));
-typedef float f4 __attribute__((ext_vector_type(4)));
-typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
-typedef _Float16 h8 __attribute__((ext_vector_type(8)));
-
-#define LOG_2PI 1.8378770664093454836
-
-// ------------------------------------------------------------------------------------------
-// wave helpers
-// ------------------------------------------------------------------------------------------
-__device__ __forceinline__ double wave_sum(double v)
-{
-#pragma unroll
-    for (int o = 32; o; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-__device__ __forceinline__ double wave_max(double v)
-{
-#pragma unroll
-    for (int o = 32; o; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-    return v;
-}
-__device__ __forceinline__ float wave_sumf(float v)
-{
-#pragma unroll
-    for (int o = 32; o; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-__device__ __forceinline__ float wave_maxf(float v)
-{
-#pragma unroll
-    for (int o = 32; o; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
-    return v;
-}
-// Make this wave's LDS writes visible to its own other lanes.
-__device__ __forceinline__ void wave_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-// Reductions over the 16 lanes of a DPP row with VALU data movement (quad swaps, half-row and
-// row mirrors); every lane of the row ends with the same result.
-template <int CTRL>
-__device__ __forceinline__ float dppf(float v)
-{
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
-                                                                 CTRL, 0xF, 0xF, false));
-}
-template <int CTRL>
-__device__ __forceinline__ double dppd(double v)
-{
-    int2 p = __builtin_bit_cast(int2, v);
-    p.x = __builtin_amdgcn_update_dpp(0, p.x, CTRL, 0xF, 0xF, false);
-    p.y = __builtin_amdgcn_update_dpp(0, p.y, CTRL, 0xF, 0xF, false);
-    return __builtin_bit_cast(double, p);
-}
-#define DPP_XOR1 0xB1   /* quad_perm [1,0,3,2] */
-#define DPP_XOR2 0x4E   /* quad_perm [2,3,0,1] */
-#define DPP_HMIR 0x141  /* row_half_mirror */
-#define DPP_RMIR 0x140  /* row_mirror */
-__device__ __forceinline__ float row_sum16(float v)
-{
-    v += dppf<DPP_XOR1>(v); v += dppf<DPP_XOR2>(v); v += dppf<DPP_HMIR>(v); v += dppf<DPP_RMIR>(v);
-    return v;
-}
-__device__ __forceinline__ float row_max16(float v)
-{
-    v = fmaxf(v, dppf<DPP_XOR1>(v)); v = fmaxf(v, dppf<DPP_XOR2>(v));
-    v = fmaxf(v, dppf<DPP_HMIR>(v)); v = fmaxf(v, dppf<DPP_RMIR>(v));
-    return v;
-}
-__device__ __forceinline__ double row_sum16(double v)
-{
-    v += dppd<DPP_XOR1>(v); v += dppd<DPP_XOR2>(v); v += dppd<DPP_HMIR>(v); v += dppd<DPP_RMIR>(v);
-    return v;
-}
-__device__ __forceinline__ double row_max16(double v)
-{
-    v = fmax(v, dppd<DPP_XOR1>(v)); v = fmax(v, dppd<DPP_XOR2>(v));
-    v = fmax(v, dppd<DPP_HMIR>(v)); v = fmax(v, dppd<DPP_RMIR>(v));
-    return v;
-}
-__device__ __forceinline__ double readlane_d(double v, int lane)
-{
-    int2 p = __builtin_bit_cast(int2, v);
-    p.x = __builtin_amdgcn_readlane(p.x, lane);
-    p.y = __builtin_amdgcn_readlane(p.y, lane);
-    return __builtin_bit_cast(double, p);
-}
-__device__ __forceinline__ int uniform_i(int v) { return __builtin_amdgcn_readfirstlane(v); }
-__device__ __forceinline__ double uniform_d(double v) { return readlane_d(v, 0); }
-
-// Sum over the wave: row sums, then the four row results combined (uniform result).
-__device__ __forceinline__ double wave_sum_fast(double v)
-{
-    v = row_sum16(v);
-    return (readlane_d(v, 0) + readlane_d(v, 16)) + (readlane_d(v, 32) + readlane_d(v, 48));
-}
-
-__device__ __forceinline__ double sanitize(double L, unsigned long long &nonfinite)
-{
-    if (L != L || L == INFINITY) { ++nonfinite; return -INFINITY; }
-    return L;
-}
 
 // ------------------------------------------------------------------------------------------
 // LDS layout of the chain / evaluation workgroups (byte offsets; identical on host)
@@ -1203,15 +1098,19 @@ __global__ __launch_bounds__(256) void k_hrss(Launch Lc)
 
     // next step's direction and uniforms, prefetched into registers one step ahead (the
     // uniforms sit in lanes 0..7: U, uh, then shrink uniforms 0..5)
-    double pv[NA], pu = 0.0, cu = 0.0;
+    double pv[NA], pu[kStepU], cu[kStepU];
 #pragma unroll
     for (int i = 0; i < NA; ++i) pv[i] = 0.0;
+#pragma unroll
+    for (int q = 0; q < kStepU; ++q) { pu[q] = 0.0; cu[q] = 0.0; }
     auto prefetch_dir = [&](int st) {
         if (has_chain && st < p) {
             const double *srcv = R.dirbuf + ((size_t)j * p + st) * D;
 #pragma unroll
             for (int i = 0; i < NA; ++i) if (l + 64 * i < D) pv[i] = srcv[l + 64 * i];
-            if (l < kStepU) pu = R.ubuf[((size_t)j * p + st) * kStepU + l];
+            const double *su = R.ubuf + ((size_t)j * p + st) * kStepU;
+#pragma unroll
+            for (int q = 0; q < kStepU; ++q) pu[q] = su[q];
         }
     };
     if (pre) prefetch_dir(0);
@@ -1272,7 +1171,8 @@ __global__ __launch_bounds__(256) void k_hrss(Launch Lc)
                 if (pre) {
 #pragma unroll
                     for (int i = 0; i < NA; ++i) vr[i] = pv[i];
-                    cu = pu;
+#pragma unroll
+                    for (int q = 0; q < kStepU; ++q) cu[q] = pu[q];
                     prefetch_dir(step + 1);
                 } else {
                     // direction z ~ N(0, I_d), v = L z / |z|, drawn by the chain itself
@@ -1304,8 +1204,8 @@ __global__ __launch_bounds__(256) void k_hrss(Launch Lc)
                 }
                 double uh;
                 if (pre) {
-                    tL = readlane_d(cu, 0);
-                    uh = readlane_d(cu, 1);
+                    tL = cu[0];
+                    uh = cu[1];
                 } else {
                     double U;
                     draw2(R.key0, R.key1, PUR_STEP, (uint32_t)j, it, (uint32_t)step, 0u, U, uh);
@@ -1337,9 +1237,14 @@ __global__ __launch_bounds__(256) void k_hrss(Launch Lc)
 #pragma unroll
                 for (int sl = 0; sl < kSlots; ++sl) {
                     if (sl >= ns_plan && sn < cap_sh) {
-                        const double t = (dflt && sn < kStepShrinkU)
-                                             ? readlane_d(cu, 2 + sn)
-                                             : sL + shrink_u(sn) * (sR - sL);
+                        double t;
+                        if (dflt && sn < kStepShrinkU) {
+                            t = cu[2];
+#pragma unroll
+                            for (int q = 1; q < kStepShrinkU; ++q) if (sn == q) t = cu[2 + q];
+                        } else {
+                            t = sL + shrink_u(sn) * (sR - sL);
+                        }
                         kind[sl] = S_SHRINK;
                         tv[sl] = t;
                         ++sn;
@@ -1422,7 +1327,6 @@ __global__ __launch_bounds__(256) void k_hrss(Launch Lc)
                     double L;
                     if constexpr (MODE == MODE_FP64) L = T.L[r];
                     else { rc = T.rc[r]; L = rc ? T.L[r] : (double)T.L32[r]; }
-                    L = uniform_d(L);
                     const bool nf = (L != L) || L == INFINITY;
                     if (nf) L = -INFINITY;
                     Lv[sl] = L;

@@ -20,14 +20,16 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "nss.h")
 
 NS_OK, NS_DONE, NS_EINVAL, NS_ENOMEM, NS_EDEVICE, NS_ESTATE, NS_EUNSUPPORTED = 0, 1, -1, -2, -3, -4, -5
 NS_PRIOR_BOX, NS_PRIOR_GAUSS_DIAG = 0, 1
-NS_LIK_MIXTURE, NS_LIK_FUNNEL = 1, 2
-NS_FP64, NS_MIXED_BF16, NS_MIXED_FP16, NS_MIXED_BF16X3, NS_MIXED_FP16X3 = 0, 1, 2, 3, 4
+NS_LIK_MIXTURE, NS_LIK_FUNNEL, NS_LIK_GP = 1, 2, 3
+NS_FP64, NS_MIXED_BF16, NS_MIXED_FP16, NS_MIXED_BF16X3, NS_MIXED_FP16X3, NS_MIXED_FP32 = 0, 1, 2, 3, 4, 5
 NS_FLAG_TRACE, NS_FLAG_TIMING, NS_FLAG_INLINE_DIRECTIONS = 1, 2, 4
 PRECISIONS = {"fp64": NS_FP64, "bf16": NS_MIXED_BF16, "fp16": NS_MIXED_FP16,
-              "bf16x3": NS_MIXED_BF16X3, "fp16x3": NS_MIXED_FP16X3}
+              "bf16x3": NS_MIXED_BF16X3, "fp16x3": NS_MIXED_FP16X3, "fp32": NS_MIXED_FP32}
 # guard band of each mixed mode: (rel, abs) as set by the library
 GUARD = {"bf16": (0.025, 2e-3), "fp16": (0.0032, 2e-3), "bf16x3": (4e-5, 2e-4),
          "fp16x3": (6e-6, 2e-4)}
+# GP FP32 mode: rel |L| + abs + c * s * sqrt(n), s = (sf^2 + sn^2) / sn^2
+GP_GUARD = (5e-5, 1.25, 5.2e-2)
 
 _d = C.POINTER(C.c_double)
 _i32 = C.POINTER(C.c_int32)
@@ -39,7 +41,7 @@ class ns_prior(C.Structure):
 
 class ns_energy(C.Structure):
     _fields_ = [("kind", C.c_int32), ("d", C.c_int32), ("n_comp", C.c_int32), ("logw", _d),
-                ("mean", _d), ("cov", _d)]
+                ("mean", _d), ("cov", _d), ("n_obs", C.c_int32), ("x_obs", _d), ("y_obs", _d)]
 
 
 class ns_config(C.Structure):
@@ -252,6 +254,11 @@ def make_structs(prob: dict):
         en = ns_energy(NS_LIK_MIXTURE, d, K, _ptr(lw), _ptr(mu), _ptr(cov))
     elif prob["lik"] == "funnel":
         en = ns_energy(NS_LIK_FUNNEL, d, 0, None, None, None)
+    elif prob["lik"] == "gp":
+        gx = np.ascontiguousarray(prob["gp_x"], np.float64)
+        gy = np.ascontiguousarray(prob["gp_y"], np.float64)
+        keep += [gx, gy]
+        en = ns_energy(NS_LIK_GP, d, 0, None, None, None, len(gy), _ptr(gx), _ptr(gy))
     else:
         raise ValueError(prob["lik"])
     return pr, en, keep

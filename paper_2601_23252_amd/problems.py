@@ -22,6 +22,11 @@ these shapes, see the design notes):
               [-10,10]^d; m=2000, k=1000, p=5d
     gaussian20  prior N(0, I), likelihood N(x; 1, 0.01 I), d=20 (the paper's overhead example)
     funnel    prior U[-20,20]^d, Neal's funnel likelihood
+    config4   GP hyperparameter marginalisation: 256 inputs ~ U[0,10]^2, targets drawn from
+              a GP with a squared-exponential x periodic kernel (product over the two input
+              dimensions) plus N(0, 0.1^2) noise; 6 hyperparameters
+              theta = (sigma_f, l_1, l_2, l_p, P, sigma_n), log-uniform on [1e-2, 1e2]
+              (a box prior on u = log theta); m=1000, k=500, p=5d=30
     config5   batched serving: 256 independent runs, d uniform on {8, 16, ..., 128}; even runs
               a correlated Gaussian drawn as config2 (prior N(0, 4 I)), odd runs the funnel
               under U[-20,20]^d; m=500, k=250, p=5d each
@@ -103,6 +108,31 @@ def funnel(d: int, box: float = 20.0, m: int = 500, k: int = 250, p=None):
                 p=5 * d if p is None else p)
 
 
+GP_THETA_TRUE = (1.0, 2.0, 3.0, 1.0, 2.5, 0.1)
+
+
+def gp_problem(seed: int = 1004, n: int = 256, m: int = 1000, k: int = 500, p=None,
+               theta=GP_THETA_TRUE, lo=1e-2, hi=1e2):
+    """GP regression data drawn from the model at theta (the kernel matrix is built with
+    scikit-learn's kernels and factorised with numpy, so this module computes none of it
+    itself)."""
+    from sklearn.gaussian_process.kernels import RBF, ExpSineSquared
+    rng = np.random.default_rng(seed)
+    X = rng.uniform(0.0, 10.0, (n, 2))
+    sf, l1, l2, lp, per, sn = theta
+    K = (sf ** 2 * RBF([l1, l2])(X) * ExpSineSquared(lp, per)(X[:, :1])
+         * ExpSineSquared(lp, per)(X[:, 1:]) + sn ** 2 * np.eye(n))
+    y = np.linalg.cholesky(K) @ rng.standard_normal(n)
+    d = 6
+    return dict(name=f"gp_n{n}", d=d, prior="box", prior_a=np.full(d, np.log(lo)),
+                prior_b=np.full(d, np.log(hi)), lik="gp", K=0, gp_x=X, gp_y=y, m=m, k=k,
+                p=5 * d if p is None else p)
+
+
+def config4(seed: int = 1004):
+    return gp_problem(seed)
+
+
 def config5(seed: int = 1005, n_runs: int = 256, m: int = 500, k: int = 250):
     """List of n_runs problem dicts of uneven dimension (see the module docstring)."""
     rng = np.random.default_rng(seed)
@@ -121,4 +151,4 @@ def config5(seed: int = 1005, n_runs: int = 256, m: int = 500, k: int = 250):
     return out
 
 
-CONFIGS = {"config1": config1, "config2": config2, "config3": config3}
+CONFIGS = {"config1": config1, "config2": config2, "config3": config3, "config4": config4}

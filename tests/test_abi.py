@@ -70,3 +70,32 @@ def test_null_context_calls(N):
     assert N.ns_logz(None)[0] == N.NS_EINVAL
     assert N.ns_reset(None, 0) == N.NS_EINVAL
     N.ns_free(None)
+
+
+def test_invalid_gp_and_batch_arguments(N):
+    from paper_2601_23252_amd import problems as G
+    cfg = N.ns_config_default()
+    cfg.n_live, cfg.k, cfg.chain_len = 50, 10, 5
+    gp = G.gp_problem(4, n=20)
+    pr, en, keep = _structs(N, gp)
+    en.n_obs = 300
+    assert N.ns_init(pr, en, cfg, None)[0] == N.NS_EUNSUPPORTED    # n_obs > 256
+    pr, en, keep = _structs(N, gp)
+    en.n_obs = 0
+    assert N.ns_init(pr, en, cfg, None)[0] == N.NS_EINVAL
+    pr, en, keep = _structs(N, gp)
+    cfg.precision = N.NS_MIXED_BF16X3
+    assert N.ns_init(pr, en, cfg, None)[0] == N.NS_EUNSUPPORTED    # GP: FP64 or FP32
+    pr, en, keep = _structs(N, G.config1())
+    cfg.precision = N.NS_MIXED_FP32
+    assert N.ns_init(pr, en, cfg, None)[0] == N.NS_EUNSUPPORTED    # FP32: GP only
+    cfg.precision = N.NS_FP64
+    # batch: every run is validated and the failing run is named
+    pr2, en2, keep2 = _structs(N, G.funnel(8))
+    bad = N.ns_config_default()
+    bad.n_live, bad.k, bad.chain_len = 50, 50, 5                   # k > n_live - 1
+    st, ctx = N.ns_init_batch([pr, pr2], [en, en2], [cfg, bad], None)
+    assert st == N.NS_EINVAL and ctx is None
+    assert "run 1" in N.ns_last_error(None)
+    assert N.ns_init_batch([], [], [], None)[0] == N.NS_EINVAL
+    assert N.ns_num_runs(None) == 0

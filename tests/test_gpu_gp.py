@@ -1,0 +1,144 @@
+"""GP hyperparameter marginalisation on the GPU against the FP64 oracle, through the C ABI.
+
+Bars (both sides compute in FP64; they differ in the order of the Cholesky sums, in sinpi
+against sin(pi x) and in the merged exponent, each a few ulp per entry; a perturbation dK of
+the covariance moves log L by about |tr(K^-1 dK)| + |z^T dK z| / 2, which grows with the
+condition number, bounded here by kappa = n (sigma_f^2 + sigma_n^2) / sigma_n^2):
+  - likelihood values: |d log L| <= 1e-9 |log L| + 1e-14 kappa, and the same set of
+    breakdowns (-inf);
+  - per-iteration state on identical Philox streams: identical parents, deleted order,
+    evaluation counts and per-step decision traces; points and logL within 1e-9 relative;
+  - FP32 mode: identical trajectories to FP64 (decisions near L* are taken in FP64).
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def N():
+    from paper_2601_23252_amd import nss
+    nss.load()
+    return nss
+
+
+@pytest.fixture(scope="module")
+def O(oracle_lib):
+    return oracle_lib
+
+
+def _kappa(U, n):
+    th = np.exp(U)
+    return n * (th[:, 0] ** 2 + th[:, 5] ** 2) / th[:, 5] ** 2
+
+
+def _draws(prob, n_prior, n_post, seed):
+    from paper_2601_23252_amd import problems as G
+    rng = np.random.default_rng(seed)
+    U = rng.uniform(prob["prior_a"], prob["prior_b"], (n_prior, 6))
+    V = np.log(np.array(G.GP_THETA_TRUE)) + 0.3 * rng.standard_normal((n_post, 6))
+    return np.vstack([U, V])
+
+
+@pytest.mark.parametrize("n", [1, 23, 48, 100, 256])
+def test_gp_loglik_fp64_matches_oracle(N, O, n):
+    from paper_2601_23252_amd import problems as G
+    prob = G.gp_problem(4, n=n, m=64, k=16)
+    X = _draws(prob, 40, 20, n)
+    R = N.NSRun(prob, m=64, k=16, p=1, seed=0)
+    g = R.eval_loglik(X, "fp64")
+    o = O.Problem(prob).loglik(X)
+    assert np.array_equal(np.isfinite(g), np.isfinite(o))
+    f = np.isfinite(o)
+    tol = 1e-9 * np.abs(o[f]) + 1e-14 * _kappa(X, n)[f]
+    assert np.all(np.abs(g[f] - o[f]) <= tol), np.max(np.abs(g[f] - o[f]) / tol)
+    R.close()
+
+
+def test_gp_fp32_estimate_within_guard_band(N):
+    """Where the FP32 factorisation succeeds, its estimate is within the guard band of the
+    FP64 value (the band is what sends decisions near L* to FP64)."""
+    from paper_2601_23252_amd import problems as G
+    prob = G.config4()
+    X = _draws(prob, 150, 150, 7)
+    R = N.NSRun(prob, m=64, k=16, p=1, seed=0)
+    g = R.eval_loglik(X, "fp64")
+    f = R.eval_loglik(X, "fp32")
+    rel, ab, kc = N.GP_GUARD
+    n = len(prob["gp_y"])
+    ok = np.isfinite(f) & np.isfinite(g)
+    assert ok.sum() > 100
+    band = rel * np.abs(f[ok]) + ab + kc * _kappa(X, n)[ok] / np.sqrt(n)
+    assert np.all(np.abs(f[ok] - g[ok]) <= 0.5 * band), np.max(np.abs(f[ok] - g[ok]) / band)
+    R.close()
+
+
+def _gp_parity(N, O, prob, m, k, p, seed, n_iter, precision="fp64"):
+    from oracle import theory as T
+    width = T.width_whitened(6)
+    orc = O.Run(O.Problem(prob), m, k, p, width, seed, threads=8)
+    orc.init()
+    gpu = N.NSRun(prob, m=m, k=k, p=p, width=width, seed=seed, trace=True, precision=precision)
+    g, o = gpu.state(), orc.state()
+    assert np.array_equal(g["perm"], o["perm"])
+    assert np.allclose(g["logL"], o["logL"], rtol=1e-9, atol=1e-9)
+    for it in range(n_iter):
+        if orc.done:
+            break
+        orc.step()
+        gpu.step()
+        g, o = gpu.state(), orc.state()
+        _, par_o = orc.aux()
+        assert np.array_equal(g["parents"], par_o), f"iter {it}: parents"
+        assert np.array_equal(g["perm"], o["perm"]), f"iter {it}: delete-k order"
+        assert np.allclose(g["x"], o["x"], rtol=1e-9, atol=1e-12), f"iter {it}: points"
+        assert np.allclose(g["logL"], o["logL"], rtol=1e-9, atol=1e-9), f"iter {it}: logL"
+        sg = gpu.stats()
+        assert sg["evals"] == o["evals"] and sg["tests"] == o["tests"], f"iter {it}: counts"
+        assert sg["band_violations"] == 0
+    return gpu, orc
+
+
+def test_gp_parity_small_fp64(N, O):
+    from paper_2601_23252_amd import problems as G
+    prob = G.gp_problem(8, n=32)
+    _gp_parity(N, O, prob, m=60, k=20, p=30, seed=5, n_iter=12)
+
+
+def test_gp_parity_small_fp32_follows_fp64(N, O):
+    from paper_2601_23252_amd import problems as G
+    prob = G.gp_problem(8, n=40)
+    gpu, _ = _gp_parity(N, O, prob, m=60, k=20, p=30, seed=6, n_iter=12, precision="fp32")
+    assert gpu.stats()["rechecks"] > 0
+
+
+def test_gp_ragged_tiles_parity(N, O):
+    """n = 50: three full 16-row tile rows and a ragged fourth."""
+    from paper_2601_23252_amd import problems as G
+    prob = G.gp_problem(9, n=50)
+    _gp_parity(N, O, prob, m=40, k=13, p=12, seed=2, n_iter=6)
+
+
+def test_gp_config4_full_size_sampled_chains(N, O):
+    """n = 256, n_live = 1000, k = 500: after one GPU iteration, three chains recomputed by
+    the oracle from the same starting state give the same decisions, points and logL."""
+    from oracle import theory as T
+    from paper_2601_23252_amd import problems as G
+    prob = G.config4()
+    width = T.width_whitened(6)
+    gpu = N.NSRun(prob, width=width, seed=3, trace=True)
+    s0 = gpu.state()
+    gpu.step()
+    s1 = gpu.state()
+    tr = gpu.trace()
+    P = O.Problem(prob)
+    k, p = prob["k"], prob["p"]
+    for j in (0, 211, k - 1):
+        parent = s1["parents"][j]
+        x, logL, _, trace = P.hrss_chain(s0["x"][parent], s0["logL"][parent], s0["Lstar"],
+                                         s1["Lsig"], width, p, 3, 0, 1, j, trace=True)
+        slot = s0["perm"][j]
+        assert np.array_equal(tr[j], trace), f"chain {j}: decisions"
+        assert np.allclose(s1["x"][slot], x, rtol=1e-9, atol=1e-12), f"chain {j}"
+        assert abs(s1["logL"][slot] - logL) <= 1e-9 * abs(logL), f"chain {j}"

@@ -313,3 +313,71 @@ def test_loglik_matches_scipy(oracle_lib):
     v, xs = x[:, 0], x[:, 1:4]
     ref = stats.norm.logpdf(v, 0, 3) + stats.norm.logpdf(xs, 0, np.exp(v / 2)[:, None]).sum(1)
     assert np.allclose(f.loglik(x[:, :4]), ref, rtol=1e-12, atol=1e-10)
+
+
+# ------------------------------------------------------------------------------------------
+# GP hyperparameter marginalisation: log N(y; 0, K_theta + sigma_n^2 I)
+# ------------------------------------------------------------------------------------------
+def _gp_cov_sklearn(X, u):
+    """Covariance from scikit-learn's kernels (an independent implementation of the squared-
+    exponential and periodic kernels), one periodic factor per input dimension."""
+    from sklearn.gaussian_process.kernels import RBF, ExpSineSquared
+    sf, l1, l2, lp, per, sn = np.exp(u)
+    return (sf ** 2 * RBF([l1, l2])(X) * ExpSineSquared(lp, per)(X[:, :1])
+            * ExpSineSquared(lp, per)(X[:, 1:]) + sn ** 2 * np.eye(len(X)))
+
+
+def test_gp_loglik_matches_sklearn_kernel_and_scipy_density(oracle_lib):
+    from scipy.stats import multivariate_normal
+    from paper_2601_23252_amd import problems as G
+    prob = G.gp_problem(4, n=48)
+    P = oracle_lib.Problem(prob)
+    rng = np.random.default_rng(3)
+    # well-conditioned draws (sigma_n >= 0.05) so that the eigen-based density is accurate
+    U = rng.uniform(np.log(0.1), np.log(10.0), (12, 6))
+    U[:, 5] = rng.uniform(np.log(0.05), np.log(2.0), 12)
+    got = P.loglik(U)
+    for u, g in zip(U, got):
+        K = _gp_cov_sklearn(prob["gp_x"], u)
+        ref = multivariate_normal(np.zeros(len(K)), K).logpdf(prob["gp_y"])
+        assert abs(g - ref) <= 1e-8 * abs(ref) + 1e-8, (u, g, ref)
+
+
+def test_gp_loglik_closed_forms_small_n(oracle_lib):
+    """n = 1: N(y; 0, sigma_f^2 + sigma_n^2).  n = 2: the 2x2 determinant and inverse."""
+    from paper_2601_23252_amd import problems as G
+    base = G.gp_problem(5, n=2)
+    u = np.log([1.7, 0.8, 2.2, 0.6, 3.1, 0.3])
+    sf, l1, l2, lp, per, sn = np.exp(u)
+    X, y = base["gp_x"], base["gp_y"]
+    one = dict(base, gp_x=X[:1], gp_y=y[:1])
+    v = sf ** 2 + sn ** 2
+    ref1 = -0.5 * y[0] ** 2 / v - 0.5 * math.log(2 * math.pi * v)
+    assert abs(oracle_lib.Problem(one).loglik(u)[0] - ref1) < 1e-13
+    d1, d2 = X[0] - X[1]
+    c = sf ** 2 * math.exp(-0.5 * (d1 * d1 / l1 ** 2 + d2 * d2 / l2 ** 2)) * math.exp(
+        -2.0 * (math.sin(math.pi * d1 / per) ** 2 + math.sin(math.pi * d2 / per) ** 2) / lp ** 2)
+    det = v * v - c * c
+    quad = (v * y[0] ** 2 - 2 * c * y[0] * y[1] + v * y[1] ** 2) / det
+    ref2 = -0.5 * quad - 0.5 * math.log(det) - math.log(2 * math.pi)
+    assert abs(oracle_lib.Problem(base).loglik(u)[0] - ref2) < 1e-12
+
+
+def test_gp_loglik_invariances(oracle_lib):
+    """The kernel depends on input differences only, and the density on the data set, not its
+    order: shifting all inputs by a period-independent vector and permuting the points leave
+    log L unchanged; a whole-period shift of one input leaves the periodic factor unchanged but
+    not the squared-exponential one (so it must change log L)."""
+    from paper_2601_23252_amd import problems as G
+    prob = G.gp_problem(6, n=40)
+    P = oracle_lib.Problem(prob)
+    rng = np.random.default_rng(1)
+    U = rng.uniform(np.log(0.2), np.log(5.0), (6, 6))
+    base = P.loglik(U)
+    perm = rng.permutation(40)
+    moved = dict(prob, gp_x=prob["gp_x"][perm] + np.array([3.3, -1.7]), gp_y=prob["gp_y"][perm])
+    assert np.allclose(oracle_lib.Problem(moved).loglik(U), base, rtol=1e-10, atol=1e-10)
+    one = prob["gp_x"].copy()
+    one[0, 0] += np.exp(U[0, 4])
+    shifted = oracle_lib.Problem(dict(prob, gp_x=one)).loglik(U[:1])
+    assert abs(shifted[0] - base[0]) > 1e-6
