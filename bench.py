@@ -22,7 +22,19 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-FLOP_PER_EVAL_MIX = None  # set from the problem: K d (d+1) + 3 K d
+# HBM bytes per k_hrss launch (BF16x3) from the FETCH_SIZE / WRITE_SIZE counter passes, each
+# scaled by the same counter on a copy of known size (FETCH x 2, WRITE x 1), recorded for the
+# kernel source with this sha256 prefix; reported as null once the source differs.
+TRAFFIC = {"bf16x3": 748.4e6}
+TRAFFIC_SOURCE_SHA = "09951aa2b0d562d4"
+
+
+def kernel_traffic(precision):
+    import hashlib
+    src = os.path.join(ROOT, "paper_2601_23252_amd", "csrc", "nss_kernels.hip")
+    with open(src, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()[:16]
+    return TRAFFIC.get(precision) if sha == TRAFFIC_SOURCE_SHA else None
 
 
 def algorithmic_flop_per_eval(K: int, d: int) -> int:
@@ -82,6 +94,29 @@ def cpu_baseline(prob, p, seconds_budget=20.0):
                        f"(p={p}), {ev} evaluations in {dt:.1f} s, OpenMP over chains")
 
 
+def profile_run(args):
+    """A short run for rocprofv3: the reference copy kernel, then a few outer iterations."""
+    import torch
+    from paper_2601_23252_amd import nss as N, problems as G
+    N.load()
+    src = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    prob = G.config3()
+    R = N.NSRun(prob, p=args.chain_factor * prob["d"], seed=0, precision=args.precision,
+                timing=True)
+    t0 = time.perf_counter()
+    for _ in range(args.profile_iters):
+        R.step()
+    torch.cuda.synchronize()
+    st = R.stats()
+    print(json.dumps({"profile_iters": args.profile_iters, "precision": args.precision,
+                      "wall_s": time.perf_counter() - t0, "evals": st["evals"],
+                      "hrss_ms": st["hrss_ms"], "copy_bytes": 256 << 20}), flush=True)
+    R.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -95,10 +130,16 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=1, help="FP64 comparison runs (0 = skip)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--profile-iters", type=int, default=0,
+                    help="profiling run: a 256 MiB device copy (the counters' reference), then "
+                         "this many outer iterations of one run; prints their timing only")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
+    if args.profile_iters > 0:
+        profile_run(args)
+        return
 
     from paper_2601_23252_amd import nss as N, problems as G
     N.load()
@@ -138,7 +179,8 @@ def main():
                    "n_live": prob["m"], "k": prob["k"], "chain_len": p,
                    "precision": args.precision, "term_frac": 1e-3, "seeds": seeds},
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / peak,
+                     "traffic": kernel_traffic(args.precision),
                      "kernel": "k_hrss", "flop_per_eval": fpe,
                      "avg_launch_ms": 1e3 * hrss_s / max(1, launches)},
         "lnz": {"truth": truth, "z_scores": z_scores, "all_within_3sigma": within,
