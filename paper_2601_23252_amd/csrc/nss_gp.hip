@@ -28,10 +28,13 @@ namespace nss {
 
 namespace {
 
-constexpr int kGpWaves = 8;
+constexpr int kGpWaves = 8;                                           // per workgroup
 constexpr int kGpThreads = 64 * kGpWaves;
+constexpr int kGpTileWaves = 7;        // waves 0..6 hold the covariance tiles
+constexpr int kGpPivot = 7;            // wave 7 factors the diagonal tiles
 constexpr int kGpMaxTiles = 136;                                      // 16 * 17 / 2
-constexpr int kGpSlots = (kGpMaxTiles + kGpWaves - 1) / kGpWaves;     // tiles per wave
+constexpr int kGpSlots = (kGpMaxTiles + kGpTileWaves - 1) / kGpTileWaves;  // tiles per wave
+constexpr int kGpSpinMax = 1 << 22;    // bound on the pivot wave's wait for a diagonal tile
 constexpr int kGpLd = 17;                                             // LDS tile row stride
 constexpr int kTile = 16 * kGpLd;
 constexpr int kGpD = 6;                                               // hyperparameters
@@ -41,7 +44,8 @@ constexpr int kOffXs = 0;                                             // double 
 constexpr int kOffYs = kOffXs + 2 * kGpMaxObs * 8;                    // double [256]
 constexpr int kOffMisc = kOffYs + kGpMaxObs * 8;                      // double [16], int flag
 constexpr int kOffChain = kOffMisc + 256;                             // chain point, direction
-constexpr int kOffT = kOffChain + 128;
+constexpr int kOffSc = kOffChain + 128;                               // double [256][4]
+constexpr int kOffT = kOffSc + 4 * kGpMaxObs * 8;
 template <typename T>
 constexpr int gp_lds_bytes()
 {
@@ -101,24 +105,27 @@ __device__ __forceinline__ GpTheta gp_theta(const double *u)
 }
 
 // Entry (row, col) of the padded covariance: identity outside the n observations, zero above
-// the diagonal (never read as data).
+// the diagonal (never read as data).  sin(pi (a - b) / P) = s_a c_b - c_a s_b from the per-point
+// sc[i] = (sin, cos)(pi x_i1 / P), (sin, cos)(pi x_i2 / P), so an entry costs one exponential.
 template <typename T>
-__device__ __forceinline__ T gp_entry(const double *xs, int n, int row, int col, const GpTheta &h)
+__device__ __forceinline__ T gp_entry(const double *xs, const double *sc, int n, int row, int col,
+                                      const GpTheta &h)
 {
     if (row >= n || col >= n) return (row == col) ? T(1) : T(0);
     if (col > row) return T(0);
     const double d1 = xs[2 * row] - xs[2 * col], d2 = xs[2 * row + 1] - xs[2 * col + 1];
+    const double *pa = sc + 4 * row, *pb = sc + 4 * col;
+    const double s1 = pa[0] * pb[1] - pa[1] * pb[0], s2 = pa[2] * pb[3] - pa[3] * pb[2];
     if constexpr (sizeof(T) == 8) {
-        const double s1 = sinpi(d1 * h.iper), s2 = sinpi(d2 * h.iper);
         const double a1 = d1 * h.il1, a2 = d2 * h.il2;
         double v = h.sf2 * exp(-0.5 * (a1 * a1 + a2 * a2) - 2.0 * (s1 * s1 + s2 * s2) * h.ilp2);
         if (row == col) v += h.sn2;
         return v;
     } else {
-        const float s1 = sinpif((float)(d1 * h.iper)), s2 = sinpif((float)(d2 * h.iper));
         const float a1 = (float)(d1 * h.il1), a2 = (float)(d2 * h.il2);
+        const float f1 = (float)s1, f2 = (float)s2;
         float v = (float)h.sf2 *
-                  expf(-0.5f * (a1 * a1 + a2 * a2) - 2.0f * (s1 * s1 + s2 * s2) * (float)h.ilp2);
+                  expf(-0.5f * (a1 * a1 + a2 * a2) - 2.0f * (f1 * f1 + f2 * f2) * (float)h.ilp2);
         if (row == col) v += (float)h.sn2;
         return v;
     }
@@ -131,9 +138,76 @@ __device__ __forceinline__ void store_tile(const V &acc, T *p, int l)
     for (int r = 0; r < 4; ++r) p[Mf<T>::row(l, r) * kGpLd + (l & 15)] = acc[r];
 }
 
+// Factor the diagonal tile in dg (rows of stride kGpLd) in place, write the inverse of the
+// factor to li and its reciprocal pivots to dv, z = L^{-1} y_J to zb, add log det and |z|^2 to
+// this wave's (ldet, quad) (lane 0) and raise the flag on a pivot that is not positive.  Run by
+// one whole wave; lane i (mod 16) holds row i, every DPP row a copy.
+template <typename T>
+__device__ __forceinline__ void diag_block(T *dg, T *li, T *zb, T *dv, const T *yJ, int *flag,
+                                           int l, double &ldet, double &quad)
+{
+    const int i = l & 15;
+    T a[16], iv[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) a[c] = dg[i * kGpLd + c];
+    bool bad = false;
+    double prod = 1.0;
+#pragma unroll
+    for (int jj = 0; jj < 16; ++jj) {
+        const T piv = readlane_t(a[jj], jj);
+        const bool ok = piv > T(0);
+        bad = bad || !ok;
+        const T ljj = ok ? (T)sqrt(piv) : T(1);
+        const T inv = T(1) / ljj;
+        iv[jj] = inv;
+        prod *= (double)ljj;
+        a[jj] = (i > jj) ? a[jj] * inv : ((i == jj) ? ljj : a[jj]);
+#pragma unroll
+        for (int c = jj + 1; c < 16; ++c) {
+            const T lcj = readlane_t(a[jj], c);
+            if (i > jj) a[c] -= a[jj] * lcj;
+        }
+    }
+    ldet += log(prod);
+    if (l == 0 && bad) *flag = 1;
+    // inverse, one column per lane: x = L^{-1} e_c by forward substitution, L[r][t] taken from
+    // lane r's registers (one row's operands in flight at a time)
+    const int c = l & 15;
+    T x[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        T sacc = (r == c) ? T(1) : T(0);
+#pragma unroll
+        for (int t = 0; t < r; ++t) sacc -= readlane_t(a[t], r) * x[t];
+        x[r] = sacc * iv[r];
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    // z_J = L_JJ^{-1} y_J: row sums over the 16 lanes of a DPP row
+    const T yc = yJ[c];
+    double q2 = 0.0;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        if (l < 16) li[r * kGpLd + c] = x[r];
+        const T zr = row_sum16(x[r] * yc);
+        if (l == 0) zb[r] = zr;
+        q2 += (double)zr * (double)zr;
+    }
+    if (l == 0) {
+        quad += q2;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) dv[r] = iv[r];
+    }
+}
+
 // log N(y; 0, K_theta + sigma_n^2 I) at u = log theta with the factorisation in T.  Called by
 // every thread of the workgroup with the same u (the result is uniform); the inputs and
 // targets must be staged at kOffXs / kOffYs.  failed = a pivot was not positive.
+//
+// Waves 0..6 hold the covariance tiles and do the panel and trailing updates; wave 7 factors
+// each diagonal tile as soon as its owner has applied the last update to it and published it
+// (a one-block look-ahead: the factorisation of block J+1 overlaps the trailing update of
+// step J).  The two roles run separate loops with the same barrier count, so the pivot wave's
+// code holds none of the tile registers.
 template <typename T>
 __device__ __forceinline__ double gp_eval(const double *u, int n, unsigned char *smem, bool &failed)
 {
@@ -143,6 +217,8 @@ __device__ __forceinline__ double gp_eval(const double *u, int n, unsigned char 
     const double *ys = (const double *)(smem + kOffYs);
     double *red = (double *)(smem + kOffMisc);
     int *flag = (int *)(red + 16);
+    int *dflag = flag + 1;           // index of the last diagonal tile published to dg
+    double *sc = (double *)(smem + kOffSc);
     T *pan = (T *)(smem + kOffT);
     T *dg = pan + 16 * kTile;
     T *li = dg + kTile;
@@ -154,164 +230,149 @@ __device__ __forceinline__ double gp_eval(const double *u, int n, unsigned char 
     const GpTheta h = gp_theta(u);
 
     for (int i = tid; i < 16 * NT; i += kGpThreads) yb[i] = (i < n) ? (T)ys[i] : T(0);
-    if (tid == 0) *flag = 0;
-
-    int tI[kGpSlots], tK[kGpSlots];
-    v4 acc[kGpSlots];
-    {
-    const int l = lane0;
-#pragma unroll
-    for (int s = 0; s < kGpSlots; ++s) {
-        const int t = w + kGpWaves * s;
-        int I = -1, K = 0;
-        if (t < NTT) tile_ik(t, I, K);
-        tI[s] = I;
-        tK[s] = K;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) acc[s][r] = T(0);
+    for (int i = tid; i < n; i += kGpThreads) {
+        double s0, c0, s1, c1;
+        sincospi(xs[2 * i] * h.iper, &s0, &c0);
+        sincospi(xs[2 * i + 1] * h.iper, &s1, &c1);
+        sc[4 * i] = s0; sc[4 * i + 1] = c0; sc[4 * i + 2] = s1; sc[4 * i + 3] = c1;
     }
-    // entries of the wave's tiles: one tile per (not unrolled) iteration, then moved into its
-    // register slot by a uniform branch (keeps one copy of the transcendental code)
-#pragma unroll 1
-    for (int s = 0; s < kGpSlots; ++s) {
-        const int t = w + kGpWaves * s;
-        if (t >= NTT) break;
-        int I, K;
-        tile_ik(t, I, K);
-        const int col = 16 * K + (l & 15);
-        T e[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) e[r] = gp_entry<T>(xs, n, 16 * I + M::row(l, r), col, h);
-#pragma unroll
-        for (int S = 0; S < kGpSlots; ++S)
-            if (S == s) {
-#pragma unroll
-                for (int r = 0; r < 4; ++r) acc[S][r] = e[r];
-            }
-    }
-    }
+    if (tid == 0) { *flag = 0; *dflag = -1; }
     __syncthreads();
 
-    double ldet = 0.0, quad = 0.0;   // wave 0, lane 0
-    for (int J = 0; J < NT; ++J) {
-        const int tJ = J * (J + 1) / 2 + J;
-        // the lane index, opaque to the compiler inside each iteration: keeps the many
-        // lane-derived masks and LDS addresses of the unrolled code below from being hoisted
-        // out of the loop, where they would hold registers across all of it
-        int l = lane0;
-        asm volatile("" : "+v"(l));
-#pragma unroll
-        for (int s = 0; s < kGpSlots; ++s)
-            if (w + kGpWaves * s == tJ) store_tile<T>(acc[s], dg, l);
-        __syncthreads();
-
-        if (w == 0) {
-            // factor the diagonal tile: lane i holds row i (every DPP row holds a copy)
-            const int i = l & 15;
-            T a[16];
-#pragma unroll
-            for (int c = 0; c < 16; ++c) a[c] = dg[i * kGpLd + c];
-            bool bad = false;
-            double prod = 1.0;
-#pragma unroll
-            for (int jj = 0; jj < 16; ++jj) {
-                const T piv = readlane_t(a[jj], jj);
-                const bool ok = piv > T(0);
-                bad = bad || !ok;
-                const T ljj = ok ? (T)sqrt(piv) : T(1);
-                const T inv = T(1) / ljj;
-                if (l == 0) dv[jj] = inv;
-                prod *= (double)ljj;
-                a[jj] = (i > jj) ? a[jj] * inv : ((i == jj) ? ljj : a[jj]);
-#pragma unroll
-                for (int c = jj + 1; c < 16; ++c) {
-                    const T lcj = readlane_t(a[jj], c);
-                    if (i > jj) a[c] -= a[jj] * lcj;
+    if (w == kGpPivot) {
+        double ldet = 0.0, quad = 0.0;   // lane 0
+        for (int J = -1; J < NT; ++J) {
+            int l = lane0;
+            asm volatile("" : "+v"(l));
+            if (J >= 0) __syncthreads();   // the panel step of the tile waves
+            const int J1 = J + 1;
+            if (J1 < NT) {
+                int spins = 0;
+                while (__hip_atomic_load(dflag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) != J1) {
+                    if (++spins > kGpSpinMax) {   // never expected: give up on this evaluation
+                        if (l == 0) *flag = 1;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
                 }
+                diag_block<T>(dg, li, zb, dv, yb + 16 * J1, flag, l, ldet, quad);
             }
-            ldet += log(prod);
-            if (l < 16) {
+            __syncthreads();
+        }
+        if (lane0 == 0) {
+            red[0] = ldet;
+            red[1] = quad;
+        }
+    } else {
+        int tI[kGpSlots], tK[kGpSlots];
+        v4 acc[kGpSlots];
 #pragma unroll
-                for (int c = 0; c < 16; ++c) dg[i * kGpLd + c] = a[c];
-            }
-            if (l == 0 && bad) *flag = 1;
-            wave_sync();
-            // inverse of the factor, one column per lane (lanes 0..15): x = L^{-1} e_c by
-            // forward substitution; L's rows are read from LDS (same address in every lane),
-            // the column is kept in LDS (each lane reads back only what it wrote)
-            const int c = l & 15;
-            if (l < 16) {
+        for (int s = 0; s < kGpSlots; ++s) {
+            const int t = w + kGpTileWaves * s;
+            int I = -1, K = 0;
+            if (t < NTT) tile_ik(t, I, K);
+            tI[s] = I;
+            tK[s] = K;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[s][r] = T(0);
+        }
+        {
+            // entries of the wave's tiles: one tile per (not unrolled) iteration, then moved
+            // into its register slot by a uniform branch (one copy of the exponential code)
+            const int l = lane0;
 #pragma unroll 1
-                for (int r = 0; r < 16; ++r) {
-                    T sacc = (r == c) ? T(1) : T(0);
-                    for (int t = c; t < r; ++t) sacc -= dg[r * kGpLd + t] * li[t * kGpLd + c];
-                    li[r * kGpLd + c] = (r < c) ? T(0) : sacc * dv[r];
-                }
-            }
-            wave_sync();
-            // z_J = L_JJ^{-1} y_J: lane r sums row r of the inverse against y_J
-            if (l < 16) {
-                T zr = T(0);
+            for (int s = 0; s < kGpSlots; ++s) {
+                const int t = w + kGpTileWaves * s;
+                if (t >= NTT) break;
+                int I, K;
+                tile_ik(t, I, K);
+                const int col = 16 * K + (l & 15);
+                T e[4];
 #pragma unroll
-                for (int t = 0; t < 16; ++t) zr += li[l * kGpLd + t] * yb[16 * J + t];
-                zb[l] = zr;
-                const double zd = (double)zr;
-                double q2 = zd * zd;
-                q2 += __shfl_xor(q2, 1, 64);
-                q2 += __shfl_xor(q2, 2, 64);
-                q2 += __shfl_xor(q2, 4, 64);
-                q2 += __shfl_xor(q2, 8, 64);
-                if (l == 0) quad += q2;
+                for (int r = 0; r < 4; ++r)
+                    e[r] = gp_entry<T>(xs, sc, n, 16 * I + M::row(l, r), col, h);
+#pragma unroll
+                for (int S = 0; S < kGpSlots; ++S)
+                    if (S == s) {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) acc[S][r] = e[r];
+                    }
             }
         }
-        __syncthreads();
-
-        // panel: L_IJ = A_IJ L_JJ^{-T}, and y_I -= L_IJ z_J
+        for (int J = -1; J < NT; ++J) {
+            // the lane index, opaque to the compiler inside each iteration: keeps the many
+            // lane-derived masks and LDS addresses of the unrolled code below from being
+            // hoisted out of the loop, where they would hold registers across all of it
+            int l = lane0;
+            asm volatile("" : "+v"(l));
+            if (J >= 0) {
+                // panel: L_IJ = A_IJ L_JJ^{-T}, and y_I -= L_IJ z_J
 #pragma unroll
-        for (int s = 0; s < kGpSlots; ++s) {
-            if (tK[s] == J && tI[s] > J) {
-                T *pI = pan + tI[s] * kTile;
-                store_tile<T>(acc[s], pI, l);
-                wave_sync();
-                v4 o;
+                for (int s = 0; s < kGpSlots; ++s) {
+                    if (tK[s] == J && tI[s] > J) {
+                        T *pI = pan + tI[s] * kTile;
+                        store_tile<T>(acc[s], pI, l);
+                        wave_sync();
+                        v4 o;
 #pragma unroll
-                for (int r = 0; r < 4; ++r) o[r] = T(0);
+                        for (int r = 0; r < 4; ++r) o[r] = T(0);
 #pragma unroll
-                for (int ks = 0; ks < 4; ++ks) {
-                    const int ko = (l & 15) * kGpLd + 4 * ks + (l >> 4);
-                    o = M::mma(pI[ko], li[ko], o);
+                        for (int ks = 0; ks < 4; ++ks) {
+                            const int ko = (l & 15) * kGpLd + 4 * ks + (l >> 4);
+                            o = M::mma(pI[ko], li[ko], o);
+                        }
+                        wave_sync();
+                        store_tile<T>(o, pI, l);
+                        acc[s] = o;
+                        const T zc = zb[l & 15];
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const T sr = row_sum16(o[r] * zc);
+                            if ((l & 15) == 0) yb[16 * tI[s] + M::row(l, r)] -= sr;
+                        }
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
                 }
-                wave_sync();
-                store_tile<T>(o, pI, l);
-                acc[s] = o;
-                const T zc = zb[l & 15];
+                __syncthreads();
+            }
+            // trailing update A_IK -= L_IJ L_KJ^T for J < K <= I; the next diagonal tile first,
+            // published to the pivot wave as soon as it is final
+            const int J1 = J + 1;
+            const int tD = J1 * (J1 + 1) / 2 + J1;
+            if (J1 < NT && w == tD % kGpTileWaves) {
+                const T *pD = pan + J1 * kTile;
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const T sr = row_sum16(o[r] * zc);
-                    if ((l & 15) == 0) yb[16 * tI[s] + M::row(l, r)] -= sr;
+                for (int s = 0; s < kGpSlots; ++s) {
+                    if (w + kGpTileWaves * s == tD) {
+                        if (J >= 0) {
+#pragma unroll
+                            for (int ks = 0; ks < 4; ++ks) {
+                                const int ko = (l & 15) * kGpLd + 4 * ks + (l >> 4);
+                                acc[s] = M::mma(-pD[ko], pD[ko], acc[s]);
+                            }
+                        }
+                        store_tile<T>(acc[s], dg, l);
+                    }
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                if (l == 0) __hip_atomic_store(dflag, J1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+            if (J >= 0) {
+#pragma unroll
+                for (int s = 0; s < kGpSlots; ++s) {
+                    if (tK[s] > J && w + kGpTileWaves * s != tD) {
+                        const T *pI = pan + tI[s] * kTile, *pK = pan + tK[s] * kTile;
+#pragma unroll
+                        for (int ks = 0; ks < 4; ++ks) {
+                            const int ko = (l & 15) * kGpLd + 4 * ks + (l >> 4);
+                            acc[s] = M::mma(-pI[ko], pK[ko], acc[s]);
+                        }
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
                 }
             }
-            __builtin_amdgcn_sched_barrier(0);
+            __syncthreads();
         }
-        __syncthreads();
-
-        // trailing update: A_IK -= L_IJ L_KJ^T for J < K <= I
-#pragma unroll
-        for (int s = 0; s < kGpSlots; ++s) {
-            if (tK[s] > J) {
-                const T *pI = pan + tI[s] * kTile, *pK = pan + tK[s] * kTile;
-#pragma unroll
-                for (int ks = 0; ks < 4; ++ks) {
-                    const int ko = (l & 15) * kGpLd + 4 * ks + (l >> 4);
-                    acc[s] = M::mma(-pI[ko], pK[ko], acc[s]);
-                }
-            }
-            __builtin_amdgcn_sched_barrier(0);
-        }
-    }
-    if (tid == 0) {
-        red[0] = ldet;
-        red[1] = quad;
     }
     __syncthreads();
     const double ld = red[0], q = red[1];
