@@ -142,6 +142,22 @@ __device__ __forceinline__ void store_tile(const V &acc, T *p, int l)
 // factor to li and its reciprocal pivots to dv, z = L^{-1} y_J to zb, add log det and |z|^2 to
 // this wave's (ldet, quad) (lane 0) and raise the flag on a pivot that is not positive.  Run by
 // one whole wave; lane i (mod 16) holds row i, every DPP row a copy.
+// 1/sqrt(x): the hardware estimate refined by Newton steps r <- r (3/2 - x r^2 / 2)
+// (two in FP64, one in FP32), for a short dependent chain per pivot.
+__device__ __forceinline__ double rsq_refined(double x)
+{
+    double r = __builtin_amdgcn_rsq(x);
+    const double h = 0.5 * x;
+    r = r * (1.5 - h * r * r);
+    r = r * (1.5 - h * r * r);
+    return r;
+}
+__device__ __forceinline__ float rsq_refined(float x)
+{
+    float r = __builtin_amdgcn_rsqf(x);
+    return r * (1.5f - 0.5f * x * r * r);
+}
+
 template <typename T>
 __device__ __forceinline__ void diag_block(T *dg, T *li, T *zb, T *dv, const T *yJ, int *flag,
                                            int l, double &ldet, double &quad)
@@ -157,16 +173,14 @@ __device__ __forceinline__ void diag_block(T *dg, T *li, T *zb, T *dv, const T *
         const T piv = readlane_t(a[jj], jj);
         const bool ok = piv > T(0);
         bad = bad || !ok;
-        const T ljj = ok ? (T)sqrt(piv) : T(1);
-        const T inv = T(1) / ljj;
-        iv[jj] = inv;
+        const T r = ok ? rsq_refined(piv) : T(1);
+        const T ljj = ok ? piv * r : T(1);
+        iv[jj] = r;
         prod *= (double)ljj;
-        a[jj] = (i > jj) ? a[jj] * inv : ((i == jj) ? ljj : a[jj]);
+        // column jj scaled; rows above jj only touch their unused upper part
+        a[jj] = (i == jj) ? ljj : a[jj] * r;
 #pragma unroll
-        for (int c = jj + 1; c < 16; ++c) {
-            const T lcj = readlane_t(a[jj], c);
-            if (i > jj) a[c] -= a[jj] * lcj;
-        }
+        for (int c = jj + 1; c < 16; ++c) a[c] -= a[jj] * readlane_t(a[jj], c);
     }
     ldet += log(prod);
     if (l == 0 && bad) *flag = 1;
@@ -277,26 +291,20 @@ __device__ __forceinline__ double gp_eval(const double *u, int n, unsigned char 
             for (int r = 0; r < 4; ++r) acc[s][r] = T(0);
         }
         {
-            // entries of the wave's tiles: one tile per (not unrolled) iteration, then moved
-            // into its register slot by a uniform branch (one copy of the exponential code)
+            // entries of the wave's tiles (a slot's four entries in a loop that is not unrolled,
+            // so the exponential's code appears once per slot)
             const int l = lane0;
-#pragma unroll 1
+#pragma unroll
             for (int s = 0; s < kGpSlots; ++s) {
                 const int t = w + kGpTileWaves * s;
-                if (t >= NTT) break;
-                int I, K;
-                tile_ik(t, I, K);
-                const int col = 16 * K + (l & 15);
-                T e[4];
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    e[r] = gp_entry<T>(xs, sc, n, 16 * I + M::row(l, r), col, h);
-#pragma unroll
-                for (int S = 0; S < kGpSlots; ++S)
-                    if (S == s) {
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) acc[S][r] = e[r];
-                    }
+                if (t < NTT) {
+                    int I, K;
+                    tile_ik(t, I, K);
+                    const int col = 16 * K + (l & 15);
+#pragma unroll 1
+                    for (int r = 0; r < 4; ++r)
+                        acc[s][r] = gp_entry<T>(xs, sc, n, 16 * I + M::row(l, r), col, h);
+                }
             }
         }
         for (int J = -1; J < NT; ++J) {
