@@ -117,6 +117,96 @@ def profile_run(args):
     R.close()
 
 
+def gp_flop_per_eval(n: int) -> float:
+    """Cholesky n^3/3, forward solve n^2, and about 20 flops per lower-triangle entry of the
+    kernel matrix."""
+    return n ** 3 / 3 + n ** 2 + 20 * n * (n + 1) / 2
+
+
+def run_until(R, max_seconds, chunk=4):
+    """Outer iterations until termination or the time budget; returns (iterations, seconds)."""
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    it = 0
+    while time.perf_counter() - t0 < max_seconds:
+        k = R.run(max_iter=chunk)
+        it += k
+        print(f"[bench] {it} iterations, {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+              flush=True)
+        if k == 0:
+            break
+    torch.cuda.synchronize()
+    return it, time.perf_counter() - t0
+
+
+def bench_gp(args):
+    """GP hyperparameter marginalisation: one run from the prior draws, timed until it
+    terminates or the time budget ends (FP64, decisions identical to the oracle's)."""
+    from paper_2601_23252_amd import nss as N, problems as G
+    N.load()
+    prob = G.config4()
+    n = len(prob["gp_y"])
+    R = N.NSRun(prob, seed=0, precision="fp64", timing=True)
+    it, dt = run_until(R, args.max_seconds)
+    st = R.stats()
+    z, err, H = R.logz()
+    fpe = gp_flop_per_eval(n)
+    hrss_s = st["hrss_ms"] / 1e3
+    achieved = st["evals"] * fpe / hrss_s if hrss_s > 0 else 0.0
+    out = {
+        "metric": "slice-step likelihood evals/s (GP hyperparameter marginalisation)",
+        "value": st["evals"] / dt, "unit": "evals/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": 1e3 * dt, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "gp_rbfxperiodic_n256_nlive1000_k500", "n_obs": n, "d": 6,
+                   "n_live": prob["m"], "k": prob["k"], "chain_len": prob["p"],
+                   "iterations": it, "done": R.state()["done"]},
+        "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": 78.6,
+                     "unit": "TFLOP/s", "frac": achieved / 78.6e12, "traffic": None,
+                     "kernel": "k_hrss_gp", "flop_per_eval": fpe,
+                     "avg_launch_ms": st["hrss_ms"] / max(1, st["hrss_launches"])},
+        "lnz": {"logz": z, "sigma": err, "H": H},
+    }
+    print(json.dumps(out), flush=True)
+    R.close()
+
+
+def bench_batch(args):
+    """256 independent runs of uneven dimension (correlated Gaussians in BF16x3, funnels in
+    FP64) in one context, timed until all terminate or the time budget ends."""
+    import numpy as np
+    from paper_2601_23252_amd import nss as N, problems as G
+    N.load()
+    probs = G.config5()
+    runs = [(p, dict(seed=5, run_id=r, precision="bf16x3" if p["lik"] == "mixture" else "fp64",
+                     max_iter=3000, timing=True)) for r, p in enumerate(probs)]
+    B = N.NSBatch(runs)
+    it, dt = run_until(B, args.max_seconds, chunk=16)
+    stats = [B.stats(r) for r in range(len(probs))]
+    evals = sum(s["evals"] for s in stats)
+    fpe = [p["d"] * (p["d"] + 1) + 3 * p["d"] if p["lik"] == "mixture" else 3 * p["d"]
+           for p in probs]
+    flops = sum(s["evals"] * f for s, f in zip(stats, fpe))
+    hrss_s = stats[0]["hrss_ms"] / 1e3
+    done = sum(B.state(r)["done"] for r in range(len(probs)))
+    out = {
+        "metric": "slice-step likelihood evals/s (256 batched runs, d in {8..128})",
+        "value": evals / dt, "unit": "evals/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": 1e3 * dt, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": "batch256_gauss_funnel_nlive500_k250_p5d", "runs": len(probs),
+                   "runs_done": done, "max_iterations": it},
+        "roofline": {"bound": "mfma", "achieved": flops / hrss_s / 1e12 if hrss_s else 0.0,
+                     "peak": 2500.0, "unit": "TFLOP/s",
+                     "frac": flops / hrss_s / 2.5e15 if hrss_s else 0.0, "traffic": None,
+                     "kernel": "k_hrss", "flop_per_eval": "d(d+1)+3d (Gaussian), 3d (funnel)",
+                     "avg_launch_ms": stats[0]["hrss_ms"] / max(1, stats[0]["hrss_launches"])},
+    }
+    print(json.dumps(out), flush=True)
+    B.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -130,6 +220,13 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=1, help="FP64 comparison runs (0 = skip)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--workload", default="mixture8_d64",
+                    choices=["mixture8_d64", "gp_n256", "batch256"],
+                    help="mixture8_d64: the benchmark above; gp_n256: GP hyperparameter "
+                         "marginalisation (n=256, n_live=1000, k=500, p=30), FP64; batch256: "
+                         "256 independent runs of uneven d in one context")
+    ap.add_argument("--max-seconds", type=float, default=120.0,
+                    help="gp_n256 / batch256: stop the timed run after about this long")
     ap.add_argument("--profile-iters", type=int, default=0,
                     help="profiling run: a 256 MiB device copy (the counters' reference), then "
                          "this many outer iterations of one run; prints their timing only")
@@ -139,6 +236,12 @@ def main():
         sys.exit(2)
     if args.profile_iters > 0:
         profile_run(args)
+        return
+    if args.workload == "gp_n256":
+        bench_gp(args)
+        return
+    if args.workload == "batch256":
+        bench_batch(args)
         return
 
     from paper_2601_23252_amd import nss as N, problems as G
