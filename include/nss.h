@@ -133,6 +133,9 @@ typedef struct {
                                       * themselves instead of reading a per-iteration buffer
                                       * of k*p*(d+8) doubles (the buffer is also skipped when
                                       * it would exceed 4 GiB) */
+#define NS_FLAG_GRAPH  8  /* ns_run captures each batch of 16 iterations as a HIP graph and
+                           * replays it (re-captured when a run of the batch finishes); not
+                           * used together with NS_FLAG_TIMING.  Results are identical. */
 
 typedef struct {
     int64_t iterations;     /* completed ns_step iterations */

@@ -59,8 +59,14 @@ struct ns_ctx {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
     double hrss_ms = 0.0;
     long long hrss_launches = 0;
+    // NS_FLAG_GRAPH: a captured batch of kGraphIters iterations, valid for one block-map epoch
+    int use_graph = 0;
+    long long map_epoch = 0, graph_epoch = -1;
+    hipGraphExec_t gexec = nullptr;
     std::string err;
 };
+
+constexpr int kGraphIters = 16;   // iterations per host synchronisation in ns_run
 
 static std::string g_init_err = "";
 
@@ -412,6 +418,7 @@ static ns_status build_maps(ns_ctx *ctx, const std::vector<char> &act)
                      hipMemcpyHostToDevice));
     }
     ctx->mapped_active = act;
+    ++ctx->map_epoch;
     return NS_OK;
 }
 
@@ -556,6 +563,7 @@ extern "C" void ns_free(ns_ctx *ctx)
 {
     if (!ctx) return;
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
     for (auto &pr : ctx->events) { (void)hipEventDestroy(pr.first); (void)hipEventDestroy(pr.second); }
     for (void *p : ctx->allocs) if (p) (void)hipFree(p);
     if (ctx->h_iscal) (void)hipHostFree(ctx->h_iscal);
@@ -733,6 +741,7 @@ extern "C" ns_status ns_init_batch(int32_t n_runs, const ns_prior *priors,
         rh.p = cfgs[r].chain_len;
         rh.mode = cfgs[r].precision;
         if (cfgs[r].flags & NS_FLAG_TIMING) ctx->timing = 1;
+        if (cfgs[r].flags & NS_FLAG_GRAPH) ctx->use_graph = 1;
         if ((st = prepare_problem(ctx, rh, priors + r, energies + r)) != NS_OK) return bail(st);
         rh.lik = rh.P.lik_kind;
         rh.K = rh.P.K;
@@ -850,6 +859,38 @@ extern "C" ns_status ns_step(ns_ctx *ctx, int32_t *done)
     return NS_OK;
 }
 
+// kGraphIters iterations as one HIP graph: captured from the stream once per block-map epoch
+// (the launch grids change when runs finish), replayed otherwise.  The iterations contain
+// kernel launches only (no memset or copy nodes).
+static ns_status launch_graph_batch(ns_ctx *ctx)
+{
+    if (!ctx->gexec || ctx->graph_epoch != ctx->map_epoch) {
+        if (ctx->gexec) {
+            CK(hipGraphExecDestroy(ctx->gexec));
+            ctx->gexec = nullptr;
+        }
+        CK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+        ns_status st = NS_OK;
+        for (int b = 0; b < kGraphIters && st == NS_OK; ++b) st = enqueue_iteration(ctx);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(ctx->stream, &g);
+        if (st != NS_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return st;
+        }
+        if (e != hipSuccess) return device_error(ctx, "graph capture", e);
+        const hipError_t e2 = hipGraphInstantiate(&ctx->gexec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e2 != hipSuccess) {
+            ctx->gexec = nullptr;
+            return device_error(ctx, "graph instantiation", e2);
+        }
+        ctx->graph_epoch = ctx->map_epoch;
+    }
+    CK(hipGraphLaunch(ctx->gexec, ctx->stream));
+    return NS_OK;
+}
+
 extern "C" ns_status ns_run(ns_ctx *ctx, int32_t max_iter, int32_t *iters)
 {
     if (!ctx || max_iter < 0) return NS_EINVAL;
@@ -860,9 +901,13 @@ extern "C" ns_status ns_run(ns_ctx *ctx, int32_t max_iter, int32_t *iters)
     int issued = 0;
     while (!all_done(ctx) && issued < max_iter) {
         if ((st = refresh_maps(ctx)) != NS_OK) return st;
-        const int batch = (max_iter - issued) < 16 ? (max_iter - issued) : 16;
-        for (int b = 0; b < batch; ++b)
-            if ((st = enqueue_iteration(ctx)) != NS_OK) return st;
+        const int batch = (max_iter - issued) < kGraphIters ? (max_iter - issued) : kGraphIters;
+        if (ctx->use_graph && !ctx->timing && batch == kGraphIters) {
+            if ((st = launch_graph_batch(ctx)) != NS_OK) return st;
+        } else {
+            for (int b = 0; b < batch; ++b)
+                if ((st = enqueue_iteration(ctx)) != NS_OK) return st;
+        }
         issued += batch;
         if ((st = sync_flags(ctx)) != NS_OK) return st;
     }

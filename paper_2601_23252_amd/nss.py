@@ -22,7 +22,7 @@ NS_OK, NS_DONE, NS_EINVAL, NS_ENOMEM, NS_EDEVICE, NS_ESTATE, NS_EUNSUPPORTED = 0
 NS_PRIOR_BOX, NS_PRIOR_GAUSS_DIAG = 0, 1
 NS_LIK_MIXTURE, NS_LIK_FUNNEL, NS_LIK_GP = 1, 2, 3
 NS_FP64, NS_MIXED_BF16, NS_MIXED_FP16, NS_MIXED_BF16X3, NS_MIXED_FP16X3, NS_MIXED_FP32 = 0, 1, 2, 3, 4, 5
-NS_FLAG_TRACE, NS_FLAG_TIMING, NS_FLAG_INLINE_DIRECTIONS = 1, 2, 4
+NS_FLAG_TRACE, NS_FLAG_TIMING, NS_FLAG_INLINE_DIRECTIONS, NS_FLAG_GRAPH = 1, 2, 4, 8
 PRECISIONS = {"fp64": NS_FP64, "bf16": NS_MIXED_BF16, "fp16": NS_MIXED_FP16,
               "bf16x3": NS_MIXED_BF16X3, "fp16x3": NS_MIXED_FP16X3, "fp32": NS_MIXED_FP32}
 # guard band of each mixed mode: (rel, abs) as set by the library
@@ -276,7 +276,7 @@ def current_stream():
 
 def make_config(m, k, p, width=0.0, seed=0, run_id=0, precision="fp64", term_frac=1e-3,
                 stepout_cap=10, shrink_cap=100, max_iter=100000, trace=False, timing=False,
-                inline_directions=False) -> ns_config:
+                inline_directions=False, graph=False) -> ns_config:
     cfg = ns_config_default()
     cfg.n_live, cfg.k, cfg.chain_len = int(m), int(k), int(p)
     cfg.width = float(width)
@@ -286,7 +286,8 @@ def make_config(m, k, p, width=0.0, seed=0, run_id=0, precision="fp64", term_fra
     cfg.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     cfg.max_iter = int(max_iter)
     cfg.flags = ((NS_FLAG_TRACE if trace else 0) | (NS_FLAG_TIMING if timing else 0)
-                 | (NS_FLAG_INLINE_DIRECTIONS if inline_directions else 0))
+                 | (NS_FLAG_INLINE_DIRECTIONS if inline_directions else 0)
+                 | (NS_FLAG_GRAPH if graph else 0))
     return cfg
 
 
@@ -306,7 +307,7 @@ class NSRun:
     def __init__(self, prob: dict, m=None, k=None, p=None, width=0.0, seed=0, run_id=0,
                  precision="fp64", term_frac=1e-3, stepout_cap=10, shrink_cap=100,
                  max_iter=100000, trace=False, timing=False, inline_directions=False,
-                 stream="torch"):
+                 graph=False, stream="torch"):
         self.prob = prob
         self.d = int(prob["d"])
         self.m = int(m or prob["m"])
@@ -314,7 +315,8 @@ class NSRun:
         self.p = int(p or prob["p"])
         pr, en, self._keep = make_structs(prob)
         cfg = make_config(self.m, self.k, self.p, width, seed, run_id, precision, term_frac,
-                          stepout_cap, shrink_cap, max_iter, trace, timing, inline_directions)
+                          stepout_cap, shrink_cap, max_iter, trace, timing, inline_directions,
+                          graph)
         self.cfg = cfg
         s = current_stream() if stream == "torch" else stream
         st, self.ctx = ns_init(pr, en, cfg, s)
