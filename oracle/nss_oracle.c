@@ -42,7 +42,7 @@
 
 #define OR_PI 3.14159265358979323846
 
-enum { P_INIT = 1, P_RESAMPLE = 2, P_DIR = 3, P_STEP = 4, P_SHRINK = 5 };
+enum { P_INIT = 1, P_RESAMPLE = 2, P_DIR = 3, P_STEP = 4, P_SHRINK = 5, P_GEOM = 6 };
 enum { PRIOR_BOX = 0, PRIOR_GAUSS = 1 };
 enum { LIK_MIXTURE = 1, LIK_FUNNEL = 2, LIK_GP = 3 };
 
@@ -725,4 +725,76 @@ int64_t or_get_dead(const void *rr, double *out, int64_t cap)
     int64_t n = r->n_dead < cap ? r->n_dead : cap;
     if (out && n > 0) memcpy(out, r->dead, sizeof(double) * n);
     return r->n_dead;
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Post-hoc geometric uncertainty (App. "Estimation of prior volumes and propagation of         */
+/* geometric uncertainty")                                                                     */
+/* ------------------------------------------------------------------------------------------ */
+/*
+ * Deaths i = 1..N in likelihood order: the dead record (batch after batch; the j-th death of a
+ * batch has n = m - (j-1) live points) followed by the final survivors in ascending logL with
+ * n = nf, nf-1, ..., 1.  Replica r draws shrinkages t_i = u_i^(1/n_i), u_i uniform (Philox
+ * purpose GEOM, index r, counter word i-1), so log t_i = log(u_i)/n_i and
+ * log X_i = log X_{i-1} + log t_i, X_0 = 1.  Trapezoid elements dX_i = (X_{i-1} - X_{i+1})/2
+ * with X_{N+1} = 0, i.e. dX_i = X_{i-1} (1 - t_i t_{i+1}) / 2 with t_{N+1} = 0, evaluated as
+ * log dX_i = log X_{i-1} + log1p(-exp(log t_i + log t_{i+1})) - log 2.
+ * Weights log w_i = beta logL_i + log dX_i, where the tempered term is 0 at beta = 0 (prior
+ * volumes, also for logL = -inf); log Z_r = log sum_i w_i.  Geometric-mean weights
+ * log w~_i = (1/R) sum_r log w_i; Kish ESS = (sum w~)^2 / sum w~^2.
+ * Outputs: logz[R]; logw_mean[N] and *ess unless NULL.
+ */
+static double tempered(double beta, double lL) { return beta == 0.0 ? 0.0 : beta * lL; }
+
+void or_geom(const double *dead, int64_t n_dead, const double *final_sorted, int64_t nf,
+             int m, int k, int R, double beta, uint64_t seed, uint32_t run_id, double *logz,
+             double *logw_mean, double *ess)
+{
+    const int64_t N = n_dead + nf;
+    okey key = { { (uint32_t)seed, (uint32_t)(seed >> 32) ^ run_id } };
+    double *lt = (double *)malloc(sizeof(double) * (size_t)(N + 1));     /* log t_1..t_{N+1} */
+    double *lw = (double *)malloc(sizeof(double) * (size_t)(N > 0 ? N : 1));
+    double *acc = (double *)calloc((size_t)(N > 0 ? N : 1), sizeof(double));
+    for (int r = 0; r < R; ++r) {
+        for (int64_t i = 1; i <= N; ++i) {
+            const int64_t g = i - 1;
+            const double n = (g < n_dead) ? (double)(m - (int)(g % k)) : (double)(nf - (g - n_dead));
+            double u, unused;
+            draw2(key, P_GEOM, (uint32_t)r, (uint32_t)g, 0u, 0u, &u, &unused);
+            lt[i - 1] = log(u) / n;
+        }
+        lt[N] = -INFINITY;
+        double lx = 0.0, mx = -INFINITY;       /* lx = log X_{i-1} */
+        for (int64_t i = 1; i <= N; ++i) {
+            const double lL = (i - 1 < n_dead) ? dead[i - 1] : final_sorted[i - 1 - n_dead];
+            const double ldx = lx + log1p(-exp(lt[i - 1] + lt[i])) - log(2.0);
+            lw[i - 1] = tempered(beta, lL) + ldx;
+            acc[i - 1] += lw[i - 1];
+            if (lw[i - 1] > mx) mx = lw[i - 1];
+            lx += lt[i - 1];
+        }
+        double sum = 0.0;
+        if (mx > -INFINITY)
+            for (int64_t i = 0; i < N; ++i) sum += exp(lw[i] - mx);
+        logz[r] = mx > -INFINITY ? mx + log(sum) : -INFINITY;
+    }
+    double m1 = -INFINITY;
+    for (int64_t i = 0; i < N; ++i) {
+        acc[i] /= R;
+        if (logw_mean) logw_mean[i] = acc[i];
+        if (acc[i] > m1) m1 = acc[i];
+    }
+    if (ess) {
+        double s1 = 0.0, s2 = 0.0;
+        if (m1 > -INFINITY)
+            for (int64_t i = 0; i < N; ++i) {
+                const double e = exp(acc[i] - m1);
+                s1 += e;
+                s2 += e * e;
+            }
+        *ess = s2 > 0.0 ? s1 * s1 / s2 : 0.0;
+    }
+    free(lt);
+    free(lw);
+    free(acc);
 }

@@ -73,6 +73,9 @@ def lib():
         L.or_get_state.argtypes = [C.c_void_p, _dp, _dp, _ip, _dp, _lp, _lp]
         L.or_set_state.argtypes = [C.c_void_p, _dp, _dp, _dp, C.c_int64]
         L.or_get_aux.argtypes = [C.c_void_p, _dp, _ip]
+        L.or_geom.restype = None
+        L.or_geom.argtypes = [_dp, C.c_int64, _dp, C.c_int64, C.c_int, C.c_int, C.c_int,
+                              C.c_double, C.c_uint64, C.c_uint32, _dp, C.c_void_p, C.c_void_p]
         L.or_get_dead.restype = C.c_int64
         L.or_get_dead.argtypes = [C.c_void_p, C.c_void_p, C.c_int64]
         _lib = L
@@ -222,3 +225,18 @@ class Run:
     @property
     def iter(self) -> int:
         return self.state()["iter"]
+
+
+def geom(dead, final_logL, m, k, R, beta=1.0, seed=0, run_id=0, weights=True):
+    """Post-hoc geometric uncertainty of an NS run (App. "Estimation of prior volumes and
+    propagation of geometric uncertainty"): dead = dead-point logL in death order, final_logL =
+    the final survivors' logL.  Returns (logz[R], logw_mean[N] or None, ess)."""
+    dead = np.ascontiguousarray(dead, np.float64)
+    fin = np.ascontiguousarray(np.sort(np.asarray(final_logL, np.float64)))
+    N = len(dead) + len(fin)
+    logz = np.zeros(R)
+    lw = np.zeros(max(N, 1)) if weights else None
+    ess = np.zeros(1)
+    lib().or_geom(dead, len(dead), fin, len(fin), int(m), int(k), int(R), float(beta), int(seed),
+                  int(run_id), logz, lw.ctypes.data if weights else None, ess.ctypes.data)
+    return logz, (lw[:N] if weights else None), float(ess[0])

@@ -381,3 +381,101 @@ def test_gp_loglik_invariances(oracle_lib):
     one[0, 0] += np.exp(U[0, 4])
     shifted = oracle_lib.Problem(dict(prob, gp_x=one)).loglik(U[:1])
     assert abs(shifted[0] - base[0]) > 1e-6
+
+
+# ------------------------------------------------------------------------------------------
+# post-hoc geometric uncertainty (shrinkage simulation, trapezoid weights, Kish ESS)
+# ------------------------------------------------------------------------------------------
+def _schedule(n_dead, nf, m, k):
+    """Live count at each death: the unrolled batches, then the final survivors one by one."""
+    g = np.arange(n_dead)
+    return np.concatenate([m - (g % k), nf - np.arange(nf)]).astype(float)
+
+
+def test_geom_shrinkage_law_on_a_step_likelihood(oracle_lib):
+    """A likelihood that is 0 for the first K deaths and A >> 0 after: Z ~ e^A (X_K + X_{K+1})/2,
+    so log Z - A has mean E[log X_K] - 1/(2 n_{K+1}) = -sum_{i<=K} 1/n_i - 1/(2 n_{K+1})
+    (t ~ Beta(n, 1) has E[log t] = -1/n, Var = 1/n^2)."""
+    m, k, nb, nf, K = 200, 50, 8, 150, 230
+    n_dead = nb * k
+    logL = np.where(np.arange(n_dead + nf) < K, 0.0, 400.0)
+    n = _schedule(n_dead, nf, m, k)
+    R = 600
+    z, _, _ = oracle_lib.geom(logL[:n_dead], logL[n_dead:], m, k, R, 1.0, seed=5)
+    x = z - 400.0
+    mean = -np.sum(1.0 / n[:K]) - 0.5 / n[K]
+    se = math.sqrt(np.sum(1.0 / n[:K] ** 2) / R)
+    assert abs(x.mean() - mean) < 4 * se, (x.mean(), mean, se)
+    assert abs(x.std() - math.sqrt(np.sum(1.0 / n[:K] ** 2))) < 0.15 * x.std()
+
+
+def test_geom_invariants(oracle_lib):
+    """beta = 0: the trapezoid elements telescope to (1 + X_1 - X_N)/2, within [0.95, 1]
+    (X_1 = t_1 ~ Beta(100, 1) is below 0.9 with probability 0.9^100 ~ 3e-5);
+    a constant likelihood c shifts log Z by exactly beta c; one death gives ESS = 1."""
+    m, k = 100, 20
+    rng = np.random.default_rng(2)
+    dead = np.sort(rng.normal(size=6 * k))
+    fin = np.sort(rng.normal(size=m - k)) + 3
+    z0, _, _ = oracle_lib.geom(dead, fin, m, k, 50, 0.0, seed=1)
+    assert np.all((z0 <= 0) & (z0 >= math.log(0.5 * (1 + 0.9))))
+    c = np.full(len(dead), 2.5)
+    zc, _, _ = oracle_lib.geom(c, np.full(m - k, 2.5), m, k, 50, 1.0, seed=1)
+    zc0, _, _ = oracle_lib.geom(c, np.full(m - k, 2.5), m, k, 50, 0.0, seed=1)
+    assert np.allclose(zc - zc0, 2.5, atol=1e-12)
+    _, _, e1 = oracle_lib.geom(np.array([1.0]), np.array([]), 10, 1, 20, 1.0, seed=3)
+    assert abs(e1 - 1.0) < 1e-12
+
+
+def test_geom_ess_on_a_geometric_tail(oracle_lib):
+    """With equal likelihoods on a long tail of deaths at a constant live count n, the
+    weights are the trapezoid elements of a geometric sequence of ratio ~e^(-1/n), whose Kish
+    ESS is (1 + q)/(1 - q) ~ 2n; a single dominant point gives ESS ~ 1."""
+    n, nd = 200, 20000
+    z, lw, ess = oracle_lib.geom(np.zeros(nd), np.array([]), n, 1, 40, 1.0, seed=9)
+    assert 0.9 * 2 * n < ess < 1.1 * 2 * n, ess
+    dead = np.zeros(500)
+    dead[250] = 50.0
+    _, _, e2 = oracle_lib.geom(dead, np.array([]), n, 1, 40, 1.0, seed=9)
+    assert 1.0 <= e2 < 1.001
+
+
+def test_geom_brute_force_on_tiny_runs(oracle_lib):
+    """Tiny runs recomputed in linear space straight from the definitions (X_i = prod t,
+    dX_i = (X_{i-1} - X_{i+1})/2 with X_{N+1} = 0, w = L^beta dX, geometric-mean weights,
+    Kish ESS), with the shrinkage draws u taken from the Philox stream the known-answer tests
+    pin (purpose 6, index r, counter word i-1).  Includes a logL = -inf death at beta = 0, where
+    the weight is the prior volume element."""
+    cases = [  # m, k, dead, final survivors, beta
+        (3, 1, [-2.0, -1.0], [0.5, -0.5], 1.0),
+        (5, 2, [-3.0, -2.5, -1.0, -0.2], [0.1, 0.4, 0.3], 0.7),
+        (4, 2, [-np.inf, -1.0], [0.0, 2.0], 0.0),
+    ]
+    R, seed, run_id = 4, 77, 3
+    for m, k, dead, fin, beta in cases:
+        fin_s = sorted(fin)
+        nf = len(fin)
+        L = list(dead) + fin_s
+        N = len(L)
+        n = [m - (g % k) for g in range(len(dead))] + [nf - q for q in range(nf)]
+        logz = []
+        logw = np.zeros((R, N))
+        for r in range(R):
+            X = [1.0]
+            for g in range(N):
+                u = oracle_lib.uniform_pair(seed, run_id, 6, r, g, 0, 0)[0]
+                X.append(X[-1] * u ** (1.0 / n[g]))
+            X.append(0.0)
+            w = []
+            for i in range(1, N + 1):
+                dX = (X[i - 1] - X[i + 1]) / 2
+                Lb = 1.0 if beta == 0 else math.exp(beta * L[i - 1])
+                w.append(Lb * dX)
+                logw[r, i - 1] = math.log(w[-1]) if w[-1] > 0 else -np.inf
+            logz.append(math.log(sum(w)))
+        gm = np.exp(logw.mean(axis=0))
+        ess = gm.sum() ** 2 / (gm ** 2).sum()
+        z, lwm, e = oracle_lib.geom(np.array(dead), np.array(fin), m, k, R, beta, seed, run_id)
+        assert np.allclose(z, logz, rtol=1e-13, atol=1e-13), (z, logz)
+        assert np.allclose(lwm, logw.mean(axis=0), rtol=1e-12, atol=1e-13)
+        assert abs(e - ess) < 1e-12 * ess
