@@ -734,8 +734,9 @@ int64_t or_get_dead(const void *rr, double *out, int64_t cap)
 /*
  * Deaths i = 1..N in likelihood order: the dead record (batch after batch; the j-th death of a
  * batch has n = m - (j-1) live points) followed by the final survivors in ascending logL with
- * n = nf, nf-1, ..., 1.  Replica r draws shrinkages t_i = u_i^(1/n_i), u_i uniform (Philox
- * purpose GEOM, index r, counter word i-1), so log t_i = log(u_i)/n_i and
+ * n = nf, nf-1, ..., 1.  Replica r draws shrinkages t_i = u_i^(1/n_i), u_i uniform: deaths
+ * 2h+1 and 2h+2 take the two uniforms of Philox (purpose GEOM, index r, counter word h), so
+ * log t_i = log(u_i)/n_i and
  * log X_i = log X_{i-1} + log t_i, X_0 = 1.  Trapezoid elements dX_i = (X_{i-1} - X_{i+1})/2
  * with X_{N+1} = 0, i.e. dX_i = X_{i-1} (1 - t_i t_{i+1}) / 2 with t_{N+1} = 0, evaluated as
  * log dX_i = log X_{i-1} + log1p(-exp(log t_i + log t_{i+1})) - log 2.
@@ -759,9 +760,9 @@ void or_geom(const double *dead, int64_t n_dead, const double *final_sorted, int
         for (int64_t i = 1; i <= N; ++i) {
             const int64_t g = i - 1;
             const double n = (g < n_dead) ? (double)(m - (int)(g % k)) : (double)(nf - (g - n_dead));
-            double u, unused;
-            draw2(key, P_GEOM, (uint32_t)r, (uint32_t)g, 0u, 0u, &u, &unused);
-            lt[i - 1] = log(u) / n;
+            double ua, ub;
+            draw2(key, P_GEOM, (uint32_t)r, (uint32_t)(g >> 1), 0u, 0u, &ua, &ub);
+            lt[i - 1] = log((g & 1) ? ub : ua) / n;
         }
         lt[N] = -INFINITY;
         double lx = 0.0, mx = -INFINITY;       /* lx = log X_{i-1} */

@@ -444,8 +444,8 @@ def test_geom_brute_force_on_tiny_runs(oracle_lib):
     """Tiny runs recomputed in linear space straight from the definitions (X_i = prod t,
     dX_i = (X_{i-1} - X_{i+1})/2 with X_{N+1} = 0, w = L^beta dX, geometric-mean weights,
     Kish ESS), with the shrinkage draws u taken from the Philox stream the known-answer tests
-    pin (purpose 6, index r, counter word i-1).  Includes a logL = -inf death at beta = 0, where
-    the weight is the prior volume element."""
+    pin (purpose 6, index r, counter word h for deaths 2h+1 and 2h+2).  Includes a logL = -inf
+    death at beta = 0, where the weight is the prior volume element."""
     cases = [  # m, k, dead, final survivors, beta
         (3, 1, [-2.0, -1.0], [0.5, -0.5], 1.0),
         (5, 2, [-3.0, -2.5, -1.0, -0.2], [0.1, 0.4, 0.3], 0.7),
@@ -463,7 +463,7 @@ def test_geom_brute_force_on_tiny_runs(oracle_lib):
         for r in range(R):
             X = [1.0]
             for g in range(N):
-                u = oracle_lib.uniform_pair(seed, run_id, 6, r, g, 0, 0)[0]
+                u = oracle_lib.uniform_pair(seed, run_id, 6, r, g // 2, 0, 0)[g % 2]
                 X.append(X[-1] * u ** (1.0 / n[g]))
             X.append(0.0)
             w = []
