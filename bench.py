@@ -207,6 +207,89 @@ def bench_batch(args):
     B.close()
 
 
+# The geometric-uncertainty kernels are bound by vector-ALU issue (Philox, FP64 log, exp and
+# log1p per replica-death; no HBM stream).  VALU lane-instructions per replica-death of one
+# ns_geom_uncertainty call (SQ_INSTS_VALU over its five kernels x 64 lanes / (R N)), recorded
+# for the kernel source with this sha256 prefix; the peak is one lane-instruction per lane per
+# cycle: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
+GEOM_VALU_PER_UNIT = 455.2
+GEOM_SOURCE_SHA = "73c14d3bbef4cd9c"
+VALU_PEAK = 256 * 4 * 16 * 2.4e9
+
+
+def geom_ops():
+    import hashlib
+    src = os.path.join(ROOT, "paper_2601_23252_amd", "csrc", "nss_post.hip")
+    with open(src, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()[:16]
+    return GEOM_VALU_PER_UNIT if sha == GEOM_SOURCE_SHA else None
+
+
+def bench_geom(args):
+    """Post-hoc geometric uncertainty of one full mixture run (the d=64 workload above, BF16x3,
+    seed 0): R = 100 replicas of the shrinkage trajectory over all N deaths, log Z per replica,
+    geometric-mean weights and the Kish ESS.  The run itself is set-up (untimed); each step is one
+    ns_geom_uncertainty call, timed on the device with events around its launches."""
+    import numpy as np
+    from paper_2601_23252_amd import nss as N, problems as G
+    N.load()
+    prob = G.config3()
+    R_rep = args.replicas
+    run = N.NSRun(prob, p=args.chain_factor * prob["d"], seed=0, precision="bf16x3")
+    run.run()
+    print(f"[bench] setup run done: {run.stats()['n_dead']} dead points", file=sys.stderr,
+          flush=True)
+    for _ in range(args.warmup):
+        run.geom(R=R_rep, beta=1.0, seed=1)
+    ms, walls = [], []
+    for i in range(args.steps):
+        t0 = time.perf_counter()
+        g = run.geom(R=R_rep, beta=1.0, seed=1, timing=True)
+        walls.append(time.perf_counter() - t0)
+        ms.append(g["device_ms"])
+    n_deaths = len(g["logw_mean"])
+    units = R_rep * n_deaths
+    t = float(np.mean(ms)) / 1e3
+    out = {
+        "metric": "replica-deaths/s (post-hoc geometric uncertainty, R=100)",
+        "value": units / t, "unit": "replica-deaths/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * t, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "geom_mixture8_d64_nlive2000_k1000_R100", "replicas": R_rep,
+                   "deaths": n_deaths, "beta": 1.0,
+                   "wall_ms_with_copies": 1e3 * float(np.mean(walls))},
+        "result": {"logz_mean": float(np.mean(g["logz"])), "logz_std": float(np.std(g["logz"])),
+                   "ess": g["ess"], "sigma_from_H": run.logz()[1]},
+    }
+    ops = geom_ops()
+    if ops is not None:
+        achieved = ops * units / t
+        out["roofline"] = {"bound": "alu", "achieved": achieved / 1e12,
+                           "peak": VALU_PEAK / 1e12, "unit": "TOP/s (VALU lane-instructions)",
+                           "frac": achieved / VALU_PEAK, "traffic": None,
+                           "kernel": "ns_geom_uncertainty (k_geom_weights 71%, k_geom_sums 26%)",
+                           "valu_per_replica_death": ops}
+    else:
+        out["roofline"] = None
+    if not args.no_cpu:
+        from oracle import oracle as O
+        dead = run.dead()
+        s = run.state()
+        fin = s["logL"][s["perm"][run.k:]]
+        t0 = time.perf_counter()
+        O.geom(dead, fin, run.m, run.k, 2, 1.0, seed=1)
+        t2 = time.perf_counter() - t0
+        r_cpu = max(2, min(R_rep, int(args.cpu_seconds / max(t2 / 2, 1e-6))))
+        t0 = time.perf_counter()
+        O.geom(dead, fin, run.m, run.k, r_cpu, 1.0, seed=1)
+        tc = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": r_cpu * n_deaths / tc, "unit": "replica-deaths/s",
+                               "cores": 1, "kind": "oracle",
+                               "sample": f"{r_cpu} replicas over the same {n_deaths} deaths"}
+    print(json.dumps(out), flush=True)
+    run.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -221,10 +304,12 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--workload", default="mixture8_d64",
-                    choices=["mixture8_d64", "gp_n256", "batch256"],
+                    choices=["mixture8_d64", "gp_n256", "batch256", "geom"],
                     help="mixture8_d64: the benchmark above; gp_n256: GP hyperparameter "
                          "marginalisation (n=256, n_live=1000, k=500, p=30), FP64; batch256: "
-                         "256 independent runs of uneven d in one context")
+                         "256 independent runs of uneven d in one context; geom: post-hoc "
+                         "geometric uncertainty of a full mixture run")
+    ap.add_argument("--replicas", type=int, default=100, help="geom: shrinkage replicas")
     ap.add_argument("--max-seconds", type=float, default=120.0,
                     help="gp_n256 / batch256: stop the timed run after about this long")
     ap.add_argument("--profile-iters", type=int, default=0,
@@ -242,6 +327,9 @@ def main():
         return
     if args.workload == "batch256":
         bench_batch(args)
+        return
+    if args.workload == "geom":
+        bench_geom(args)
         return
 
     from paper_2601_23252_amd import nss as N, problems as G

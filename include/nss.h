@@ -210,6 +210,32 @@ ns_status ns_set_state(ns_ctx *ctx, const ns_state_view *view);
 /* Copy the dead-point log-likelihoods (ascending death order) to out[0..cap); *n = total. */
 ns_status ns_get_dead(ns_ctx *ctx, double *out, int64_t cap, int64_t *n);
 
+/* Post-hoc geometric uncertainty of run `run` (App. "Estimation of prior volumes and
+ * propagation of geometric uncertainty"; the within-batch live counts of the unrolled
+ * evidence, Sec. 2.1).  The deaths, in likelihood order, are the dead record followed by the
+ * run's current survivors (the m - k live points not yet accounted) in ascending logL; the
+ * j-th death of a batch sees m - j live points (j = 0..k-1) and the q-th survivor m - k - q.
+ * Each of R replicas draws the shrinkages t = u^(1/n) (u uniform: deaths 2h+1 and 2h+2 take the
+ * two uniforms of Philox block (purpose 6, replica, h), keyed by (seed, run_id) as the run's
+ * own draws), forms the trapezoid elements dX_i = (X_{i-1} - X_{i+1}) / 2 with X_0 = 1 and
+ * X_{N+1} = 0, and the weights w_i = L_i^beta dX_i (L^0 = 1, also where L = 0).
+ * Outputs (host pointers; the call waits for the device):
+ *   logz[R]       log sum_i w_i per replica (required); its spread is the error of ln Z;
+ *   logw_mean     if not NULL, the first min(N, cap) geometric-mean log weights
+ *                 (1/R) sum_r log w_i^(r), in death order (unnormalised);
+ *   ess           if not NULL, the Kish effective sample size (sum w~)^2 / sum w~^2 of the
+ *                 geometric-mean weights w~;
+ *   n_deaths      if not NULL, N;
+ *   device_ms     if not NULL, the device time of the computation (events around it).
+ * Any beta >= 0 reweights the same run (beta-reweighting); nothing of size R x N is stored.
+ * The library keeps one device buffer of about (R / 8 + 2) N doubles per context.
+ * Errors: NS_EINVAL (NULL ctx or logz, run out of range, R outside [1, 65535], beta negative,
+ * infinite or NaN, cap < 0), NS_ESTATE if the dead record was truncated (more deaths than
+ * max_iter + 1 iterations hold), NS_EUNSUPPORTED for N >= 2^31, NS_EDEVICE. */
+ns_status ns_geom_uncertainty(ns_ctx *ctx, int32_t run, int32_t R, double beta, uint64_t seed,
+                              uint32_t run_id, double *logz, double *logw_mean, int64_t cap,
+                              double *ess, int64_t *n_deaths, double *device_ms);
+
 /* NS_FLAG_TRACE: copy the last iteration's trace, out[(j*p + s)*4 + {0,1,2,3}] = left
  * expansions, right expansions, shrink proposals, accepted, for chain j and step s. */
 ns_status ns_get_trace(ns_ctx *ctx, int32_t *out);

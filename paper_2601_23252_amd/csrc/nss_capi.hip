@@ -63,6 +63,9 @@ struct ns_ctx {
     int use_graph = 0;
     long long map_epoch = 0, graph_epoch = -1;
     hipGraphExec_t gexec = nullptr;
+    // ns_geom_uncertainty's device buffer (outputs and partial results), grown on demand
+    void *geom_buf = nullptr;
+    size_t geom_bytes = 0;
     std::string err;
 };
 
@@ -566,6 +569,7 @@ extern "C" void ns_free(ns_ctx *ctx)
     if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
     for (auto &pr : ctx->events) { (void)hipEventDestroy(pr.first); (void)hipEventDestroy(pr.second); }
     for (void *p : ctx->allocs) if (p) (void)hipFree(p);
+    if (ctx->geom_buf) (void)hipFree(ctx->geom_buf);
     if (ctx->h_iscal) (void)hipHostFree(ctx->h_iscal);
     if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
@@ -1063,6 +1067,80 @@ extern "C" ns_status ns_get_dead(ns_ctx *ctx, double *out, int64_t cap, int64_t 
     if (out && cap > 0) {
         const long long c = stored < cap ? stored : cap;
         if (c > 0) CK(hipMemcpy(out, R.dead, c * 8, hipMemcpyDeviceToHost));
+    }
+    return NS_OK;
+}
+
+extern "C" ns_status ns_geom_uncertainty(ns_ctx *ctx, int32_t run, int32_t R, double beta,
+                                         uint64_t seed, uint32_t run_id, double *logz,
+                                         double *logw_mean, int64_t cap, double *ess,
+                                         int64_t *n_deaths, double *device_ms)
+{
+    if (!run_ok(ctx, run) || !logz) return NS_EINVAL;
+    if (R < 1 || R > 65535) return fail(ctx, NS_EINVAL, "replicas must be in [1, 65535]");
+    if (!(beta >= 0.0) || beta == INFINITY) return fail(ctx, NS_EINVAL, "beta must be finite and >= 0");
+    if (cap < 0) return fail(ctx, NS_EINVAL, "cap < 0");
+    const RunHost &rh = ctx->runs[run];
+    const DevRun &D = rh.R;
+    unsigned long long nd = 0;
+    CK(hipMemcpyAsync(&nd, D.ctr + 9, 8, hipMemcpyDeviceToHost, ctx->stream));
+    CK(hipStreamSynchronize(ctx->stream));
+    if ((long long)nd > D.dead_cap)
+        return fail(ctx, NS_ESTATE, "dead record truncated: more deaths than max_iter + 1 iterations hold");
+    const long long N = (long long)nd + (rh.m - rh.k);
+    if (n_deaths) *n_deaths = N;
+    if (N >= (1ll << 31)) return fail(ctx, NS_EUNSUPPORTED, "more than 2^31 - 1 deaths");
+    const int groups = geom_groups(N, R);
+    auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+    const size_t out_bytes = up((size_t)R * 8) + up((size_t)N * 8) + up(8);
+    const size_t need = out_bytes + geom_workspace_bytes(N, R, groups);
+    if (need > ctx->geom_bytes) {
+        if (ctx->geom_buf) CK(hipFree(ctx->geom_buf));
+        ctx->geom_buf = nullptr;
+        ctx->geom_bytes = 0;
+        CK(hipMalloc(&ctx->geom_buf, need));
+        ctx->geom_bytes = need;
+    }
+    char *b = (char *)ctx->geom_buf;
+    GeomLaunch G{};
+    G.dead = D.dead;
+    G.n_dead = (long long)nd;
+    G.N = N;
+    G.logL = D.logL;
+    G.perm = D.perm;
+    G.m = rh.m;
+    G.k = rh.k;
+    G.R = R;
+    G.groups = groups;
+    G.beta = beta;
+    G.key0 = (uint32_t)seed;
+    G.key1 = (uint32_t)(seed >> 32) ^ run_id;
+    G.logz = (double *)b;
+    G.logw_mean = (double *)(b + up((size_t)R * 8));
+    G.ess = (double *)(b + up((size_t)R * 8) + up((size_t)N * 8));
+    G.ws = b + out_bytes;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (device_ms) {
+        CK(hipEventCreate(&e0));
+        CK(hipEventCreate(&e1));
+        CK(hipEventRecord(e0, ctx->stream));
+    }
+    hipError_t e = launch_geom(G, ctx->stream);
+    if (e != hipSuccess) return device_error(ctx, "geometric-uncertainty launch", e);
+    if (device_ms) CK(hipEventRecord(e1, ctx->stream));
+    CK(hipMemcpyAsync(logz, G.logz, (size_t)R * 8, hipMemcpyDeviceToHost, ctx->stream));
+    const long long nc = cap < N ? (long long)cap : N;
+    if (logw_mean && nc > 0)
+        CK(hipMemcpyAsync(logw_mean, G.logw_mean, (size_t)nc * 8, hipMemcpyDeviceToHost,
+                          ctx->stream));
+    if (ess) CK(hipMemcpyAsync(ess, G.ess, 8, hipMemcpyDeviceToHost, ctx->stream));
+    CK(hipStreamSynchronize(ctx->stream));
+    if (device_ms) {
+        float ms = 0.f;
+        CK(hipEventElapsedTime(&ms, e0, e1));
+        *device_ms = ms;
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
     }
     return NS_OK;
 }

@@ -113,4 +113,22 @@ int upw_template(int D, int upw);         // the compiled UPW that covers upw (0
 size_t hrss_lds_bytes(int D, int K);
 int dirs_rows();                          // directions per k_dirs block
 
+// Post-hoc geometric uncertainty (nss_post.hip).  Deaths: the dead record, then the final
+// survivors logL[perm[k..m-1]]; outputs logz[R], logw_mean[N], ess[1] on the device; ws holds
+// geom_workspace_bytes(N, R, groups) bytes of partial results.
+struct GeomLaunch {
+    const double *dead;
+    long long n_dead, N;
+    const double *logL;
+    const int *perm;
+    int m, k, R, groups;
+    double beta;
+    uint32_t key0, key1;
+    double *logz, *logw_mean, *ess;
+    void *ws;
+};
+size_t geom_workspace_bytes(long long N, int R, int groups);
+int geom_groups(long long N, int R);
+hipError_t launch_geom(const GeomLaunch &G, hipStream_t s);
+
 }  // namespace nss

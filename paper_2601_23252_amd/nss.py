@@ -134,6 +134,10 @@ def load(build_if_missing: bool = True):
     L.ns_stats_run.argtypes = [vp, C.c_int32, C.POINTER(ns_stats_t)]
     L.ns_get_state_run.restype = C.c_int
     L.ns_get_state_run.argtypes = [vp, C.c_int32, C.POINTER(ns_state_view)]
+    L.ns_geom_uncertainty.restype = C.c_int
+    L.ns_geom_uncertainty.argtypes = [vp, C.c_int32, C.c_int32, C.c_double, C.c_uint64,
+                                      C.c_uint32, _d, _d, C.c_int64, _d, C.POINTER(C.c_int64),
+                                      _d]
     _lib = L
     return L
 
@@ -301,6 +305,40 @@ def _state_of(ctx, run, m, d, k):
                 logX=v.logX, M=v.M, iter=int(v.iter), done=int(v.done))
 
 
+def ns_geom_uncertainty(ctx, run, R, beta, seed, run_id, n_deaths=None, timing=False):
+    """One call of the C function.  With n_deaths (= dead points + n_live - k) the mean log
+    weights are returned too.  Returns (status, logz[R], logw_mean or None, ess, N,
+    device_ms or None)."""
+    L = load()
+    n = C.c_int64(0)
+    logz = np.zeros(max(int(R), 1))
+    ess = C.c_double(0.0)
+    ms = C.c_double(0.0)
+    lw = None if n_deaths is None else np.zeros(int(n_deaths))
+    st = L.ns_geom_uncertainty(ctx, int(run), int(R), float(beta), int(seed), int(run_id),
+                               _ptr(logz), _ptr(lw), 0 if lw is None else len(lw),
+                               C.byref(ess), C.byref(n), C.byref(ms) if timing else None)
+    if lw is not None and st == NS_OK and n.value != len(lw):
+        raise NSError(NS_EINVAL, f"{n.value} deaths, {len(lw)} expected")
+    return st, logz[:int(R)], lw, ess.value, n.value, (ms.value if timing else None)
+
+
+def _geom(ctx, run, cfg, R, beta, seed, run_id, weights, timing):
+    seed = cfg.seed if seed is None else seed
+    run_id = cfg.run_id if run_id is None else run_id
+    nd = None
+    if weights:
+        st, s = ns_stats_run(ctx, run)
+        _check(st, ctx)
+        nd = int(s["n_dead"]) + cfg.n_live - cfg.k
+    st, logz, lw, ess, _, ms = ns_geom_uncertainty(ctx, run, R, beta, seed, run_id, nd, timing)
+    _check(st, ctx)
+    out = dict(logz=logz, logw_mean=lw, ess=ess)
+    if timing:
+        out["device_ms"] = ms
+    return out
+
+
 class NSRun:
     """One nested-sampling run on the GPU (wraps one ns_ctx)."""
 
@@ -370,6 +408,11 @@ class NSRun:
         _check(load().ns_get_dead(self.ctx, _ptr(out), n.value, C.byref(n)), self.ctx)
         return out
 
+    def geom(self, R=100, beta=1.0, seed=None, run_id=None, weights=True, timing=False):
+        """Post-hoc geometric uncertainty (ns_geom_uncertainty): dict(logz[R], logw_mean[N],
+        ess[, device_ms]); the shrinkage stream defaults to the run's (seed, run_id)."""
+        return _geom(self.ctx, 0, self.cfg, R, beta, seed, run_id, weights, timing)
+
     def trace(self) -> np.ndarray:
         out = np.zeros((self.k, self.p, 4), np.int32)
         _check(load().ns_get_trace(self.ctx, _ptr(out, _i32)), self.ctx)
@@ -402,6 +445,7 @@ class NSBatch:
         st, self.ctx = ns_init_batch(prs, ens, cfgs, s)
         _check(st)
         self.n = len(runs)
+        self.cfgs = cfgs
 
     def close(self):
         if getattr(self, "ctx", None):
@@ -437,3 +481,7 @@ class NSBatch:
     def state(self, run) -> dict:
         m, d, k = self.shapes[run]
         return _state_of(self.ctx, run, m, d, k)
+
+    def geom(self, run, R=100, beta=1.0, seed=None, run_id=None, weights=True, timing=False):
+        """ns_geom_uncertainty for run `run`; the stream defaults to the run's own key."""
+        return _geom(self.ctx, run, self.cfgs[run], R, beta, seed, run_id, weights, timing)
