@@ -44,7 +44,7 @@
 
 enum { P_INIT = 1, P_RESAMPLE = 2, P_DIR = 3, P_STEP = 4, P_SHRINK = 5, P_GEOM = 6 };
 enum { PRIOR_BOX = 0, PRIOR_GAUSS = 1 };
-enum { LIK_MIXTURE = 1, LIK_FUNNEL = 2, LIK_GP = 3 };
+enum { LIK_MIXTURE = 1, LIK_FUNNEL = 2, LIK_GP = 3, LIK_RG = 4 };
 
 /* ------------------------------------------------------------------------------------------ */
 /* Philox4x32-10                                                                               */
@@ -115,6 +115,7 @@ typedef struct {
     int gp_n;                 /* GP regression: n observations */
     double *gp_x;             /* n x 2 inputs */
     double *gp_y;             /* n targets */
+    double rg_alpha, rg_amp;  /* Gaussian-Rastrigin mixture weight alpha and amplitude A */
 } oprob;
 
 static int cholesky_lower(const double *A, double *L, int n)
@@ -202,6 +203,44 @@ void *or_problem_new_gp(int n, const double *X, const double *y, const double *p
     memcpy(p->gp_x, X, sizeof(double) * 2 * (size_t)n);
     memcpy(p->gp_y, y, sizeof(double) * (size_t)n);
     return p;
+}
+
+/* Gaussian-Rastrigin test likelihood (the evidence comparison of the constrained samplers):
+ * L = alpha f + (1 - alpha) g with f = exp(-|x|^2 / 2) and
+ * g = exp(-A d + A sum_i cos(2 pi x_i)), any prior.  Returns NULL on invalid input. */
+void *or_problem_new_rg(int d, int prior_kind, const double *pa, const double *pb, double alpha,
+                        double amp)
+{
+    if (d < 1 || !(alpha >= 0.0 && alpha <= 1.0) || !(amp >= 0.0)) return NULL;
+    oprob *p = (oprob *)calloc(1, sizeof(oprob));
+    p->d = d;
+    p->prior_kind = prior_kind;
+    p->pa = (double *)malloc(sizeof(double) * d);
+    p->pb = (double *)malloc(sizeof(double) * d);
+    memcpy(p->pa, pa, sizeof(double) * d);
+    memcpy(p->pb, pb, sizeof(double) * d);
+    p->lik_kind = LIK_RG;
+    p->rg_alpha = alpha;
+    p->rg_amp = amp;
+    return p;
+}
+
+/* log L of the Gaussian-Rastrigin likelihood: log(alpha e^{-|x|^2/2} + (1-alpha) e^{-A d +
+ * A sum cos(2 pi x_i)}) as a log-sum-exp of the two terms; cos(2 pi x) is taken at the
+ * distance of x to the nearest integer (the same value; the argument stays below pi, so its
+ * rounding does not grow with |x|). */
+static double rg_loglik(const oprob *p, const double *x)
+{
+    double s2 = 0.0, sc = 0.0;
+    for (int j = 0; j < p->d; ++j) {
+        s2 += x[j] * x[j];
+        sc += cos(2.0 * OR_PI * (x[j] - nearbyint(x[j])));
+    }
+    const double tf = p->rg_alpha > 0.0 ? log(p->rg_alpha) - 0.5 * s2 : -INFINITY;
+    const double tg = p->rg_alpha < 1.0 ? log1p(-p->rg_alpha) - p->rg_amp * p->d + p->rg_amp * sc
+                                        : -INFINITY;
+    const double mx = tf > tg ? tf : tg;
+    return mx + log(exp(tf - mx) + exp(tg - mx));
 }
 
 /* Prior support test. */
@@ -297,6 +336,7 @@ double or_loglik(const void *pp, const double *x)
     const oprob *p = (const oprob *)pp;
     int d = p->d;
     if (p->lik_kind == LIK_GP) return gp_loglik(p, x);
+    if (p->lik_kind == LIK_RG) return rg_loglik(p, x);
     if (p->lik_kind == LIK_MIXTURE) {
         double terms[256];
         double mx = -INFINITY;

@@ -17,7 +17,7 @@ SRC = os.path.join(HERE, "nss_oracle.c")
 LIB = os.path.join(HERE, "libnss_oracle.so")
 
 PRIOR_BOX, PRIOR_GAUSS = 0, 1
-LIK_MIXTURE, LIK_FUNNEL, LIK_GP = 1, 2, 3
+LIK_MIXTURE, LIK_FUNNEL, LIK_GP, LIK_RG = 1, 2, 3, 4
 P_INIT, P_RESAMPLE, P_DIR, P_STEP, P_SHRINK = 1, 2, 3, 4, 5
 
 _dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
@@ -53,6 +53,8 @@ def lib():
                                      C.c_void_p, C.c_void_p, C.c_void_p]
         L.or_problem_new_gp.restype = C.c_void_p
         L.or_problem_new_gp.argtypes = [C.c_int, _dp, _dp, _dp, _dp]
+        L.or_problem_new_rg.restype = C.c_void_p
+        L.or_problem_new_rg.argtypes = [C.c_int, C.c_int, _dp, _dp, C.c_double, C.c_double]
         L.or_problem_free.argtypes = [C.c_void_p]
         L.or_loglik.restype = C.c_double
         L.or_loglik.argtypes = [C.c_void_p, _dp]
@@ -113,6 +115,9 @@ class Problem:
             self.h = lib().or_problem_new(d, pk, pa, pb, LIK_MIXTURE, K, *ptrs)
         elif prob["lik"] == "funnel":
             self.h = lib().or_problem_new(d, pk, pa, pb, LIK_FUNNEL, 0, None, None, None)
+        elif prob["lik"] == "rastrigin":
+            self.h = lib().or_problem_new_rg(d, pk, pa, pb, float(prob["alpha"]),
+                                             float(prob["amp"]))
         elif prob["lik"] == "gp":
             gx = np.ascontiguousarray(prob["gp_x"], np.float64)
             gy = np.ascontiguousarray(prob["gp_y"], np.float64)

@@ -7,8 +7,9 @@ A problem is a dict with
     d                   dimension
     prior               "box" (prior_a = lower, prior_b = upper) or
                         "gauss" (prior_a = mean, prior_b = standard deviation), per coordinate
-    lik                 "mixture" (K, logw[K], mu[K,d], cov[K,d,d]) or "funnel"
-                        (v = x_0 ~ N(0, 9), x_j | v ~ N(0, e^v) for j >= 1)
+    lik                 "mixture" (K, logw[K], mu[K,d], cov[K,d,d]), "funnel"
+                        (v = x_0 ~ N(0, 9), x_j | v ~ N(0, e^v) for j >= 1), "gp" (gp_x, gp_y)
+                        or "rastrigin" (alpha, amp)
     name, and the run shape m (live points), k (deletions per iteration), p (chain length).
 
 Workloads (synthetic, seeded; the paper's experiments use real datasets that stand behind
@@ -30,6 +31,8 @@ these shapes, see the design notes):
     config5   batched serving: 256 independent runs, d uniform on {8, 16, ..., 128}; even runs
               a correlated Gaussian drawn as config2 (prior N(0, 4 I)), odd runs the funnel
               under U[-20,20]^d; m=500, k=250, p=5d each
+    rastrigin_gauss   L = alpha N-shaped f + (1 - alpha) Rastrigin-shaped g under U[-5.14,5.14]^d,
+              A = 10; m=1000, k=500, p=5d
 """
 from __future__ import annotations
 
@@ -127,6 +130,17 @@ def gp_problem(seed: int = 1004, n: int = 256, m: int = 1000, k: int = 500, p=No
     return dict(name=f"gp_n{n}", d=d, prior="box", prior_a=np.full(d, np.log(lo)),
                 prior_b=np.full(d, np.log(hi)), lik="gp", K=0, gp_x=X, gp_y=y, m=m, k=k,
                 p=5 * d if p is None else p)
+
+
+def rastrigin_gauss(d: int, alpha: float, r: float = 5.14, amp: float = 10.0, m: int = 1000,
+                    k: int = 500, p=None):
+    """The Gaussian-Rastrigin test likelihood L = alpha f + (1 - alpha) g under the uniform prior
+    on [-r, r]^d (the paper's constrained-sampler evidence comparison): f a unit Gaussian, g the
+    Rastrigin-shaped exp(-A d + A sum cos(2 pi x_i)) with A = amp.  d in {2, 4, 10, 30, 100}
+    (the paper also uses 300), 1000 live points."""
+    return dict(name=f"rastrigin_d{d}_a{alpha:g}", d=d, prior="box", prior_a=np.full(d, -r),
+                prior_b=np.full(d, r), lik="rastrigin", alpha=float(alpha), amp=float(amp),
+                K=0, m=m, k=k, p=5 * d if p is None else p)
 
 
 def config4(seed: int = 1004):

@@ -479,3 +479,52 @@ def test_geom_brute_force_on_tiny_runs(oracle_lib):
         assert np.allclose(z, logz, rtol=1e-13, atol=1e-13), (z, logz)
         assert np.allclose(lwm, logw.mean(axis=0), rtol=1e-12, atol=1e-13)
         assert abs(e - ess) < 1e-12 * ess
+
+
+# ------------------------------------------------------------------------------------------
+# Gaussian-Rastrigin test likelihood (evidence comparison of constrained samplers)
+# ------------------------------------------------------------------------------------------
+def test_rastrigin_loglik_special_points_and_limits(oracle_lib):
+    """At the origin both terms are 1 (log L = 0); at a lattice point e_1 the Rastrigin term is
+    1 and the Gaussian e^{-1/2}; at (1/2, 0, ...) the cosine is -1 (g = e^{-2A}).  alpha = 1 is
+    the unnormalised unit Gaussian (scipy's density + d/2 log 2 pi), and alpha = 0 is separable:
+    the d-dimensional log L is the sum of the one-dimensional ones."""
+    from paper_2601_23252_amd import problems as G
+    d, a, A = 6, 0.3, 10.0
+    P = oracle_lib.Problem(G.rastrigin_gauss(d, a))
+    e1 = np.zeros(d); e1[0] = 1.0
+    h = np.zeros(d); h[0] = 0.5
+    got = P.loglik(np.stack([np.zeros(d), e1, h, -3 * e1]))
+    want = [0.0, math.log(a * math.exp(-0.5) + 1 - a),
+            math.log(a * math.exp(-0.125) + (1 - a) * math.exp(-2 * A)),
+            math.log(a * math.exp(-4.5) + 1 - a)]
+    assert np.allclose(got, want, rtol=1e-14, atol=1e-14), (got, want)
+    rng = np.random.default_rng(4)
+    X = rng.uniform(-5.14, 5.14, (50, d))
+    P1 = oracle_lib.Problem(G.rastrigin_gauss(d, 1.0))
+    ref = stats.multivariate_normal(np.zeros(d), np.eye(d)).logpdf(X) + 0.5 * d * math.log(2 * math.pi)
+    assert np.allclose(P1.loglik(X), ref, rtol=1e-13, atol=1e-12)
+    P0 = oracle_lib.Problem(G.rastrigin_gauss(d, 0.0))
+    Q0 = oracle_lib.Problem(G.rastrigin_gauss(1, 0.0))
+    sep = sum(Q0.loglik(X[:, j:j + 1]) for j in range(d))
+    assert np.allclose(P0.loglik(X), sep, rtol=1e-13, atol=1e-11)
+
+
+def test_rastrigin_semi_analytic_evidence():
+    """The Bessel-function evidence against brute-force 2-D quadrature at d = 2."""
+    for a in (0.0, 0.4, 1.0):
+        def ll(pts):
+            f = -0.5 * (pts ** 2).sum(1)
+            g = -20.0 + 10.0 * np.cos(2 * np.pi * pts).sum(1)
+            with np.errstate(divide="ignore"):
+                return np.logaddexp(np.log(a) + f, np.log1p(-a) + g)
+        brute = truth.lnz_grid_2d(ll, -5.14, 5.14, n=4001)
+        assert abs(brute - truth.lnz_rastrigin_gauss(2, a)) < 1e-6
+
+
+@pytest.mark.parametrize("d,alpha", [(2, 0.0), (2, 0.5), (2, 1.0), (4, 0.1)])
+def test_lnz_rastrigin_gauss(oracle_lib, d, alpha):
+    from paper_2601_23252_amd import problems as G
+    prob = G.rastrigin_gauss(d, alpha, m=500, k=100, p=5 * d)
+    zs = _z_scores(oracle_lib, prob, truth.lnz_rastrigin_gauss(d, alpha), range(3))
+    assert np.all(np.abs(zs) < 3.5), zs

@@ -41,3 +41,25 @@ def lnz_grid_2d(loglik, lo, hi, n=2001):
     inner = integrate.simpson(np.exp(ll - mx), x=xs, axis=1)
     tot = integrate.simpson(inner, x=xs)
     return mx + math.log(tot) - 2 * math.log(hi - lo)
+
+
+def lnz_rastrigin_gauss(d, alpha, r=5.14, amp=10.0):
+    """Semi-analytic evidence of L = alpha f + (1 - alpha) g under U[-r, r]^d (the paper's
+    evidence comparison of constrained samplers): the d-dimensional integrals factor into
+    one-dimensional ones, int_{-r}^{r} e^{-x^2/2} dx = sqrt(2 pi) erf(r / sqrt 2) and
+    int_{-r}^{r} e^{A cos 2 pi x} dx = 2 n I0(A) + 2 int_n^r e^{A cos 2 pi x} dx with n = floor(r)
+    whole periods (each period integrates to the modified Bessel value I0(A))."""
+    from scipy.special import i0e
+    n = math.floor(r)
+    tail, _ = integrate.quad(lambda x: math.exp(amp * (math.cos(2 * math.pi * x) - 1.0)), n, r,
+                             epsabs=0, epsrel=1e-13)
+    # log int e^{A cos} = A + log(2 n I0(A) e^{-A} + 2 tail e^{-A})
+    log_ig = amp + math.log(2 * n * float(i0e(amp)) + 2 * tail)
+    log_if = 0.5 * math.log(2 * math.pi) + math.log(erf(r / math.sqrt(2)))
+    terms = []
+    if alpha > 0:
+        terms.append(math.log(alpha) + d * log_if)
+    if alpha < 1:
+        terms.append(math.log1p(-alpha) - amp * d + d * log_ig)
+    mx = max(terms)
+    return mx + math.log(sum(math.exp(t - mx) for t in terms)) - d * math.log(2 * r)
