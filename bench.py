@@ -290,6 +290,100 @@ def bench_geom(args):
     run.close()
 
 
+def lnz_rastrigin_gauss(d, alpha, r=5.14, amp=10.0):
+    """Semi-analytic evidence of the Gaussian-Rastrigin workload: the d-dimensional integrals
+    factor into one-dimensional ones; the Rastrigin one is floor(r) whole periods, each the
+    modified Bessel value I0(A), plus the remainder by quadrature."""
+    from scipy import integrate
+    from scipy.special import erf, i0e
+    n = math.floor(r)
+    tail, _ = integrate.quad(lambda x: math.exp(amp * (math.cos(2 * math.pi * x) - 1.0)), n, r,
+                             epsabs=0, epsrel=1e-13)
+    log_ig = amp + math.log(2 * n * float(i0e(amp)) + 2 * tail)
+    log_if = 0.5 * math.log(2 * math.pi) + math.log(erf(r / math.sqrt(2)))
+    terms = ([math.log(alpha) + d * log_if] if alpha > 0 else []) + \
+            ([math.log1p(-alpha) - amp * d + d * log_ig] if alpha < 1 else [])
+    mx = max(terms)
+    return mx + math.log(sum(math.exp(t - mx) for t in terms)) - d * math.log(2 * r)
+
+
+# VALU lane-instructions per likelihood evaluation of the Gaussian-Rastrigin k_hrss at d=100
+# (SQ_INSTS_VALU x 64 / evaluations of the profiled launches), for the kernel source with this
+# sha256 prefix.
+RG_VALU_PER_EVAL = 53065.0
+RG_SOURCE_SHA = "3f20f7a70e975f78"
+
+
+def bench_rastrigin(args):
+    """The Gaussian-Rastrigin evidence workload: full runs at d = 100, alpha = 0.5 (n_live 1000,
+    k 500, p = 25d, FP64), timed; then one untimed run per (d, alpha) in {2, 4, 10, 30, 100} x
+    {0, 0.5, 1} for the ln Z table against the semi-analytic evidence."""
+    import hashlib
+    import numpy as np
+    import torch
+    from paper_2601_23252_amd import nss as N, problems as G
+    N.load()
+    d, alpha = 100, 0.5
+    prob = G.rastrigin_gauss(d, alpha)
+    R = N.NSRun(prob, seed=0, timing=True)
+    for w in range(args.warmup):
+        R.reset(10_000 + w)
+        R.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    evals = hrss_ms = launches = 0
+    zs = []
+    tz = lnz_rastrigin_gauss(d, alpha)
+    for sd in range(args.steps):
+        R.reset(sd)
+        R.run()
+        st = R.stats()
+        evals += st["evals"]
+        hrss_ms += st["hrss_ms"]
+        launches += st["hrss_launches"]
+        z, err, _ = R.logz()
+        zs.append((z - tz) / err)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    print(f"[bench] timed runs done in {dt:.1f} s", file=sys.stderr, flush=True)
+    table = []
+    for dd in (() if args.no_table else (2, 4, 10, 30, 100)):
+        for a in (0.0, 0.5, 1.0):
+            Q = N.NSRun(G.rastrigin_gauss(dd, a), seed=1)
+            Q.run()
+            z, err, _ = Q.logz()
+            t = lnz_rastrigin_gauss(dd, a)
+            table.append({"d": dd, "alpha": a, "logz": z, "sigma": err, "truth": t,
+                          "z": (z - t) / err})
+            Q.close()
+    print(f"[bench] ln Z table done", file=sys.stderr, flush=True)
+    src = os.path.join(ROOT, "paper_2601_23252_amd", "csrc", "nss_kernels.hip")
+    with open(src, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()[:16]
+    roof = None
+    if RG_VALU_PER_EVAL is not None and sha == RG_SOURCE_SHA and hrss_ms > 0:
+        achieved = RG_VALU_PER_EVAL * evals / (hrss_ms / 1e3)
+        roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
+                "unit": "TOP/s (VALU lane-instructions)", "frac": achieved / VALU_PEAK,
+                "traffic": None, "kernel": "k_hrss<128, FP64, Gaussian-Rastrigin>",
+                "valu_per_eval": RG_VALU_PER_EVAL,
+                "avg_launch_ms": hrss_ms / max(1, launches)}
+    out = {
+        "metric": "slice-step likelihood evals/s (Gaussian-Rastrigin, d=100, alpha=0.5)",
+        "value": evals / dt, "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * dt / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "rastrigin_gauss_d100_alpha0.5_nlive1000_k500_p25d", "d": d,
+                   "alpha": alpha, "n_live": prob["m"], "k": prob["k"], "chain_len": prob["p"]},
+        "roofline": roof,
+        "lnz": {"truth": tz, "z_scores": zs, "table": table},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(prob, prob["p"], args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+    R.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -304,12 +398,15 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--workload", default="mixture8_d64",
-                    choices=["mixture8_d64", "gp_n256", "batch256", "geom"],
+                    choices=["mixture8_d64", "gp_n256", "batch256", "geom", "rastrigin"],
                     help="mixture8_d64: the benchmark above; gp_n256: GP hyperparameter "
                          "marginalisation (n=256, n_live=1000, k=500, p=30), FP64; batch256: "
                          "256 independent runs of uneven d in one context; geom: post-hoc "
-                         "geometric uncertainty of a full mixture run")
+                         "geometric uncertainty of a full mixture run; rastrigin: the "
+                         "Gaussian-Rastrigin evidence workload at d = 100")
     ap.add_argument("--replicas", type=int, default=100, help="geom: shrinkage replicas")
+    ap.add_argument("--no-table", action="store_true",
+                    help="rastrigin: skip the untimed ln Z table over (d, alpha)")
     ap.add_argument("--max-seconds", type=float, default=120.0,
                     help="gp_n256 / batch256: stop the timed run after about this long")
     ap.add_argument("--profile-iters", type=int, default=0,
@@ -330,6 +427,9 @@ def main():
         return
     if args.workload == "geom":
         bench_geom(args)
+        return
+    if args.workload == "rastrigin":
+        bench_rastrigin(args)
         return
 
     from paper_2601_23252_amd import nss as N, problems as G

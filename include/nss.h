@@ -67,7 +67,11 @@ typedef enum {
      * over n_obs observations (x_obs[i] in R^2, y_obs[i]) with the product kernel
      * K_ab = sigma_f^2 exp(-1/2 sum_j (a_j - b_j)^2 / l_j^2 - 2 sum_j sin^2(pi (a_j - b_j)/P)
      * / l_p^2), j = 1, 2.  A Cholesky factorisation that breaks down gives log L = -inf. */
-    NS_LIK_GP = 3
+    NS_LIK_GP = 3,
+    /* Gaussian-Rastrigin test likelihood (the evidence comparison of constrained samplers):
+     * L = alpha exp(-|x|^2 / 2) + (1 - alpha) exp(-A d + A sum_i cos(2 pi x_i)), alpha in
+     * [0, 1], A = amp >= 0 (the paper: A = 10, uniform prior on [-5.14, 5.14]^d).  FP64. */
+    NS_LIK_GAUSS_RASTRIGIN = 4
 } ns_lik_kind;
 
 /* Arithmetic of the likelihood evaluations inside the chains. */
@@ -107,6 +111,8 @@ typedef struct {
     int32_t n_obs;      /* NS_LIK_GP: observations, 1 <= n_obs <= 256 */
     const double *x_obs;/* NS_LIK_GP: [n_obs * 2] inputs, row-major */
     const double *y_obs;/* NS_LIK_GP: [n_obs] targets */
+    double alpha;       /* NS_LIK_GAUSS_RASTRIGIN: weight of the Gaussian term, 0..1 */
+    double amp;         /* NS_LIK_GAUSS_RASTRIGIN: amplitude A >= 0 */
 } ns_energy;
 
 typedef struct {

@@ -210,9 +210,18 @@ static ns_status prepare_problem(ns_ctx *ctx, RunHost &rh, const ns_prior *prior
     P.pa = dpa;
     P.pb = dpb;
     P.lik_kind = en->kind == NS_LIK_MIXTURE ? LIK_MIXTURE
-                                            : (en->kind == NS_LIK_GP ? LIK_GP : LIK_FUNNEL);
+                 : en->kind == NS_LIK_GP      ? LIK_GP
+                 : en->kind == NS_LIK_GAUSS_RASTRIGIN ? LIK_RG
+                                              : LIK_FUNNEL;
     if (P.lik_kind == LIK_FUNNEL) {
         P.K = 0;
+        return NS_OK;
+    }
+    if (P.lik_kind == LIK_RG) {
+        P.K = 0;
+        P.rg_la = en->alpha > 0.0 ? log(en->alpha) : -INFINITY;
+        P.rg_l1a = en->alpha < 1.0 ? log1p(-en->alpha) : -INFINITY;
+        P.rg_amp = en->amp;
         return NS_OK;
     }
     if (P.lik_kind == LIK_GP) {
@@ -600,6 +609,12 @@ static ns_status validate_run(const ns_prior *prior, const ns_energy *energy, co
             return NS_EINVAL;
         }
         if (energy->n_obs > kGpMaxObs) { msg = "GP n_obs > 256"; return NS_EUNSUPPORTED; }
+    } else if (energy->kind == NS_LIK_GAUSS_RASTRIGIN) {
+        if (!(energy->alpha >= 0.0 && energy->alpha <= 1.0) || !(energy->amp >= 0.0) ||
+            energy->amp == INFINITY) {
+            msg = "Gaussian-Rastrigin likelihood needs 0 <= alpha <= 1 and finite amp >= 0";
+            return NS_EINVAL;
+        }
     } else if (energy->kind != NS_LIK_FUNNEL) {
         msg = "unknown likelihood kind";
         return NS_EINVAL;

@@ -17,7 +17,7 @@ constexpr int kMaxLive = 8192;
 enum Mode { MODE_FP64 = 0, MODE_BF16 = 1, MODE_FP16 = 2, MODE_BF16X3 = 3, MODE_FP16X3 = 4,
             MODE_FP32 = 5 };
 enum PriorKind { PRIOR_BOX = 0, PRIOR_GAUSS = 1 };
-enum LikKind { LIK_MIXTURE = 1, LIK_FUNNEL = 2, LIK_GP = 3 };
+enum LikKind { LIK_MIXTURE = 1, LIK_FUNNEL = 2, LIK_GP = 3, LIK_RG = 4 };
 constexpr int kGpMaxObs = 256;   // GP observations per problem
 
 // Problem, resident on the device for the lifetime of a context.
@@ -44,6 +44,8 @@ struct DevProblem {
     int gp_n;              // GP: observations
     const double *gp_x;    // GP: [n][2] inputs
     const double *gp_y;    // GP: [n] targets
+    double rg_la, rg_l1a;  // Gaussian-Rastrigin: log alpha, log(1 - alpha) (-inf at 0 / 1)
+    double rg_amp;         // Gaussian-Rastrigin: A
 };
 
 // Run state on the device.

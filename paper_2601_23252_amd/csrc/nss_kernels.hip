@@ -437,11 +437,42 @@ __device__ void funnel_eval64(const DevProblem &P, const Tile &T, const int *mas
     __syncthreads();
 }
 
+// Gaussian-Rastrigin test likelihood, FP64: log(alpha e^{-|x|^2/2} + (1 - alpha)
+// e^{-A d + A sum cos(2 pi x_i)}) as a log-sum-exp of the two terms; cos(2 pi x) = cospi(2x)
+// (no rounding of the argument by pi).  Each wave takes 4 rows, lane l coordinates l, l+64.
+template <int D>
+__device__ void rg_eval64(const DevProblem &P, const Tile &T, const int *mask, double *out)
+{
+    constexpr int LDC = D + 1;
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    __syncthreads();
+    for (int rr = 0; rr < 4; ++rr) {
+        const int r = 4 * w + rr;
+        if (!mask[r]) continue;
+        double s2 = 0.0, sc = 0.0;
+        for (int a = l; a < P.d; a += 64) {
+            const double x = T.cand[r * LDC + a];
+            s2 += x * x;
+            sc += cospi(2.0 * x);
+        }
+        s2 = wave_sum_fast(s2);
+        sc = wave_sum_fast(sc);
+        if (l == 0) {
+            const double tf = P.rg_la - 0.5 * s2;
+            const double tg = P.rg_l1a - P.rg_amp * P.d + P.rg_amp * sc;
+            const double mx = fmax(tf, tg);
+            out[r] = mx + log(exp(tf - mx) + exp(tg - mx));
+        }
+    }
+    __syncthreads();
+}
+
 template <int D, int LIK>
 __device__ __forceinline__ void eval64(const DevProblem &P, const Tile &T, const int *mask,
                                        double *out)
 {
     if constexpr (LIK == LIK_MIXTURE) mix_eval64<D>(P, T, mask, out);
+    else if constexpr (LIK == LIK_RG) rg_eval64<D>(P, T, mask, out);
     else funnel_eval64<D>(P, T, mask, out);
 }
 
@@ -1558,6 +1589,12 @@ static hipError_t hrss_t(const Launch &L, hipStream_t s)
             if (D == 32) return FN<32, MODE_FP64, LIK_FUNNEL, 1>(__VA_ARGS__);                \
             if (D == 64) return FN<64, MODE_FP64, LIK_FUNNEL, 1>(__VA_ARGS__);                \
             return FN<128, MODE_FP64, LIK_FUNNEL, 1>(__VA_ARGS__);                            \
+        }                                                                                     \
+        if (lik == LIK_RG) {                                                                  \
+            if (mode != MODE_FP64) return hipErrorNotSupported;                               \
+            if (D == 32) return FN<32, MODE_FP64, LIK_RG, 1>(__VA_ARGS__);                    \
+            if (D == 64) return FN<64, MODE_FP64, LIK_RG, 1>(__VA_ARGS__);                    \
+            return FN<128, MODE_FP64, LIK_RG, 1>(__VA_ARGS__);                                \
         }                                                                                     \
         if (lik != LIK_MIXTURE) return hipErrorInvalidValue;                                  \
         if (mode == MODE_FP64) {                                                              \

@@ -20,7 +20,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "nss.h")
 
 NS_OK, NS_DONE, NS_EINVAL, NS_ENOMEM, NS_EDEVICE, NS_ESTATE, NS_EUNSUPPORTED = 0, 1, -1, -2, -3, -4, -5
 NS_PRIOR_BOX, NS_PRIOR_GAUSS_DIAG = 0, 1
-NS_LIK_MIXTURE, NS_LIK_FUNNEL, NS_LIK_GP = 1, 2, 3
+NS_LIK_MIXTURE, NS_LIK_FUNNEL, NS_LIK_GP, NS_LIK_GAUSS_RASTRIGIN = 1, 2, 3, 4
 NS_FP64, NS_MIXED_BF16, NS_MIXED_FP16, NS_MIXED_BF16X3, NS_MIXED_FP16X3, NS_MIXED_FP32 = 0, 1, 2, 3, 4, 5
 NS_FLAG_TRACE, NS_FLAG_TIMING, NS_FLAG_INLINE_DIRECTIONS, NS_FLAG_GRAPH = 1, 2, 4, 8
 PRECISIONS = {"fp64": NS_FP64, "bf16": NS_MIXED_BF16, "fp16": NS_MIXED_FP16,
@@ -41,7 +41,8 @@ class ns_prior(C.Structure):
 
 class ns_energy(C.Structure):
     _fields_ = [("kind", C.c_int32), ("d", C.c_int32), ("n_comp", C.c_int32), ("logw", _d),
-                ("mean", _d), ("cov", _d), ("n_obs", C.c_int32), ("x_obs", _d), ("y_obs", _d)]
+                ("mean", _d), ("cov", _d), ("n_obs", C.c_int32), ("x_obs", _d), ("y_obs", _d),
+                ("alpha", C.c_double), ("amp", C.c_double)]
 
 
 class ns_config(C.Structure):
@@ -258,6 +259,9 @@ def make_structs(prob: dict):
         en = ns_energy(NS_LIK_MIXTURE, d, K, _ptr(lw), _ptr(mu), _ptr(cov))
     elif prob["lik"] == "funnel":
         en = ns_energy(NS_LIK_FUNNEL, d, 0, None, None, None)
+    elif prob["lik"] == "rastrigin":
+        en = ns_energy(NS_LIK_GAUSS_RASTRIGIN, d, 0, None, None, None, 0, None, None,
+                       float(prob["alpha"]), float(prob["amp"]))
     elif prob["lik"] == "gp":
         gx = np.ascontiguousarray(prob["gp_x"], np.float64)
         gy = np.ascontiguousarray(prob["gp_y"], np.float64)

@@ -32,7 +32,7 @@ these shapes, see the design notes):
               a correlated Gaussian drawn as config2 (prior N(0, 4 I)), odd runs the funnel
               under U[-20,20]^d; m=500, k=250, p=5d each
     rastrigin_gauss   L = alpha N-shaped f + (1 - alpha) Rastrigin-shaped g under U[-5.14,5.14]^d,
-              A = 10; m=1000, k=500, p=5d
+              A = 10; m=1000, k=500, p=25d
 """
 from __future__ import annotations
 
@@ -137,10 +137,11 @@ def rastrigin_gauss(d: int, alpha: float, r: float = 5.14, amp: float = 10.0, m:
     """The Gaussian-Rastrigin test likelihood L = alpha f + (1 - alpha) g under the uniform prior
     on [-r, r]^d (the paper's constrained-sampler evidence comparison): f a unit Gaussian, g the
     Rastrigin-shaped exp(-A d + A sum cos(2 pi x_i)) with A = amp.  d in {2, 4, 10, 30, 100}
-    (the paper also uses 300), 1000 live points."""
+    (the paper also uses 300), 1000 live points, and 25 d slice steps per replacement (the
+    slice sampler's default number of repeats in that comparison)."""
     return dict(name=f"rastrigin_d{d}_a{alpha:g}", d=d, prior="box", prior_a=np.full(d, -r),
                 prior_b=np.full(d, r), lik="rastrigin", alpha=float(alpha), amp=float(amp),
-                K=0, m=m, k=k, p=5 * d if p is None else p)
+                K=0, m=m, k=k, p=25 * d if p is None else p)
 
 
 def config4(seed: int = 1004):
