@@ -474,6 +474,72 @@ void or_hrss_chain(const void *pp, double *x, double *logL, double Lstar, const 
     }
 }
 
+/*
+ * One chain of p constrained Gaussian random-walk Metropolis steps, the alternative replacement
+ * kernel (Sec. 3.1 "Replacement strategies"; App. "Slice Sampling vs Random Walk"): the
+ * proposal is x' = x + s Lsig z with z ~ N(0, I), i.e. Gaussian with the live-set covariance
+ * scaled by s^2; it is accepted if x' lies in the prior support, passes the Metropolis test of
+ * the prior ratio (non-uniform priors: log Pi(x') > log Pi(x) + log uh) and has
+ * logL(x') > Lstar; otherwise the chain stays where it is.  z uses the draws of an HRSS
+ * direction (purpose DIR) and uh the second uniform of the step draw (purpose STEP).
+ * trace (optional, 4 ints per step): 0, 0, 1 if the proposal was evaluated, accepted (1 / 0).
+ * x and *logL are updated in place.
+ */
+void or_rw_chain(const void *pp, double *x, double *logL, double Lstar, const double *Lsig,
+                 double scale, int p_steps, uint64_t seed, uint32_t run_id, uint32_t iter,
+                 uint32_t chain, int64_t *counters, int32_t *trace)
+{
+    const oprob *p = (const oprob *)pp;
+    const int d = p->d;
+    okey key = { { (uint32_t)seed, (uint32_t)(seed >> 32) ^ run_id } };
+    double *z = (double *)malloc(sizeof(double) * d * 2);
+    double *y = z + d;
+    octr c; memset(&c, 0, sizeof c);
+    const int uniform_prior = (p->prior_kind == PRIOR_BOX);
+    for (int st = 0; st < p_steps; ++st) {
+        for (int q = 0; 2 * q < d; ++q) {
+            double ua, ub, z0, z1;
+            draw2(key, P_DIR, chain, iter, (uint32_t)st, (uint32_t)q, &ua, &ub);
+            box_muller(ua, ub, &z0, &z1);
+            z[2 * q] = z0;
+            if (2 * q + 1 < d) z[2 * q + 1] = z1;
+        }
+        for (int a = 0; a < d; ++a) {
+            double s2 = 0.0;
+            for (int b = 0; b <= a; ++b) s2 += Lsig[a * d + b] * z[b];
+            y[a] = x[a] + s2 * scale;
+        }
+        double U, uh;
+        draw2(key, P_STEP, chain, iter, (uint32_t)st, 0u, &U, &uh);
+        (void)U;
+        int evald = 0, acc = 0;
+        c.tests++;
+        if (!prior_in_support(p, y) ||
+            (!uniform_prior && !(or_logprior(p, y) > or_logprior(p, x) + log(uh)))) {
+            c.prior_rejects++;
+        } else {
+            double L = or_loglik(p, y);
+            c.evals++;
+            evald = 1;
+            if (isnan(L) || L == INFINITY) { c.nonfinite++; L = -INFINITY; }
+            if (L > Lstar) {
+                memcpy(x, y, sizeof(double) * d);
+                *logL = L;
+                acc = 1;
+            }
+        }
+        if (trace) {
+            trace[4 * st + 0] = 0; trace[4 * st + 1] = 0;
+            trace[4 * st + 2] = evald; trace[4 * st + 3] = acc;
+        }
+    }
+    free(z);
+    if (counters) {
+        counters[0] += c.evals; counters[1] += c.tests; counters[2] += c.prior_rejects;
+        counters[5] += c.nonfinite;
+    }
+}
+
 /* ------------------------------------------------------------------------------------------ */
 /* NS outer loop                                                                               */
 /* ------------------------------------------------------------------------------------------ */
@@ -496,6 +562,7 @@ typedef struct {
     double *dead;     /* dead logL record */
     int64_t n_dead, cap_dead;
     int whiten_fallbacks;
+    int replacement;  /* 0: HRSS (width = slice width); 1: random walk (width = step scale) */
 } orun;
 
 void or_run_free(void *rr)
@@ -677,8 +744,13 @@ int or_step(void *rr, int n_threads)
         int64_t cc[6] = { 0, 0, 0, 0, 0, 0 };
         memcpy(xn + (size_t)j * d, r->x + (size_t)r->parents[j] * d, sizeof(double) * d);
         ln[j] = r->logL[r->parents[j]];
-        or_hrss_chain(p, xn + (size_t)j * d, &ln[j], r->Lstar, r->Lsig, r->width, r->p_steps,
-                      r->stepout_cap, r->shrink_cap, r->seed, r->run_id, it, (uint32_t)j, cc, NULL);
+        if (r->replacement == 1)
+            or_rw_chain(p, xn + (size_t)j * d, &ln[j], r->Lstar, r->Lsig, r->width, r->p_steps,
+                        r->seed, r->run_id, it, (uint32_t)j, cc, NULL);
+        else
+            or_hrss_chain(p, xn + (size_t)j * d, &ln[j], r->Lstar, r->Lsig, r->width, r->p_steps,
+                          r->stepout_cap, r->shrink_cap, r->seed, r->run_id, it, (uint32_t)j, cc,
+                          NULL);
         c0 += cc[0]; c1 += cc[1]; c2 += cc[2]; c3 += cc[3]; c4 += cc[4]; c5 += cc[5];
     }
     (void)n_threads;
@@ -694,6 +766,16 @@ int or_step(void *rr, int n_threads)
     r->iter = it;
     select_and_account(r);
     return termination_reached(r);
+}
+
+/* Replacement kernel of the run: 0 HRSS (the default), 1 constrained random walk with the
+ * run's width as the proposal scale.  Returns 0, or -1 for an unknown kind. */
+int or_run_set_replacement(void *rr, int kind)
+{
+    orun *r = (orun *)rr;
+    if (!r || (kind != 0 && kind != 1)) return -1;
+    r->replacement = kind;
+    return 0;
 }
 
 /* Evidence with the live set's remaining contribution added (non-destructive):

@@ -71,6 +71,12 @@ def lib():
         L.or_init.argtypes = [C.c_void_p]
         L.or_step.restype = C.c_int
         L.or_step.argtypes = [C.c_void_p, C.c_int]
+        L.or_run_set_replacement.restype = C.c_int
+        L.or_run_set_replacement.argtypes = [C.c_void_p, C.c_int]
+        L.or_rw_chain.restype = None
+        L.or_rw_chain.argtypes = [C.c_void_p, _dp, _dp, C.c_double, _dp, C.c_double, C.c_int,
+                                  C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, _lp,
+                                  C.c_void_p]
         L.or_logz.argtypes = [C.c_void_p, _dp]
         L.or_get_state.argtypes = [C.c_void_p, _dp, _dp, _ip, _dp, _lp, _lp]
         L.or_set_state.argtypes = [C.c_void_p, _dp, _dp, _dp, C.c_int64]
@@ -157,12 +163,25 @@ class Problem:
                             int(chain), ctr, tr.ctypes.data if trace else None)
         return x, float(lv[0]), ctr, tr
 
+    def rw_chain(self, x, logL, Lstar, Lsig, scale, p, seed, run_id, it, chain, trace=False):
+        """One chain of p constrained random-walk steps; returns (x, logL, counters[6],
+        trace or None)."""
+        x = np.array(x, np.float64, copy=True)
+        lv = np.array([logL], np.float64)
+        ctr = np.zeros(6, np.int64)
+        tr = np.zeros((p, 4), np.int32) if trace else None
+        lib().or_rw_chain(self.h, x, lv, float(Lstar), np.ascontiguousarray(Lsig, np.float64),
+                          float(scale), int(p), int(seed), int(run_id), int(it), int(chain), ctr,
+                          tr.ctypes.data if trace else None)
+        return x, float(lv[0]), ctr, tr
+
 
 class Run:
     """One NS run of the oracle: init, step until done, logz."""
 
     def __init__(self, problem: Problem, m, k, p, width, seed, run_id=0, term_frac=1e-3,
-                 stepout_cap=10, shrink_cap=100, threads=1):
+                 stepout_cap=10, shrink_cap=100, threads=1, replacement="hrss"):
+        """replacement "hrss" (width = slice width) or "rw" (width = random-walk scale)."""
         self.P = problem
         self.m, self.k, self.p, self.d = m, k, p, problem.d
         self.threads = threads
@@ -170,6 +189,8 @@ class Run:
                                   float(term_frac), int(seed), int(run_id))
         if not self.h:
             raise ValueError("oracle rejected the run configuration")
+        if lib().or_run_set_replacement(self.h, {"hrss": 0, "rw": 1}[replacement]) != 0:
+            raise ValueError(replacement)
         self.done = False
 
     def __del__(self):

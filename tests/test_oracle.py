@@ -528,3 +528,77 @@ def test_lnz_rastrigin_gauss(oracle_lib, d, alpha):
     prob = G.rastrigin_gauss(d, alpha, m=500, k=100, p=5 * d)
     zs = _z_scores(oracle_lib, prob, truth.lnz_rastrigin_gauss(d, alpha), range(3))
     assert np.all(np.abs(zs) < 3.5), zs
+
+
+# ------------------------------------------------------------------------------------------
+# constrained Gaussian random walk (the alternative replacement kernel)
+# ------------------------------------------------------------------------------------------
+def test_rw_ball_radial_law(oracle_lib):
+    """Uniform in a d-ball (Gaussian likelihood thresholded at radius r0): the random walk's
+    draws, thinned over many chain calls, follow P(r < s) = (s/r0)^d; every state stays inside,
+    and a proposal outside the ball is a rejection (the point does not move)."""
+    from paper_2601_23252_amd import problems as G
+    d, r0 = 6, 1.5
+    prob = G.gaussian_problem(d, np.zeros(d), np.eye(d), "box", -100.0, 100.0)
+    P = oracle_lib.Problem(prob)
+    Lstar = float(P.loglik(np.r_[r0, np.zeros(d - 1)][None])[0])
+    x = np.full(d, 0.1)
+    lx = float(P.loglik(x[None])[0])
+    rs, acc = [], 0
+    for it in range(3000):
+        x, lx, ctr, tr = P.rw_chain(x, lx, Lstar, np.eye(d), 2.38 * r0 / 3 / math.sqrt(d), 10,
+                                    5, 0, it, 1, trace=True)
+        acc += tr[:, 3].sum()
+        assert np.all(tr[:, 2] == 1) and ctr[0] == 10 and ctr[1] == 10
+        rs.append(np.linalg.norm(x))
+        assert lx > Lstar
+    rs = np.array(rs)
+    assert rs.max() < r0
+    assert 0.1 < acc / 30000 < 0.9
+    assert stats.kstest(rs, lambda s: np.clip(s / r0, 0, 1) ** d).pvalue > 1e-3
+
+
+def test_rw_truncated_gaussian_prior_interval(oracle_lib):
+    """Gaussian prior N(0, 1), flat-topped constraint |x| < 1.2 (via a wide Gaussian likelihood):
+    the Metropolis prior ratio makes the stationary law the prior truncated to (-1.2, 1.2)."""
+    from paper_2601_23252_amd import problems as G
+    prob = G.gaussian_problem(1, np.zeros(1), np.eye(1), "gauss", 0.0, 1.0)
+    P = oracle_lib.Problem(prob)
+    Lstar = float(P.loglik(np.array([[1.2]]))[0])
+    x = np.array([0.2])
+    lx = float(P.loglik(x[None])[0])
+    xs = []
+    for it in range(6000):
+        x, lx, _, _ = P.rw_chain(x, lx, Lstar, np.eye(1), 1.0, 5, 8, 0, it, 0)
+        xs.append(x[0])
+    tn = stats.truncnorm(-1.2, 1.2)
+    assert stats.kstest(np.array(xs), tn.cdf).pvalue > 1e-3
+
+
+def test_rw_prior_support_rejections_counted(oracle_lib):
+    """A proposal outside the box prior is a test and a prior rejection, not an evaluation."""
+    from paper_2601_23252_amd import problems as G
+    prob = G.gaussian_problem(1, np.zeros(1), np.eye(1), "box", -0.5, 0.5)
+    P = oracle_lib.Problem(prob)
+    x, lx, ctr, tr = P.rw_chain(np.array([0.45]), float(P.loglik(np.array([[0.45]]))[0]), -50.0,
+                                np.eye(1), 5.0, 400, 3, 0, 1, 0, trace=True)
+    assert ctr[1] == 400 and ctr[0] + ctr[2] == 400 and ctr[2] > 100
+    assert ctr[0] == tr[:, 2].sum()
+    assert np.all(tr[tr[:, 2] == 0, 3] == 0)   # a prior rejection never moves the chain
+
+
+def test_lnz_config1_random_walk(oracle_lib):
+    """NS with the random-walk replacement (proposal N(x, (2.38^2/d) Sigma_live), p = 25 d) on
+    config 1: ln Z within 3.5 sigma of the closed form."""
+    from paper_2601_23252_amd import problems as G
+    prob = G.config1()
+    tz = truth.lnz_gauss_box_isotropic(5, 0.1, 1.0)
+    zs = []
+    for s in range(4):
+        R = oracle_lib.Run(oracle_lib.Problem(prob), 200, 50, 125, 2.38 / math.sqrt(5), s,
+                           threads=8, replacement="rw")
+        R.init()
+        R.run()
+        lz, err, _ = R.logz()
+        zs.append((lz - tz) / err)
+    assert np.all(np.abs(zs) < 3.5), zs
