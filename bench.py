@@ -384,6 +384,90 @@ def bench_rastrigin(args):
     R.close()
 
 
+def _step_costs(tr, rw):
+    """Evaluations per step (slice: both bracket ends, the expansions and the shrink proposals)
+    or, for the random walk, evaluations per accepted move (runs of steps up to and including
+    an acceptance; a chain's unfinished run is dropped)."""
+    import numpy as np
+    if not rw:
+        return (2 + tr[:, :, 0] + tr[:, :, 1] + tr[:, :, 2]).ravel().astype(float)
+    cs = np.cumsum(tr[:, :, 2], axis=1)
+    rows, cols = np.nonzero(tr[:, :, 3])
+    vals = cs[rows, cols]
+    prev = np.zeros_like(vals)
+    same = np.r_[False, rows[1:] == rows[:-1]]
+    prev[same] = vals[:-1][same[1:]]
+    return (vals - prev).astype(float)
+
+
+def bench_rw(args):
+    """Slice (HRSS) against the constrained random walk on the condition-100 Gaussian at
+    d = 10, 50, 100 (n_live 1000, k 500, FP64): HRSS with p = d steps, the random walk with
+    p = 5d proposals at scale 2.38 / sqrt(d) of the live-set covariance.  Whole runs: per-step
+    evaluation counts over every iteration (the paper's table of evaluations per step), ln Z
+    against the closed form -d ln 40, and the random-walk kernel's throughput at d = 100 with
+    its FP64 MFMA roofline."""
+    import numpy as np
+    import torch
+    from paper_2601_23252_amd import nss as N, problems as G
+    N.load()
+    table = []
+    timed = None
+    for d in (10, 50, 100):
+        prob = G.illcond_gaussian(d)
+        tz = -d * math.log(40.0)
+        row = {"d": d}
+        for kind, p in (("hrss", d), ("rw", 5 * d)):
+            # timed run (no trace), then the same trajectory again with traces for the costs
+            R = N.NSRun(prob, p=p, seed=0, timing=True, replacement=kind)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            R.run()
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            st = R.stats()
+            z, err, _ = R.logz()
+            R.close()
+            R = N.NSRun(prob, p=p, seed=0, trace=True, replacement=kind)
+            costs = []
+            done = False
+            while not done:
+                done = R.step()
+                costs.append(_step_costs(R.trace(), kind == "rw"))
+            c = np.concatenate(costs)
+            row[kind] = {"mean": float(c.mean()), "std": float(c.std()), "max": float(c.max()),
+                         "p": p, "iterations": st["iterations"], "evals": st["evals"],
+                         "tests": st["tests"], "evals_per_s": st["evals"] / dt,
+                         "kernel_ms": st["hrss_ms"] / max(1, st["hrss_launches"]),
+                         "logz": z, "z": (z - tz) / err}
+            if d == 100 and kind == "rw":
+                timed = (st, dt)
+            R.close()
+        table.append(row)
+        print(f"[bench] d={d}: slice {row['hrss']['mean']:.2f} +- {row['hrss']['std']:.2f} "
+              f"(z {row['hrss']['z']:.2f}), rw {row['rw']['mean']:.2f} +- "
+              f"{row['rw']['std']:.2f} (z {row['rw']['z']:.2f})", file=sys.stderr, flush=True)
+    st, dt = timed
+    fpe = algorithmic_flop_per_eval(1, 100)
+    hrss_s = st["hrss_ms"] / 1e3
+    achieved = st["evals"] * fpe / hrss_s
+    out = {
+        "metric": "random-walk replacement likelihood evals/s (condition-100 Gaussian, d=100)",
+        "value": st["evals"] / dt, "unit": "evals/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": 1e3 * dt, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "illcond_gaussian_d100_rw_p5d_nlive1000_k500", "d": 100,
+                   "kappa": 100, "replacement": "rw", "scale": 2.38 / 10.0,
+                   "tests_per_s": st["tests"] / dt},
+        "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": 78.6,
+                     "unit": "TFLOP/s", "frac": achieved / 78.6e12, "traffic": None,
+                     "kernel": "k_rw<128, FP64, mixture, 1>", "flop_per_eval": fpe,
+                     "avg_launch_ms": st["hrss_ms"] / max(1, st["hrss_launches"])},
+        "evals_per_step": table,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -398,12 +482,14 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--workload", default="mixture8_d64",
-                    choices=["mixture8_d64", "gp_n256", "batch256", "geom", "rastrigin"],
+                    choices=["mixture8_d64", "gp_n256", "batch256", "geom", "rastrigin",
+                             "rw"],
                     help="mixture8_d64: the benchmark above; gp_n256: GP hyperparameter "
                          "marginalisation (n=256, n_live=1000, k=500, p=30), FP64; batch256: "
                          "256 independent runs of uneven d in one context; geom: post-hoc "
                          "geometric uncertainty of a full mixture run; rastrigin: the "
-                         "Gaussian-Rastrigin evidence workload at d = 100")
+                         "Gaussian-Rastrigin evidence workload at d = 100; rw: slice against "
+                         "random-walk replacement on a condition-100 Gaussian")
     ap.add_argument("--replicas", type=int, default=100, help="geom: shrinkage replicas")
     ap.add_argument("--no-table", action="store_true",
                     help="rastrigin: skip the untimed ln Z table over (d, alpha)")
@@ -430,6 +516,9 @@ def main():
         return
     if args.workload == "rastrigin":
         bench_rastrigin(args)
+        return
+    if args.workload == "rw":
+        bench_rw(args)
         return
 
     from paper_2601_23252_amd import nss as N, problems as G

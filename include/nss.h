@@ -131,7 +131,23 @@ typedef struct {
     int32_t precision;    /* ns_precision */
     int32_t max_iter;     /* capacity of the dead-point record in iterations (>= 1) */
     int32_t flags;        /* NS_FLAG_* */
+    int32_t replacement;  /* ns_replacement: the constrained kernel that replaces deleted
+                           * points (Sec. 3.1 "Replacement strategies"); default HRSS */
 } ns_config;
+
+/* Replacement kernels.  NS_REPLACE_RW runs chain_len constrained Gaussian random-walk
+ * Metropolis steps per replacement (App. "Slice Sampling vs Random Walk"): the proposal is
+ * x' = x + s L_Sigma z, z ~ N(0, I) (Gaussian with the live-set covariance scaled by s^2),
+ * accepted if x' lies in the prior support, passes the Metropolis test of the prior ratio
+ * (non-uniform priors: log Pi(x') > log Pi(x) + log uh) and has logL > L*; otherwise the
+ * chain stays.  For it `width` is s (<= 0 selects 2.38 / sqrt(d)); the step-out and shrink
+ * caps are unused; traces record (0, 0, evaluated, accepted) per step.  Not available for
+ * NS_LIK_GP or with NS_FLAG_INLINE_DIRECTIONS (the proposals come from the per-iteration
+ * direction buffer, which must fit in 4 GiB). */
+typedef enum {
+    NS_REPLACE_HRSS = 0,
+    NS_REPLACE_RW = 1
+} ns_replacement;
 
 #define NS_FLAG_TRACE  1  /* record per-chain, per-step (left, right, shrinks, accepted) */
 #define NS_FLAG_TIMING 2  /* time every HRSS kernel with HIP events on the context's stream */

@@ -28,7 +28,7 @@ struct RunHost {
 // Runs that share one compiled HRSS kernel: (padded dimension, likelihood, precision, fragment
 // capacity).
 struct Group {
-    int D, lik, mode, upwT;
+    int D, lik, mode, upwT, rw;
     std::vector<int> runs;
 };
 
@@ -118,6 +118,7 @@ extern "C" void ns_config_default(ns_config *c)
     c->precision = NS_FP64;
     c->max_iter = 100000;
     c->flags = 0;
+    c->replacement = NS_REPLACE_HRSS;
 }
 
 // ---- host-side problem preparation (FP64) ----
@@ -498,6 +499,7 @@ static ns_status enqueue_iteration(ns_ctx *ctx)
     for (size_t g = 0; g < ctx->groups.size(); ++g) {
         const Group &G = ctx->groups[g];
         e = G.lik == LIK_GP ? launch_hrss_gp(ctx->L_hrss[g], G.mode, ctx->stream)
+            : G.rw          ? launch_rw(ctx->L_hrss[g], G.D, G.lik, G.mode, G.upwT, ctx->stream)
                             : launch_hrss(ctx->L_hrss[g], G.D, G.lik, G.mode, G.upwT, ctx->stream);
         if (e != hipSuccess) return device_error(ctx, "HRSS launch", e);
     }
@@ -633,6 +635,14 @@ static ns_status validate_run(const ns_prior *prior, const ns_energy *energy, co
         return NS_EINVAL;
     }
     if (!precision_valid(cfg->precision)) { msg = "unknown precision"; return NS_EINVAL; }
+    if (cfg->replacement != NS_REPLACE_HRSS && cfg->replacement != NS_REPLACE_RW) {
+        msg = "unknown replacement kernel";
+        return NS_EINVAL;
+    }
+    if (cfg->replacement == NS_REPLACE_RW && energy->kind == NS_LIK_GP) {
+        msg = "random-walk replacement is not implemented for the GP likelihood";
+        return NS_EUNSUPPORTED;
+    }
     if (energy->kind == NS_LIK_GP) {
         if (cfg->precision != NS_FP64 && cfg->precision != NS_MIXED_FP32) {
             msg = "GP likelihood: precision NS_FP64 or NS_MIXED_FP32";
@@ -664,7 +674,9 @@ static ns_status alloc_run(ns_ctx *ctx, int r)
     const int d = rh.d, D = rh.D, m = rh.m, k = rh.k, p = rh.p;
     R.m = m; R.m_pad = rh.m_pad; R.k = k; R.p = p;
     const double kappa = 1.3035;
+    R.rw = cfg->replacement == NS_REPLACE_RW;
     R.width = cfg->width > 0.0 ? cfg->width
+              : R.rw           ? 2.38 / sqrt((double)d)
                                : 4.0 * kappa * sqrt((double)d + 2.0) * sqrt(2.0 / (M_PI * d));
     R.stepout_cap = cfg->stepout_cap;
     R.shrink_cap = cfg->shrink_cap;
@@ -693,6 +705,10 @@ static ns_status alloc_run(ns_ctx *ctx, int r)
         rh.lik != LIK_GP) {  // GP chains draw their directions themselves
         if ((st = dalloc(ctx, &R.dirbuf, (size_t)k * p * D))) return st;
         if ((st = dalloc(ctx, &R.ubuf, (size_t)k * p * 8))) return st;
+    } else if (R.rw) {
+        return fail(ctx, NS_EUNSUPPORTED,
+                    "random-walk replacement needs the direction buffer (k p (d+8) doubles "
+                    "<= 4 GiB, no NS_FLAG_INLINE_DIRECTIONS)");
     }
     const int n = m - k;
     R.covG = n / 64 < 1 ? 1 : (n / 64 > 32 ? 32 : n / 64);
@@ -776,10 +792,12 @@ extern "C" ns_status ns_init_batch(int32_t n_runs, const ns_prior *priors,
         int g = -1;
         for (size_t i = 0; i < ctx->groups.size(); ++i) {
             const Group &G = ctx->groups[i];
-            if (G.D == rh.D && G.lik == rh.lik && G.mode == rh.mode && G.upwT == rh.upw) g = (int)i;
+            if (G.D == rh.D && G.lik == rh.lik && G.mode == rh.mode && G.upwT == rh.upw &&
+                G.rw == rh.R.rw)
+                g = (int)i;
         }
         if (g < 0) {
-            ctx->groups.push_back(Group{rh.D, rh.lik, rh.mode, rh.upw, {}});
+            ctx->groups.push_back(Group{rh.D, rh.lik, rh.mode, rh.upw, rh.R.rw, {}});
             g = (int)ctx->groups.size() - 1;
         }
         ctx->groups[g].runs.push_back(r);

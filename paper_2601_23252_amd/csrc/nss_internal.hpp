@@ -73,6 +73,7 @@ struct DevRun {
     unsigned long long *prof;  // per-phase cycle counters of the HRSS kernel (timing builds)
     double *dirbuf;        // [k][p][D] directions of the current iteration, or null (inline)
     double *ubuf;          // [k][p][8] per-step default plan (tL0, uh, 6 shrink), with dirbuf
+    int rw;                // replacement by constrained random walk (width = its scale)
     int C;                 // chains per HRSS workgroup
     int covG;              // survivor groups of the covariance partial sums
     double *part1, *part2; // covariance partials [covG][D], [covG][ntile][256]
@@ -103,6 +104,8 @@ hipError_t launch_select(const Launch &L, int op, hipStream_t s);
 hipError_t launch_cov(const Launch &cov, const Launch &one, int D, hipStream_t s);
 hipError_t launch_dirs(const Launch &L, int D, hipStream_t s);
 hipError_t launch_hrss(const Launch &L, int D, int lik, int mode, int upw, hipStream_t s);
+// the random-walk replacement kernel (same grid and tile evaluators as the HRSS kernel)
+hipError_t launch_rw(const Launch &L, int D, int lik, int mode, int upw, hipStream_t s);
 hipError_t launch_logz(const Launch &L, hipStream_t s);
 // GP likelihood (nss_gp.hip): chains one per workgroup (map: (run, chain)); evaluation one
 // point per workgroup (map: (run, point)), from_run = 1 evaluates the run's live set

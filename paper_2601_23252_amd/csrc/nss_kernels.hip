@@ -910,8 +910,9 @@ __global__ __launch_bounds__(1024) void k_chol(Launch Lc)
 
 // ------------------------------------------------------------------------------------------
 // directions of every chain and step of the iteration (they do not depend on the chains'
-// outcomes): z ~ N(0, I_d) from Philox purpose DIR, v = L z / |z| (unit Mahalanobis length),
-// dirbuf[(j p + s) D + a], zero for a >= d.  64 directions per workgroup.
+// outcomes): z ~ N(0, I_d) from Philox purpose DIR, v = L z / |z| (unit Mahalanobis length;
+// random-walk runs: the proposal step v = s L z), dirbuf[(j p + s) D + a], zero for a >= d.
+// 64 directions per workgroup.
 // ------------------------------------------------------------------------------------------
 constexpr int kDirRows = 64;
 constexpr int kStepU = 8;                 // per step: tL0, uh, default shrink proposals 0..5
@@ -1008,7 +1009,8 @@ __global__ __launch_bounds__(256) void k_dirs(Launch Lc)
             const double *z = zs + r * (D + 1);
             double s2 = 0.0;
             for (int b = 0; b <= a; ++b) s2 += Lr[b] * z[b];
-            v = s2 / nz[r];
+            // HRSS: unit Mahalanobis length; random walk: the proposal step s L z
+            v = R.rw ? s2 * R.width : s2 / nz[r];
         }
         R.dirbuf[idx * D + a] = v;
     }
@@ -1469,6 +1471,230 @@ __global__ __launch_bounds__(256) void k_hrss(Launch Lc)
 }
 
 // ------------------------------------------------------------------------------------------
+// the k chains of the random-walk replacement
+// ------------------------------------------------------------------------------------------
+// Constrained Gaussian random-walk Metropolis: step st of chain j proposes x + u_{j,st} with
+// u = s L z from the direction buffer; the proposal is accepted if it is in the prior support,
+// passes the prior-ratio test (Gaussian prior: log Pi(x') > log Pi(x) + log uh, uh from the step
+// plan) and has logL > L*.  Same grid, tile and evaluators as k_hrss: chain c <-> wave c.  While
+// proposals are rejected the chain stays, so the proposals of steps st, st+1, ... all start
+// from the current point and a round plans up to four of them; the plan is exact up to its
+// first acceptance, the rest is discarded uncounted.  Mixed precision re-checks near-threshold
+// rows in FP64 exactly as the HRSS kernel does.
+template <int D, int MODE, int LIK, int UPW>
+__global__ __launch_bounds__(256) void k_rw(Launch Lc)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int2 bm = Lc.map[blockIdx.x];
+    const DevProblem P = Lc.P[bm.x];
+    const DevRun R = Lc.R[bm.x];
+    const int C = R.C;
+    if (R.iscal[0]) return;
+    if (R.iscal[2] <= 0) return;
+    constexpr int LDC = D + 1, LDC32 = D + 4;
+    constexpr int NA = (D + 63) / 64;
+    constexpr int NP = NPOf<MODE>::v;
+    const HLayout lay = hrss_layout(D, P.K);
+    const Tile T = tile_of(smem, lay);
+    double *scand = T.cand;
+    float *scand32 = T.cand32;
+    int *smask = T.mask;
+
+    const int tid = threadIdx.x, w = uniform_i(tid >> 6), l = tid & 63;
+    const int d = P.d;
+    const double Lstar = R.scal[0];
+    const int t0 = R.iscal[1], nsurv = R.iscal[2];
+    const uint32_t it = (uint32_t)R.iscal[3] + 1u;
+    const int p = R.p;
+    const bool box = (P.prior_kind == PRIOR_BOX);
+
+    stage_problem<D>(P, T);
+    if (tid < kRows) { smask[tid] = 0; T.rc[tid] = 0; }
+    for (int i = tid; i < kRows * LDC; i += 256) scand[i] = 0.0;
+    for (int i = tid; i < kRows * LDC32; i += 256) scand32[i] = 0.f;
+    WFrag<D, UPW, NP> wr;
+    if constexpr (MODE != MODE_FP64) load_wfrag<D, UPW, NP>(P, wr);
+
+    const int j = bm.y * C + w;
+    const bool has_chain = (w < C) && (j < R.k);
+    double x0r[NA], par[NA], pbr[NA];
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+        const int a = l + 64 * i;
+        x0r[i] = 0.0;
+        par[i] = (a < D) ? P.pa[a] : 0.0;
+        pbr[i] = (a < D) ? P.pb[a] : 1.0;
+    }
+    int step = 0;
+    double logL0 = -INFINITY, lp0 = 0.0;   // lp0: log prior density of the current point
+    unsigned long long c_evals = 0, c_tests = 0, c_prej = 0, c_nonfin = 0, c_rc = 0, c_viol = 0;
+    if (has_chain) {
+        double u, unused;
+        draw2(R.key0, R.key1, PUR_RESAMPLE, (uint32_t)j, it, 0u, 0u, u, unused);
+        int qi = (int)floor(u * (double)nsurv);
+        if (qi > nsurv - 1) qi = nsurv - 1;
+        const int parent = R.perm[t0 + qi];
+        if (l == 0) R.parents[j] = parent;
+        double lp = 0.0;
+#pragma unroll
+        for (int i = 0; i < NA; ++i) {
+            const int a = l + 64 * i;
+            if (a < d) {
+                x0r[i] = R.X[(size_t)a * R.m_pad + parent];
+                const double zt = (x0r[i] - par[i]) / pbr[i];
+                lp += -0.5 * zt * zt;
+            }
+        }
+        if (!box) lp0 = wave_sum_fast(lp) + P.logprior_norm;
+        logL0 = R.logL[parent];
+    }
+    __syncthreads();
+    const Guard guard = {Lstar, P.guard_rel, P.guard_abs, P.cmax32};
+
+    for (;;) {
+        const bool act = has_chain && step < p;
+        const int np = act ? min(kSlots, p - step) : 0;   // proposals planned this round
+        int ok[kSlots];
+        double lpv[kSlots];
+#pragma unroll
+        for (int sl = 0; sl < kSlots; ++sl) { ok[sl] = 0; lpv[sl] = 0.0; }
+        if (act) {
+            bool inb[kSlots];
+#pragma unroll
+            for (int sl = 0; sl < kSlots; ++sl) inb[sl] = true;
+#pragma unroll
+            for (int i = 0; i < NA; ++i) {
+                const int a = l + 64 * i;
+                if (a < D) {
+#pragma unroll
+                    for (int sl = 0; sl < kSlots; ++sl) {
+                        if (sl >= np) continue;
+                        const int r = w * kSlots + sl;
+                        const double y = x0r[i] + R.dirbuf[((size_t)j * p + step + sl) * D + a];
+                        scand[r * LDC + a] = y;
+                        if constexpr (MODE != MODE_FP64) scand32[r * LDC32 + a] = (float)y;
+                        if (a < d) {
+                            if (box) inb[sl] = inb[sl] && (y >= par[i] && y <= pbr[i]);
+                            else { const double zt = (y - par[i]) / pbr[i]; lpv[sl] += -0.5 * zt * zt; }
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (int sl = 0; sl < kSlots; ++sl) {
+                if (sl >= np) continue;
+                if (box) {
+                    ok[sl] = __all(inb[sl]) != 0;
+                } else {
+                    const double uh = R.ubuf[((size_t)j * p + step + sl) * kStepU + 1];
+                    lpv[sl] = wave_sum_fast(lpv[sl]) + P.logprior_norm;
+                    ok[sl] = lpv[sl] > lp0 + log(uh);
+                }
+            }
+        }
+        if (l == 0) {
+#pragma unroll
+            for (int sl = 0; sl < kSlots; ++sl) smask[w * kSlots + sl] = (sl < np) && ok[sl];
+        }
+        if (!__syncthreads_or(act)) break;
+
+        const int any_rc = eval_tile<D, MODE, LIK, UPW, NP>(P, wr, T, smask, guard);
+        if constexpr (MODE != MODE_FP64) {
+            if (any_rc) eval64<D, LIK>(P, T, T.rc, T.L);
+        }
+
+        if (act) {
+            unsigned okm = 0, inm = 0, rcm = 0, nfm = 0;
+            const unsigned planned = (1u << np) - 1u;
+            double Lv[kSlots];
+#pragma unroll
+            for (int sl = 0; sl < kSlots; ++sl) {
+                Lv[sl] = -INFINITY;
+                if (sl < np && ok[sl]) {
+                    const int r = w * kSlots + sl;
+                    int rc = 0;
+                    double L;
+                    if constexpr (MODE == MODE_FP64) L = T.L[r];
+                    else { rc = T.rc[r]; L = rc ? T.L[r] : (double)T.L32[r]; }
+                    const bool nf = (L != L) || L == INFINITY;
+                    if (nf) L = -INFINITY;
+                    Lv[sl] = L;
+                    okm |= 1u << sl;
+                    if (L > Lstar) inm |= 1u << sl;
+                    if (rc) rcm |= 1u << sl;
+                    if (nf) nfm |= 1u << sl;
+                }
+            }
+            const unsigned acc = inm & planned;
+            const int last = acc ? __builtin_ctz(acc) : np - 1;
+            const unsigned cons = planned & ((2u << last) - 1u);
+            c_tests += __builtin_popcount(cons);
+            c_evals += __builtin_popcount(cons & okm);
+            c_prej += __builtin_popcount(cons & ~okm);
+            c_rc += __builtin_popcount(cons & rcm);
+            c_nonfin += __builtin_popcount(cons & nfm);
+            if (R.trace && l == 0) {
+#pragma unroll
+                for (int sl = 0; sl < kSlots; ++sl) {
+                    if (!((cons >> sl) & 1u)) continue;
+                    int *tr = R.trace + ((size_t)j * p + step + sl) * 4;
+                    tr[0] = 0; tr[1] = 0; tr[2] = (okm >> sl) & 1u; tr[3] = (acc && sl == last) ? 1 : 0;
+                }
+            }
+            if (acc) {
+                // the accepted point is the evaluated candidate row, bit for bit
+                const int r = w * kSlots + last;
+#pragma unroll
+                for (int i = 0; i < NA; ++i)
+                    if (l + 64 * i < D) x0r[i] = scand[r * LDC + l + 64 * i];
+                double La = Lv[0], lpa = lpv[0];
+#pragma unroll
+                for (int sl = 1; sl < kSlots; ++sl)
+                    if (sl == last) { La = Lv[sl]; lpa = lpv[sl]; }
+                logL0 = La;
+                lp0 = lpa;
+            }
+            step += last + 1;
+        }
+    }
+
+    if constexpr (MODE != MODE_FP64) {
+        // stored log-likelihoods are FP64: re-evaluate each chain's final point
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < NA; ++i)
+            if (l + 64 * i < D) scand[w * LDC + l + 64 * i] = has_chain ? x0r[i] : 0.0;
+        if (tid < kRows) smask[tid] = (tid < kMaxChainsPerWG) && (tid < C) &&
+                                      (bm.y * C + tid < R.k);
+        __syncthreads();
+        eval64<D, LIK>(P, T, smask, T.L);
+        if (has_chain) {
+            unsigned long long dummy = 0;
+            logL0 = sanitize(T.L[w], dummy);
+            if (!(logL0 > Lstar)) ++c_viol;
+        }
+    }
+
+    if (has_chain) {
+        const int slot = R.perm[j];
+#pragma unroll
+        for (int i = 0; i < NA; ++i) {
+            const int a = l + 64 * i;
+            if (a < d) R.X[(size_t)a * R.m_pad + slot] = x0r[i];
+        }
+        if (l == 0) {
+            R.logL[slot] = logL0;
+            atomicAdd(&R.ctr[0], c_evals);
+            atomicAdd(&R.ctr[1], c_tests);
+            atomicAdd(&R.ctr[2], c_prej);
+            atomicAdd(&R.ctr[5], c_nonfin);
+            atomicAdd(&R.ctr[6], c_rc);
+            atomicAdd(&R.ctr[7], c_viol);
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------------
 // final live-set contribution (non-destructive): scal[4..6] = ln Z, sqrt(H/m), H
 // ------------------------------------------------------------------------------------------
 __global__ __launch_bounds__(1024) void k_logz(Launch Lc)
@@ -1568,6 +1794,17 @@ static hipError_t hrss_t(const Launch &L, hipStream_t s)
     return hipGetLastError();
 }
 
+template <int D, int MODE, int LIK, int UPW>
+static hipError_t rw_t(const Launch &L, hipStream_t s)
+{
+    const size_t lds = hrss_lds_bytes(D, L.max_K);
+    auto f = k_rw<D, MODE, LIK, UPW>;
+    hipError_t e = set_lds(f, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(f, dim3(L.nblocks), dim3(256), lds, s, L);
+    return hipGetLastError();
+}
+
 // dispatch over (D, mode, likelihood); UPW = register fragment units per wave (mixed only)
 #define NSS_MIXED_D(FN, MODE_, ...)                                                           \
     do {                                                                                      \
@@ -1628,6 +1865,12 @@ hipError_t launch_hrss(const Launch &L, int D, int lik, int mode, int upw, hipSt
 {
     if (L.nblocks <= 0) return hipSuccess;
     NSS_DISPATCH(hrss_t, L, s);
+}
+
+hipError_t launch_rw(const Launch &L, int D, int lik, int mode, int upw, hipStream_t s)
+{
+    if (L.nblocks <= 0) return hipSuccess;
+    NSS_DISPATCH(rw_t, L, s);
 }
 
 hipError_t launch_select(const Launch &L, int op, hipStream_t s)

@@ -21,6 +21,8 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "nss.h")
 NS_OK, NS_DONE, NS_EINVAL, NS_ENOMEM, NS_EDEVICE, NS_ESTATE, NS_EUNSUPPORTED = 0, 1, -1, -2, -3, -4, -5
 NS_PRIOR_BOX, NS_PRIOR_GAUSS_DIAG = 0, 1
 NS_LIK_MIXTURE, NS_LIK_FUNNEL, NS_LIK_GP, NS_LIK_GAUSS_RASTRIGIN = 1, 2, 3, 4
+NS_REPLACE_HRSS, NS_REPLACE_RW = 0, 1
+REPLACEMENTS = {"hrss": NS_REPLACE_HRSS, "rw": NS_REPLACE_RW}
 NS_FP64, NS_MIXED_BF16, NS_MIXED_FP16, NS_MIXED_BF16X3, NS_MIXED_FP16X3, NS_MIXED_FP32 = 0, 1, 2, 3, 4, 5
 NS_FLAG_TRACE, NS_FLAG_TIMING, NS_FLAG_INLINE_DIRECTIONS, NS_FLAG_GRAPH = 1, 2, 4, 8
 PRECISIONS = {"fp64": NS_FP64, "bf16": NS_MIXED_BF16, "fp16": NS_MIXED_FP16,
@@ -49,7 +51,8 @@ class ns_config(C.Structure):
     _fields_ = [("n_live", C.c_int32), ("k", C.c_int32), ("chain_len", C.c_int32),
                 ("width", C.c_double), ("stepout_cap", C.c_int32), ("shrink_cap", C.c_int32),
                 ("term_frac", C.c_double), ("seed", C.c_uint64), ("run_id", C.c_uint32),
-                ("precision", C.c_int32), ("max_iter", C.c_int32), ("flags", C.c_int32)]
+                ("precision", C.c_int32), ("max_iter", C.c_int32), ("flags", C.c_int32),
+                ("replacement", C.c_int32)]
 
 
 class ns_stats_t(C.Structure):
@@ -284,7 +287,7 @@ def current_stream():
 
 def make_config(m, k, p, width=0.0, seed=0, run_id=0, precision="fp64", term_frac=1e-3,
                 stepout_cap=10, shrink_cap=100, max_iter=100000, trace=False, timing=False,
-                inline_directions=False, graph=False) -> ns_config:
+                inline_directions=False, graph=False, replacement="hrss") -> ns_config:
     cfg = ns_config_default()
     cfg.n_live, cfg.k, cfg.chain_len = int(m), int(k), int(p)
     cfg.width = float(width)
@@ -296,6 +299,7 @@ def make_config(m, k, p, width=0.0, seed=0, run_id=0, precision="fp64", term_fra
     cfg.flags = ((NS_FLAG_TRACE if trace else 0) | (NS_FLAG_TIMING if timing else 0)
                  | (NS_FLAG_INLINE_DIRECTIONS if inline_directions else 0)
                  | (NS_FLAG_GRAPH if graph else 0))
+    cfg.replacement = REPLACEMENTS[replacement] if isinstance(replacement, str) else int(replacement)
     return cfg
 
 
@@ -349,7 +353,7 @@ class NSRun:
     def __init__(self, prob: dict, m=None, k=None, p=None, width=0.0, seed=0, run_id=0,
                  precision="fp64", term_frac=1e-3, stepout_cap=10, shrink_cap=100,
                  max_iter=100000, trace=False, timing=False, inline_directions=False,
-                 graph=False, stream="torch"):
+                 graph=False, stream="torch", replacement="hrss"):
         self.prob = prob
         self.d = int(prob["d"])
         self.m = int(m or prob["m"])
@@ -358,7 +362,7 @@ class NSRun:
         pr, en, self._keep = make_structs(prob)
         cfg = make_config(self.m, self.k, self.p, width, seed, run_id, precision, term_frac,
                           stepout_cap, shrink_cap, max_iter, trace, timing, inline_directions,
-                          graph)
+                          graph, replacement)
         self.cfg = cfg
         s = current_stream() if stream == "torch" else stream
         st, self.ctx = ns_init(pr, en, cfg, s)

@@ -33,6 +33,8 @@ these shapes, see the design notes):
               under U[-20,20]^d; m=500, k=250, p=5d each
     rastrigin_gauss   L = alpha N-shaped f + (1 - alpha) Rastrigin-shaped g under U[-5.14,5.14]^d,
               A = 10; m=1000, k=500, p=25d
+    illcond_gaussian  Gaussian N(0, C) with condition number 100 under U[-20,20]^d (the
+              slice-versus-random-walk comparison); m=1000, k=500
 """
 from __future__ import annotations
 
@@ -78,6 +80,22 @@ def config2(seed: int = 1002, d: int = 32, m: int = 1000, k: int = 500):
     cov = _sym((q * lam[None, :]) @ q.T)
     return gaussian_problem(d, mean, cov, "gauss", 0.0, 2.0, name=f"config2_corr{d}",
                             m=m, k=k)
+
+
+def illcond_gaussian(d: int, seed: int = 1006, kappa: float = 100.0, m: int = 1000,
+                     k: int = 500, p=None):
+    """The slice-versus-random-walk comparison target: a Gaussian likelihood N(0, C) with
+    C = Q diag(lam) Q^T, Q Haar, log lam uniform on [-log10 kappa, 0] with both ends pinned
+    (condition number kappa = 100), under the uniform prior [-20, 20]^d (wide enough that the
+    constraint, not the prior, bounds the chains)."""
+    rng = np.random.default_rng(seed + d)
+    q = haar_orthogonal(rng, d)
+    u = rng.uniform(0.0, 1.0, d)
+    u[0], u[1] = 0.0, 1.0
+    lam = 10.0 ** (-np.log10(kappa) * (1.0 - u))
+    cov = _sym((q * lam[None, :]) @ q.T)
+    return gaussian_problem(d, np.zeros(d), cov, "box", -20.0, 20.0, name=f"illcond{d}",
+                            m=m, k=k, p=d if p is None else p)
 
 
 def mixture_problem(seed: int, d: int, K: int, mean_lo=-5.0, mean_hi=5.0, s_lo=0.05, s_hi=0.5,

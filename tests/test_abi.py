@@ -100,3 +100,24 @@ def test_invalid_gp_and_batch_arguments(N):
     assert "run 1" in N.ns_last_error(None)
     assert N.ns_init_batch([], [], [], None)[0] == N.NS_EINVAL
     assert N.ns_num_runs(None) == 0
+
+
+def test_invalid_replacement_and_rastrigin_arguments(N):
+    from paper_2601_23252_amd import problems as G
+    cfg = N.ns_config_default()
+    cfg.n_live, cfg.k, cfg.chain_len = 50, 10, 5
+    assert cfg.replacement == N.NS_REPLACE_HRSS
+    pr, en, keep = _structs(N, G.config1())
+    cfg.replacement = 7
+    assert N.ns_init(pr, en, cfg, None)[0] == N.NS_EINVAL
+    cfg.replacement = N.NS_REPLACE_RW
+    pr, en, keep = _structs(N, G.gp_problem(4, n=20))
+    assert N.ns_init(pr, en, cfg, None)[0] == N.NS_EUNSUPPORTED    # RW: not for the GP
+    cfg.replacement = N.NS_REPLACE_HRSS
+    for alpha, amp in ((-0.1, 10.0), (1.5, 10.0), (0.5, -1.0), (0.5, float("inf"))):
+        pr, en, keep = _structs(N, G.rastrigin_gauss(4, 0.5))
+        en.alpha, en.amp = alpha, amp
+        assert N.ns_init(pr, en, cfg, None)[0] == N.NS_EINVAL
+    pr, en, keep = _structs(N, G.rastrigin_gauss(4, 0.5))
+    cfg.precision = N.NS_MIXED_BF16X3
+    assert N.ns_init(pr, en, cfg, None)[0] == N.NS_EUNSUPPORTED    # Rastrigin: FP64 only

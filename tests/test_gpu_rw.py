@@ -1,0 +1,140 @@
+"""The constrained random-walk replacement kernel (NS_REPLACE_RW) on the GPU against the FP64
+oracle, through the C ABI.
+
+Bars as for the HRSS kernel (both sides compute in FP64; the proposal step s L z is summed in
+the same order; they differ in fused multiply-adds, libm against device math and the prior
+sums, each ~1e-16 relative per operation):
+  - per-iteration state on identical Philox streams: identical parents, deleted order,
+    evaluation / test / prior-rejection counts and per-step traces (evaluated, accepted);
+    points and logL within 1e-10 relative; L*, log Z, log X within 1e-12;
+  - end to end: identical stop iteration and |d ln Z| <= 1e-9, ln Z within 3.5 sigma of the
+    closed form;
+  - mixed precision: decisions equal the FP64 ones (guard band + FP64 re-check).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from tests import truth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def N():
+    from paper_2601_23252_amd import nss
+    nss.load()
+    return nss
+
+
+def _parity(N, O, prob, m, k, p, seed, n_iter, precision="fp64"):
+    scale = 2.38 / math.sqrt(prob["d"])
+    orc = O.Run(O.Problem(prob), m, k, p, scale, seed, threads=8, replacement="rw")
+    orc.init()
+    gpu = N.NSRun(prob, m=m, k=k, p=p, seed=seed, trace=True, precision=precision,
+                  replacement="rw")
+    assert abs(gpu.stats()["width"] - scale) < 1e-15
+    g, o = gpu.state(), orc.state()
+    assert np.array_equal(g["perm"], o["perm"])
+    done_o = orc.done
+    for it in range(n_iter):
+        if done_o:
+            break
+        done_o = orc.step()
+        done_g = gpu.step()
+        g, o = gpu.state(), orc.state()
+        _, par_o = orc.aux()
+        assert np.array_equal(g["parents"], par_o), f"iter {it}: parents"
+        assert np.array_equal(g["perm"], o["perm"]), f"iter {it}: delete-k order"
+        assert np.allclose(g["x"], o["x"], rtol=1e-10, atol=1e-12), f"iter {it}: points"
+        assert np.allclose(g["logL"], o["logL"], rtol=1e-10, atol=1e-10), f"iter {it}: logL"
+        assert math.isclose(g["logZ"], o["logZ"], rel_tol=1e-12, abs_tol=1e-12)
+        sg = gpu.stats()
+        assert sg["evals"] == o["evals"] and sg["tests"] == o["tests"], f"iter {it}: counts"
+        assert sg["prior_rejects"] == o["prior_rejects"]
+        assert sg["band_violations"] == 0
+        assert done_g == done_o
+    return gpu, orc
+
+
+def test_rw_traces_match_oracle_chains(N, oracle_lib):
+    """One iteration of config 1: every chain's per-step (evaluated, accepted) sequence equals
+    the oracle's chain from the same parent."""
+    from paper_2601_23252_amd import problems as G
+    prob = G.config1()
+    scale = 2.38 / math.sqrt(5)
+    gpu = N.NSRun(prob, p=40, seed=2, trace=True, replacement="rw")
+    s0 = gpu.state()
+    gpu.step()
+    s1 = gpu.state()
+    tr = gpu.trace()
+    P = oracle_lib.Problem(prob)
+    for j in range(prob["k"]):
+        par = s1["parents"][j]
+        x, lx, ctr, otr = P.rw_chain(s0["x"][par], s0["logL"][par], s0["Lstar"], s1["Lsig"],
+                                     scale, 40, 2, 0, 1, j, trace=True)
+        assert np.array_equal(tr[j], otr), f"chain {j}"
+        slot = s0["perm"][j]
+        assert np.allclose(s1["x"][slot], x, rtol=1e-10, atol=1e-12)
+    gpu.close()
+
+
+def test_rw_parity_config1_end_to_end(N, oracle_lib):
+    from paper_2601_23252_amd import problems as G
+    gpu, orc = _parity(N, oracle_lib, G.config1(), 200, 50, 125, seed=3, n_iter=100_000)
+    assert gpu.state()["done"] == 1
+    zg, eg, _ = gpu.logz()
+    zo, _, _ = orc.logz()
+    assert abs(zg - zo) <= 1e-9
+    tz = truth.lnz_gauss_box_isotropic(5, 0.1, 1.0)
+    assert abs(zg - tz) < 3.5 * eg, (zg, tz, eg)
+
+
+def test_rw_parity_gaussian_prior(N, oracle_lib):
+    """Gaussian prior: the Metropolis prior-ratio test decides as the oracle's."""
+    from paper_2601_23252_amd import problems as G
+    prob = G.config2(d=12, m=300, k=100)
+    gpu, _ = _parity(N, oracle_lib, prob, 300, 100, 30, seed=5, n_iter=6)
+    assert gpu.stats()["prior_rejects"] > 0
+
+
+def test_rw_parity_box_edge_and_k(N, oracle_lib):
+    """Funnel under a box prior (proposals leave the box) with k = 1 and a ragged tile."""
+    from paper_2601_23252_amd import problems as G
+    prob = G.funnel(6, box=3.0, m=40, k=1)
+    _parity(N, oracle_lib, prob, 40, 1, 7, seed=9, n_iter=20)
+    prob = G.funnel(6, box=3.0, m=33, k=17)
+    gpu, _ = _parity(N, oracle_lib, prob, 33, 17, 6, seed=1, n_iter=5)
+    assert gpu.stats()["prior_rejects"] > 0
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+def test_rw_config3_full_size_sampled_chains(N, oracle_lib, prec):
+    from paper_2601_23252_amd import problems as G
+    prob = G.config3()
+    scale = 2.38 / 8.0
+    gpu = N.NSRun(prob, p=100, seed=6, precision=prec, trace=True, replacement="rw")
+    s0 = gpu.state()
+    gpu.step()
+    s1 = gpu.state()
+    tr = gpu.trace()
+    assert gpu.stats()["band_violations"] == 0
+    P = oracle_lib.Problem(prob)
+    for j in (0, 313, prob["k"] - 1):
+        par = s1["parents"][j]
+        x, lx, _, otr = P.rw_chain(s0["x"][par], s0["logL"][par], s0["Lstar"], s1["Lsig"],
+                                   scale, 100, 6, 0, 1, j, trace=True)
+        assert np.array_equal(tr[j], otr), f"chain {j} ({prec})"
+        slot = s0["perm"][j]
+        assert np.allclose(s1["x"][slot], x, rtol=1e-10, atol=1e-12)
+        assert math.isclose(s1["logL"][slot], lx, rel_tol=1e-10, abs_tol=1e-10)
+    gpu.close()
+
+
+def test_rw_needs_the_direction_buffer(N):
+    from paper_2601_23252_amd import problems as G
+    pr, en, keep = N.make_structs(G.config1())
+    cfg = N.make_config(200, 50, 10, replacement="rw", inline_directions=True)
+    st, ctx = N.ns_init(pr, en, cfg, None)
+    assert st == N.NS_EUNSUPPORTED
