@@ -375,25 +375,35 @@ typedef struct {
     const oprob *p;
     const double *x0, *v;
     double Lstar, logy;
+    double beta;            /* < 0: nested-sampling slice; >= 0: tempered slice at beta */
     int uniform_prior;
     double *y;              /* scratch, d */
     octr *c;
     double last_logL;
 } inside_ctx;
 
-/* The slice predicate along the line: x0 + t v inside the prior support, above the prior
- * height (non-uniform priors only) and strictly above the likelihood threshold. */
+/* The slice predicate along the line.  Nested sampling: x0 + t v inside the prior support,
+ * above the prior height (non-uniform priors only) and strictly above the likelihood
+ * threshold.  Tempered (the SMC mutation, no hard constraint): inside the prior support and
+ * log Pi(y) + beta log L(y) above the slice height, log Pi taken as 0 for a box prior. */
 static int inside(inside_ctx *s, double t)
 {
     const int d = s->p->d;
     for (int a = 0; a < d; ++a) s->y[a] = s->x0[a] + t * s->v[a];
     s->c->tests++;
     if (!prior_in_support(s->p, s->y)) { s->c->prior_rejects++; return 0; }
-    if (!s->uniform_prior && !(or_logprior(s->p, s->y) > s->logy)) { s->c->prior_rejects++; return 0; }
+    if (s->beta < 0.0 && !s->uniform_prior && !(or_logprior(s->p, s->y) > s->logy)) {
+        s->c->prior_rejects++;
+        return 0;
+    }
     double L = or_loglik(s->p, s->y);
     s->c->evals++;
     if (isnan(L) || L == INFINITY) { s->c->nonfinite++; L = -INFINITY; }
     s->last_logL = L;
+    if (s->beta >= 0.0) {
+        const double lp = s->uniform_prior ? 0.0 : or_logprior(s->p, s->y);
+        return lp + s->beta * L > s->logy;
+    }
     return L > s->Lstar;
 }
 
@@ -404,19 +414,18 @@ static int inside(inside_ctx *s, double t)
  * accepted (1) or null move (0).
  * x and *logL are updated in place.
  */
-void or_hrss_chain(const void *pp, double *x, double *logL, double Lstar, const double *Lsig,
-                   double w, int p_steps, int stepout_cap, int shrink_cap, uint64_t seed,
-                   uint32_t run_id, uint32_t iter, uint32_t chain, int64_t *counters,
-                   int32_t *trace)
+static void hrss_chain(const oprob *p, double *x, double *logL, double Lstar, double beta,
+                       const double *Lsig, double w, int p_steps, int stepout_cap,
+                       int shrink_cap, uint64_t seed, uint32_t run_id, uint32_t iter,
+                       uint32_t chain, int64_t *counters, int32_t *trace)
 {
-    const oprob *p = (const oprob *)pp;
     const int d = p->d;
     okey key = { { (uint32_t)seed, (uint32_t)(seed >> 32) ^ run_id } };
     double *z = (double *)malloc(sizeof(double) * d * 3);
     double *v = z + d, *y = z + 2 * d;
     octr c; memset(&c, 0, sizeof c);
     inside_ctx s;
-    s.p = p; s.x0 = x; s.v = v; s.Lstar = Lstar; s.y = y; s.c = &c;
+    s.p = p; s.x0 = x; s.v = v; s.Lstar = Lstar; s.y = y; s.c = &c; s.beta = beta;
     s.uniform_prior = (p->prior_kind == PRIOR_BOX);
     for (int st = 0; st < p_steps; ++st) {
         /* direction: z ~ N(0, I), v = Lsig z / |z| (unit length in the Mahalanobis metric) */
@@ -438,7 +447,10 @@ void or_hrss_chain(const void *pp, double *x, double *logL, double Lstar, const 
         /* initial bracket position and slice height */
         double U, uh;
         draw2(key, P_STEP, chain, iter, (uint32_t)st, 0u, &U, &uh);
-        s.logy = s.uniform_prior ? -INFINITY : or_logprior(p, x) + log(uh);
+        if (beta >= 0.0)   /* tempered slice height: log Pi(x) + beta log L(x) + log uh */
+            s.logy = (s.uniform_prior ? 0.0 : or_logprior(p, x)) + beta * (*logL) + log(uh);
+        else
+            s.logy = s.uniform_prior ? -INFINITY : or_logprior(p, x) + log(uh);
         double tL = -w * U, tR = tL + w;
         /* linear stepping-out, at most stepout_cap expansions per side */
         int nl = 0, nr = 0;
@@ -472,6 +484,27 @@ void or_hrss_chain(const void *pp, double *x, double *logL, double Lstar, const 
         counters[0] += c.evals; counters[1] += c.tests; counters[2] += c.prior_rejects;
         counters[3] += c.stepout_caps; counters[4] += c.shrink_caps; counters[5] += c.nonfinite;
     }
+}
+
+void or_hrss_chain(const void *pp, double *x, double *logL, double Lstar, const double *Lsig,
+                   double w, int p_steps, int stepout_cap, int shrink_cap, uint64_t seed,
+                   uint32_t run_id, uint32_t iter, uint32_t chain, int64_t *counters,
+                   int32_t *trace)
+{
+    hrss_chain((const oprob *)pp, x, logL, Lstar, -1.0, Lsig, w, p_steps, stepout_cap,
+               shrink_cap, seed, run_id, iter, chain, counters, trace);
+}
+
+/* The same chain on the tempered density Pi(x) L(x)^beta, beta >= 0, without a hard
+ * constraint (the slice-sampling mutation of adaptive tempered SMC, App. "Adaptive
+ * non-equilibrium samplers", SMC-SS): slice height log Pi(x0) + beta log L(x0) - Exp(1). */
+void or_hrss_chain_tempered(const void *pp, double *x, double *logL, double beta,
+                            const double *Lsig, double w, int p_steps, int stepout_cap,
+                            int shrink_cap, uint64_t seed, uint32_t run_id, uint32_t iter,
+                            uint32_t chain, int64_t *counters, int32_t *trace)
+{
+    hrss_chain((const oprob *)pp, x, logL, 0.0, beta < 0.0 ? 0.0 : beta, Lsig, w, p_steps,
+               stepout_cap, shrink_cap, seed, run_id, iter, chain, counters, trace);
 }
 
 /*
@@ -563,6 +596,9 @@ typedef struct {
     int64_t n_dead, cap_dead;
     int whiten_fallbacks;
     int replacement;  /* 0: HRSS (width = slice width); 1: random walk (width = step scale) */
+    /* adaptive tempered SMC (or_smc_*): all m particles move each step */
+    int smc;
+    double beta, ess_frac;
 } orun;
 
 void or_run_free(void *rr)
@@ -648,9 +684,8 @@ static int termination_reached(const orun *r)
 
 /* Draw m points from the prior, evaluate them, then the first delete-k.  Returns 1 if the
  * termination test already holds, 0 otherwise. */
-int or_init(void *rr)
+static void draw_initial(orun *r)
 {
-    orun *r = (orun *)rr;
     const oprob *p = r->p;
     const int d = p->d, m = r->m;
     okey key = { { (uint32_t)r->seed, (uint32_t)(r->seed >> 32) ^ r->run_id } };
@@ -674,16 +709,23 @@ int or_init(void *rr)
         if (isnan(L) || L == INFINITY) { r->counters[5]++; L = -INFINITY; }
         r->logL[i] = L;
     }
+}
+
+int or_init(void *rr)
+{
+    orun *r = (orun *)rr;
+    draw_initial(r);
     r->logZ = -INFINITY; r->logX = 0.0; r->M = 0.0; r->iter = 0; r->n_dead = 0;
     select_and_account(r);
     return termination_reached(r);
 }
 
-/* Whitening: covariance (divided by n) of the m-k survivors plus 1e-12 tr/d jitter, and its
- * lower Cholesky factor; diagonal fallback if the factorisation fails. */
+/* Whitening: covariance (divided by n) of the m-k survivors (SMC: of all m particles) plus
+ * 1e-12 tr/d jitter, and its lower Cholesky factor; diagonal fallback if the factorisation
+ * fails. */
 static void whiten(orun *r)
 {
-    const int d = r->p->d, m = r->m, k = r->k, n = m - k;
+    const int d = r->p->d, m = r->m, k = r->smc ? 0 : r->k, n = m - k;
     double *mean = (double *)calloc(d, sizeof(double));
     double *C = (double *)calloc((size_t)d * d, sizeof(double));
     for (int t = k; t < m; ++t) {
@@ -766,6 +808,132 @@ int or_step(void *rr, int n_threads)
     r->iter = it;
     select_and_account(r);
     return termination_reached(r);
+}
+
+/* ------------------------------------------------------------------------------------------ */
+/* Adaptive tempered SMC with the slice-sampling mutation (App. "Adaptive Tempered SMC";       */
+/* SMC-SS in App. "Adaptive non-equilibrium samplers")                                        */
+/* ------------------------------------------------------------------------------------------ */
+/* m particles; each step: the next inverse temperature by bisection on the ESS of the
+ * incremental weights, the log-mean-weight evidence increment, systematic resampling, then p
+ * tempered HRSS steps per particle with directions whitened by the particle covariance.
+ * ess_frac is the ESS target rho in (0, 1).  Returns NULL on invalid input. */
+void *or_smc_new(const void *pp, int m, int p_steps, double width, int stepout_cap,
+                 int shrink_cap, double ess_frac, uint64_t seed, uint32_t run_id)
+{
+    const oprob *p = (const oprob *)pp;
+    if (!p || m < 2 || p_steps < 1 || !(width > 0.0) || !(ess_frac > 0.0 && ess_frac < 1.0))
+        return NULL;
+    orun *r = (orun *)calloc(1, sizeof(orun));
+    const int d = p->d;
+    r->p = p; r->m = m; r->k = m; r->p_steps = p_steps; r->width = width;
+    r->stepout_cap = stepout_cap; r->shrink_cap = shrink_cap; r->term_frac = 0.0;
+    r->seed = seed; r->run_id = run_id;
+    r->smc = 1; r->ess_frac = ess_frac;
+    r->x = (double *)malloc(sizeof(double) * (size_t)m * d);
+    r->logL = (double *)malloc(sizeof(double) * m);
+    r->perm = (int *)malloc(sizeof(int) * m);
+    r->Lsig = (double *)calloc((size_t)d * d, sizeof(double));
+    r->parents = (int *)calloc(m, sizeof(int));
+    r->cap_dead = 1;
+    r->dead = (double *)malloc(sizeof(double));
+    return r;
+}
+
+/* Prior draws (the same stream as nested sampling's) at beta = 0, log Z = 0. */
+void or_smc_init(void *rr)
+{
+    orun *r = (orun *)rr;
+    draw_initial(r);
+    for (int i = 0; i < r->m; ++i) r->perm[i] = i;
+    r->beta = 0.0; r->logZ = 0.0; r->logX = 0.0; r->M = 0.0; r->iter = 0; r->Lstar = 0.0;
+}
+
+/* ESS of the incremental weights exp((b - beta) (L_i - Lmax)), L = -inf weighing 0. */
+static double smc_ess(const orun *r, double b, double Lmax)
+{
+    double s1 = 0.0, s2 = 0.0;
+    for (int i = 0; i < r->m; ++i) {
+        if (r->logL[i] == -INFINITY) continue;
+        const double e = exp((b - r->beta) * (r->logL[i] - Lmax));
+        s1 += e;
+        s2 += e * e;
+    }
+    return s1 * s1 / s2;
+}
+
+/* One SMC step.  Returns 1 once beta has reached 1 (after that step's mutation), 0 otherwise,
+ * -4 if every particle has log L = -inf. */
+int or_smc_step(void *rr, int n_threads)
+{
+    orun *r = (orun *)rr;
+    const oprob *p = r->p;
+    const int d = p->d, m = r->m;
+    const uint32_t it = (uint32_t)(r->iter + 1);
+    okey key = { { (uint32_t)r->seed, (uint32_t)(r->seed >> 32) ^ r->run_id } };
+    double Lmax = -INFINITY;
+    for (int i = 0; i < m; ++i) if (r->logL[i] > Lmax) Lmax = r->logL[i];
+    if (Lmax == -INFINITY) return -4;
+    /* next temperature: ESS(b) = rho m by 50 bisection steps on (beta, 1] */
+    const double target = r->ess_frac * m;
+    double nb = 1.0;
+    if (smc_ess(r, 1.0, Lmax) < target) {
+        double lo = r->beta, hi = 1.0;
+        for (int t = 0; t < 50; ++t) {
+            const double mid = 0.5 * (lo + hi);
+            if (smc_ess(r, mid, Lmax) >= target) lo = mid; else hi = mid;
+        }
+        nb = lo > r->beta ? lo : hi;
+    }
+    /* evidence increment: log of the mean incremental weight */
+    const double db = nb - r->beta;
+    double *w = (double *)malloc(sizeof(double) * m);
+    double sw = 0.0;
+    for (int i = 0; i < m; ++i) {
+        w[i] = r->logL[i] == -INFINITY ? 0.0 : exp(db * (r->logL[i] - Lmax));
+        sw += w[i];
+    }
+    r->logZ += db * Lmax + log(sw) - log((double)m);
+    /* systematic resampling: positions (u + j) / m against the cumulative normalised weights */
+    double u, unused;
+    draw2(key, P_RESAMPLE, 0u, it, 0u, 0u, &u, &unused);
+    int i = 0;
+    double cum = w[0] / sw;
+    for (int j = 0; j < m; ++j) {
+        const double pos = (u + j) / m;
+        while (cum < pos && i < m - 1) { ++i; cum += w[i] / sw; }
+        r->parents[j] = i;
+    }
+    double *xn = (double *)malloc(sizeof(double) * (size_t)m * d);
+    double *ln = (double *)malloc(sizeof(double) * m);
+    for (int j = 0; j < m; ++j) {
+        memcpy(xn + (size_t)j * d, r->x + (size_t)r->parents[j] * d, sizeof(double) * d);
+        ln[j] = r->logL[r->parents[j]];
+    }
+    memcpy(r->x, xn, sizeof(double) * (size_t)m * d);
+    memcpy(r->logL, ln, sizeof(double) * m);
+    r->beta = nb;
+    r->Lstar = nb;
+    r->iter = it;
+    /* mutation at the new temperature, particle j by chain j */
+    whiten(r);
+    int64_t c0 = 0, c1 = 0, c2 = 0, c3 = 0, c4 = 0, c5 = 0;
+#ifdef _OPENMP
+    if (n_threads < 1) n_threads = 1;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(n_threads) reduction(+:c0,c1,c2,c3,c4,c5)
+#endif
+    for (int j = 0; j < m; ++j) {
+        int64_t cc[6] = { 0, 0, 0, 0, 0, 0 };
+        hrss_chain(p, r->x + (size_t)j * d, &r->logL[j], 0.0, nb, r->Lsig, r->width,
+                   r->p_steps, r->stepout_cap, r->shrink_cap, r->seed, r->run_id, it,
+                   (uint32_t)j, cc, NULL);
+        c0 += cc[0]; c1 += cc[1]; c2 += cc[2]; c3 += cc[3]; c4 += cc[4]; c5 += cc[5];
+    }
+    (void)n_threads;
+    r->counters[0] += c0; r->counters[1] += c1; r->counters[2] += c2;
+    r->counters[3] += c3; r->counters[4] += c4; r->counters[5] += c5;
+    free(w); free(xn); free(ln);
+    return nb == 1.0;
 }
 
 /* Replacement kernel of the run: 0 HRSS (the default), 1 constrained random walk with the

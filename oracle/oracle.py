@@ -71,6 +71,17 @@ def lib():
         L.or_init.argtypes = [C.c_void_p]
         L.or_step.restype = C.c_int
         L.or_step.argtypes = [C.c_void_p, C.c_int]
+        L.or_smc_new.restype = C.c_void_p
+        L.or_smc_new.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_double, C.c_int, C.c_int,
+                                 C.c_double, C.c_uint64, C.c_uint32]
+        L.or_smc_init.restype = None
+        L.or_smc_init.argtypes = [C.c_void_p]
+        L.or_smc_step.restype = C.c_int
+        L.or_smc_step.argtypes = [C.c_void_p, C.c_int]
+        L.or_hrss_chain_tempered.restype = None
+        L.or_hrss_chain_tempered.argtypes = [C.c_void_p, _dp, _dp, C.c_double, _dp, C.c_double,
+                                             C.c_int, C.c_int, C.c_int, C.c_uint64, C.c_uint32,
+                                             C.c_uint32, C.c_uint32, _lp, C.c_void_p]
         L.or_run_set_replacement.restype = C.c_int
         L.or_run_set_replacement.argtypes = [C.c_void_p, C.c_int]
         L.or_rw_chain.restype = None
@@ -161,6 +172,21 @@ class Problem:
                             np.ascontiguousarray(Lsig, np.float64), float(width), int(p),
                             int(stepout_cap), int(shrink_cap), int(seed), int(run_id), int(it),
                             int(chain), ctr, tr.ctypes.data if trace else None)
+        return x, float(lv[0]), ctr, tr
+
+    def hrss_chain_tempered(self, x, logL, beta, Lsig, width, p, seed, run_id, it, chain,
+                            stepout_cap=10, shrink_cap=100, trace=False):
+        """One chain of p HRSS steps on Pi L^beta (no hard constraint); returns (x, logL,
+        counters[6], trace or None)."""
+        x = np.array(x, np.float64, copy=True)
+        lv = np.array([logL], np.float64)
+        ctr = np.zeros(6, np.int64)
+        tr = np.zeros((p, 4), np.int32) if trace else None
+        lib().or_hrss_chain_tempered(self.h, x, lv, float(beta),
+                                     np.ascontiguousarray(Lsig, np.float64), float(width),
+                                     int(p), int(stepout_cap), int(shrink_cap), int(seed),
+                                     int(run_id), int(it), int(chain), ctr,
+                                     tr.ctypes.data if trace else None)
         return x, float(lv[0]), ctr, tr
 
     def rw_chain(self, x, logL, Lstar, Lsig, scale, p, seed, run_id, it, chain, trace=False):
@@ -266,3 +292,41 @@ def geom(dead, final_logL, m, k, R, beta=1.0, seed=0, run_id=0, weights=True):
     lib().or_geom(dead, len(dead), fin, len(fin), int(m), int(k), int(R), float(beta), int(seed),
                   int(run_id), logz, lw.ctypes.data if weights else None, ess.ctypes.data)
     return logz, (lw[:N] if weights else None), float(ess[0])
+
+
+class SMC(Run):
+    """Adaptive tempered SMC with the slice-sampling mutation (the oracle's or_smc_*): init(),
+    step() -> True once beta = 1, run(); state()["Lstar"] holds beta, "logZ" the estimate."""
+
+    def __init__(self, problem: Problem, m, p, width, seed, run_id=0, ess_frac=0.5,
+                 stepout_cap=10, shrink_cap=100, threads=1):
+        self.P = problem
+        self.m, self.k, self.p, self.d = m, m, p, problem.d
+        self.threads = threads
+        self.h = lib().or_smc_new(problem.h, m, p, float(width), stepout_cap, shrink_cap,
+                                  float(ess_frac), int(seed), int(run_id))
+        if not self.h:
+            raise ValueError("oracle rejected the SMC configuration")
+        self.done = False
+
+    def init(self) -> bool:
+        lib().or_smc_init(self.h)
+        self.done = False
+        return False
+
+    def step(self) -> bool:
+        r = lib().or_smc_step(self.h, int(self.threads))
+        if r < 0:
+            raise RuntimeError(f"or_smc_step failed ({r})")
+        self.done = bool(r)
+        return self.done
+
+    def run(self, max_iter=100000) -> int:
+        n = 0
+        while not self.done and n < max_iter:
+            self.step()
+            n += 1
+        return n
+
+    def beta(self) -> float:
+        return self.state()["Lstar"]

@@ -602,3 +602,86 @@ def test_lnz_config1_random_walk(oracle_lib):
         lz, err, _ = R.logz()
         zs.append((lz - tz) / err)
     assert np.all(np.abs(zs) < 3.5), zs
+
+
+# ------------------------------------------------------------------------------------------
+# adaptive tempered SMC with the slice-sampling mutation (SMC-SS)
+# ------------------------------------------------------------------------------------------
+def test_tempered_hrss_stationary_laws(oracle_lib):
+    """The tempered slice chain leaves Pi L^beta invariant: a box prior with a unit Gaussian
+    likelihood at beta = 0.5 gives N(0, 2) truncated to the box; a N(0, 1) prior with a
+    N(1, 1) likelihood at beta = 0.7 gives N(0.7/1.7, 1/1.7)."""
+    from paper_2601_23252_amd import problems as G
+    prob = G.gaussian_problem(1, np.zeros(1), np.eye(1), "box", -2.0, 2.0)
+    P = oracle_lib.Problem(prob)
+    x = np.array([0.1]); lx = float(P.loglik(x[None])[0]); xs = []
+    for it in range(5000):
+        x, lx, _, _ = P.hrss_chain_tempered(x, lx, 0.5, np.eye(1), 3.0, 2, 7, 0, it, 0)
+        xs.append(x[0])
+    tn = stats.truncnorm(-2.0 / math.sqrt(2), 2.0 / math.sqrt(2), scale=math.sqrt(2))
+    assert stats.kstest(np.array(xs), tn.cdf).pvalue > 1e-3
+    prob = G.gaussian_problem(1, np.ones(1), np.eye(1), "gauss", 0.0, 1.0)
+    P = oracle_lib.Problem(prob)
+    x = np.array([0.0]); lx = float(P.loglik(x[None])[0]); xs = []
+    for it in range(5000):
+        x, lx, _, _ = P.hrss_chain_tempered(x, lx, 0.7, np.eye(1), 2.0, 2, 8, 0, it, 0)
+        xs.append(x[0])
+    post = stats.norm(0.7 / 1.7, 1 / math.sqrt(1.7))
+    assert stats.kstest(np.array(xs), post.cdf).pvalue > 1e-3
+
+
+def test_smc_step_invariants(oracle_lib):
+    """Each step: beta rises; the ESS of the incremental weights at the new beta is rho m (or
+    beta = 1 with ESS >= rho m); log Z grows by the log mean incremental weight; systematic
+    resampling gives particle i floor(m w_i) or floor(m w_i) + 1 copies."""
+    from oracle import theory as T
+    from paper_2601_23252_amd import problems as G
+    prob = G.config1()
+    m, rho = 300, 0.5
+    S = oracle_lib.SMC(oracle_lib.Problem(prob), m, 10, T.width_whitened(5), 4, ess_frac=rho)
+    S.init()
+    done = False
+    steps = 0
+    while not done:
+        pre = S.state()
+        done = S.step()
+        post = S.state()
+        _, parents = S.aux()
+        b0, b1 = pre["Lstar"], post["Lstar"]
+        assert b1 > b0
+        L = pre["logL"]
+        lw = (b1 - b0) * (L - L.max())
+        w = np.exp(lw)
+        ess = w.sum() ** 2 / (w ** 2).sum()
+        if b1 < 1.0:
+            assert abs(ess / (rho * m) - 1.0) < 1e-6, ess
+        else:
+            assert ess >= rho * m * (1 - 1e-12)
+        inc = (b1 - b0) * L.max() + math.log(w.mean())
+        assert abs((post["logZ"] - pre["logZ"]) - inc) < 1e-10
+        counts = np.bincount(parents, minlength=m)
+        wb = m * w / w.sum()
+        assert np.all((counts >= np.floor(wb) - 1e-9) & (counts <= np.floor(wb) + 1 + 1e-9))
+        steps += 1
+    assert post["Lstar"] == 1.0 and steps >= 3
+
+
+def test_smc_lnz_config1_unbiased(oracle_lib):
+    """12 independent runs on config 1 (m = 500, p = 5d, rho = 0.5): the mean ln Z lies within
+    4 standard errors of the closed form and the final particles' mean is near the origin."""
+    from oracle import theory as T
+    from paper_2601_23252_amd import problems as G
+    prob = G.config1()
+    tz = truth.lnz_gauss_box_isotropic(5, 0.1, 1.0)
+    zs = []
+    for s in range(12):
+        S = oracle_lib.SMC(oracle_lib.Problem(prob), 500, 25, T.width_whitened(5), s,
+                           threads=8)
+        S.init()
+        S.run()
+        st = S.state()
+        zs.append(st["logZ"])
+        assert np.all(np.abs(st["x"].mean(0)) < 0.05)
+    zs = np.array(zs)
+    assert abs(zs.mean() - tz) < 4 * zs.std() / math.sqrt(len(zs)), (zs.mean(), tz, zs.std())
+    assert 0.02 < zs.std() < 0.5
