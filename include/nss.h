@@ -133,7 +133,27 @@ typedef struct {
     int32_t flags;        /* NS_FLAG_* */
     int32_t replacement;  /* ns_replacement: the constrained kernel that replaces deleted
                            * points (Sec. 3.1 "Replacement strategies"); default HRSS */
+    int32_t outer;        /* ns_outer: nested sampling (default) or adaptive tempered SMC */
+    double ess_frac;      /* NS_OUTER_SMC: ESS target rho in (0, 1) of each next temperature,
+                           * default 0.5 */
 } ns_config;
+
+/* Outer loops.  NS_OUTER_SMC is adaptive tempered SMC with the slice-sampling mutation
+ * (App. "Adaptive Tempered SMC"; SMC-SS in App. "Adaptive non-equilibrium samplers"): n_live
+ * particles start from the prior at beta = 0; each ns_step picks the next inverse temperature
+ * by 50 bisection steps so that the ESS of the incremental weights exp((b - beta) log L) is
+ * ess_frac * n_live (or beta = 1), adds the log mean incremental weight to log Z, resamples
+ * systematically, whitens with the covariance of all particles and moves every particle by
+ * chain_len HRSS steps on Pi L^beta without a hard constraint (slice height
+ * log Pi + beta log L - Exp(1)).  The run is done after the step that reaches beta = 1.
+ * k, term_frac and the dead record are unused; ns_get_state's Lstar holds beta; ns_logz
+ * returns the accumulated log Z with NaN error and H; ns_set_state, ns_geom_uncertainty and
+ * NS_REPLACE_RW are not available; FP64 only; not for NS_LIK_GP.  All runs of a context share
+ * the outer loop. */
+typedef enum {
+    NS_OUTER_NESTED = 0,
+    NS_OUTER_SMC = 1
+} ns_outer;
 
 /* Replacement kernels.  NS_REPLACE_RW runs chain_len constrained Gaussian random-walk
  * Metropolis steps per replacement (App. "Slice Sampling vs Random Walk"): the proposal is

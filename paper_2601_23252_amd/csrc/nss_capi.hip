@@ -37,6 +37,7 @@ struct ns_ctx {
     bool own_stream = false;
     int n = 0;                       // runs
     int timing = 0;
+    int smc = 0;                     // every run uses the adaptive tempered SMC outer loop
     std::vector<RunHost> runs;
     std::vector<Group> groups;
     DevProblem *dP = nullptr;        // [n + 1] device descriptors; slot n is ns_eval_loglik's
@@ -119,6 +120,8 @@ extern "C" void ns_config_default(ns_config *c)
     c->max_iter = 100000;
     c->flags = 0;
     c->replacement = NS_REPLACE_HRSS;
+    c->outer = NS_OUTER_NESTED;
+    c->ess_frac = 0.5;
 }
 
 // ---- host-side problem preparation (FP64) ----
@@ -464,6 +467,11 @@ static bool any_error(const ns_ctx *ctx)
     return false;
 }
 
+static const char *state_error_text(const ns_ctx *ctx)
+{
+    return ctx->smc ? "every particle has log L = -inf" : "no live point lies strictly above L*";
+}
+
 // drop finished runs from the launches once they are known to be finished
 static ns_status refresh_maps(ns_ctx *ctx)
 {
@@ -484,7 +492,12 @@ static ns_status device_error(ns_ctx *ctx, const char *what, hipError_t e)
 
 static ns_status enqueue_iteration(ns_ctx *ctx)
 {
-    hipError_t e = launch_cov(ctx->L_cov, ctx->L_one, ctx->Dmax, ctx->stream);
+    hipError_t e;
+    if (ctx->smc) {   // next temperature, evidence increment, resampling
+        e = launch_smc(ctx->L_one, 1, ctx->stream);
+        if (e != hipSuccess) return device_error(ctx, "SMC reweighting launch", e);
+    }
+    e = launch_cov(ctx->L_cov, ctx->L_one, ctx->Dmax, ctx->stream);
     if (e != hipSuccess) return device_error(ctx, "whitening launch", e);
     for (int di = 0; di < 3; ++di) {
         e = launch_dirs(ctx->L_dirs[di], 32 << di, ctx->stream);
@@ -507,7 +520,7 @@ static ns_status enqueue_iteration(ns_ctx *ctx)
         CK(hipEventRecord(e1, ctx->stream));
         ctx->events.emplace_back(e0, e1);
     }
-    e = launch_select(ctx->L_one, 1, ctx->stream);
+    e = ctx->smc ? launch_smc(ctx->L_one, 2, ctx->stream) : launch_select(ctx->L_one, 1, ctx->stream);
     if (e != hipSuccess) return device_error(ctx, "select launch", e);
     return NS_OK;
 }
@@ -558,7 +571,7 @@ static ns_status start_runs(ns_ctx *ctx)
                 : launch_eval_init(ctx->L_eval[g], G.D, G.lik, ctx->stream);
         if (e != hipSuccess) return device_error(ctx, "initial evaluation", e);
     }
-    e = launch_select(ctx->L_one, 0, ctx->stream);
+    e = ctx->smc ? launch_smc(ctx->L_one, 0, ctx->stream) : launch_select(ctx->L_one, 0, ctx->stream);
     if (e != hipSuccess) return device_error(ctx, "select launch", e);
     for (auto &pr : ctx->events) { (void)hipEventDestroy(pr.first); (void)hipEventDestroy(pr.second); }
     ctx->events.clear();
@@ -624,10 +637,24 @@ static ns_status validate_run(const ns_prior *prior, const ns_energy *energy, co
         msg = "funnel needs d >= 2";
         return NS_EINVAL;
     }
-    const int m = cfg->n_live, k = cfg->k, p = cfg->chain_len;
+    const int m = cfg->n_live, p = cfg->chain_len;
+    const bool smc = cfg->outer == NS_OUTER_SMC;
+    const int k = smc ? 1 : cfg->k;   // SMC moves every particle; k is unused
+    if (cfg->outer != NS_OUTER_NESTED && !smc) { msg = "unknown outer loop"; return NS_EINVAL; }
     if (m < 2 || k < 1 || k > m - 1 || p < 1) {
         msg = "need 2 <= n_live, 1 <= k <= n_live-1, chain_len >= 1";
         return NS_EINVAL;
+    }
+    if (smc) {
+        if (!(cfg->ess_frac > 0.0 && cfg->ess_frac < 1.0)) {
+            msg = "SMC needs 0 < ess_frac < 1";
+            return NS_EINVAL;
+        }
+        if (energy->kind == NS_LIK_GP || cfg->precision != NS_FP64 ||
+            cfg->replacement != NS_REPLACE_HRSS) {
+            msg = "SMC is implemented for FP64 slice mutation of the non-GP likelihoods";
+            return NS_EUNSUPPORTED;
+        }
     }
     if (m > kMaxLive) { msg = "n_live > 8192"; return NS_EUNSUPPORTED; }
     if (cfg->stepout_cap < 0 || cfg->shrink_cap < 0 || cfg->max_iter < 1) {
@@ -683,7 +710,9 @@ static ns_status alloc_run(ns_ctx *ctx, int r)
     R.term_on = cfg->term_frac > 0.0;
     R.log_term = cfg->term_frac > 0.0 ? log(cfg->term_frac) : 0.0;
     set_key(R, cfg->seed, cfg->run_id);
-    R.dead_cap = (long long)(cfg->max_iter + 1) * k;
+    R.smc = cfg->outer == NS_OUTER_SMC;
+    R.ess_frac = cfg->ess_frac;
+    R.dead_cap = R.smc ? 1 : (long long)(cfg->max_iter + 1) * k;
     R.iscal = ctx->d_iscal + 8 * r;
     R.scal = ctx->d_scal + 8 * r;
     R.ctr = ctx->d_ctr + 16 * r;
@@ -710,8 +739,11 @@ static ns_status alloc_run(ns_ctx *ctx, int r)
                     "random-walk replacement needs the direction buffer (k p (d+8) doubles "
                     "<= 4 GiB, no NS_FLAG_INLINE_DIRECTIONS)");
     }
-    const int n = m - k;
+    const int n = R.smc ? m : m - k;   // points of the whitening covariance
     R.covG = n / 64 < 1 ? 1 : (n / 64 > 32 ? 32 : n / 64);
+    if (R.smc)
+        if ((st = dalloc(ctx, &R.Xtmp, (size_t)D * rh.m_pad)) || (st = dalloc(ctx, &R.Ltmp, m)))
+            return st;
     const int nt = D / 16, ntile = nt * (nt + 1) / 2;
     if ((st = dalloc(ctx, &R.part1, (size_t)R.covG * D)) ||
         (st = dalloc(ctx, &R.part2, (size_t)R.covG * ntile * 256)))
@@ -772,11 +804,16 @@ extern "C" ns_status ns_init_batch(int32_t n_runs, const ns_prior *priors,
         rh.D = pad_dim(rh.d);
         rh.m = cfgs[r].n_live;
         rh.m_pad = (rh.m + 63) & ~63;
-        rh.k = cfgs[r].k;
+        rh.k = cfgs[r].outer == NS_OUTER_SMC ? cfgs[r].n_live : cfgs[r].k;   // SMC: every particle
         rh.p = cfgs[r].chain_len;
         rh.mode = cfgs[r].precision;
         if (cfgs[r].flags & NS_FLAG_TIMING) ctx->timing = 1;
         if (cfgs[r].flags & NS_FLAG_GRAPH) ctx->use_graph = 1;
+        if (r == 0) ctx->smc = cfgs[r].outer == NS_OUTER_SMC;
+        if ((cfgs[r].outer == NS_OUTER_SMC) != (ctx->smc != 0)) {
+            ctx->err = "run " + std::to_string(r) + ": all runs of a context share the outer loop";
+            return bail(NS_EINVAL);
+        }
         if ((st = prepare_problem(ctx, rh, priors + r, energies + r)) != NS_OK) return bail(st);
         rh.lik = rh.P.lik_kind;
         rh.K = rh.P.K;
@@ -875,7 +912,7 @@ extern "C" ns_status ns_reset(ns_ctx *ctx, uint64_t seed, uint32_t run_id)
     CK(hipMemcpy(ctx->dR, hr.data(), hr.size() * sizeof(DevRun), hipMemcpyHostToDevice));
     ns_status st = start_runs(ctx);
     if (st != NS_OK) return st;
-    if (any_error(ctx)) return fail(ctx, NS_ESTATE, "no live point lies strictly above L*");
+    if (any_error(ctx)) return fail(ctx, NS_ESTATE, state_error_text(ctx));
     return NS_OK;
 }
 
@@ -892,7 +929,7 @@ extern "C" ns_status ns_step(ns_ctx *ctx, int32_t *done)
     if ((st = collect_events(ctx)) != NS_OK) return st;
     if ((st = refresh_maps(ctx)) != NS_OK) return st;
     if (done) *done = all_done(ctx) ? 1 : 0;
-    if (any_error(ctx)) return fail(ctx, NS_ESTATE, "no live point lies strictly above L*");
+    if (any_error(ctx)) return fail(ctx, NS_ESTATE, state_error_text(ctx));
     return NS_OK;
 }
 
@@ -955,7 +992,7 @@ extern "C" ns_status ns_run(ns_ctx *ctx, int32_t max_iter, int32_t *iters)
         if (a > adv) adv = a;
     }
     if (iters) *iters = adv;
-    if (any_error(ctx)) return fail(ctx, NS_ESTATE, "no live point lies strictly above L*");
+    if (any_error(ctx)) return fail(ctx, NS_ESTATE, state_error_text(ctx));
     return NS_OK;
 }
 
@@ -963,16 +1000,18 @@ extern "C" ns_status ns_logz_batch(ns_ctx *ctx, double *logz, double *logz_err, 
 {
     if (!ctx) return NS_EINVAL;
     // every run, finished or not (the finalisation does not change the run's state)
-    Launch L{ctx->dP, ctx->dR, ctx->d_map1, ctx->n, 0, 0};
-    hipError_t e = launch_logz(L, ctx->stream);
-    if (e != hipSuccess) return device_error(ctx, "ns_logz", e);
+    if (!ctx->smc) {
+        Launch L{ctx->dP, ctx->dR, ctx->d_map1, ctx->n, 0, 0};
+        hipError_t e = launch_logz(L, ctx->stream);
+        if (e != hipSuccess) return device_error(ctx, "ns_logz", e);
+    }
     std::vector<double> sc((size_t)ctx->n * 8);
     CK(hipMemcpyAsync(sc.data(), ctx->d_scal, sc.size() * 8, hipMemcpyDeviceToHost, ctx->stream));
     CK(hipStreamSynchronize(ctx->stream));
     for (int r = 0; r < ctx->n; ++r) {
-        if (logz) logz[r] = sc[(size_t)8 * r + 4];
-        if (logz_err) logz_err[r] = sc[(size_t)8 * r + 5];
-        if (H) H[r] = sc[(size_t)8 * r + 6];
+        if (logz) logz[r] = sc[(size_t)8 * r + (ctx->smc ? 1 : 4)];
+        if (logz_err) logz_err[r] = ctx->smc ? NAN : sc[(size_t)8 * r + 5];
+        if (H) H[r] = ctx->smc ? NAN : sc[(size_t)8 * r + 6];
     }
     return NS_OK;
 }
@@ -980,6 +1019,16 @@ extern "C" ns_status ns_logz_batch(ns_ctx *ctx, double *logz, double *logz_err, 
 extern "C" ns_status ns_logz(ns_ctx *ctx, double *logz, double *logz_err, double *H)
 {
     if (!ctx) return NS_EINVAL;
+    if (ctx->smc) {   // the accumulated estimate; a single SMC run gives no error estimate
+        double z = 0.0;
+        CK(hipMemcpyAsync(&z, ctx->d_scal + 1, sizeof(double), hipMemcpyDeviceToHost,
+                          ctx->stream));
+        CK(hipStreamSynchronize(ctx->stream));
+        if (logz) *logz = z;
+        if (logz_err) *logz_err = NAN;
+        if (H) *H = NAN;
+        return NS_OK;
+    }
     const Launch L = launch_one(ctx, 0);
     hipError_t e = launch_logz(L, ctx->stream);
     if (e != hipSuccess) return device_error(ctx, "ns_logz", e);
@@ -1063,6 +1112,7 @@ extern "C" ns_status ns_get_state(ns_ctx *ctx, ns_state_view *v)
 extern "C" ns_status ns_set_state(ns_ctx *ctx, const ns_state_view *v)
 {
     if (!ctx || !v || !v->x || !v->logL) return NS_EINVAL;
+    if (ctx->smc) return fail(ctx, NS_EUNSUPPORTED, "ns_set_state is for nested-sampling runs");
     RunHost &rh = ctx->runs[0];
     const DevRun &R = rh.R;
     const int d = rh.d, D = rh.D, m = rh.m, mp = rh.m_pad;
@@ -1110,6 +1160,7 @@ extern "C" ns_status ns_geom_uncertainty(ns_ctx *ctx, int32_t run, int32_t R, do
                                          int64_t *n_deaths, double *device_ms)
 {
     if (!run_ok(ctx, run) || !logz) return NS_EINVAL;
+    if (ctx->smc) return fail(ctx, NS_EUNSUPPORTED, "an SMC run has no dead record");
     if (R < 1 || R > 65535) return fail(ctx, NS_EINVAL, "replicas must be in [1, 65535]");
     if (!(beta >= 0.0) || beta == INFINITY) return fail(ctx, NS_EINVAL, "beta must be finite and >= 0");
     if (cap < 0) return fail(ctx, NS_EINVAL, "cap < 0");

@@ -74,6 +74,9 @@ struct DevRun {
     double *dirbuf;        // [k][p][D] directions of the current iteration, or null (inline)
     double *ubuf;          // [k][p][8] per-step default plan (tL0, uh, 6 shrink), with dirbuf
     int rw;                // replacement by constrained random walk (width = its scale)
+    int smc;               // adaptive tempered SMC outer loop (k = m chains, no hard constraint)
+    double ess_frac;       // SMC: ESS target rho of the next temperature
+    double *Xtmp, *Ltmp;   // SMC: gather buffers [D][m_pad], [m]
     int C;                 // chains per HRSS workgroup
     int covG;              // survivor groups of the covariance partial sums
     double *part1, *part2; // covariance partials [covG][D], [covG][ntile][256]
@@ -100,6 +103,8 @@ hipError_t launch_eval_points(const Launch &L, int D, int lik, int mode, int upw
 // op: 0 = initial delete-k (accounted), 1 = delete-k of an iteration (accounted, iter + 1),
 //     2 = re-sort only (no accounting; after an external state overwrite); one block per run
 hipError_t launch_select(const Launch &L, int op, hipStream_t s);
+// adaptive tempered SMC: op 0 start, 1 next temperature + resampling, 2 end of step
+hipError_t launch_smc(const Launch &L, int op, hipStream_t s);
 // survivors' covariance (cov map: (run, tile + ntile * group)) and factorisation (one per run)
 hipError_t launch_cov(const Launch &cov, const Launch &one, int D, hipStream_t s);
 hipError_t launch_dirs(const Launch &L, int D, hipStream_t s);

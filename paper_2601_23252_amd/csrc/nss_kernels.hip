@@ -777,7 +777,8 @@ __global__ __launch_bounds__(256) void k_cov(Launch Lc)
     const int tile = bm.y % ntile, g = bm.y / ntile, tid = threadIdx.x;
     int ta, tb;
     unpack_tri(tile, ta, tb);
-    const int n = R.m - R.k;
+    const int off = R.smc ? 0 : R.k;   // SMC: every particle
+    const int n = R.m - off;
     const int s0 = (int)((long long)n * g / G), s1 = (int)((long long)n * (g + 1) / G);
     const int cidx = R.perm[R.m - 1];
     __shared__ double ca[32][17], cb[32][17];
@@ -796,7 +797,7 @@ __global__ __launch_bounds__(256) void k_cov(Launch Lc)
             const int ss = sb + s;
             double v = 0.0;
             if (ss < s1) {
-                const int pi = R.perm[R.k + ss];
+                const int pi = R.perm[off + ss];
                 const int coord = (c < 16) ? ta * 16 + c : tb * 16 + (c - 16);
                 if (coord < d) v = R.X[(size_t)coord * R.m_pad + pi] - shift[c];
             }
@@ -827,7 +828,7 @@ __global__ __launch_bounds__(1024) void k_chol(Launch Lc)
     double *mc = A + D * (D + 1) / 2;        // mean - shift, [D]
     double *red = mc + D;                    // [32]
     int *fail = (int *)(red + 32);
-    const int n = R.m - R.k;
+    const int n = R.smc ? R.m : R.m - R.k;
     for (int a = tid; a < D; a += blockDim.x) {
         double s = 0.0;
         if (a < d) for (int g = 0; g < G; ++g) s += part1[(size_t)g * D + a];
@@ -1053,6 +1054,10 @@ __global__ __launch_bounds__(256) void k_hrss(Launch Lc)
     const int tid = threadIdx.x, w = uniform_i(tid >> 6), l = tid & 63;
     const int d = P.d;
     const double Lstar = R.scal[0];
+    // adaptive tempered SMC (FP64 only): no hard constraint; scal[0] holds the inverse
+    // temperature
+    const bool tempered = MODE == MODE_FP64 && R.smc != 0;
+    const double beta = Lstar;
     const int t0 = R.iscal[1], nsurv = R.iscal[2];
     const uint32_t it = (uint32_t)R.iscal[3] + 1u;
     const double width = R.width;
@@ -1111,12 +1116,15 @@ __global__ __launch_bounds__(256) void k_hrss(Launch Lc)
                        c_nonfin = 0, c_rc = 0, c_viol = 0;
 
     if (has_chain) {
-        double u, unused;
-        draw2(R.key0, R.key1, PUR_RESAMPLE, (uint32_t)j, it, 0u, 0u, u, unused);
-        int qi = (int)floor(u * (double)nsurv);
-        if (qi > nsurv - 1) qi = nsurv - 1;
-        const int parent = R.perm[t0 + qi];
-        if (l == 0) R.parents[j] = parent;
+        int parent = j;   // tempered SMC: the resampled particle j, gathered into slot j
+        if (!tempered) {
+            double u, unused;
+            draw2(R.key0, R.key1, PUR_RESAMPLE, (uint32_t)j, it, 0u, 0u, u, unused);
+            int qi = (int)floor(u * (double)nsurv);
+            if (qi > nsurv - 1) qi = nsurv - 1;
+            parent = R.perm[t0 + qi];
+            if (l == 0) R.parents[j] = parent;
+        }
 #pragma unroll
         for (int i = 0; i < NA; ++i) {
             const int a = l + 64 * i;
@@ -1194,9 +1202,11 @@ __global__ __launch_bounds__(256) void k_hrss(Launch Lc)
         const bool act = has_chain && phase != PH_DONE;
         int kind[kSlots], ok[kSlots];
         double tv[kSlots], bLa[kSlots], bRa[kSlots];   // t per slot; bracket after rejecting it
+        double lps[kSlots];                             // log prior density (Gaussian prior)
 #pragma unroll
         for (int sl = 0; sl < kSlots; ++sl) {
             kind[sl] = S_NONE; ok[sl] = 0; tv[sl] = 0.0; bLa[sl] = 0.0; bRa[sl] = 0.0;
+            lps[sl] = 0.0;
         }
         if (act) {
             PT(6);
@@ -1245,7 +1255,10 @@ __global__ __launch_bounds__(256) void k_hrss(Launch Lc)
                     tL = -width * U;
                 }
                 dflt = pre;
-                logy = box ? -INFINITY : logprior_x0() + log(uh);
+                if (tempered)   // slice of Pi L^beta: log Pi(x0) + beta log L(x0) - Exp(1)
+                    logy = (box ? 0.0 : logprior_x0()) + beta * logL0 + log(uh);
+                else
+                    logy = box ? -INFINITY : logprior_x0() + log(uh);
                 tR = tL + width;
                 nl = nr = 0;
                 la = ra = (cap_out > 0);
@@ -1316,8 +1329,12 @@ __global__ __launch_bounds__(256) void k_hrss(Launch Lc)
 #pragma unroll
                 for (int sl = 0; sl < kSlots; ++sl) {
                     if (kind[sl] == S_NONE) continue;
-                    if (box) ok[sl] = __all(inb[sl]) != 0;
-                    else ok[sl] = (wave_sum_fast(lp[sl]) + P.logprior_norm) > logy;
+                    if (box) {
+                        ok[sl] = __all(inb[sl]) != 0;
+                    } else {
+                        lps[sl] = wave_sum_fast(lp[sl]) + P.logprior_norm;
+                        ok[sl] = tempered || lps[sl] > logy;   // tempered: no prior gate
+                    }
                 }
             }
             PT(11);
@@ -1364,7 +1381,7 @@ __global__ __launch_bounds__(256) void k_hrss(Launch Lc)
                     if (nf) L = -INFINITY;
                     Lv[sl] = L;
                     okm |= 1u << sl;
-                    if (L > Lstar) inm |= 1u << sl;
+                    if (tempered ? (lps[sl] + beta * L > logy) : (L > Lstar)) inm |= 1u << sl;
                     if (rc) rcm |= 1u << sl;
                     if (nf) nfm |= 1u << sl;
                 }
@@ -1450,7 +1467,7 @@ __global__ __launch_bounds__(256) void k_hrss(Launch Lc)
     }
 
     if (has_chain) {
-        const int slot = R.perm[j];
+        const int slot = tempered ? j : R.perm[j];
 #pragma unroll
         for (int i = 0; i < NA; ++i) {
             const int a = l + 64 * i;
@@ -1695,6 +1712,136 @@ __global__ __launch_bounds__(256) void k_rw(Launch Lc)
 }
 
 // ------------------------------------------------------------------------------------------
+// adaptive tempered SMC (the slice-sampling mutation runs in k_hrss with R.smc set)
+// ------------------------------------------------------------------------------------------
+// One workgroup per run.  op 0: start at beta = 0 (identity order, log Z = 0).  op 1 (the
+// start of a step): the next inverse temperature by 50 bisection steps on the ESS of the
+// incremental weights exp((b - beta) (logL - max logL)) (target rho m, or beta = 1), the log
+// mean incremental weight added to log Z, systematic resampling with one uniform (purpose
+// RESAMPLE, counter (0, step)) against the cumulative normalised weights, and the gather of
+// the resampled particles into slots 0..m-1.  op 2 (the end of a step): the step count, and
+// done once beta = 1.  scal[0] = beta, scal[1] = log Z; iscal[5] = this step reached beta = 1.
+// The step's draws (resampling, directions, chains) use iteration number iscal[3] + 1.
+constexpr int kSmcPer = kMaxLive / kSelectThreads;   // particles per thread, contiguous
+
+__global__ __launch_bounds__(kSelectThreads) void k_smc(Launch Lc, int op)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double red[32];
+    const int2 bm = Lc.map[blockIdx.x];
+    const DevProblem P = Lc.P[bm.x];
+    const DevRun R = Lc.R[bm.x];
+    const int m = R.m, tid = threadIdx.x;
+    if (op == 0) {
+        for (int i = tid; i < m; i += blockDim.x) R.perm[i] = i;
+        if (tid == 0) {
+            R.scal[0] = 0.0; R.scal[1] = 0.0; R.scal[2] = 0.0; R.scal[3] = 0.0;
+            R.iscal[1] = 0; R.iscal[2] = m; R.iscal[5] = 0;
+        }
+        return;
+    }
+    if (op == 2) {   // the step's draws used iteration number iscal[3] + 1
+        if (tid == 0 && !R.iscal[0]) {
+            R.iscal[3] += 1;
+            if (R.iscal[5]) R.iscal[0] = 1;
+        }
+        return;
+    }
+    if (R.iscal[0]) return;
+    double *cum = (double *)smem;                         // [m]
+    int *par = (int *)(smem + (size_t)kMaxLive * 8);      // [m]
+    const double beta = R.scal[0];
+    const int i0 = tid * kSmcPer;
+    double Lr[kSmcPer];
+    double lmax = -INFINITY;
+#pragma unroll
+    for (int q = 0; q < kSmcPer; ++q) {
+        Lr[q] = (i0 + q < m) ? R.logL[i0 + q] : -INFINITY;
+        lmax = fmax(lmax, Lr[q]);
+    }
+    lmax = block_max(lmax, red);
+    if (!(lmax > -INFINITY)) {   // every particle has log L = -inf: nothing to weigh
+        if (tid == 0) { R.iscal[4] = 1; R.iscal[0] = 1; }
+        return;
+    }
+    auto ess = [&](double b) -> double {
+        double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+        for (int q = 0; q < kSmcPer; ++q) {
+            if (Lr[q] > -INFINITY) {
+                const double e = exp((b - beta) * (Lr[q] - lmax));
+                s1 += e;
+                s2 += e * e;
+            }
+        }
+        s1 = block_sum(s1, red);
+        s2 = block_sum(s2, red);
+        return s1 * s1 / s2;
+    };
+    const double target = R.ess_frac * m;
+    double nb = 1.0;
+    if (ess(1.0) < target) {
+        double lo = beta, hi = 1.0;
+        for (int t = 0; t < 50; ++t) {
+            const double mid = 0.5 * (lo + hi);
+            if (ess(mid) >= target) lo = mid; else hi = mid;
+        }
+        nb = lo > beta ? lo : hi;
+    }
+    const double db = nb - beta;
+    double w[kSmcPer], loc = 0.0;
+#pragma unroll
+    for (int q = 0; q < kSmcPer; ++q) {
+        w[q] = (Lr[q] > -INFINITY) ? exp(db * (Lr[q] - lmax)) : 0.0;
+        loc += w[q];
+    }
+    const double pre = block_exscan(loc, red);
+    const double sw = block_sum(loc, red);
+    double c = pre;
+#pragma unroll
+    for (int q = 0; q < kSmcPer; ++q) {
+        c += w[q];
+        if (i0 + q < m) cum[i0 + q] = c / sw;
+    }
+    const uint32_t it = (uint32_t)R.iscal[3] + 1u;
+    double u, unused;
+    draw2(R.key0, R.key1, PUR_RESAMPLE, 0u, it, 0u, 0u, u, unused);
+    __syncthreads();
+    // parent of slot j: the first particle whose cumulative weight reaches (u + j) / m
+    for (int j = tid; j < m; j += blockDim.x) {
+        const double pos = (u + j) / m;
+        int lo = 0, hi = m - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (cum[mid] >= pos) hi = mid; else lo = mid + 1;
+        }
+        par[j] = lo;
+        R.parents[j] = lo;
+    }
+    __syncthreads();
+    // gather through the scratch copy, then back into the live arrays
+    const int d = P.d;
+    for (long long e = tid; e < (long long)d * m; e += blockDim.x) {
+        const int a = (int)(e / m), j = (int)(e - (long long)a * m);
+        R.Xtmp[(size_t)a * R.m_pad + j] = R.X[(size_t)a * R.m_pad + par[j]];
+    }
+    for (int j = tid; j < m; j += blockDim.x) R.Ltmp[j] = R.logL[par[j]];
+    __syncthreads();
+    for (long long e = tid; e < (long long)d * m; e += blockDim.x) {
+        const int a = (int)(e / m), j = (int)(e - (long long)a * m);
+        R.X[(size_t)a * R.m_pad + j] = R.Xtmp[(size_t)a * R.m_pad + j];
+    }
+    for (int j = tid; j < m; j += blockDim.x) R.logL[j] = R.Ltmp[j];
+    if (tid == 0) {
+        R.scal[0] = nb;
+        R.scal[1] += db * lmax + log(sw) - log((double)m);
+        R.iscal[1] = 0;
+        R.iscal[2] = m;
+        R.iscal[5] = (nb == 1.0) ? 1 : 0;
+    }
+}
+
+// ------------------------------------------------------------------------------------------
 // final live-set contribution (non-destructive): scal[4..6] = ln Z, sqrt(H/m), H
 // ------------------------------------------------------------------------------------------
 __global__ __launch_bounds__(1024) void k_logz(Launch Lc)
@@ -1871,6 +2018,16 @@ hipError_t launch_rw(const Launch &L, int D, int lik, int mode, int upw, hipStre
 {
     if (L.nblocks <= 0) return hipSuccess;
     NSS_DISPATCH(rw_t, L, s);
+}
+
+hipError_t launch_smc(const Launch &L, int op, hipStream_t s)
+{
+    if (L.nblocks <= 0) return hipSuccess;
+    const size_t lds = (size_t)kMaxLive * 12;
+    hipError_t e = set_lds(k_smc, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_smc, dim3(L.nblocks), dim3(kSelectThreads), lds, s, L, op);
+    return hipGetLastError();
 }
 
 hipError_t launch_select(const Launch &L, int op, hipStream_t s)

@@ -22,6 +22,8 @@ NS_OK, NS_DONE, NS_EINVAL, NS_ENOMEM, NS_EDEVICE, NS_ESTATE, NS_EUNSUPPORTED = 0
 NS_PRIOR_BOX, NS_PRIOR_GAUSS_DIAG = 0, 1
 NS_LIK_MIXTURE, NS_LIK_FUNNEL, NS_LIK_GP, NS_LIK_GAUSS_RASTRIGIN = 1, 2, 3, 4
 NS_REPLACE_HRSS, NS_REPLACE_RW = 0, 1
+NS_OUTER_NESTED, NS_OUTER_SMC = 0, 1
+OUTERS = {"ns": NS_OUTER_NESTED, "smc": NS_OUTER_SMC}
 REPLACEMENTS = {"hrss": NS_REPLACE_HRSS, "rw": NS_REPLACE_RW}
 NS_FP64, NS_MIXED_BF16, NS_MIXED_FP16, NS_MIXED_BF16X3, NS_MIXED_FP16X3, NS_MIXED_FP32 = 0, 1, 2, 3, 4, 5
 NS_FLAG_TRACE, NS_FLAG_TIMING, NS_FLAG_INLINE_DIRECTIONS, NS_FLAG_GRAPH = 1, 2, 4, 8
@@ -52,7 +54,7 @@ class ns_config(C.Structure):
                 ("width", C.c_double), ("stepout_cap", C.c_int32), ("shrink_cap", C.c_int32),
                 ("term_frac", C.c_double), ("seed", C.c_uint64), ("run_id", C.c_uint32),
                 ("precision", C.c_int32), ("max_iter", C.c_int32), ("flags", C.c_int32),
-                ("replacement", C.c_int32)]
+                ("replacement", C.c_int32), ("outer", C.c_int32), ("ess_frac", C.c_double)]
 
 
 class ns_stats_t(C.Structure):
@@ -287,7 +289,8 @@ def current_stream():
 
 def make_config(m, k, p, width=0.0, seed=0, run_id=0, precision="fp64", term_frac=1e-3,
                 stepout_cap=10, shrink_cap=100, max_iter=100000, trace=False, timing=False,
-                inline_directions=False, graph=False, replacement="hrss") -> ns_config:
+                inline_directions=False, graph=False, replacement="hrss", outer="ns",
+                ess_frac=0.5) -> ns_config:
     cfg = ns_config_default()
     cfg.n_live, cfg.k, cfg.chain_len = int(m), int(k), int(p)
     cfg.width = float(width)
@@ -300,6 +303,8 @@ def make_config(m, k, p, width=0.0, seed=0, run_id=0, precision="fp64", term_fra
                  | (NS_FLAG_INLINE_DIRECTIONS if inline_directions else 0)
                  | (NS_FLAG_GRAPH if graph else 0))
     cfg.replacement = REPLACEMENTS[replacement] if isinstance(replacement, str) else int(replacement)
+    cfg.outer = OUTERS[outer] if isinstance(outer, str) else int(outer)
+    cfg.ess_frac = float(ess_frac)
     return cfg
 
 
@@ -353,16 +358,18 @@ class NSRun:
     def __init__(self, prob: dict, m=None, k=None, p=None, width=0.0, seed=0, run_id=0,
                  precision="fp64", term_frac=1e-3, stepout_cap=10, shrink_cap=100,
                  max_iter=100000, trace=False, timing=False, inline_directions=False,
-                 graph=False, stream="torch", replacement="hrss"):
+                 graph=False, stream="torch", replacement="hrss", outer="ns", ess_frac=0.5):
         self.prob = prob
         self.d = int(prob["d"])
         self.m = int(m or prob["m"])
         self.k = int(k or prob["k"])
+        if outer == "smc":
+            self.k = self.m   # every particle moves
         self.p = int(p or prob["p"])
         pr, en, self._keep = make_structs(prob)
         cfg = make_config(self.m, self.k, self.p, width, seed, run_id, precision, term_frac,
                           stepout_cap, shrink_cap, max_iter, trace, timing, inline_directions,
-                          graph, replacement)
+                          graph, replacement, outer, ess_frac)
         self.cfg = cfg
         s = current_stream() if stream == "torch" else stream
         st, self.ctx = ns_init(pr, en, cfg, s)

@@ -121,3 +121,26 @@ def test_invalid_replacement_and_rastrigin_arguments(N):
     pr, en, keep = _structs(N, G.rastrigin_gauss(4, 0.5))
     cfg.precision = N.NS_MIXED_BF16X3
     assert N.ns_init(pr, en, cfg, None)[0] == N.NS_EUNSUPPORTED    # Rastrigin: FP64 only
+
+
+def test_invalid_smc_arguments(N):
+    from paper_2601_23252_amd import problems as G
+    cfg = N.ns_config_default()
+    cfg.n_live, cfg.k, cfg.chain_len = 50, 10, 5
+    assert cfg.outer == N.NS_OUTER_NESTED and cfg.ess_frac == 0.5
+    pr, en, keep = _structs(N, G.config1())
+    cfg.outer = 5
+    assert N.ns_init(pr, en, cfg, None)[0] == N.NS_EINVAL
+    cfg.outer = N.NS_OUTER_SMC
+    for rho in (0.0, 1.0, -0.2):
+        cfg.ess_frac = rho
+        assert N.ns_init(pr, en, cfg, None)[0] == N.NS_EINVAL
+    cfg.ess_frac = 0.5
+    cfg.precision = N.NS_MIXED_BF16X3
+    assert N.ns_init(pr, en, cfg, None)[0] == N.NS_EUNSUPPORTED     # SMC: FP64 only
+    cfg.precision = N.NS_FP64
+    cfg.replacement = N.NS_REPLACE_RW
+    assert N.ns_init(pr, en, cfg, None)[0] == N.NS_EUNSUPPORTED     # SMC: slice mutation
+    cfg.replacement = N.NS_REPLACE_HRSS
+    pr, en, keep = _structs(N, G.gp_problem(4, n=20))
+    assert N.ns_init(pr, en, cfg, None)[0] == N.NS_EUNSUPPORTED     # SMC: not for the GP
