@@ -25,8 +25,8 @@ sys.path.insert(0, ROOT)
 # HBM bytes per k_hrss launch (BF16x3) from the FETCH_SIZE / WRITE_SIZE counter passes, each
 # scaled by the same counter on a copy of known size (FETCH x 2, WRITE x 1), recorded for the
 # kernel source with this sha256 prefix; reported as null once the source differs.
-TRAFFIC = {"bf16x3": 748.4e6}
-TRAFFIC_SOURCE_SHA = "09951aa2b0d562d4"
+TRAFFIC = {"bf16x3": 748.3e6}
+TRAFFIC_SOURCE_SHA = "8e1d57660b83f62e"
 
 
 def kernel_traffic(precision):
@@ -310,8 +310,8 @@ def lnz_rastrigin_gauss(d, alpha, r=5.14, amp=10.0):
 # VALU lane-instructions per likelihood evaluation of the Gaussian-Rastrigin k_hrss at d=100
 # (SQ_INSTS_VALU x 64 / evaluations of the profiled launches), for the kernel source with this
 # sha256 prefix.
-RG_VALU_PER_EVAL = 53065.0
-RG_SOURCE_SHA = "3f20f7a70e975f78"
+RG_VALU_PER_EVAL = 54596.0
+RG_SOURCE_SHA = "8e1d57660b83f62e"
 
 
 def bench_rastrigin(args):
