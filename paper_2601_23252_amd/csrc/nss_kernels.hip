@@ -920,10 +920,17 @@ constexpr int kStepU = 8;                 // per step: tL0, uh, default shrink p
 constexpr int kStepShrinkU = kStepU - 2;
 __host__ __device__ inline int dirs_lds_bytes(int D)
 {
-    return al16(lsig_doubles(D) * 8) + al16(kDirRows * (D + 1) * 8) + kDirRows * 8 +
-           kDirRows * kStepU * 8;
+    return al16(kDirRows * (D + 1) * 8) + kDirRows * 8 + kDirRows * kStepU * 8 +
+           2 * kDirRows * 4;
 }
 
+// The normals and uniforms are drawn by all threads; v = L z is one small FP64 MFMA product per
+// workgroup: wave w takes directions 16w..16w+15 as the B operand (lane l: direction
+// 16w + (l & 15), coordinate 4ks + (l >> 4)) against L as the A operand (read from the run's
+// row-major factor, cached; only the normals occupy LDS), and gets
+// V[16w + (l & 15)][16t + (l >> 4) + 4i] in register i of tile t; the lower-triangular L skips
+// k-steps above each tile.  The results go back through the wave's own rows of the normals
+// buffer so that the stores to the direction buffer are whole rows.
 template <int D>
 __global__ __launch_bounds__(256) void k_dirs(Launch Lc)
 {
@@ -932,43 +939,43 @@ __global__ __launch_bounds__(256) void k_dirs(Launch Lc)
     const DevProblem P = Lc.P[bm.x];
     const DevRun R = Lc.R[bm.x];
     if (R.iscal[0] || R.iscal[2] <= 0) return;
-    double *Ls = (double *)smem;
-    double *zs = (double *)(smem + al16(lsig_doubles(D) * 8));
-    double *nz = zs + kDirRows * (D + 1);
+    constexpr int LDZ = D + 1;
+    double *zs = (double *)smem;
+    double *nz = zs + kDirRows * LDZ;
+    double *udraw = nz + kDirRows;              // [kDirRows][kStepU] raw uniforms
+    int *rj = (int *)(udraw + kDirRows * kStepU);   // chain of each row (-1 past the end)
+    int *rs = rj + kDirRows;                    // step of each row
     const int tid = threadIdx.x, d = P.d, p = R.p;
     const long long total = (long long)R.k * p;
     const long long base = (long long)bm.y * kDirRows;
     const uint32_t it = (uint32_t)R.iscal[3] + 1u;
-    if constexpr (D <= 64) {
-        for (int i = tid; i < D * D; i += 256) {
-            const int a = i / D, b = i - a * D;
-            Ls[a * (D + 1) + b] = R.Lsig[i];
-        }
-    } else {
-        for (int i = tid; i < D * (D + 1) / 2; i += 256) Ls[i] = R.Lpk[i];
+    if (tid < kDirRows) {
+        const long long idx = base + tid;
+        int j = -1, st = 0;
+        if (idx < total) { j = (int)(idx / p); st = (int)(idx - (long long)j * p); }
+        rj[tid] = j;
+        rs[tid] = st;
     }
+    __syncthreads();
     const int nq = (d + 1) >> 1;
     for (int i = tid; i < kDirRows * nq; i += 256) {
         const int r = i / nq, q = i - r * nq;
-        const long long idx = base + r;
-        if (idx >= total) continue;
-        const int j = (int)(idx / p), st = (int)(idx - (long long)j * p);
+        const int j = rj[r];
+        if (j < 0) continue;
         double ua, ub, z0, z1;
-        draw2(R.key0, R.key1, PUR_DIR, (uint32_t)j, it, (uint32_t)st, (uint32_t)q, ua, ub);
+        draw2(R.key0, R.key1, PUR_DIR, (uint32_t)j, it, (uint32_t)rs[r], (uint32_t)q, ua, ub);
         box_muller(ua, ub, z0, z1);
-        zs[r * (D + 1) + 2 * q] = z0;
-        if (2 * q + 1 < d) zs[r * (D + 1) + 2 * q + 1] = z1;
+        zs[r * LDZ + 2 * q] = z0;
+        if (2 * q + 1 < d) zs[r * LDZ + 2 * q + 1] = z1;
     }
     // The step's default plan (what the chain proposes while no bracket end has expanded):
     // ubuf[0] = tL0 = -w U, ubuf[1] = the height uniform uh (purpose STEP), ubuf[2 + i] = the
     // i-th shrink proposal of the bracket [tL0, tL0 + w] after i rejections (purpose SHRINK,
     // draws 0, 1, ...), with the same arithmetic as the chain's own proposals.
-    double *udraw = nz + kDirRows;   // [kDirRows][kStepU] raw uniforms
     for (int i = tid; i < kDirRows * kStepU; i += 256) {
         const int r = i / kStepU, q = i - r * kStepU;
-        const long long idx = base + r;
-        if (idx >= total) continue;
-        const int j = (int)(idx / p), st = (int)(idx - (long long)j * p);
+        const int j = rj[r], st = rs[r];
+        if (j < 0) continue;
         double ua, ub;
         if (q < 2) {
             draw2(R.key0, R.key1, PUR_STEP, (uint32_t)j, it, (uint32_t)st, 0u, ua, ub);
@@ -979,7 +986,7 @@ __global__ __launch_bounds__(256) void k_dirs(Launch Lc)
         }
     }
     __syncthreads();
-    if (tid < kDirRows && base + tid < total) {
+    if (tid < kDirRows && rj[tid] >= 0) {
         const double *u = udraw + tid * kStepU;
         double *o = R.ubuf + (base + tid) * kStepU;
         const double width = R.width;
@@ -993,27 +1000,48 @@ __global__ __launch_bounds__(256) void k_dirs(Launch Lc)
             if (t < 0.0) sL = t; else sR = t;
         }
     }
-    __syncthreads();
-    if (tid < kDirRows) {
-        double s2 = 0.0;
-        for (int a = 0; a < d; ++a) s2 += zs[tid * (D + 1) + a] * zs[tid * (D + 1) + a];
-        nz[tid] = sqrt(s2);
+    const int w = tid >> 6, l = tid & 63, li = l & 15, lk = l >> 4;
+    const int r = 16 * w + li;
+    // |z| of the wave's 16 directions: four partial sums per direction, then lane exchanges
+    double s2 = 0.0;
+    for (int a = lk; a < d; a += 4) {
+        const double z = zs[r * LDZ + a];
+        s2 += z * z;
     }
-    __syncthreads();
-    for (int i = tid; i < kDirRows * D; i += 256) {
-        const int r = i / D, a = i - r * D;
-        const long long idx = base + r;
-        if (idx >= total) continue;
-        double v = 0.0;
-        if (a < d) {
-            const double *Lr = (D <= 64) ? Ls + a * (D + 1) : Ls + a * (a + 1) / 2;
-            const double *z = zs + r * (D + 1);
-            double s2 = 0.0;
-            for (int b = 0; b <= a; ++b) s2 += Lr[b] * z[b];
-            // HRSS: unit Mahalanobis length; random walk: the proposal step s L z
-            v = R.rw ? s2 * R.width : s2 / nz[r];
+    s2 += __shfl_xor(s2, 16, 64);
+    s2 += __shfl_xor(s2, 32, 64);
+    const double nrm = sqrt(s2);
+    constexpr int NT = D / 16, NKS = D / 4;
+    d4 acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = (d4){0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int ks = 0; ks < NKS; ++ks) {
+        const int b = 4 * ks + lk;
+        const double bz = (b < d) ? zs[r * LDZ + b] : 0.0;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            if (ks < 4 * t + 4) {   // L is zero above its diagonal
+                const double la = R.Lsig[(16 * t + li) * D + b];
+                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(la, bz, acc[t], 0, 0, 0);
+            }
         }
-        R.dirbuf[idx * D + a] = v;
+    }
+    // HRSS: unit Mahalanobis length; random walk: the proposal step s L z
+    wave_sync();   // this wave's reads of its rows are done
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int a = 16 * t + lk + 4 * i;
+            zs[r * LDZ + a] = (a < d) ? (R.rw ? acc[t][i] * R.width : acc[t][i] / nrm) : 0.0;
+        }
+    }
+    wave_sync();
+    for (int e = l; e < 16 * D; e += 64) {
+        const int rr = e / D, a = e - rr * D;
+        const int row = 16 * w + rr;
+        if (rj[row] >= 0) R.dirbuf[(base + row) * D + a] = zs[row * LDZ + a];
     }
 }
 
