@@ -316,8 +316,9 @@ RG_SOURCE_SHA = "8e1d57660b83f62e"
 
 def bench_rastrigin(args):
     """The Gaussian-Rastrigin evidence workload: full runs at d = 100, alpha = 0.5 (n_live 1000,
-    k 500, p = 25d, FP64), timed; then one untimed run per (d, alpha) in {2, 4, 10, 30, 100} x
-    {0, 0.5, 1} for the ln Z table against the semi-analytic evidence."""
+    k 500, p = 25d, FP64), timed; then one untimed run per (d, alpha) in
+    {2, 4, 10, 30, 100, 300} x {0, 0.5, 1} for the ln Z table against the semi-analytic
+    evidence."""
     import hashlib
     import numpy as np
     import torch
@@ -347,14 +348,18 @@ def bench_rastrigin(args):
     dt = time.perf_counter() - t0
     print(f"[bench] timed runs done in {dt:.1f} s", file=sys.stderr, flush=True)
     table = []
-    for dd in (() if args.no_table else (2, 4, 10, 30, 100)):
+    for dd in (() if args.no_table else (2, 4, 10, 30, 100, 300)):
         for a in (0.0, 0.5, 1.0):
             Q = N.NSRun(G.rastrigin_gauss(dd, a), seed=1)
+            t0 = time.perf_counter()
             Q.run()
             z, err, _ = Q.logz()
             t = lnz_rastrigin_gauss(dd, a)
             table.append({"d": dd, "alpha": a, "logz": z, "sigma": err, "truth": t,
-                          "z": (z - t) / err})
+                          "z": (z - t) / err, "seconds": time.perf_counter() - t0,
+                          "evals": Q.stats()["evals"]})
+            print(f"[bench] table d={dd} alpha={a}: z {(z - t) / err:.2f}", file=sys.stderr,
+                  flush=True)
             Q.close()
     print(f"[bench] ln Z table done", file=sys.stderr, flush=True)
     src = os.path.join(ROOT, "paper_2601_23252_amd", "csrc", "nss_kernels.hip")

@@ -96,7 +96,8 @@ typedef enum {
 
 typedef struct {
     int32_t kind;       /* ns_prior_kind */
-    int32_t d;          /* dimension, 1 <= d <= 128 */
+    int32_t d;          /* dimension, 1 <= d <= 128; up to 320 for NS_LIK_FUNNEL and
+                         * NS_LIK_GAUSS_RASTRIGIN in FP64 with the direction buffer */
     const double *a;    /* [d] box lower bound | Gaussian mean */
     const double *b;    /* [d] box upper bound | Gaussian standard deviation */
 } ns_prior;
@@ -163,7 +164,7 @@ typedef enum {
  * chain stays.  For it `width` is s (<= 0 selects 2.38 / sqrt(d)); the step-out and shrink
  * caps are unused; traces record (0, 0, evaluated, accepted) per step.  Not available for
  * NS_LIK_GP or with NS_FLAG_INLINE_DIRECTIONS (the proposals come from the per-iteration
- * direction buffer, which must fit in 4 GiB). */
+ * direction buffer, which must fit in 32 GiB). */
 typedef enum {
     NS_REPLACE_HRSS = 0,
     NS_REPLACE_RW = 1
@@ -174,7 +175,7 @@ typedef enum {
 #define NS_FLAG_INLINE_DIRECTIONS 4  /* chains draw their directions and step uniforms
                                       * themselves instead of reading a per-iteration buffer
                                       * of k*p*(d+8) doubles (the buffer is also skipped when
-                                      * it would exceed 4 GiB) */
+                                      * it would exceed 32 GiB; not for d > 128) */
 #define NS_FLAG_GRAPH  8  /* ns_run captures each batch of 16 iterations as a HIP graph and
                            * replays it (re-captured when a run of the batch finishes); not
                            * used together with NS_FLAG_TIMING.  Results are identical. */

@@ -51,7 +51,7 @@ struct ns_ctx {
     size_t map_cap = 0;
     std::vector<int2> h_map;
     // launches over the unfinished runs (rebuilt when the set changes)
-    Launch L_init, L_one, L_cov, L_dirs[3];
+    Launch L_init, L_one, L_cov, L_dirs[4];   // directions per padded dimension 32/64/128/320
     std::vector<Launch> L_eval;      // per group (FP64 initial evaluation)
     std::vector<Launch> L_hrss;      // per group
     int Dmax = 32;
@@ -314,7 +314,8 @@ static ns_status prepare_problem(ns_ctx *ctx, RunHost &rh, const ns_prior *prior
     return NS_OK;
 }
 
-static int pad_dim(int d) { return d <= 32 ? 32 : (d <= 64 ? 64 : 128); }
+static int pad_dim(int d) { return d <= 32 ? 32 : (d <= 64 ? 64 : (d <= 128 ? 128 : 320)); }
+static constexpr int kDims[4] = {32, 64, 128, 320};
 
 // Problem descriptor for one precision.  Guard band of the mixed modes (a candidate whose
 // FP32 estimate L satisfies |L - L*| <= rel * max(0, cmax - L) + abs is re-evaluated in FP64):
@@ -352,7 +353,6 @@ static DevProblem problem_for_mode(const RunHost &rh, int mode)
 }
 
 static bool precision_valid(int p) { return p >= NS_FP64 && p <= NS_MIXED_FP32; }
-static int d_index(int D) { return D == 32 ? 0 : (D == 64 ? 1 : 2); }
 
 // ---- block maps of the launches over the unfinished runs ----
 static int init_blocks(const RunHost &r) { return (r.m * ((r.d + 1) / 2) + 255) / 256; }
@@ -369,7 +369,7 @@ static int dirs_blocks(const RunHost &r)
 {
     if (!r.R.dirbuf) return 0;
     const long long t = (long long)r.k * r.p;
-    return (int)((t + dirs_rows() - 1) / dirs_rows());
+    return (int)((t + dirs_rows(r.D) - 1) / dirs_rows(r.D));
 }
 static int hrss_blocks(const RunHost &r) { return (r.k + r.R.C - 1) / r.R.C; }  // GP: C = 1
 
@@ -407,8 +407,8 @@ static ns_status build_maps(ns_ctx *ctx, const std::vector<char> &act)
     mb.add(ctx, ctx->L_init, all, act, init_blocks);
     mb.add(ctx, ctx->L_one, all, act, [](const RunHost &) { return 1; });
     mb.add(ctx, ctx->L_cov, all, act, cov_blocks);
-    for (int di = 0; di < 3; ++di) {
-        const int D = 32 << di;
+    for (int di = 0; di < 4; ++di) {
+        const int D = kDims[di];
         std::vector<int> rs;
         for (int r = 0; r < ctx->n; ++r)
             if (ctx->runs[r].D == D) rs.push_back(r);
@@ -499,8 +499,8 @@ static ns_status enqueue_iteration(ns_ctx *ctx)
     }
     e = launch_cov(ctx->L_cov, ctx->L_one, ctx->Dmax, ctx->stream);
     if (e != hipSuccess) return device_error(ctx, "whitening launch", e);
-    for (int di = 0; di < 3; ++di) {
-        e = launch_dirs(ctx->L_dirs[di], 32 << di, ctx->stream);
+    for (int di = 0; di < 4; ++di) {
+        e = launch_dirs(ctx->L_dirs[di], kDims[di], ctx->stream);
         if (e != hipSuccess) return device_error(ctx, "direction launch", e);
     }
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -606,7 +606,13 @@ static ns_status validate_run(const ns_prior *prior, const ns_energy *energy, co
     if (!prior || !energy || !cfg || !prior->a || !prior->b) { msg = "NULL argument"; return NS_EINVAL; }
     const int d = prior->d;
     if (d < 1 || energy->d != d) { msg = "dimension mismatch or d < 1"; return NS_EINVAL; }
-    if (d > 128) { msg = "d > 128"; return NS_EUNSUPPORTED; }
+    if (d > 320) { msg = "d > 320"; return NS_EUNSUPPORTED; }
+    if (d > 128 && ((energy->kind != NS_LIK_FUNNEL && energy->kind != NS_LIK_GAUSS_RASTRIGIN) ||
+                    cfg->precision != NS_FP64 || (cfg->flags & NS_FLAG_INLINE_DIRECTIONS))) {
+        msg = "d > 128 is implemented for the funnel and Gaussian-Rastrigin likelihoods in FP64 "
+              "with the direction buffer";
+        return NS_EUNSUPPORTED;
+    }
     if (prior->kind != NS_PRIOR_BOX && prior->kind != NS_PRIOR_GAUSS_DIAG) {
         msg = "unknown prior kind";
         return NS_EINVAL;
@@ -727,17 +733,17 @@ static ns_status alloc_run(ns_ctx *ctx, int r)
 #ifdef NSS_PHASE_TIMING
     if ((st = dalloc(ctx, &R.prof, 16))) return st;
 #endif
-    // per-iteration direction buffer (k p D doubles) unless it would exceed 4 GiB; without it
-    // the chains generate their directions inline
+    // per-iteration direction buffer (k p D doubles) unless it would exceed 32 GiB; without it
+    // the chains generate their directions inline (D <= 128 only)
     const size_t bytes = (size_t)k * p * (D + 8) * 8;
-    if (bytes <= ((size_t)4 << 30) && !(cfg->flags & NS_FLAG_INLINE_DIRECTIONS) &&
+    if (bytes <= ((size_t)32 << 30) && !(cfg->flags & NS_FLAG_INLINE_DIRECTIONS) &&
         rh.lik != LIK_GP) {  // GP chains draw their directions themselves
         if ((st = dalloc(ctx, &R.dirbuf, (size_t)k * p * D))) return st;
         if ((st = dalloc(ctx, &R.ubuf, (size_t)k * p * 8))) return st;
-    } else if (R.rw) {
+    } else if (R.rw || D > 128) {
         return fail(ctx, NS_EUNSUPPORTED,
-                    "random-walk replacement needs the direction buffer (k p (d+8) doubles "
-                    "<= 4 GiB, no NS_FLAG_INLINE_DIRECTIONS)");
+                    "random-walk replacement and d > 128 need the direction buffer "
+                    "(k p (d+8) doubles <= 32 GiB, no NS_FLAG_INLINE_DIRECTIONS)");
     }
     const int n = R.smc ? m : m - k;   // points of the whitening covariance
     R.covG = n / 64 < 1 ? 1 : (n / 64 > 32 ? 32 : n / 64);

@@ -121,7 +121,7 @@ int mode_supported(const DevProblem &P, int mode);
 int upw_for(const DevProblem &P);
 int upw_template(int D, int upw);         // the compiled UPW that covers upw (0 if none)
 size_t hrss_lds_bytes(int D, int K);
-int dirs_rows();                          // directions per k_dirs block
+int dirs_rows(int D);                     // directions per k_dirs block
 
 // Post-hoc geometric uncertainty (nss_post.hip).  Deaths: the dead record, then the final
 // survivors logL[perm[k..m-1]]; outputs logz[R], logw_mean[N], ess[1] on the device; ws holds

@@ -51,7 +51,8 @@ __host__ __device__ inline HLayout hrss_layout(int D, int K)
     o.rc = off; off += al16(kRows * 4);
     o.q = off; off += al16(kRows * q_stride(D, K) * 8);
     o.q32 = off; off += al16(kRows * q_stride(D, K) * 4);
-    o.lsig = off; off += al16(lsig_doubles(D) * 8);
+    // the factor is staged only for chains that draw their own directions (D <= 128)
+    o.lsig = off; off += D <= 128 ? al16(lsig_doubles(D) * 8) : 0;
     o.total = off;
     return o;
 }
@@ -824,8 +825,10 @@ __global__ __launch_bounds__(1024) void k_chol(Launch Lc)
     const int G = R.covG, ntile = (P.D / 16) * (P.D / 16 + 1) / 2;
     const double *part1 = R.part1, *part2 = R.part2;
     const int D = P.D, d = P.d, tid = threadIdx.x;
-    double *A = (double *)smem;              // packed lower, D(D+1)/2
-    double *mc = A + D * (D + 1) / 2;        // mean - shift, [D]
+    // packed lower triangle, D(D+1)/2: in LDS up to D = 128, else worked in place in the run's
+    // packed factor (global memory, coherent within the workgroup across its barriers)
+    double *A = D <= 128 ? (double *)smem : R.Lpk;
+    double *mc = (double *)smem + (D <= 128 ? D * (D + 1) / 2 : 0);   // mean - shift, [D]
     double *red = mc + D;                    // [32]
     int *fail = (int *)(red + 32);
     const int n = R.smc ? R.m : R.m - R.k;
@@ -915,13 +918,14 @@ __global__ __launch_bounds__(1024) void k_chol(Launch Lc)
 // random-walk runs: the proposal step v = s L z), dirbuf[(j p + s) D + a], zero for a >= d.
 // 64 directions per workgroup.
 // ------------------------------------------------------------------------------------------
-constexpr int kDirRows = 64;
+// directions per k_dirs workgroup: 64, or 32 at D = 320 (their normals fill the LDS)
+__host__ __device__ constexpr int dir_rows(int D) { return D > 128 ? 32 : 64; }
 constexpr int kStepU = 8;                 // per step: tL0, uh, default shrink proposals 0..5
 constexpr int kStepShrinkU = kStepU - 2;
 __host__ __device__ inline int dirs_lds_bytes(int D)
 {
-    return al16(kDirRows * (D + 1) * 8) + kDirRows * 8 + kDirRows * kStepU * 8 +
-           2 * kDirRows * 4;
+    const int rows = dir_rows(D);
+    return al16(rows * (D + 1) * 8) + rows * 8 + rows * kStepU * 8 + 2 * rows * 4;
 }
 
 // The normals and uniforms are drawn by all threads; v = L z is one small FP64 MFMA product per
@@ -939,17 +943,17 @@ __global__ __launch_bounds__(256) void k_dirs(Launch Lc)
     const DevProblem P = Lc.P[bm.x];
     const DevRun R = Lc.R[bm.x];
     if (R.iscal[0] || R.iscal[2] <= 0) return;
-    constexpr int LDZ = D + 1;
+    constexpr int LDZ = D + 1, ROWS = dir_rows(D);
     double *zs = (double *)smem;
-    double *nz = zs + kDirRows * LDZ;
-    double *udraw = nz + kDirRows;              // [kDirRows][kStepU] raw uniforms
-    int *rj = (int *)(udraw + kDirRows * kStepU);   // chain of each row (-1 past the end)
-    int *rs = rj + kDirRows;                    // step of each row
+    double *nz = zs + ROWS * LDZ;
+    double *udraw = nz + ROWS;              // [ROWS][kStepU] raw uniforms
+    int *rj = (int *)(udraw + ROWS * kStepU);   // chain of each row (-1 past the end)
+    int *rs = rj + ROWS;                    // step of each row
     const int tid = threadIdx.x, d = P.d, p = R.p;
     const long long total = (long long)R.k * p;
-    const long long base = (long long)bm.y * kDirRows;
+    const long long base = (long long)bm.y * ROWS;
     const uint32_t it = (uint32_t)R.iscal[3] + 1u;
-    if (tid < kDirRows) {
+    if (tid < ROWS) {
         const long long idx = base + tid;
         int j = -1, st = 0;
         if (idx < total) { j = (int)(idx / p); st = (int)(idx - (long long)j * p); }
@@ -958,7 +962,7 @@ __global__ __launch_bounds__(256) void k_dirs(Launch Lc)
     }
     __syncthreads();
     const int nq = (d + 1) >> 1;
-    for (int i = tid; i < kDirRows * nq; i += 256) {
+    for (int i = tid; i < ROWS * nq; i += 256) {
         const int r = i / nq, q = i - r * nq;
         const int j = rj[r];
         if (j < 0) continue;
@@ -972,7 +976,7 @@ __global__ __launch_bounds__(256) void k_dirs(Launch Lc)
     // ubuf[0] = tL0 = -w U, ubuf[1] = the height uniform uh (purpose STEP), ubuf[2 + i] = the
     // i-th shrink proposal of the bracket [tL0, tL0 + w] after i rejections (purpose SHRINK,
     // draws 0, 1, ...), with the same arithmetic as the chain's own proposals.
-    for (int i = tid; i < kDirRows * kStepU; i += 256) {
+    for (int i = tid; i < ROWS * kStepU; i += 256) {
         const int r = i / kStepU, q = i - r * kStepU;
         const int j = rj[r], st = rs[r];
         if (j < 0) continue;
@@ -986,7 +990,7 @@ __global__ __launch_bounds__(256) void k_dirs(Launch Lc)
         }
     }
     __syncthreads();
-    if (tid < kDirRows && rj[tid] >= 0) {
+    if (tid < ROWS && rj[tid] >= 0) {
         const double *u = udraw + tid * kStepU;
         double *o = R.ubuf + (base + tid) * kStepU;
         const double width = R.width;
@@ -1001,6 +1005,7 @@ __global__ __launch_bounds__(256) void k_dirs(Launch Lc)
         }
     }
     const int w = tid >> 6, l = tid & 63, li = l & 15, lk = l >> 4;
+    if (16 * w >= ROWS) return;   // D = 320: two waves hold the 32 directions
     const int r = 16 * w + li;
     // |z| of the wave's 16 directions: four partial sums per direction, then lane exchanges
     double s2 = 0.0;
@@ -1091,7 +1096,7 @@ __global__ __launch_bounds__(256) void k_hrss(Launch Lc)
     const double width = R.width;
     const int p = R.p, cap_out = R.stepout_cap, cap_sh = R.shrink_cap;
     const bool box = (P.prior_kind == PRIOR_BOX);
-    const bool pre = (R.dirbuf != nullptr);
+    const bool pre = D > 128 || R.dirbuf != nullptr;   // D = 320 always reads the buffer
 
     if (!pre) {
         if constexpr (D <= 64) {
@@ -1922,7 +1927,7 @@ int upw_template(int D, int upw)
 }
 
 size_t hrss_lds_bytes(int D, int K) { return (size_t)hrss_layout(D, K).total; }
-int dirs_rows() { return kDirRows; }
+int dirs_rows(int D) { return dir_rows(D); }
 
 int mode_supported(const DevProblem &P, int mode)
 {
@@ -1995,20 +2000,22 @@ static hipError_t rw_t(const Launch &L, hipStream_t s)
     } while (0)
 #define NSS_DISPATCH(FN, ...)                                                                 \
     do {                                                                                      \
-        if (D != 32 && D != 64 && D != 128) return hipErrorInvalidValue;                      \
+        if (D != 32 && D != 64 && D != 128 && D != 320) return hipErrorInvalidValue;          \
         if (lik == LIK_FUNNEL) {                                                              \
             if (mode != MODE_FP64) return hipErrorNotSupported;                               \
             if (D == 32) return FN<32, MODE_FP64, LIK_FUNNEL, 1>(__VA_ARGS__);                \
             if (D == 64) return FN<64, MODE_FP64, LIK_FUNNEL, 1>(__VA_ARGS__);                \
-            return FN<128, MODE_FP64, LIK_FUNNEL, 1>(__VA_ARGS__);                            \
+            if (D == 128) return FN<128, MODE_FP64, LIK_FUNNEL, 1>(__VA_ARGS__);              \
+            return FN<320, MODE_FP64, LIK_FUNNEL, 1>(__VA_ARGS__);                            \
         }                                                                                     \
         if (lik == LIK_RG) {                                                                  \
             if (mode != MODE_FP64) return hipErrorNotSupported;                               \
             if (D == 32) return FN<32, MODE_FP64, LIK_RG, 1>(__VA_ARGS__);                    \
             if (D == 64) return FN<64, MODE_FP64, LIK_RG, 1>(__VA_ARGS__);                    \
-            return FN<128, MODE_FP64, LIK_RG, 1>(__VA_ARGS__);                                \
+            if (D == 128) return FN<128, MODE_FP64, LIK_RG, 1>(__VA_ARGS__);                  \
+            return FN<320, MODE_FP64, LIK_RG, 1>(__VA_ARGS__);                                \
         }                                                                                     \
-        if (lik != LIK_MIXTURE) return hipErrorInvalidValue;                                  \
+        if (lik != LIK_MIXTURE || D == 320) return hipErrorInvalidValue;                      \
         if (mode == MODE_FP64) {                                                              \
             if (D == 32) return FN<32, MODE_FP64, LIK_MIXTURE, 1>(__VA_ARGS__);               \
             if (D == 64) return FN<64, MODE_FP64, LIK_MIXTURE, 1>(__VA_ARGS__);               \
@@ -2076,7 +2083,8 @@ hipError_t launch_cov(const Launch &cov, const Launch &one, int D, hipStream_t s
     hipLaunchKernelGGL(k_cov, dim3(cov.nblocks), dim3(256), 0, s, cov);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const size_t lds = (size_t)(D * (D + 1) / 2 + D + 32) * 8 + 16;
+    const int Dl = D <= 128 ? D : 128;   // runs above 128 keep their factor in global memory
+    const size_t lds = (size_t)(Dl * (Dl + 1) / 2 + D + 32) * 8 + 16;
     e = set_lds(k_chol, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_chol, dim3(one.nblocks), dim3(1024), lds, s, one);
@@ -2099,6 +2107,7 @@ hipError_t launch_dirs(const Launch &L, int D, hipStream_t s)
     if (D == 32) return dirs_t<32>(L, s);
     if (D == 64) return dirs_t<64>(L, s);
     if (D == 128) return dirs_t<128>(L, s);
+    if (D == 320) return dirs_t<320>(L, s);
     return hipErrorInvalidValue;
 }
 

@@ -47,8 +47,14 @@ def test_invalid_problem(N):
     from paper_2601_23252_amd import problems as G
     cfg = N.ns_config_default()
     cfg.n_live, cfg.k, cfg.chain_len = 50, 10, 5
+    pr, en, keep = _structs(N, G.funnel(330))
+    assert N.ns_init(pr, en, cfg, None)[0] == N.NS_EUNSUPPORTED   # d > 320
+    pr, en, keep = _structs(N, G.mixture_problem(3, 200, 1))
+    assert N.ns_init(pr, en, cfg, None)[0] == N.NS_EUNSUPPORTED   # d > 128: not mixtures
     pr, en, keep = _structs(N, G.funnel(200))
-    assert N.ns_init(pr, en, cfg, None)[0] == N.NS_EUNSUPPORTED   # d > 128
+    cfg.flags = N.NS_FLAG_INLINE_DIRECTIONS
+    assert N.ns_init(pr, en, cfg, None)[0] == N.NS_EUNSUPPORTED   # d > 128: direction buffer
+    cfg.flags = 0
     pr, en, keep = _structs(N, G.funnel(1 + 1))
     en.d = 3
     assert N.ns_init(pr, en, cfg, None)[0] == N.NS_EINVAL          # dimension mismatch

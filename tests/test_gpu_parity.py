@@ -276,3 +276,13 @@ def test_config3_end_to_end_lnz(N, prec):
     assert s["band_violations"] == 0 and s["nonfinite"] == 0
     assert s["evals"] > 0 and s["iterations"] > 100
     gpu.close()
+
+
+def test_funnel_d200_padded_320(N, O):
+    """The funnel at d = 200 (padded dimension 320): per-iteration parity, including the
+    global-memory Cholesky of the 200 x 200 covariance of 500 survivors (with fewer survivors
+    than dimensions the covariance is singular up to its jitter and the last pivots amplify
+    rounding)."""
+    from paper_2601_23252_amd import problems as G
+    prob = G.funnel(200, box=20.0, m=600, k=100)
+    _parity_run(N, O, prob, 600, 100, 20, seed=6, n_iter=4)

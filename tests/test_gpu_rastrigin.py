@@ -32,7 +32,7 @@ def _width(d):
 
 
 @pytest.mark.parametrize("d,alpha", [(1, 0.5), (2, 0.0), (10, 0.3), (33, 1.0), (100, 0.5),
-                                     (128, 0.0)])
+                                     (128, 0.0), (129, 0.7), (300, 0.5)])
 def test_rastrigin_loglik_matches_oracle(N, oracle_lib, d, alpha):
     from paper_2601_23252_amd import problems as G
     prob = G.rastrigin_gauss(d, alpha, m=64, k=16)
@@ -110,6 +110,39 @@ def test_rastrigin_full_size_d100_sampled_chains(N, oracle_lib):
         parent = s1["parents"][j]
         x, logL, _, trace = P.hrss_chain(s0["x"][parent], s0["logL"][parent], s0["Lstar"],
                                          s1["Lsig"], width, prob["p"], 3, 0, 1, j, trace=True)
+        slot = s0["perm"][j]
+        assert np.array_equal(tr[j], trace), f"chain {j}: decisions"
+        assert np.allclose(s1["x"][slot], x, rtol=1e-10, atol=1e-12), f"chain {j}"
+        assert math.isclose(s1["logL"][slot], logL, rel_tol=1e-10, abs_tol=1e-10)
+    gpu.close()
+
+
+def test_rastrigin_parity_d150(N, oracle_lib):
+    """d = 150 runs on the padded-320 kernels (global-memory Cholesky, 32-row direction
+    blocks, five coordinates per lane): per-iteration parity with the oracle.  The survivors
+    (300) outnumber the dimensions, so the whitening covariance is well conditioned."""
+    from paper_2601_23252_amd import problems as G
+    prob = G.rastrigin_gauss(150, 0.5)
+    _parity(N, oracle_lib, prob, m=400, k=100, p=30, seed=4, n_iter=4)
+
+
+def test_rastrigin_full_size_d300_sampled_chains(N, oracle_lib):
+    """d = 300 (the largest dimension of the paper's comparison), 1000 live points, k = 500:
+    after one GPU iteration with 300 steps per chain, chains recomputed by the oracle from the
+    same starting state take the same decisions."""
+    from paper_2601_23252_amd import problems as G
+    prob = G.rastrigin_gauss(300, 0.5, p=300)
+    width = _width(300)
+    gpu = N.NSRun(prob, width=width, seed=5, trace=True)
+    s0 = gpu.state()
+    gpu.step()
+    s1 = gpu.state()
+    tr = gpu.trace()
+    P = oracle_lib.Problem(prob)
+    for j in (0, 250, prob["k"] - 1):
+        parent = s1["parents"][j]
+        x, logL, _, trace = P.hrss_chain(s0["x"][parent], s0["logL"][parent], s0["Lstar"],
+                                         s1["Lsig"], width, prob["p"], 5, 0, 1, j, trace=True)
         slot = s0["perm"][j]
         assert np.array_equal(tr[j], trace), f"chain {j}: decisions"
         assert np.allclose(s1["x"][slot], x, rtol=1e-10, atol=1e-12), f"chain {j}"
