@@ -42,7 +42,7 @@
 
 #define OR_PI 3.14159265358979323846
 
-enum { P_INIT = 1, P_RESAMPLE = 2, P_DIR = 3, P_STEP = 4, P_SHRINK = 5, P_GEOM = 6 };
+enum { P_INIT = 1, P_RESAMPLE = 2, P_DIR = 3, P_STEP = 4, P_SHRINK = 5, P_GEOM = 6, P_POST = 7 };
 enum { PRIOR_BOX = 0, PRIOR_GAUSS = 1 };
 enum { LIK_MIXTURE = 1, LIK_FUNNEL = 2, LIK_GP = 3, LIK_RG = 4 };
 
@@ -593,6 +593,7 @@ typedef struct {
     double *Lsig;     /* d x d, last whitening factor */
     int *parents;     /* k, last resample */
     double *dead;     /* dead logL record */
+    double *dead_x;   /* the dead points' coordinates, [cap_dead][d] */
     int64_t n_dead, cap_dead;
     int whiten_fallbacks;
     int replacement;  /* 0: HRSS (width = slice width); 1: random walk (width = step scale) */
@@ -606,6 +607,7 @@ void or_run_free(void *rr)
     orun *r = (orun *)rr;
     if (!r) return;
     free(r->x); free(r->logL); free(r->perm); free(r->Lsig); free(r->parents); free(r->dead);
+    free(r->dead_x);
     free(r);
 }
 
@@ -626,6 +628,7 @@ void *or_run_new(const void *pp, int m, int k, int p_steps, double width, int st
     r->parents = (int *)calloc(k, sizeof(int));
     r->cap_dead = 1 << 16;
     r->dead = (double *)malloc(sizeof(double) * r->cap_dead);
+    r->dead_x = (double *)malloc(sizeof(double) * (size_t)r->cap_dead * d);
     return r;
 }
 
@@ -670,7 +673,11 @@ static void select_and_account(orun *r)
         if (r->n_dead == r->cap_dead) {
             r->cap_dead *= 2;
             r->dead = (double *)realloc(r->dead, sizeof(double) * r->cap_dead);
+            r->dead_x = (double *)realloc(r->dead_x,
+                                          sizeof(double) * (size_t)r->cap_dead * r->p->d);
         }
+        memcpy(r->dead_x + (size_t)r->n_dead * r->p->d, r->x + (size_t)r->perm[j - 1] * r->p->d,
+               sizeof(double) * r->p->d);
         r->dead[r->n_dead++] = L;
     }
 }
@@ -837,6 +844,7 @@ void *or_smc_new(const void *pp, int m, int p_steps, double width, int stepout_c
     r->parents = (int *)calloc(m, sizeof(int));
     r->cap_dead = 1;
     r->dead = (double *)malloc(sizeof(double));
+    r->dead_x = (double *)malloc(sizeof(double) * d);
     return r;
 }
 
@@ -1009,6 +1017,15 @@ void or_get_aux(const void *rr, double *Lsig, int *parents)
     if (parents) memcpy(parents, r->parents, sizeof(int) * r->k);
 }
 
+/* The dead points' coordinates, [n][d] row by row; returns the number of dead points. */
+int64_t or_get_dead_x(const void *rr, double *out, int64_t cap)
+{
+    const orun *r = (const orun *)rr;
+    const int64_t n = r->n_dead < cap ? r->n_dead : cap;
+    if (out && n > 0) memcpy(out, r->dead_x, sizeof(double) * (size_t)n * r->p->d);
+    return r->n_dead;
+}
+
 int64_t or_get_dead(const void *rr, double *out, int64_t cap)
 {
     const orun *r = (const orun *)rr;
@@ -1088,4 +1105,42 @@ void or_geom(const double *dead, int64_t n_dead, const double *final_sorted, int
     free(lt);
     free(lw);
     free(acc);
+}
+
+/* Weighted posterior samples: the geometric-mean weights w~_i of or_geom (R replicas, beta),
+ * then n draws by systematic resampling: positions (u + j) / n, u uniform (Philox purpose
+ * POST, counter 0), against the cumulative normalised weights in death order; sample j is the
+ * first death whose cumulative weight reaches its position (the last if rounding leaves none).
+ * dead_x[n_dead][d] and final_x[nf][d] hold the coordinates in the order of dead and
+ * final_sorted.  Outputs x[n][d] and idx[n] (death indices). */
+void or_posterior_samples(const double *dead, const double *dead_x, int64_t n_dead,
+                          const double *final_sorted, const double *final_x, int64_t nf, int d,
+                          int m, int k, int R, double beta, uint64_t seed, uint32_t run_id,
+                          int n, double *x, int64_t *idx)
+{
+    const int64_t N = n_dead + nf;
+    double *lw = (double *)malloc(sizeof(double) * (size_t)(N > 0 ? N : 1));
+    double *lz = (double *)malloc(sizeof(double) * (size_t)R);
+    or_geom(dead, n_dead, final_sorted, nf, m, k, R, beta, seed, run_id, lz, lw, NULL);
+    double mx = -INFINITY;
+    for (int64_t i = 0; i < N; ++i) if (lw[i] > mx) mx = lw[i];
+    double *cum = (double *)malloc(sizeof(double) * (size_t)(N > 0 ? N : 1));
+    double s = 0.0;
+    for (int64_t i = 0; i < N; ++i) {
+        s += lw[i] > -INFINITY ? exp(lw[i] - mx) : 0.0;
+        cum[i] = s;
+    }
+    for (int64_t i = 0; i < N; ++i) cum[i] /= s;
+    okey key = { { (uint32_t)seed, (uint32_t)(seed >> 32) ^ run_id } };
+    double u, unused;
+    draw2(key, P_POST, 0u, 0u, 0u, 0u, &u, &unused);
+    int64_t i = 0;
+    for (int j = 0; j < n; ++j) {
+        const double pos = (u + j) / n;
+        while (i < N - 1 && cum[i] < pos) ++i;
+        idx[j] = i;
+        const double *src = i < n_dead ? dead_x + (size_t)i * d : final_x + (size_t)(i - n_dead) * d;
+        memcpy(x + (size_t)j * d, src, sizeof(double) * d);
+    }
+    free(lw); free(lz); free(cum);
 }

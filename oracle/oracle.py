@@ -82,6 +82,13 @@ def lib():
         L.or_hrss_chain_tempered.argtypes = [C.c_void_p, _dp, _dp, C.c_double, _dp, C.c_double,
                                              C.c_int, C.c_int, C.c_int, C.c_uint64, C.c_uint32,
                                              C.c_uint32, C.c_uint32, _lp, C.c_void_p]
+        L.or_get_dead_x.restype = C.c_int64
+        L.or_get_dead_x.argtypes = [C.c_void_p, C.c_void_p, C.c_int64]
+        L.or_posterior_samples.restype = None
+        L.or_posterior_samples.argtypes = [_dp, C.c_void_p, C.c_int64, _dp, C.c_void_p,
+                                           C.c_int64, C.c_int, C.c_int, C.c_int, C.c_int,
+                                           C.c_double, C.c_uint64, C.c_uint32, C.c_int,
+                                           C.c_void_p, C.c_void_p]
         L.or_run_set_replacement.restype = C.c_int
         L.or_run_set_replacement.argtypes = [C.c_void_p, C.c_int]
         L.or_rw_chain.restype = None
@@ -274,9 +281,33 @@ class Run:
         lib().or_get_dead(self.h, out.ctypes.data, n)
         return out
 
+    def dead_x(self) -> np.ndarray:
+        n = lib().or_get_dead_x(self.h, None, 0)
+        out = np.zeros((n, self.d))
+        lib().or_get_dead_x(self.h, out.ctypes.data, n)
+        return out
+
     @property
     def iter(self) -> int:
         return self.state()["iter"]
+
+
+def posterior_samples(dead, dead_x, final_logL, final_x, m, k, R, n, beta=1.0, seed=0,
+                      run_id=0):
+    """Weighted posterior samples (resampling with the geometric-mean weights of geom()).
+    final_logL / final_x are the survivors in ascending (logL, index) order.  Returns
+    (x[n, d], idx[n])."""
+    dead = np.ascontiguousarray(dead, np.float64)
+    dx = np.ascontiguousarray(dead_x, np.float64)
+    fl = np.ascontiguousarray(final_logL, np.float64)
+    fx = np.ascontiguousarray(final_x, np.float64)
+    d = fx.shape[1]
+    x = np.zeros((n, d))
+    idx = np.zeros(n, np.int64)
+    lib().or_posterior_samples(dead, dx.ctypes.data, len(dead), fl, fx.ctypes.data, len(fl), d,
+                               int(m), int(k), int(R), float(beta), int(seed), int(run_id),
+                               int(n), x.ctypes.data, idx.ctypes.data)
+    return x, idx
 
 
 def geom(dead, final_logL, m, k, R, beta=1.0, seed=0, run_id=0, weights=True):

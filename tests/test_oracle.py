@@ -685,3 +685,34 @@ def test_smc_lnz_config1_unbiased(oracle_lib):
     zs = np.array(zs)
     assert abs(zs.mean() - tz) < 4 * zs.std() / math.sqrt(len(zs)), (zs.mean(), tz, zs.std())
     assert 0.02 < zs.std() < 0.5
+
+
+def test_posterior_samples_resampling_and_moments(oracle_lib):
+    """config 1 run to termination: the posterior samples are rows of the recorded deaths,
+    each death drawn floor(n w) or floor(n w) + 1 times for its normalised geometric-mean
+    weight w (systematic resampling), and their mean and variance match the truncated
+    N(0, 0.01 I) posterior within the sampling error of the Kish ESS."""
+    from oracle import theory as T
+    from paper_2601_23252_amd import problems as G
+    prob = G.config1()
+    R = oracle_lib.Run(oracle_lib.Problem(prob), 200, 50, 25, T.width_whitened(5), 2, threads=8)
+    R.init()
+    R.run()
+    st = R.state()
+    dead, dx = R.dead(), R.dead_x()
+    assert dx.shape == (len(dead), 5)
+    assert np.allclose(oracle_lib.Problem(prob).loglik(dx), dead)   # rows match their logL
+    fin = st["perm"][50:]
+    fl, fx = st["logL"][fin], st["x"][fin]
+    n = 5000
+    x, idx = oracle_lib.posterior_samples(dead, dx, fl, fx, 200, 50, 40, n, 1.0, seed=3)
+    allx = np.vstack([dx, fx])
+    assert np.array_equal(x, allx[idx])
+    _, lw, ess = oracle_lib.geom(dead, fl, 200, 50, 40, 1.0, seed=3)
+    w = np.exp(lw - lw.max())
+    w /= w.sum()
+    counts = np.bincount(idx, minlength=len(w))
+    assert np.all((counts >= np.floor(n * w) - 1e-9) & (counts <= np.floor(n * w) + 1 + 1e-9))
+    se = 0.1 / math.sqrt(ess)
+    assert np.all(np.abs(x.mean(0)) < 5 * se), (x.mean(0), se)
+    assert np.all(np.abs(x.var(0) / 0.01 - 1) < 0.25), x.var(0)
