@@ -235,7 +235,8 @@ def bench_geom(args):
     N.load()
     prob = G.config3()
     R_rep = args.replicas
-    run = N.NSRun(prob, p=args.chain_factor * prob["d"], seed=0, precision="bf16x3")
+    run = N.NSRun(prob, p=args.chain_factor * prob["d"], seed=0, precision="bf16x3",
+                  record_points=True)
     run.run()
     print(f"[bench] setup run done: {run.stats()['n_dead']} dead points", file=sys.stderr,
           flush=True)
@@ -261,6 +262,13 @@ def bench_geom(args):
         "result": {"logz_mean": float(np.mean(g["logz"])), "logz_std": float(np.std(g["logz"])),
                    "ess": g["ess"], "sigma_from_H": run.logz()[1]},
     }
+    # weighted posterior samples from the same weights (10^4 draws), wall time with copies
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    xs, _ = run.posterior_samples(10000, R=R_rep, beta=1.0, seed=1)
+    out["config"]["posterior_samples_10k_wall_ms"] = 1e3 * (time.perf_counter() - t0)
+    out["result"]["posterior_samples"] = int(xs.shape[0])
     ops = geom_ops()
     if ops is not None:
         achieved = ops * units / t

@@ -176,6 +176,8 @@ typedef enum {
                                       * themselves instead of reading a per-iteration buffer
                                       * of k*p*(d+8) doubles (the buffer is also skipped when
                                       * it would exceed 32 GiB; not for d > 128) */
+#define NS_FLAG_RECORD_POINTS 16  /* keep the dead points' coordinates beside their logL
+                                  * ((max_iter + 1) k d doubles) for ns_posterior_samples */
 #define NS_FLAG_GRAPH  8  /* ns_run captures each batch of 16 iterations as a HIP graph and
                            * replays it (re-captured when a run of the batch finishes); not
                            * used together with NS_FLAG_TIMING.  Results are identical. */
@@ -278,6 +280,17 @@ ns_status ns_get_dead(ns_ctx *ctx, double *out, int64_t cap, int64_t *n);
 ns_status ns_geom_uncertainty(ns_ctx *ctx, int32_t run, int32_t R, double beta, uint64_t seed,
                               uint32_t run_id, double *logz, double *logw_mean, int64_t cap,
                               double *ess, int64_t *n_deaths, double *device_ms);
+
+/* Weighted posterior samples of run `run` (App. "Estimation of prior volumes and propagation
+ * of geometric uncertainty": resampling with the geometric-mean weights): the weights of
+ * ns_geom_uncertainty(run, R, beta, seed, run_id), then n samples by systematic resampling of
+ * the deaths (one uniform: Philox purpose 7, counter 0, the same key).  x[n * d] (host)
+ * receives the samples' coordinates, row by row; idx[n] (host, may be NULL) their death
+ * indices (dead record first, then the survivors in ascending logL).  Needs a context created
+ * with NS_FLAG_RECORD_POINTS.  Errors: as ns_geom_uncertainty, NS_EINVAL for NULL x or
+ * n < 1, NS_ESTATE if the coordinates were not recorded. */
+ns_status ns_posterior_samples(ns_ctx *ctx, int32_t run, int32_t R, double beta, uint64_t seed,
+                               uint32_t run_id, int32_t n, double *x, int64_t *idx);
 
 /* NS_FLAG_TRACE: copy the last iteration's trace, out[(j*p + s)*4 + {0,1,2,3}] = left
  * expansions, right expansions, shrink proposals, accepted, for chain j and step s. */

@@ -730,6 +730,8 @@ static ns_status alloc_run(ns_ctx *ctx, int r)
         return st;
     if (cfg->flags & NS_FLAG_TRACE)
         if ((st = dalloc(ctx, &R.trace, (size_t)k * p * 4))) return st;
+    if ((cfg->flags & NS_FLAG_RECORD_POINTS) && !R.smc)
+        if ((st = dalloc(ctx, &R.deadx, (size_t)R.dead_cap * d))) return st;
 #ifdef NSS_PHASE_TIMING
     if ((st = dalloc(ctx, &R.prof, 16))) return st;
 #endif
@@ -1160,16 +1162,14 @@ extern "C" ns_status ns_get_dead(ns_ctx *ctx, double *out, int64_t cap, int64_t 
     return NS_OK;
 }
 
-extern "C" ns_status ns_geom_uncertainty(ns_ctx *ctx, int32_t run, int32_t R, double beta,
-                                         uint64_t seed, uint32_t run_id, double *logz,
-                                         double *logw_mean, int64_t cap, double *ess,
-                                         int64_t *n_deaths, double *device_ms)
+// The geometric-uncertainty computation of run `run` on the context's stream, outputs left in
+// the context's buffer (extra = further bytes reserved after them, at *extra_ptr).
+static ns_status enqueue_geom(ns_ctx *ctx, int run, int R, double beta, uint64_t seed,
+                              uint32_t run_id, size_t extra, GeomLaunch &G, char **extra_ptr)
 {
-    if (!run_ok(ctx, run) || !logz) return NS_EINVAL;
     if (ctx->smc) return fail(ctx, NS_EUNSUPPORTED, "an SMC run has no dead record");
     if (R < 1 || R > 65535) return fail(ctx, NS_EINVAL, "replicas must be in [1, 65535]");
     if (!(beta >= 0.0) || beta == INFINITY) return fail(ctx, NS_EINVAL, "beta must be finite and >= 0");
-    if (cap < 0) return fail(ctx, NS_EINVAL, "cap < 0");
     const RunHost &rh = ctx->runs[run];
     const DevRun &D = rh.R;
     unsigned long long nd = 0;
@@ -1178,12 +1178,12 @@ extern "C" ns_status ns_geom_uncertainty(ns_ctx *ctx, int32_t run, int32_t R, do
     if ((long long)nd > D.dead_cap)
         return fail(ctx, NS_ESTATE, "dead record truncated: more deaths than max_iter + 1 iterations hold");
     const long long N = (long long)nd + (rh.m - rh.k);
-    if (n_deaths) *n_deaths = N;
     if (N >= (1ll << 31)) return fail(ctx, NS_EUNSUPPORTED, "more than 2^31 - 1 deaths");
     const int groups = geom_groups(N, R);
     auto up = [](size_t b) { return (b + 255) / 256 * 256; };
     const size_t out_bytes = up((size_t)R * 8) + up((size_t)N * 8) + up(8);
-    const size_t need = out_bytes + geom_workspace_bytes(N, R, groups);
+    const size_t wsb = up(geom_workspace_bytes(N, R, groups));
+    const size_t need = out_bytes + wsb + extra;
     if (need > ctx->geom_bytes) {
         if (ctx->geom_buf) CK(hipFree(ctx->geom_buf));
         ctx->geom_buf = nullptr;
@@ -1192,7 +1192,7 @@ extern "C" ns_status ns_geom_uncertainty(ns_ctx *ctx, int32_t run, int32_t R, do
         ctx->geom_bytes = need;
     }
     char *b = (char *)ctx->geom_buf;
-    GeomLaunch G{};
+    G = GeomLaunch{};
     G.dead = D.dead;
     G.n_dead = (long long)nd;
     G.N = N;
@@ -1209,17 +1209,35 @@ extern "C" ns_status ns_geom_uncertainty(ns_ctx *ctx, int32_t run, int32_t R, do
     G.logw_mean = (double *)(b + up((size_t)R * 8));
     G.ess = (double *)(b + up((size_t)R * 8) + up((size_t)N * 8));
     G.ws = b + out_bytes;
+    if (extra_ptr) *extra_ptr = b + out_bytes + wsb;
+    hipError_t e = launch_geom(G, ctx->stream);
+    if (e != hipSuccess) return device_error(ctx, "geometric-uncertainty launch", e);
+    return NS_OK;
+}
+
+extern "C" ns_status ns_geom_uncertainty(ns_ctx *ctx, int32_t run, int32_t R, double beta,
+                                         uint64_t seed, uint32_t run_id, double *logz,
+                                         double *logw_mean, int64_t cap, double *ess,
+                                         int64_t *n_deaths, double *device_ms)
+{
+    if (!run_ok(ctx, run) || !logz) return NS_EINVAL;
+    if (cap < 0) return fail(ctx, NS_EINVAL, "cap < 0");
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (device_ms) {
         CK(hipEventCreate(&e0));
         CK(hipEventCreate(&e1));
-        CK(hipEventRecord(e0, ctx->stream));
     }
-    hipError_t e = launch_geom(G, ctx->stream);
-    if (e != hipSuccess) return device_error(ctx, "geometric-uncertainty launch", e);
+    GeomLaunch G;
+    ns_status st;
+    if (device_ms) CK(hipEventRecord(e0, ctx->stream));
+    if ((st = enqueue_geom(ctx, run, R, beta, seed, run_id, 0, G, nullptr)) != NS_OK) {
+        if (e0) { (void)hipEventDestroy(e0); (void)hipEventDestroy(e1); }
+        return st;
+    }
     if (device_ms) CK(hipEventRecord(e1, ctx->stream));
+    if (n_deaths) *n_deaths = G.N;
     CK(hipMemcpyAsync(logz, G.logz, (size_t)R * 8, hipMemcpyDeviceToHost, ctx->stream));
-    const long long nc = cap < N ? (long long)cap : N;
+    const long long nc = cap < G.N ? (long long)cap : G.N;
     if (logw_mean && nc > 0)
         CK(hipMemcpyAsync(logw_mean, G.logw_mean, (size_t)nc * 8, hipMemcpyDeviceToHost,
                           ctx->stream));
@@ -1232,6 +1250,34 @@ extern "C" ns_status ns_geom_uncertainty(ns_ctx *ctx, int32_t run, int32_t R, do
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
     }
+    return NS_OK;
+}
+
+extern "C" ns_status ns_posterior_samples(ns_ctx *ctx, int32_t run, int32_t R, double beta,
+                                          uint64_t seed, uint32_t run_id, int32_t n, double *x,
+                                          int64_t *idx)
+{
+    if (!run_ok(ctx, run) || !x || n < 1) return NS_EINVAL;
+    const RunHost &rh = ctx->runs[run];
+    if (!rh.R.deadx)
+        return fail(ctx, NS_ESTATE, "the dead points' coordinates were not recorded "
+                                    "(NS_FLAG_RECORD_POINTS)");
+    auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+    const long long nd_cap = rh.R.dead_cap + (rh.m - rh.k);   // bound on N for the scratch
+    const size_t extra = up((size_t)nd_cap * 8) + up((size_t)n * rh.d * 8) + up((size_t)n * 8);
+    GeomLaunch G;
+    char *xb = nullptr;
+    ns_status st;
+    if ((st = enqueue_geom(ctx, run, R, beta, seed, run_id, extra, G, &xb)) != NS_OK) return st;
+    double *cum = (double *)xb;
+    double *xo = (double *)(xb + up((size_t)nd_cap * 8));
+    long long *io = (long long *)(xb + up((size_t)nd_cap * 8) + up((size_t)n * rh.d * 8));
+    hipError_t e = launch_post_samples(G, rh.R.deadx, rh.R.X, rh.m_pad, rh.d, n, cum, xo, io,
+                                       ctx->stream);
+    if (e != hipSuccess) return device_error(ctx, "posterior-sample launch", e);
+    CK(hipMemcpyAsync(x, xo, (size_t)n * rh.d * 8, hipMemcpyDeviceToHost, ctx->stream));
+    if (idx) CK(hipMemcpyAsync(idx, io, (size_t)n * 8, hipMemcpyDeviceToHost, ctx->stream));
+    CK(hipStreamSynchronize(ctx->stream));
     return NS_OK;
 }
 

@@ -68,6 +68,7 @@ struct DevRun {
     double *Lpk;           // packed lower factor, D(D+1)/2
     int *parents;          // [k]
     double *dead;          // dead logL record
+    double *deadx;         // NS_FLAG_RECORD_POINTS: dead coordinates [dead_cap][d], or null
     long long dead_cap;
     int *trace;            // [k][p][4] or null
     unsigned long long *prof;  // per-phase cycle counters of the HRSS kernel (timing builds)
@@ -140,5 +141,11 @@ struct GeomLaunch {
 size_t geom_workspace_bytes(long long N, int R, int groups);
 int geom_groups(long long N, int R);
 hipError_t launch_geom(const GeomLaunch &G, hipStream_t s);
+// Posterior samples from the geometric-mean weights left in G.logw_mean: systematic resampling
+// of n deaths (one uniform, purpose 7), coordinates from deadx (point-major, stride d) or the
+// survivors' columns of X.  cum: [N] scratch; xo: [n][d]; io: [n] death indices.
+hipError_t launch_post_samples(const GeomLaunch &G, const double *deadx, const double *X,
+                               int m_pad, int d, int n, double *cum, double *xo, long long *io,
+                               hipStream_t s);
 
 }  // namespace nss

@@ -745,6 +745,14 @@ __global__ __launch_bounds__(1024) void k_select(Launch Lc, int op)
     const long long nd0 = (long long)R.ctr[9];
     for (int t = tid; t < k; t += blockDim.x)
         if (nd0 + t < R.dead_cap) R.dead[nd0 + t] = val_of(key[t]);
+    if (R.deadx) {   // NS_FLAG_RECORD_POINTS: the dead points' coordinates, point-major [n][d]
+        const int d = Lc.P[Lc.map[blockIdx.x].x].d;
+        for (long long e = tid; e < (long long)k * d; e += blockDim.x) {
+            const int t = (int)(e / d), a = (int)(e - (long long)t * d);
+            if (nd0 + t < R.dead_cap)
+                R.deadx[(nd0 + t) * d + a] = R.X[(size_t)a * R.m_pad + idx[t]];
+        }
+    }
     __syncthreads();
     if (tid == 0) {
         const int t0 = *st0;

@@ -311,6 +311,84 @@ __global__ __launch_bounds__(256) void k_geom_final(GeomArgs a)
     }
 }
 
+// ------------------------------------------------------------------------------------------
+// weighted posterior samples (resampling with the geometric-mean weights)
+// ------------------------------------------------------------------------------------------
+constexpr uint32_t PUR_POST = 7;
+
+// One workgroup: cum[i] = sum_{l <= i} w_l / sum w with w = exp(logw_mean - max), in index
+// order (chunked block scans with a running carry).
+__global__ __launch_bounds__(1024) void k_post_cum(const double *lw, long long N, double *cum)
+{
+    __shared__ double red[16];
+    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+    double mx = -INFINITY;
+    for (long long i = tid; i < N; i += 1024) mx = fmax(mx, lw[i]);
+    mx = wave_max(mx);
+    if (l == 0) red[w] = mx;
+    __syncthreads();
+    mx = -INFINITY;
+    for (int i = 0; i < 16; ++i) mx = fmax(mx, red[i]);
+    __syncthreads();
+    double carry = 0.0;
+    for (long long c0 = 0; c0 < N; c0 += 1024) {
+        const long long i = c0 + tid;
+        const double e = (i < N && lw[i] > -INFINITY) ? exp(lw[i] - mx) : 0.0;
+        double inc = e;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const double t = __shfl_up(inc, o, 64);
+            if (l >= o) inc += t;
+        }
+        if (l == 63) red[w] = inc;
+        __syncthreads();
+        double pre = carry, all = carry;
+        for (int q = 0; q < 16; ++q) {
+            if (q < w) pre += red[q];
+            all += red[q];
+        }
+        if (i < N) cum[i] = pre + inc;
+        carry = all;
+        __syncthreads();
+    }
+    for (long long i = tid; i < N; i += 1024) cum[i] /= carry;
+}
+
+// Sample j: the first death whose cumulative weight reaches (u + j) / n; its coordinates.
+__global__ __launch_bounds__(256) void k_post_pick(const double *cum, long long N, long long n_dead,
+                                                   const double *deadx, const double *X,
+                                                   const int *perm, int k, int m_pad, int d,
+                                                   int n, uint32_t key0, uint32_t key1,
+                                                   double *xo, long long *io)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    double u, unused;
+    draw2(key0, key1, PUR_POST, 0u, 0u, 0u, 0u, u, unused);
+    const double pos = (u + j) / n;
+    long long lo = 0, hi = N - 1;
+    while (lo < hi) {
+        const long long mid = (lo + hi) >> 1;
+        if (cum[mid] >= pos) hi = mid; else lo = mid + 1;
+    }
+    io[j] = lo;
+    for (int a = 0; a < d; ++a)
+        xo[(size_t)j * d + a] = lo < n_dead ? deadx[lo * d + a]
+                                            : X[(size_t)a * m_pad + perm[k + (int)(lo - n_dead)]];
+}
+
+hipError_t launch_post_samples(const GeomLaunch &G, const double *deadx, const double *X,
+                               int m_pad, int d, int n, double *cum, double *xo, long long *io,
+                               hipStream_t s)
+{
+    hipLaunchKernelGGL(k_post_cum, dim3(1), dim3(1024), 0, s, G.logw_mean, G.N, cum);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_post_pick, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, cum, G.N,
+                       G.n_dead, deadx, X, G.perm, G.k, m_pad, d, n, G.key0, G.key1, xo, io);
+    return hipGetLastError();
+}
+
 size_t geom_workspace_bytes(long long N, int R, int groups)
 {
     const long long nchunk = (N + kGeomC - 1) / kGeomC;

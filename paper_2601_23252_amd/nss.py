@@ -27,6 +27,7 @@ OUTERS = {"ns": NS_OUTER_NESTED, "smc": NS_OUTER_SMC}
 REPLACEMENTS = {"hrss": NS_REPLACE_HRSS, "rw": NS_REPLACE_RW}
 NS_FP64, NS_MIXED_BF16, NS_MIXED_FP16, NS_MIXED_BF16X3, NS_MIXED_FP16X3, NS_MIXED_FP32 = 0, 1, 2, 3, 4, 5
 NS_FLAG_TRACE, NS_FLAG_TIMING, NS_FLAG_INLINE_DIRECTIONS, NS_FLAG_GRAPH = 1, 2, 4, 8
+NS_FLAG_RECORD_POINTS = 16
 PRECISIONS = {"fp64": NS_FP64, "bf16": NS_MIXED_BF16, "fp16": NS_MIXED_FP16,
               "bf16x3": NS_MIXED_BF16X3, "fp16x3": NS_MIXED_FP16X3, "fp32": NS_MIXED_FP32}
 # guard band of each mixed mode: (rel, abs) as set by the library
@@ -140,6 +141,9 @@ def load(build_if_missing: bool = True):
     L.ns_stats_run.argtypes = [vp, C.c_int32, C.POINTER(ns_stats_t)]
     L.ns_get_state_run.restype = C.c_int
     L.ns_get_state_run.argtypes = [vp, C.c_int32, C.POINTER(ns_state_view)]
+    L.ns_posterior_samples.restype = C.c_int
+    L.ns_posterior_samples.argtypes = [vp, C.c_int32, C.c_int32, C.c_double, C.c_uint64,
+                                       C.c_uint32, C.c_int32, _d, C.POINTER(C.c_int64)]
     L.ns_geom_uncertainty.restype = C.c_int
     L.ns_geom_uncertainty.argtypes = [vp, C.c_int32, C.c_int32, C.c_double, C.c_uint64,
                                       C.c_uint32, _d, _d, C.c_int64, _d, C.POINTER(C.c_int64),
@@ -290,7 +294,7 @@ def current_stream():
 def make_config(m, k, p, width=0.0, seed=0, run_id=0, precision="fp64", term_frac=1e-3,
                 stepout_cap=10, shrink_cap=100, max_iter=100000, trace=False, timing=False,
                 inline_directions=False, graph=False, replacement="hrss", outer="ns",
-                ess_frac=0.5) -> ns_config:
+                ess_frac=0.5, record_points=False) -> ns_config:
     cfg = ns_config_default()
     cfg.n_live, cfg.k, cfg.chain_len = int(m), int(k), int(p)
     cfg.width = float(width)
@@ -301,7 +305,8 @@ def make_config(m, k, p, width=0.0, seed=0, run_id=0, precision="fp64", term_fra
     cfg.max_iter = int(max_iter)
     cfg.flags = ((NS_FLAG_TRACE if trace else 0) | (NS_FLAG_TIMING if timing else 0)
                  | (NS_FLAG_INLINE_DIRECTIONS if inline_directions else 0)
-                 | (NS_FLAG_GRAPH if graph else 0))
+                 | (NS_FLAG_GRAPH if graph else 0)
+                 | (NS_FLAG_RECORD_POINTS if record_points else 0))
     cfg.replacement = REPLACEMENTS[replacement] if isinstance(replacement, str) else int(replacement)
     cfg.outer = OUTERS[outer] if isinstance(outer, str) else int(outer)
     cfg.ess_frac = float(ess_frac)
@@ -336,6 +341,15 @@ def ns_geom_uncertainty(ctx, run, R, beta, seed, run_id, n_deaths=None, timing=F
     return st, logz[:int(R)], lw, ess.value, n.value, (ms.value if timing else None)
 
 
+def ns_posterior_samples(ctx, run, R, beta, seed, run_id, n, d):
+    """Returns (status, x[n, d], idx[n])."""
+    x = np.zeros((max(int(n), 1), int(d)))
+    idx = np.zeros(max(int(n), 1), np.int64)
+    st = load().ns_posterior_samples(ctx, int(run), int(R), float(beta), int(seed), int(run_id),
+                                     int(n), _ptr(x), idx.ctypes.data_as(C.POINTER(C.c_int64)))
+    return st, x[:int(n)], idx[:int(n)]
+
+
 def _geom(ctx, run, cfg, R, beta, seed, run_id, weights, timing):
     seed = cfg.seed if seed is None else seed
     run_id = cfg.run_id if run_id is None else run_id
@@ -358,7 +372,8 @@ class NSRun:
     def __init__(self, prob: dict, m=None, k=None, p=None, width=0.0, seed=0, run_id=0,
                  precision="fp64", term_frac=1e-3, stepout_cap=10, shrink_cap=100,
                  max_iter=100000, trace=False, timing=False, inline_directions=False,
-                 graph=False, stream="torch", replacement="hrss", outer="ns", ess_frac=0.5):
+                 graph=False, stream="torch", replacement="hrss", outer="ns", ess_frac=0.5,
+                 record_points=False):
         self.prob = prob
         self.d = int(prob["d"])
         self.m = int(m or prob["m"])
@@ -369,7 +384,7 @@ class NSRun:
         pr, en, self._keep = make_structs(prob)
         cfg = make_config(self.m, self.k, self.p, width, seed, run_id, precision, term_frac,
                           stepout_cap, shrink_cap, max_iter, trace, timing, inline_directions,
-                          graph, replacement, outer, ess_frac)
+                          graph, replacement, outer, ess_frac, record_points)
         self.cfg = cfg
         s = current_stream() if stream == "torch" else stream
         st, self.ctx = ns_init(pr, en, cfg, s)
@@ -427,6 +442,14 @@ class NSRun:
         """Post-hoc geometric uncertainty (ns_geom_uncertainty): dict(logz[R], logw_mean[N],
         ess[, device_ms]); the shrinkage stream defaults to the run's (seed, run_id)."""
         return _geom(self.ctx, 0, self.cfg, R, beta, seed, run_id, weights, timing)
+
+    def posterior_samples(self, n, R=100, beta=1.0, seed=None, run_id=None):
+        """ns_posterior_samples (needs record_points=True): (x[n, d], death indices[n])."""
+        seed = self.cfg.seed if seed is None else seed
+        run_id = self.cfg.run_id if run_id is None else run_id
+        st, x, idx = ns_posterior_samples(self.ctx, 0, R, beta, seed, run_id, n, self.d)
+        _check(st, self.ctx)
+        return x, idx
 
     def trace(self) -> np.ndarray:
         out = np.zeros((self.k, self.p, 4), np.int32)

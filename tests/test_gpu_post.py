@@ -113,3 +113,41 @@ def test_geom_batch_run_and_truncated_record(N, oracle_lib):
     st = N.ns_geom_uncertainty(run.ctx, 0, 4, 1.0, 0, 0)[0]
     assert st == N.NS_ESTATE
     run.close()
+
+
+def test_posterior_samples_match_oracle(N, oracle_lib):
+    """Config 1 run to termination with the dead coordinates recorded: the GPU's posterior
+    samples are the oracle's (same deaths, coordinates within FP64 rounding); the recorded
+    coordinates reproduce the dead record's logL."""
+    from paper_2601_23252_amd import problems as G
+    prob = G.config1()
+    run = N.NSRun(prob, seed=11, record_points=True)
+    run.run()
+    s = run.state()
+    dead = run.dead()
+    x, idx = run.posterior_samples(3000, R=50, beta=1.0, seed=4, run_id=1)
+    k = run.k
+    fin = s["perm"][k:]
+    n_dead = len(dead)
+    assert np.all((idx >= 0) & (idx < n_dead + len(fin)))
+    # the dead rows among the samples reproduce their recorded logL
+    dmask = idx < n_dead
+    L = oracle_lib.Problem(prob).loglik(x[dmask])
+    assert np.allclose(L, dead[idx[dmask]], rtol=1e-12, atol=1e-12)
+    # the oracle, fed the GPU's deaths and coordinates, draws the same samples
+    dead_x = np.zeros((n_dead, prob["d"]))
+    dead_x[idx[dmask]] = x[dmask]
+    ox, oidx = oracle_lib.posterior_samples(dead, dead_x, s["logL"][fin], s["x"][fin], run.m, k,
+                                            50, 3000, 1.0, seed=4, run_id=1)
+    assert np.array_equal(idx, oidx)
+    assert np.allclose(x, ox, rtol=0, atol=0)
+    run.close()
+
+
+def test_posterior_samples_need_recorded_points(N):
+    from paper_2601_23252_amd import problems as G
+    run = N.NSRun(G.config1(), seed=1)
+    run.step()
+    st, _, _ = N.ns_posterior_samples(run.ctx, 0, 10, 1.0, 0, 0, 100, 5)
+    assert st == N.NS_ESTATE
+    run.close()
