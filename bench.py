@@ -25,8 +25,8 @@ sys.path.insert(0, ROOT)
 # HBM bytes per k_hrss launch (BF16x3) from the FETCH_SIZE / WRITE_SIZE counter passes, each
 # scaled by the same counter on a copy of known size (FETCH x 2, WRITE x 1), recorded for the
 # kernel source with this sha256 prefix; reported as null once the source differs.
-TRAFFIC = {"bf16x3": 748.3e6}
-TRAFFIC_SOURCE_SHA = "8e1d57660b83f62e"
+TRAFFIC = {"bf16x3": 748.4e6}
+TRAFFIC_SOURCE_SHA = "dcc5b843009ec19e"
 
 
 def kernel_traffic(precision):
@@ -213,7 +213,7 @@ def bench_batch(args):
 # for the kernel source with this sha256 prefix; the peak is one lane-instruction per lane per
 # cycle: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
 GEOM_VALU_PER_UNIT = 455.2
-GEOM_SOURCE_SHA = "73c14d3bbef4cd9c"
+GEOM_SOURCE_SHA = "df64d5a03b0920b6"
 VALU_PEAK = 256 * 4 * 16 * 2.4e9
 
 
@@ -319,7 +319,7 @@ def lnz_rastrigin_gauss(d, alpha, r=5.14, amp=10.0):
 # (SQ_INSTS_VALU x 64 / evaluations of the profiled launches), for the kernel source with this
 # sha256 prefix.
 RG_VALU_PER_EVAL = 54596.0
-RG_SOURCE_SHA = "8e1d57660b83f62e"
+RG_SOURCE_SHA = "dcc5b843009ec19e"
 
 
 def bench_rastrigin(args):
