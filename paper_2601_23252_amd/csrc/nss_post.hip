@@ -317,13 +317,24 @@ __global__ __launch_bounds__(256) void k_geom_final(GeomArgs a)
 constexpr uint32_t PUR_POST = 7;
 
 // One workgroup: cum[i] = sum_{l <= i} w_l / sum w with w = exp(logw_mean - max), in index
-// order (chunked block scans with a running carry).
+// order: chunks of 8192 deaths, eight consecutive per thread, a block scan of the thread sums
+// and a running carry between chunks.
 __global__ __launch_bounds__(1024) void k_post_cum(const double *lw, long long N, double *cum)
 {
+    constexpr int PER = 8;
     __shared__ double red[16];
     const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
     double mx = -INFINITY;
-    for (long long i = tid; i < N; i += 1024) mx = fmax(mx, lw[i]);
+    for (long long c0 = 0; c0 < N; c0 += 1024 * PER) {   // eight loads in flight per thread
+        double v[PER];
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const long long i = c0 + (long long)q * 1024 + tid;
+            v[q] = i < N ? lw[i] : -INFINITY;
+        }
+#pragma unroll
+        for (int q = 0; q < PER; ++q) mx = fmax(mx, v[q]);
+    }
     mx = wave_max(mx);
     if (l == 0) red[w] = mx;
     __syncthreads();
@@ -331,10 +342,16 @@ __global__ __launch_bounds__(1024) void k_post_cum(const double *lw, long long N
     for (int i = 0; i < 16; ++i) mx = fmax(mx, red[i]);
     __syncthreads();
     double carry = 0.0;
-    for (long long c0 = 0; c0 < N; c0 += 1024) {
-        const long long i = c0 + tid;
-        const double e = (i < N && lw[i] > -INFINITY) ? exp(lw[i] - mx) : 0.0;
-        double inc = e;
+    for (long long c0 = 0; c0 < N; c0 += 1024 * PER) {
+        const long long i0 = c0 + (long long)tid * PER;
+        double v[PER], s = 0.0;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const long long i = i0 + q;
+            s += (i < N && lw[i] > -INFINITY) ? exp(lw[i] - mx) : 0.0;
+            v[q] = s;
+        }
+        double inc = s;
 #pragma unroll
         for (int o = 1; o < 64; o <<= 1) {
             const double t = __shfl_up(inc, o, 64);
@@ -347,11 +364,19 @@ __global__ __launch_bounds__(1024) void k_post_cum(const double *lw, long long N
             if (q < w) pre += red[q];
             all += red[q];
         }
-        if (i < N) cum[i] = pre + inc;
+        pre += inc - s;
+#pragma unroll
+        for (int q = 0; q < PER; ++q)
+            if (i0 + q < N) cum[i0 + q] = pre + v[q];
         carry = all;
         __syncthreads();
     }
-    for (long long i = tid; i < N; i += 1024) cum[i] /= carry;
+    for (long long c0 = 0; c0 < N; c0 += 1024 * PER)
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const long long i = c0 + (long long)tid * PER + q;
+            if (i < N) cum[i] /= carry;
+        }
 }
 
 // Sample j: the first death whose cumulative weight reaches (u + j) / n; its coordinates.

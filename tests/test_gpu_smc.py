@@ -118,3 +118,20 @@ def test_smc_rejects_unsupported_combinations(N):
     st = N.ns_geom_uncertainty(R.ctx, 0, 4, 1.0, 0, 0)[0]
     assert st == N.NS_EUNSUPPORTED
     R.close()
+
+
+def test_smc_graph_replay_equals_eager(N):
+    """ns_run with NS_FLAG_GRAPH (batches of 16 steps captured and replayed) reproduces the
+    eager SMC run bit for bit."""
+    from paper_2601_23252_amd import problems as G
+    prob = G.config2(d=12, m=300, k=100)
+    a = N.NSRun(prob, m=300, p=24, seed=9, outer="smc")
+    b = N.NSRun(prob, m=300, p=24, seed=9, outer="smc", graph=True)
+    a.run()
+    b.run()
+    sa, sb = a.state(), b.state()
+    assert sa["done"] == sb["done"] == 1 and sa["iter"] == sb["iter"]
+    assert np.array_equal(sa["x"], sb["x"]) and np.array_equal(sa["logL"], sb["logL"])
+    assert a.logz()[0] == b.logz()[0]
+    a.close()
+    b.close()
