@@ -16,6 +16,7 @@ import argparse
 import json
 import math
 import os
+import statistics
 import sys
 import time
 
@@ -91,7 +92,22 @@ def cpu_baseline(prob, p, seconds_budget=20.0):
     ev = run.state()["evals"] - e0
     return dict(value=ev / dt, unit="evals/s", cores=threads, kind="oracle",
                 sample=f"first {iters} iterations after init of the same workload "
-                       f"(p={p}), {ev} evaluations in {dt:.1f} s, OpenMP over chains")
+                       f"(p={p}), {ev} evaluations in {dt:.1f} s, OpenMP over chains",
+                **host_info())
+
+
+def host_info():
+    """The host's logical CPU count and model (for the oracle timings)."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "cpu_model": model}
 
 
 def profile_run(args):
@@ -168,6 +184,21 @@ def bench_gp(args):
                      "avg_launch_ms": st["hrss_ms"] / max(1, st["hrss_launches"])},
         "lnz": {"logz": z, "sigma": err, "H": H},
     }
+    if not args.no_cpu:
+        # the oracle's GP likelihood (one host thread) on prior draws for the time budget
+        import numpy as np
+        from oracle import oracle as O
+        P = O.Problem(prob)
+        rng = np.random.default_rng(0)
+        ev, t0 = 0, time.perf_counter()
+        while time.perf_counter() - t0 < args.cpu_seconds:
+            P.loglik(rng.uniform(prob["prior_a"], prob["prior_b"], (64, 6)))
+            ev += 64
+        tc = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": ev / tc, "unit": "evals/s", "cores": 1, "kind": "oracle",
+                               "sample": f"{ev} GP likelihood evaluations at prior draws in "
+                                         f"{tc:.1f} s (the chains' evaluations cost the same)",
+                               **host_info()}
     print(json.dumps(out), flush=True)
     R.close()
 
@@ -203,6 +234,30 @@ def bench_batch(args):
                      "kernel": "k_hrss", "flop_per_eval": "d(d+1)+3d (Gaussian), 3d (funnel)",
                      "avg_launch_ms": stats[0]["hrss_ms"] / max(1, stats[0]["hrss_launches"])},
     }
+    if not args.no_cpu:
+        # the oracle on a stratified subset: every 16th run, each for an equal share of the
+        # time budget (init plus whole iterations)
+        from oracle import oracle as O, theory as T
+        threads = min(os.cpu_count() or 1, 16)
+        ev_tot, t_tot, iters = 0, 0.0, 0
+        sub = list(range(0, len(probs), 16))
+        for r in sub:
+            pr = probs[r]
+            run = O.Run(O.Problem(pr), pr["m"], pr["k"], pr["p"], T.width_whitened(pr["d"]), 5,
+                        run_id=r, threads=threads)
+            run.init()
+            e0 = run.state()["evals"]
+            t0 = time.perf_counter()
+            while time.perf_counter() - t0 < args.cpu_seconds / len(sub) and not run.done:
+                run.step()
+                iters += 1
+            t_tot += time.perf_counter() - t0
+            ev_tot += run.state()["evals"] - e0
+        out["cpu_baseline"] = {"value": ev_tot / t_tot, "unit": "evals/s", "cores": threads,
+                               "kind": "oracle",
+                               "sample": f"runs 0, 16, ..., 240 of the batch, {iters} iterations "
+                                         f"after init in total, {ev_tot} evaluations in "
+                                         f"{t_tot:.1f} s, OpenMP over chains", **host_info()}
     print(json.dumps(out), flush=True)
     B.close()
 
@@ -545,10 +600,75 @@ def bench_smc(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_small(args, which):
+    """The two small Gaussian configurations as benchmark lines: config 1 (d = 5, n_live 200,
+    k 50, p = 25, FP64; evals/s only, RNG and control dominate) or config 2 (the d = 32
+    correlated Gaussian under N(0, 4I), n_live 1000, k 500, p = 160) in BF16x3 and FP64, with
+    ln Z against the closed form; --steps seeds each."""
+    import numpy as np
+    from paper_2601_23252_amd import nss as N, problems as G
+    from scipy.stats import multivariate_normal
+    from scipy.special import erf
+    N.load()
+    if which == "gauss5":
+        prob, precs = G.config1(), ["fp64"]
+        truth = -5 * math.log(2.0) + 5 * math.log(erf(1.0 / (0.1 * math.sqrt(2.0))))
+        fpe, workload = 3 * 5 + 2, "gauss5_box1_nlive200_k50_p25"
+    else:
+        prob, precs = G.config2(), ["bf16x3", "fp64"]
+        d = prob["d"]
+        truth = float(multivariate_normal(mean=np.zeros(d), cov=prob["cov"][0] + 4 * np.eye(d))
+                      .logpdf(prob["mu"][0]))
+        fpe, workload = algorithmic_flop_per_eval(1, d), "corr32_cond1e3_prior4_nlive1000_k500_p160"
+    seeds = list(range(args.steps))
+    res = {}
+    for prec in precs:
+        recs, total = run_gpu(N, prob, prec, seeds, prob["p"], args.warmup)
+        evals = sum(r["evals"] for r in recs)
+        hrss_s = sum(r["hrss_ms"] for r in recs) / 1e3
+        res[prec] = dict(recs=recs, total=total, evals=evals, hrss_s=hrss_s,
+                         launches=sum(r["hrss_launches"] for r in recs))
+    main_prec = precs[0]
+    r0 = res[main_prec]
+    mixed = main_prec != "fp64"
+    peak = 2.5e15 if mixed else 78.6e12
+    achieved = r0["evals"] * fpe / r0["hrss_s"] if r0["hrss_s"] > 0 else 0.0
+    rates = [r["evals"] / r["wall_s"] for r in r0["recs"]]
+    out = {
+        "metric": f"slice-step likelihood evals/s ({which})", "value": r0["evals"] / r0["total"],
+        "unit": "evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * r0["total"] / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16" if mixed else "f64",
+        "data": "synthetic",
+        "config": {"workload": workload, "d": prob["d"], "n_live": prob["m"], "k": prob["k"],
+                   "chain_len": prob["p"], "precision": main_prec, "seeds": seeds},
+        "roofline": {"bound": "mfma" if which == "corr32" else "alu", "achieved": achieved / 1e12,
+                     "peak": peak / 1e12, "unit": "TFLOP/s", "frac": achieved / peak,
+                     "traffic": None, "kernel": "k_hrss", "flop_per_eval": fpe,
+                     "avg_launch_ms": 1e3 * r0["hrss_s"] / max(1, r0["launches"])},
+        "per_seed_evals_per_s": {"median": statistics.median(rates),
+                                 "range": [min(rates), max(rates)]},
+        "lnz": {"truth": truth, prec_key(main_prec): [(r["logz"] - truth) / r["err"]
+                                                      for r in r0["recs"]]},
+    }
+    for prec in precs[1:]:
+        r1 = res[prec]
+        out[prec] = {"value": r1["evals"] / r1["total"], "unit": "evals/s",
+                     "z_scores": [(r["logz"] - truth) / r["err"] for r in r1["recs"]],
+                     "frac_of_fp64_peak": r1["evals"] * fpe / max(r1["hrss_s"], 1e-12) / 78.6e12}
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(prob, prob["p"], args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+def prec_key(p):
+    return f"z_scores_{p}"
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3, help="timed full runs (seeds 0..K-1)")
+    ap.add_argument("--steps", type=int, default=5, help="timed full runs (seeds 0..K-1)")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", default="bf16x3",
                     choices=["bf16", "fp16", "bf16x3", "fp16x3", "fp64"])
@@ -560,14 +680,15 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--workload", default="mixture8_d64",
                     choices=["mixture8_d64", "gp_n256", "batch256", "geom", "rastrigin",
-                             "rw", "smc"],
+                             "rw", "smc", "gauss5", "corr32"],
                     help="mixture8_d64: the benchmark above; gp_n256: GP hyperparameter "
                          "marginalisation (n=256, n_live=1000, k=500, p=30), FP64; batch256: "
                          "256 independent runs of uneven d in one context; geom: post-hoc "
                          "geometric uncertainty of a full mixture run; rastrigin: the "
                          "Gaussian-Rastrigin evidence workload at d = 100; rw: slice against "
                          "random-walk replacement on a condition-100 Gaussian; smc: "
-                         "tempered SMC with the slice mutation against nested sampling")
+                         "tempered SMC with the slice mutation against nested sampling; "
+                         "gauss5 / corr32: the small Gaussian configurations")
     ap.add_argument("--replicas", type=int, default=100, help="geom: shrinkage replicas")
     ap.add_argument("--no-table", action="store_true",
                     help="rastrigin: skip the untimed ln Z table over (d, alpha)")
@@ -600,6 +721,9 @@ def main():
         return
     if args.workload == "smc":
         bench_smc(args)
+        return
+    if args.workload in ("gauss5", "corr32"):
+        bench_small(args, args.workload)
         return
 
     from paper_2601_23252_amd import nss as N, problems as G
@@ -645,7 +769,15 @@ def main():
                      "kernel": "k_hrss", "flop_per_eval": fpe,
                      "avg_launch_ms": 1e3 * hrss_s / max(1, launches)},
         "lnz": {"truth": truth, "z_scores": z_scores, "all_within_3sigma": within,
+                "evals_per_s_of_runs_within_3sigma": (
+                    sum(r["evals"] for r, z in zip(recs, z_scores) if abs(z) < 3.0)
+                    / max(1e-12, sum(r["wall_s"] for r, z in zip(recs, z_scores) if abs(z) < 3.0))),
                 "logz": [r["logz"] for r in recs], "sigma": [r["err"] for r in recs]},
+        "per_seed_evals_per_s": {"values": [r["evals"] / r["wall_s"] for r in recs],
+                                 "median": statistics.median(r["evals"] / r["wall_s"]
+                                                             for r in recs),
+                                 "range": [min(r["evals"] / r["wall_s"] for r in recs),
+                                           max(r["evals"] / r["wall_s"] for r in recs)]},
         "rechecks_per_eval": sum(r["rechecks"] for r in recs) / max(1, evals),
         "band_violations": sum(r["band_violations"] for r in recs),
         "iterations": [r["iters"] for r in recs],
