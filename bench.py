@@ -80,20 +80,26 @@ def cpu_baseline(prob, p, seconds_budget=20.0):
     from oracle import oracle as O, theory as T
     threads = min(os.cpu_count() or 1, 16)
     P = O.Problem(prob)
-    run = O.Run(P, prob["m"], prob["k"], p, T.width_whitened(prob["d"]), 0, threads=threads)
-    run.init()
-    e0 = run.state()["evals"]
-    t0 = time.perf_counter()
-    iters = 0
-    while time.perf_counter() - t0 < seconds_budget and iters < 50:
-        run.step()
-        iters += 1
-    dt = time.perf_counter() - t0
-    ev = run.state()["evals"] - e0
+    iters = ev = runs = 0
+    dt = 0.0
+    seed = 0
+    while dt < seconds_budget:
+        run = O.Run(P, prob["m"], prob["k"], p, T.width_whitened(prob["d"]), seed,
+                    threads=threads)
+        run.init()
+        e0 = run.state()["evals"]
+        t0 = time.perf_counter()
+        while dt + (time.perf_counter() - t0) < seconds_budget and not run.done:
+            run.step()
+            iters += 1
+        dt += time.perf_counter() - t0
+        ev += run.state()["evals"] - e0
+        runs += 1
+        seed += 1
     return dict(value=ev / dt, unit="evals/s", cores=threads, kind="oracle",
-                sample=f"first {iters} iterations after init of the same workload "
-                       f"(p={p}), {ev} evaluations in {dt:.1f} s, OpenMP over chains",
-                **host_info())
+                sample=f"{iters} iterations after init over {runs} run(s) (seeds 0..{runs - 1}) "
+                       f"of the same workload (p={p}), {ev} evaluations in {dt:.1f} s, "
+                       "OpenMP over chains", **host_info())
 
 
 def host_info():
@@ -268,7 +274,7 @@ def bench_batch(args):
 # for the kernel source with this sha256 prefix; the peak is one lane-instruction per lane per
 # cycle: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
 GEOM_VALU_PER_UNIT = 455.2
-GEOM_SOURCE_SHA = "df64d5a03b0920b6"
+GEOM_SOURCE_SHA = "475c7dcca08ac910"
 VALU_PEAK = 256 * 4 * 16 * 2.4e9
 
 
