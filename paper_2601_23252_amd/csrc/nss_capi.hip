@@ -1264,15 +1264,19 @@ extern "C" ns_status ns_posterior_samples(ns_ctx *ctx, int32_t run, int32_t R, d
                                     "(NS_FLAG_RECORD_POINTS)");
     auto up = [](size_t b) { return (b + 255) / 256 * 256; };
     const long long nd_cap = rh.R.dead_cap + (rh.m - rh.k);   // bound on N for the scratch
-    const size_t extra = up((size_t)nd_cap * 8) + up((size_t)n * rh.d * 8) + up((size_t)n * 8);
+    const size_t b_cum = up((size_t)nd_cap * 8), b_x = up((size_t)n * rh.d * 8),
+                 b_i = up((size_t)n * 8), b_ws = up((size_t)(2 + 2 * post_cum_blocks(nd_cap)) * 8);
     GeomLaunch G;
     char *xb = nullptr;
     ns_status st;
-    if ((st = enqueue_geom(ctx, run, R, beta, seed, run_id, extra, G, &xb)) != NS_OK) return st;
+    if ((st = enqueue_geom(ctx, run, R, beta, seed, run_id, b_cum + b_x + b_i + b_ws, G, &xb)) !=
+        NS_OK)
+        return st;
     double *cum = (double *)xb;
-    double *xo = (double *)(xb + up((size_t)nd_cap * 8));
-    long long *io = (long long *)(xb + up((size_t)nd_cap * 8) + up((size_t)n * rh.d * 8));
-    hipError_t e = launch_post_samples(G, rh.R.deadx, rh.R.X, rh.m_pad, rh.d, n, cum, xo, io,
+    double *xo = (double *)(xb + b_cum);
+    long long *io = (long long *)(xb + b_cum + b_x);
+    double *cws = (double *)(xb + b_cum + b_x + b_i);
+    hipError_t e = launch_post_samples(G, rh.R.deadx, rh.R.X, rh.m_pad, rh.d, n, cum, cws, xo, io,
                                        ctx->stream);
     if (e != hipSuccess) return device_error(ctx, "posterior-sample launch", e);
     CK(hipMemcpyAsync(x, xo, (size_t)n * rh.d * 8, hipMemcpyDeviceToHost, ctx->stream));

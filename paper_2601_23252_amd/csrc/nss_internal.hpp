@@ -143,9 +143,11 @@ int geom_groups(long long N, int R);
 hipError_t launch_geom(const GeomLaunch &G, hipStream_t s);
 // Posterior samples from the geometric-mean weights left in G.logw_mean: systematic resampling
 // of n deaths (one uniform, purpose 7), coordinates from deadx (point-major, stride d) or the
-// survivors' columns of X.  cum: [N] scratch; xo: [n][d]; io: [n] death indices.
+// survivors' columns of X.  cum: [N] scratch; cws: [2 + 2 post_cum_blocks(N)] scratch;
+// xo: [n][d]; io: [n] death indices.
+long long post_cum_blocks(long long N);
 hipError_t launch_post_samples(const GeomLaunch &G, const double *deadx, const double *X,
-                               int m_pad, int d, int n, double *cum, double *xo, long long *io,
-                               hipStream_t s);
+                               int m_pad, int d, int n, double *cum, double *cws, double *xo,
+                               long long *io, hipStream_t s);
 
 }  // namespace nss

@@ -316,67 +316,120 @@ __global__ __launch_bounds__(256) void k_geom_final(GeomArgs a)
 // ------------------------------------------------------------------------------------------
 constexpr uint32_t PUR_POST = 7;
 
-// One workgroup: cum[i] = sum_{l <= i} w_l / sum w with w = exp(logw_mean - max), in index
-// order: chunks of 8192 deaths, eight consecutive per thread, a block scan of the thread sums
-// and a running carry between chunks.
-__global__ __launch_bounds__(1024) void k_post_cum(const double *lw, long long N, double *cum)
+// Normalised cumulative weights cum[i] = sum_{l <= i} w_l / sum w, w = exp(logw_mean - max), in
+// index order, over blocks of 8192 deaths (eight consecutive per thread).  The scratch ws holds
+// [0] the maximum, [1] the total, [2, 2 + nb) the block maxima and then the blocks' exclusive
+// offsets, [2 + nb, 2 + 2 nb) the block sums.
+constexpr int kCumT = 1024, kCumPer = 8;
+constexpr long long kCumChunk = (long long)kCumT * kCumPer;
+
+long long post_cum_blocks(long long N) { return (N + kCumChunk - 1) / kCumChunk; }
+
+__global__ __launch_bounds__(kCumT) void k_post_bmax(const double *lw, long long N, double *ws)
 {
-    constexpr int PER = 8;
     __shared__ double red[16];
     const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+    const long long base = (long long)blockIdx.x * kCumChunk;
     double mx = -INFINITY;
-    for (long long c0 = 0; c0 < N; c0 += 1024 * PER) {   // eight loads in flight per thread
-        double v[PER];
 #pragma unroll
-        for (int q = 0; q < PER; ++q) {
-            const long long i = c0 + (long long)q * 1024 + tid;
-            v[q] = i < N ? lw[i] : -INFINITY;
-        }
-#pragma unroll
-        for (int q = 0; q < PER; ++q) mx = fmax(mx, v[q]);
+    for (int q = 0; q < kCumPer; ++q) {
+        const long long i = base + (long long)q * kCumT + tid;
+        if (i < N) mx = fmax(mx, lw[i]);
     }
     mx = wave_max(mx);
     if (l == 0) red[w] = mx;
     __syncthreads();
-    mx = -INFINITY;
-    for (int i = 0; i < 16; ++i) mx = fmax(mx, red[i]);
-    __syncthreads();
-    double carry = 0.0;
-    for (long long c0 = 0; c0 < N; c0 += 1024 * PER) {
-        const long long i0 = c0 + (long long)tid * PER;
-        double v[PER], s = 0.0;
-#pragma unroll
-        for (int q = 0; q < PER; ++q) {
-            const long long i = i0 + q;
-            s += (i < N && lw[i] > -INFINITY) ? exp(lw[i] - mx) : 0.0;
-            v[q] = s;
-        }
-        double inc = s;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const double t = __shfl_up(inc, o, 64);
-            if (l >= o) inc += t;
-        }
-        if (l == 63) red[w] = inc;
-        __syncthreads();
-        double pre = carry, all = carry;
-        for (int q = 0; q < 16; ++q) {
-            if (q < w) pre += red[q];
-            all += red[q];
-        }
-        pre += inc - s;
-#pragma unroll
-        for (int q = 0; q < PER; ++q)
-            if (i0 + q < N) cum[i0 + q] = pre + v[q];
-        carry = all;
-        __syncthreads();
+    if (tid == 0) {
+        double m = red[0];
+        for (int i = 1; i < 16; ++i) m = fmax(m, red[i]);
+        ws[2 + blockIdx.x] = m;
     }
-    for (long long c0 = 0; c0 < N; c0 += 1024 * PER)
+}
+
+// One workgroup: the maximum of the nb block maxima into ws[0].
+__global__ __launch_bounds__(kCumT) void k_post_gmax(double *ws, int nb)
+{
+    __shared__ double red[16];
+    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+    double mx = -INFINITY;
+    for (int b = tid; b < nb; b += kCumT) mx = fmax(mx, ws[2 + b]);
+    mx = wave_max(mx);
+    if (l == 0) red[w] = mx;
+    __syncthreads();
+    if (tid == 0) {
+        double m = red[0];
+        for (int i = 1; i < 16; ++i) m = fmax(m, red[i]);
+        ws[0] = m;
+    }
+}
+
+// exp(lw - M) over this workgroup's block: thread t takes deaths i0 .. i0 + 7 (i0 = base + 8 t),
+// v[q] its running sums, pre the sum of the block's earlier deaths; returns the block's total.
+// The block sums and the final pass both use this, so their totals agree bit for bit.
+__device__ __forceinline__ double block_cum(const double *lw, long long N, double M, long long i0,
+                                            double (&v)[kCumPer], double &pre, double *red)
+{
+    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+    double s = 0.0;
 #pragma unroll
-        for (int q = 0; q < PER; ++q) {
-            const long long i = c0 + (long long)tid * PER + q;
-            if (i < N) cum[i] /= carry;
-        }
+    for (int q = 0; q < kCumPer; ++q) {
+        const long long i = i0 + q;
+        const double x = i < N ? lw[i] : -INFINITY;
+        s += x > -INFINITY ? exp(x - M) : 0.0;
+        v[q] = s;
+    }
+    double inc = s;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const double t = __shfl_up(inc, o, 64);
+        if (l >= o) inc += t;
+    }
+    if (l == 63) red[w] = inc;
+    __syncthreads();
+    double p = 0.0, all = 0.0;
+    for (int q = 0; q < 16; ++q) {
+        if (q < w) p += red[q];
+        all += red[q];
+    }
+    pre = p + (inc - s);
+    return all;
+}
+
+__global__ __launch_bounds__(kCumT) void k_post_bsum(const double *lw, long long N, double *ws,
+                                                     int nb)
+{
+    __shared__ double red[16];
+    const long long i0 = (long long)blockIdx.x * kCumChunk + (long long)threadIdx.x * kCumPer;
+    double v[kCumPer], pre;
+    const double all = block_cum(lw, N, ws[0], i0, v, pre, red);
+    if (threadIdx.x == 0) ws[2 + nb + blockIdx.x] = all;
+}
+
+// One thread, in block order: the exclusive offsets (over the block maxima, no longer needed)
+// and the total, so that each offset plus its block's sum is exactly the next offset.
+__global__ void k_post_offsets(double *ws, int nb)
+{
+    if (threadIdx.x != 0) return;
+    double acc = 0.0;
+    for (int b = 0; b < nb; ++b) {
+        const double sb = ws[2 + nb + b];
+        ws[2 + b] = acc;
+        acc += sb;
+    }
+    ws[1] = acc;
+}
+
+__global__ __launch_bounds__(kCumT) void k_post_cum(const double *lw, long long N,
+                                                    const double *ws, double *cum)
+{
+    __shared__ double red[16];
+    const long long i0 = (long long)blockIdx.x * kCumChunk + (long long)threadIdx.x * kCumPer;
+    double v[kCumPer], pre;
+    (void)block_cum(lw, N, ws[0], i0, v, pre, red);
+    const double off = ws[2 + blockIdx.x] + pre, tot = ws[1];
+#pragma unroll
+    for (int q = 0; q < kCumPer; ++q)
+        if (i0 + q < N) cum[i0 + q] = (off + v[q]) / tot;
 }
 
 // Sample j: the first death whose cumulative weight reaches (u + j) / n; its coordinates.
@@ -403,12 +456,24 @@ __global__ __launch_bounds__(256) void k_post_pick(const double *cum, long long 
 }
 
 hipError_t launch_post_samples(const GeomLaunch &G, const double *deadx, const double *X,
-                               int m_pad, int d, int n, double *cum, double *xo, long long *io,
-                               hipStream_t s)
+                               int m_pad, int d, int n, double *cum, double *cws, double *xo,
+                               long long *io, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_post_cum, dim3(1), dim3(1024), 0, s, G.logw_mean, G.N, cum);
+    const long long nbl = post_cum_blocks(G.N);
+    const int nb = (int)nbl;
+    hipLaunchKernelGGL(k_post_bmax, dim3((unsigned)nb), dim3(kCumT), 0, s, G.logw_mean, G.N, cws);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_post_gmax, dim3(1), dim3(kCumT), 0, s, cws, nb);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_post_bsum, dim3((unsigned)nb), dim3(kCumT), 0, s, G.logw_mean, G.N, cws,
+                       nb);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_post_offsets, dim3(1), dim3(64), 0, s, cws, nb);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_post_cum, dim3((unsigned)nb), dim3(kCumT), 0, s, G.logw_mean, G.N, cws,
+                       cum);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(k_post_pick, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, cum, G.N,
                        G.n_dead, deadx, X, G.perm, G.k, m_pad, d, n, G.key0, G.key1, xo, io);
     return hipGetLastError();

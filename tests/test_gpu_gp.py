@@ -124,24 +124,31 @@ def test_gp_ragged_tiles_parity(N, O):
 
 
 def test_gp_config4_full_size_sampled_chains(N, O):
-    """n = 256, n_live = 1000, k = 500: after one GPU iteration, three chains recomputed by
-    the oracle from the same starting state give the same decisions, points and logL."""
+    """n = 256, n_live = 1000, k = 500: the first iteration against the oracle's (every new
+    point and logL; three chains' decision traces recomputed from the oracle's own state,
+    whitening and parents)."""
     from oracle import theory as T
     from paper_2601_23252_amd import problems as G
+    from tests import oracle_runs
     prob = G.config4()
     width = T.width_whitened(6)
+    k, p = prob["k"], prob["p"]
     gpu = N.NSRun(prob, width=width, seed=3, trace=True)
     s0 = gpu.state()
     gpu.step()
     s1 = gpu.state()
     tr = gpu.trace()
-    P = O.Problem(prob)
-    k, p = prob["k"], prob["p"]
+    P, _, o0, o1, Ls_o, par_o = oracle_runs.first_iteration(O, prob, prob["m"], k, p, width, 3)
+    assert np.array_equal(s0["perm"], o0["perm"])
+    assert np.array_equal(s1["parents"], par_o)
+    assert np.allclose(s1["Lsig"], Ls_o, rtol=1e-9, atol=1e-12)
+    assert np.allclose(s1["x"], o1["x"], rtol=1e-9, atol=1e-12)
+    assert np.allclose(s1["logL"], o1["logL"], rtol=1e-9, atol=1e-12)
     for j in (0, 211, k - 1):
-        parent = s1["parents"][j]
-        x, logL, _, trace = P.hrss_chain(s0["x"][parent], s0["logL"][parent], s0["Lstar"],
-                                         s1["Lsig"], width, p, 3, 0, 1, j, trace=True)
-        slot = s0["perm"][j]
+        parent = par_o[j]
+        x, logL, _, trace = P.hrss_chain(o0["x"][parent], o0["logL"][parent], o0["Lstar"],
+                                         Ls_o, width, p, 3, 0, 1, j, trace=True)
+        slot = o0["perm"][j]
         assert np.array_equal(tr[j], trace), f"chain {j}: decisions"
         assert np.allclose(s1["x"][slot], x, rtol=1e-9, atol=1e-12), f"chain {j}"
         assert abs(s1["logL"][slot] - logL) <= 1e-9 * abs(logL), f"chain {j}"

@@ -15,7 +15,7 @@ import math
 import numpy as np
 import pytest
 
-from tests import truth
+from tests import oracle_runs, truth
 
 pytestmark = pytest.mark.gpu
 
@@ -156,7 +156,8 @@ def test_parity_config1_end_to_end(N, O):
 
 
 def test_parity_traces_config1(N, O):
-    """Per-chain, per-step decision sequence of one iteration against the oracle's chain."""
+    """Per-chain, per-step decision sequence of one iteration against the oracle's chains run
+    from the oracle's own state, threshold, whitening and parents."""
     prob = _problems()["config1"]
     width = _width(5)
     gpu = N.NSRun(prob, width=width, seed=5, trace=True)
@@ -164,15 +165,19 @@ def test_parity_traces_config1(N, O):
     gpu.step()
     st = gpu.state()
     tr = gpu.trace()
-    P = O.Problem(prob)
+    P, _, o0, o1, Ls_o, par_o = oracle_runs.first_iteration(O, prob, prob["m"], prob["k"],
+                                                            prob["p"], width, 5)
+    _cmp_state(pre, o0, prob["k"], "init")
+    assert np.array_equal(st["parents"], par_o)
     for j in range(prob["k"]):
-        par = st["parents"][j]
-        x, lx, ctr, otr = P.hrss_chain(pre["x"][par], pre["logL"][par], pre["Lstar"], st["Lsig"],
+        par = par_o[j]
+        x, lx, ctr, otr = P.hrss_chain(o0["x"][par], o0["logL"][par], o0["Lstar"], Ls_o,
                                        width, prob["p"], 5, 0, 1, j, trace=True)
         assert np.array_equal(tr[j], otr), f"chain {j}"
-        slot = pre["perm"][j]
+        slot = o0["perm"][j]
         assert np.allclose(st["x"][slot], x, rtol=1e-10, atol=1e-12)
         assert math.isclose(st["logL"][slot], lx, rel_tol=1e-10, abs_tol=1e-10)
+    _cmp_state(st, o1, prob["k"], "iteration 1")
 
 
 def test_parity_gaussian_prior_config2_small(N, O):
@@ -227,38 +232,57 @@ def test_set_state_roundtrip_and_step(N, O):
 # ------------------------------------------------------------------------------------------
 # full-size d=64 mixture (the benchmark workload): sampled chains against the oracle
 # ------------------------------------------------------------------------------------------
+_CONFIG3_ORACLE = {}
+
+
+def _config3_oracle(O, width):
+    """The oracle's first iteration of the full-size mixture (seed 11), shared by the
+    precisions."""
+    if "it1" not in _CONFIG3_ORACLE:
+        prob = _problems()["config3"]
+        _CONFIG3_ORACLE["it1"] = oracle_runs.first_iteration(O, prob, prob["m"], prob["k"],
+                                                             prob["p"], width, 11)
+    return _CONFIG3_ORACLE["it1"]
+
+
 @pytest.mark.parametrize("prec", ["fp64", "bf16", "fp16", "bf16x3", "fp16x3"])
 def test_config3_full_size_sampled_chains(N, O, prec):
+    """The benchmark workload at full size: the first iteration against the oracle's (all
+    chains' new points; sampled chains' decision traces recomputed from the oracle's state)."""
     prob = _problems()["config3"]
     width = _width(64)
     gpu = N.NSRun(prob, width=width, seed=11, precision=prec, trace=True)
     pre = gpu.state()
-    # whitening of the first iteration against a direct covariance of the survivors
     gpu.step()
     st = gpu.state()
-    surv = pre["x"][pre["perm"][prob["k"]:]]
+    P, _, o0, o1, Ls_o, par_o = _config3_oracle(O, width)
+    assert np.array_equal(pre["perm"], o0["perm"])
+    assert np.allclose(pre["x"], o0["x"], rtol=1e-12, atol=1e-14)
+    assert np.array_equal(st["parents"], par_o)
+    # whitening of the first iteration against the oracle's and a direct covariance of the
+    # oracle's survivors
+    assert np.allclose(st["Lsig"], Ls_o, rtol=1e-9, atol=1e-12)
+    surv = o0["x"][o0["perm"][prob["k"]:]]
     C = np.cov(surv.T, bias=True)
     C += 1e-12 * np.trace(C) / 64 * np.eye(64)
-    assert np.allclose(st["Lsig"] @ st["Lsig"].T, C, rtol=1e-9, atol=1e-12)
+    assert np.allclose(Ls_o @ Ls_o.T, C, rtol=1e-9, atol=1e-12)
     tr = gpu.trace()
-    P = O.Problem(prob)
     sg = gpu.stats()
     assert sg["band_violations"] == 0
-    new_slots = pre["perm"][: prob["k"]]
-    assert np.all(st["logL"][new_slots] > pre["Lstar"])
+    new_slots = o0["perm"][: prob["k"]]
+    assert np.all(st["logL"][new_slots] > o0["Lstar"])
+    # every chain's new point (mixed precision takes every decision as FP64 does)
+    xtol = (1e-10, 1e-12) if prec == "fp64" else (1e-9, 1e-11)
+    assert np.allclose(st["x"], o1["x"], rtol=xtol[0], atol=xtol[1])
+    assert np.allclose(st["logL"], o1["logL"], rtol=1e-10, atol=1e-10)
     for j in (0, 1, 2, 255, 256, 511, 777, prob["k"] - 1):
-        par = st["parents"][j]
-        x, lx, ctr, otr = P.hrss_chain(pre["x"][par], pre["logL"][par], pre["Lstar"], st["Lsig"],
+        par = par_o[j]
+        x, lx, ctr, otr = P.hrss_chain(o0["x"][par], o0["logL"][par], o0["Lstar"], Ls_o,
                                        width, prob["p"], 11, 0, 1, j, trace=True)
-        slot = pre["perm"][j]
-        if prec == "fp64":
-            assert np.array_equal(tr[j], otr), f"chain {j}"
-            assert np.allclose(st["x"][slot], x, rtol=1e-10, atol=1e-12)
-            assert math.isclose(st["logL"][slot], lx, rel_tol=1e-10, abs_tol=1e-10)
-        else:
-            # with the guard band every decision equals the FP64 one
-            assert np.array_equal(tr[j], otr), f"chain {j} ({prec})"
-            assert np.allclose(st["x"][slot], x, rtol=1e-9, atol=1e-11)
+        slot = o0["perm"][j]
+        assert np.array_equal(tr[j], otr), f"chain {j} ({prec})"
+        assert np.allclose(st["x"][slot], x, rtol=xtol[0], atol=xtol[1])
+        assert math.isclose(st["logL"][slot], lx, rel_tol=1e-10, abs_tol=1e-10)
     gpu.close()
 
 

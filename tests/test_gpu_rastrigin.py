@@ -14,7 +14,7 @@ import math
 import numpy as np
 import pytest
 
-from tests import truth
+from tests import oracle_runs, truth
 
 pytestmark = pytest.mark.gpu
 
@@ -94,27 +94,38 @@ def test_rastrigin_end_to_end_lnz(N, oracle_lib, d, alpha):
     assert abs(zg - tz) < 3.5 * eg, (zg, tz, eg)
 
 
-def test_rastrigin_full_size_d100_sampled_chains(N, oracle_lib):
-    """d = 100, 1000 live points, k = 500, p = 5 d: after one GPU iteration, chains recomputed
-    by the oracle from the same starting state take the same decisions."""
-    from paper_2601_23252_amd import problems as G
-    prob = G.rastrigin_gauss(100, 0.5)
-    width = _width(100)
-    gpu = N.NSRun(prob, width=width, seed=3, trace=True)
+def _sampled_chains(N, O, prob, seed, chains):
+    """The first iteration at full size against the oracle's: every new point and logL, and
+    the sampled chains' decision traces recomputed from the oracle's own state, whitening and
+    parents."""
+    width = _width(prob["d"])
+    gpu = N.NSRun(prob, width=width, seed=seed, trace=True)
     s0 = gpu.state()
     gpu.step()
     s1 = gpu.state()
     tr = gpu.trace()
-    P = oracle_lib.Problem(prob)
-    for j in (0, 137, prob["k"] - 1):
-        parent = s1["parents"][j]
-        x, logL, _, trace = P.hrss_chain(s0["x"][parent], s0["logL"][parent], s0["Lstar"],
-                                         s1["Lsig"], width, prob["p"], 3, 0, 1, j, trace=True)
-        slot = s0["perm"][j]
+    P, _, o0, o1, Ls_o, par_o = oracle_runs.first_iteration(O, prob, prob["m"], prob["k"],
+                                                            prob["p"], width, seed)
+    assert np.array_equal(s0["perm"], o0["perm"])
+    assert np.array_equal(s1["parents"], par_o)
+    assert np.allclose(s1["x"], o1["x"], rtol=1e-10, atol=1e-12)
+    assert np.allclose(s1["logL"], o1["logL"], rtol=1e-10, atol=1e-10)
+    for j in chains:
+        parent = par_o[j]
+        x, logL, _, trace = P.hrss_chain(o0["x"][parent], o0["logL"][parent], o0["Lstar"],
+                                         Ls_o, width, prob["p"], seed, 0, 1, j, trace=True)
+        slot = o0["perm"][j]
         assert np.array_equal(tr[j], trace), f"chain {j}: decisions"
         assert np.allclose(s1["x"][slot], x, rtol=1e-10, atol=1e-12), f"chain {j}"
         assert math.isclose(s1["logL"][slot], logL, rel_tol=1e-10, abs_tol=1e-10)
     gpu.close()
+
+
+def test_rastrigin_full_size_d100_sampled_chains(N, oracle_lib):
+    """d = 100, 1000 live points, k = 500, p = 25 d."""
+    from paper_2601_23252_amd import problems as G
+    prob = G.rastrigin_gauss(100, 0.5)
+    _sampled_chains(N, oracle_lib, prob, 3, (0, 137, prob["k"] - 1))
 
 
 def test_rastrigin_parity_d150(N, oracle_lib):
@@ -127,24 +138,8 @@ def test_rastrigin_parity_d150(N, oracle_lib):
 
 
 def test_rastrigin_full_size_d300_sampled_chains(N, oracle_lib):
-    """d = 300 (the largest dimension of the paper's comparison), 1000 live points, k = 500:
-    after one GPU iteration with 300 steps per chain, chains recomputed by the oracle from the
-    same starting state take the same decisions."""
+    """d = 300 (the largest dimension of the paper's comparison), 1000 live points, k = 500,
+    300 steps per chain."""
     from paper_2601_23252_amd import problems as G
     prob = G.rastrigin_gauss(300, 0.5, p=300)
-    width = _width(300)
-    gpu = N.NSRun(prob, width=width, seed=5, trace=True)
-    s0 = gpu.state()
-    gpu.step()
-    s1 = gpu.state()
-    tr = gpu.trace()
-    P = oracle_lib.Problem(prob)
-    for j in (0, 250, prob["k"] - 1):
-        parent = s1["parents"][j]
-        x, logL, _, trace = P.hrss_chain(s0["x"][parent], s0["logL"][parent], s0["Lstar"],
-                                         s1["Lsig"], width, prob["p"], 5, 0, 1, j, trace=True)
-        slot = s0["perm"][j]
-        assert np.array_equal(tr[j], trace), f"chain {j}: decisions"
-        assert np.allclose(s1["x"][slot], x, rtol=1e-10, atol=1e-12), f"chain {j}"
-        assert math.isclose(s1["logL"][slot], logL, rel_tol=1e-10, abs_tol=1e-10)
-    gpu.close()
+    _sampled_chains(N, oracle_lib, prob, 5, (0, 250, prob["k"] - 1))

@@ -16,7 +16,7 @@ import math
 import numpy as np
 import pytest
 
-from tests import truth
+from tests import oracle_runs, truth
 
 pytestmark = pytest.mark.gpu
 
@@ -60,7 +60,7 @@ def _parity(N, O, prob, m, k, p, seed, n_iter, precision="fp64"):
 
 def test_rw_traces_match_oracle_chains(N, oracle_lib):
     """One iteration of config 1: every chain's per-step (evaluated, accepted) sequence equals
-    the oracle's chain from the same parent."""
+    the oracle's chain run from the oracle's own state, whitening and parents."""
     from paper_2601_23252_amd import problems as G
     prob = G.config1()
     scale = 2.38 / math.sqrt(5)
@@ -69,13 +69,17 @@ def test_rw_traces_match_oracle_chains(N, oracle_lib):
     gpu.step()
     s1 = gpu.state()
     tr = gpu.trace()
-    P = oracle_lib.Problem(prob)
+    P, _, o0, o1, Ls_o, par_o = oracle_runs.first_iteration(
+        oracle_lib, prob, prob["m"], prob["k"], 40, scale, 2, replacement="rw")
+    assert np.array_equal(s0["perm"], o0["perm"])
+    assert np.array_equal(s1["parents"], par_o)
+    assert np.allclose(s1["x"], o1["x"], rtol=1e-10, atol=1e-12)
     for j in range(prob["k"]):
-        par = s1["parents"][j]
-        x, lx, ctr, otr = P.rw_chain(s0["x"][par], s0["logL"][par], s0["Lstar"], s1["Lsig"],
+        par = par_o[j]
+        x, lx, ctr, otr = P.rw_chain(o0["x"][par], o0["logL"][par], o0["Lstar"], Ls_o,
                                      scale, 40, 2, 0, 1, j, trace=True)
         assert np.array_equal(tr[j], otr), f"chain {j}"
-        slot = s0["perm"][j]
+        slot = o0["perm"][j]
         assert np.allclose(s1["x"][slot], x, rtol=1e-10, atol=1e-12)
     gpu.close()
 
@@ -120,13 +124,18 @@ def test_rw_config3_full_size_sampled_chains(N, oracle_lib, prec):
     s1 = gpu.state()
     tr = gpu.trace()
     assert gpu.stats()["band_violations"] == 0
-    P = oracle_lib.Problem(prob)
+    P, _, o0, o1, Ls_o, par_o = oracle_runs.first_iteration(
+        oracle_lib, prob, prob["m"], prob["k"], 100, scale, 6, replacement="rw")
+    assert np.array_equal(s0["perm"], o0["perm"])
+    assert np.array_equal(s1["parents"], par_o)
+    assert np.allclose(s1["x"], o1["x"], rtol=1e-10, atol=1e-12)
+    assert np.allclose(s1["logL"], o1["logL"], rtol=1e-10, atol=1e-10)
     for j in (0, 313, prob["k"] - 1):
-        par = s1["parents"][j]
-        x, lx, _, otr = P.rw_chain(s0["x"][par], s0["logL"][par], s0["Lstar"], s1["Lsig"],
+        par = par_o[j]
+        x, lx, _, otr = P.rw_chain(o0["x"][par], o0["logL"][par], o0["Lstar"], Ls_o,
                                    scale, 100, 6, 0, 1, j, trace=True)
         assert np.array_equal(tr[j], otr), f"chain {j} ({prec})"
-        slot = s0["perm"][j]
+        slot = o0["perm"][j]
         assert np.allclose(s1["x"][slot], x, rtol=1e-10, atol=1e-12)
         assert math.isclose(s1["logL"][slot], lx, rel_tol=1e-10, abs_tol=1e-10)
     gpu.close()

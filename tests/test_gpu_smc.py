@@ -14,7 +14,7 @@ import math
 import numpy as np
 import pytest
 
-from tests import truth
+from tests import oracle_runs, truth
 
 pytestmark = pytest.mark.gpu
 
@@ -83,22 +83,32 @@ def test_smc_parity_rastrigin_and_funnel(N, oracle_lib):
 
 
 def test_smc_chain_traces_full_size(N, oracle_lib):
-    """config 3 (d = 64 mixture, 2000 particles): after the first step, sampled tempered chains
-    recomputed by the oracle from the gathered particles take the same decisions."""
+    """config 3 (d = 64 mixture, 2000 particles): the first step against the oracle's (beta,
+    parents, every particle), and sampled tempered chains recomputed by the oracle from its own
+    particles, temperature, whitening and parents take the same decisions."""
     from paper_2601_23252_amd import problems as G
     prob = G.config3()
     width = _width(64)
     gpu = N.NSRun(prob, m=2000, p=64, width=width, seed=4, outer="smc", trace=True)
-    s0 = gpu.state()
     gpu.step()
     s1 = gpu.state()
     tr = gpu.trace()
-    beta = s1["Lstar"]
-    assert 0.0 < beta < 1.0
     P = oracle_lib.Problem(prob)
+    orc = oracle_lib.SMC(P, 2000, 64, width, 4, threads=oracle_runs.THREADS)
+    orc.init()
+    o0 = orc.state()
+    orc.step()
+    o1 = orc.state()
+    Ls_o, par_o = orc.aux()
+    beta = o1["Lstar"]
+    assert 0.0 < beta < 1.0
+    assert math.isclose(s1["Lstar"], beta, rel_tol=1e-12, abs_tol=1e-15)
+    assert np.array_equal(s1["parents"], par_o)
+    assert np.allclose(s1["x"], o1["x"], rtol=1e-10, atol=1e-12)
+    assert np.allclose(s1["logL"], o1["logL"], rtol=1e-10, atol=1e-10)
     for j in (0, 777, 1999):
-        par = s1["parents"][j]
-        x, lx, _, otr = P.hrss_chain_tempered(s0["x"][par], s0["logL"][par], beta, s1["Lsig"],
+        par = par_o[j]
+        x, lx, _, otr = P.hrss_chain_tempered(o0["x"][par], o0["logL"][par], beta, Ls_o,
                                               width, 64, 4, 0, 1, j, trace=True)
         assert np.array_equal(tr[j], otr), f"chain {j}"
         assert np.allclose(s1["x"][j], x, rtol=1e-10, atol=1e-12)
