@@ -30,6 +30,21 @@ TRAFFIC = {"bf16x3": 748.4e6}
 TRAFFIC_SOURCE_SHA = "dcc5b843009ec19e"
 
 
+# VALU lane-instructions per evaluation issued by k_hrss (BF16x3) over one full run of the
+# mixture workload (SQ_INSTS_VALU x 64 / evaluations), for the kernel source with this prefix:
+# the instruction view of the same kernel (its chain logic runs on the vector ALU).
+HRSS_VALU_PER_EVAL = {"bf16x3": 22167.0}
+HRSS_VALU_SOURCE_SHA = "dcc5b843009ec19e"
+
+
+def hrss_valu_per_eval(precision):
+    import hashlib
+    src = os.path.join(ROOT, "paper_2601_23252_amd", "csrc", "nss_kernels.hip")
+    with open(src, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()[:16]
+    return HRSS_VALU_PER_EVAL.get(precision) if sha == HRSS_VALU_SOURCE_SHA else None
+
+
 def kernel_traffic(precision):
     import hashlib
     src = os.path.join(ROOT, "paper_2601_23252_amd", "csrc", "nss_kernels.hip")
@@ -61,7 +76,7 @@ def run_gpu(N, prob, precision, seeds, p, warmup, timing=True):
         z, err, H = R.logz()
         dt = time.perf_counter() - t0
         st = R.stats()
-        print(f"[bench] {precision} seed {s}: {it} iterations, {dt:.2f} s, "
+        print(f"[bench] {precision} seed {s}: {it} iterations, {dt:.2f} s, {st['evals']} evals, "
               f"{st['evals'] / dt:.3e} evals/s, ln Z {z:.3f} +- {err:.3f}", file=sys.stderr,
               flush=True)
         recs.append(dict(seed=s, iters=it, wall_s=dt, evals=st["evals"], logz=z, err=err, H=H,
@@ -274,7 +289,7 @@ def bench_batch(args):
 # for the kernel source with this sha256 prefix; the peak is one lane-instruction per lane per
 # cycle: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
 GEOM_VALU_PER_UNIT = 455.2
-GEOM_SOURCE_SHA = "475c7dcca08ac910"
+GEOM_SOURCE_SHA = "ac3a36c198ebef19"
 VALU_PEAK = 256 * 4 * 16 * 2.4e9
 
 
@@ -788,10 +803,17 @@ def main():
                                                              for r in recs),
                                  "range": [min(r["evals"] / r["wall_s"] for r in recs),
                                            max(r["evals"] / r["wall_s"] for r in recs)]},
+        "valu_issue": None,
         "rechecks_per_eval": sum(r["rechecks"] for r in recs) / max(1, evals),
         "band_violations": sum(r["band_violations"] for r in recs),
         "iterations": [r["iters"] for r in recs],
     }
+    vpe = hrss_valu_per_eval(args.precision)
+    if vpe is not None and hrss_s > 0:
+        a = vpe * evals / hrss_s
+        out["valu_issue"] = {"kernel": "k_hrss", "lane_instr_per_eval": vpe,
+                             "achieved": a / 1e12, "peak": VALU_PEAK / 1e12,
+                             "unit": "T lane-instr/s", "frac": a / VALU_PEAK}
     if args.fp64_steps > 0 and mixed:
         r64, t64 = run_gpu(N, prob, "fp64", list(range(args.fp64_steps)), p, 0)
         ev64 = sum(r["evals"] for r in r64)
