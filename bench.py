@@ -232,9 +232,14 @@ def bench_batch(args):
     N.load()
     probs = G.config5()
     runs = [(p, dict(seed=5, run_id=r, precision="bf16x3" if p["lik"] == "mixture" else "fp64",
-                     max_iter=3000, timing=True)) for r, p in enumerate(probs)]
+                     max_iter=3000, timing=True, autotune=not args.no_autotune))
+            for r, p in enumerate(probs)]
     B = N.NSBatch(runs)
     it, dt = run_until(B, args.max_seconds, chunk=16)
+    cpw = {}
+    for r in range(len(probs)):
+        c = N.ns_chains_per_workgroup(B.ctx, r)
+        cpw[str(c)] = cpw.get(str(c), 0) + 1
     stats = [B.stats(r) for r in range(len(probs))]
     evals = sum(s["evals"] for s in stats)
     fpe = [p["d"] * (p["d"] + 1) + 3 * p["d"] if p["lik"] == "mixture" else 3 * p["d"]
@@ -248,7 +253,8 @@ def bench_batch(args):
         "ms_per_step": 1e3 * dt, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
         "config": {"workload": "batch256_gauss_funnel_nlive500_k250_p5d", "runs": len(probs),
-                   "runs_done": done, "max_iterations": it},
+                   "runs_done": done, "max_iterations": it,
+                   "autotune": not args.no_autotune, "runs_by_chains_per_workgroup": cpw},
         "roofline": {"bound": "mfma", "achieved": flops / hrss_s / 1e12 if hrss_s else 0.0,
                      "peak": 2500.0, "unit": "TFLOP/s",
                      "frac": flops / hrss_s / 2.5e15 if hrss_s else 0.0, "traffic": None,
@@ -702,6 +708,8 @@ def main():
                          "check on this mixture; 5 is biased)")
     ap.add_argument("--fp64-steps", type=int, default=1, help="FP64 comparison runs (0 = skip)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="batch256: keep the chains-per-workgroup rule instead of timing")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--workload", default="mixture8_d64",
                     choices=["mixture8_d64", "gp_n256", "batch256", "geom", "rastrigin",

@@ -178,6 +178,15 @@ typedef enum {
                                       * it would exceed 32 GiB; not for d > 128) */
 #define NS_FLAG_RECORD_POINTS 16  /* keep the dead points' coordinates beside their logL
                                   * ((max_iter + 1) k d doubles) for ns_posterior_samples */
+#define NS_FLAG_AUTOTUNE 32  /* choose the chains per HRSS workgroup (1..4) of each compiled
+                              * kernel group by timing: the first iterations cycle through the
+                              * candidates (two timed iterations each, one host synchronisation
+                              * per iteration) and the group keeps the one with the least HRSS
+                              * time per evaluation; the choice is cached for later contexts of
+                              * the same shape (padded dimension, likelihood, precision, fragment
+                              * capacity, replacement, total chains) in this process.  Results
+                              * are identical with and without it.  Not used by NS_LIK_GP (one
+                              * chain per workgroup). */
 #define NS_FLAG_GRAPH  8  /* ns_run captures each batch of 16 iterations as a HIP graph and
                            * replays it (re-captured when a run of the batch finishes); not
                            * used together with NS_FLAG_TIMING.  Results are identical. */
@@ -322,6 +331,11 @@ ns_status ns_init_batch(int32_t n_runs, const ns_prior *priors, const ns_energy 
 
 /* Number of runs of a context (0 for NULL). */
 int32_t ns_num_runs(const ns_ctx *ctx);
+
+/* Chains per HRSS workgroup that run `run`'s next iteration uses (1..4; under
+ * NS_FLAG_AUTOTUNE the tuned value once tuning has finished); 0 for a NULL context or a run
+ * index out of range. */
+int32_t ns_chains_per_workgroup(const ns_ctx *ctx, int32_t run);
 
 /* ns_logz for every run: logz[r], logz_err[r], H[r] (any array may be NULL). */
 ns_status ns_logz_batch(ns_ctx *ctx, double *logz, double *logz_err, double *H);

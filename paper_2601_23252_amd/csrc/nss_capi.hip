@@ -6,6 +6,8 @@
 #include <math.h>
 #include <string.h>
 
+#include <map>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -30,6 +32,18 @@ struct RunHost {
 struct Group {
     int D, lik, mode, upwT, rw;
     std::vector<int> runs;
+};
+
+// Autotuning state of one group: candidate chains-per-workgroup values, their summed cost
+// (HRSS milliseconds per evaluation) and sample counts, and the candidate the next tuning
+// iteration uses.
+struct GroupTune {
+    std::vector<int> cand;
+    std::vector<double> cost;
+    std::vector<int> samples;
+    int turn = 0;
+    int initial = 1;   // the chains-per-workgroup rule's value, kept if nothing is measured
+    bool done = true;
 };
 
 struct ns_ctx {
@@ -64,6 +78,11 @@ struct ns_ctx {
     int use_graph = 0;
     long long map_epoch = 0, graph_epoch = -1;
     hipGraphExec_t gexec = nullptr;
+    // NS_FLAG_AUTOTUNE: chains per HRSS workgroup chosen per group by timing the candidates on
+    // the run's own iterations (per-group events around the HRSS launch, cost per evaluation)
+    int autotune = 0;
+    std::vector<GroupTune> tune;                                // per group
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> tune_ev;     // per group, tuning iterations
     // ns_geom_uncertainty's device buffer (outputs and partial results), grown on demand
     void *geom_buf = nullptr;
     size_t geom_bytes = 0;
@@ -509,12 +528,15 @@ static ns_status enqueue_iteration(ns_ctx *ctx)
         CK(hipEventCreate(&e1));
         CK(hipEventRecord(e0, ctx->stream));
     }
+    const bool tuning = !ctx->tune_ev.empty();
     for (size_t g = 0; g < ctx->groups.size(); ++g) {
         const Group &G = ctx->groups[g];
+        if (tuning) CK(hipEventRecord(ctx->tune_ev[g].first, ctx->stream));
         e = G.lik == LIK_GP ? launch_hrss_gp(ctx->L_hrss[g], G.mode, ctx->stream)
             : G.rw          ? launch_rw(ctx->L_hrss[g], G.D, G.lik, G.mode, G.upwT, ctx->stream)
                             : launch_hrss(ctx->L_hrss[g], G.D, G.lik, G.mode, G.upwT, ctx->stream);
         if (e != hipSuccess) return device_error(ctx, "HRSS launch", e);
+        if (tuning) CK(hipEventRecord(ctx->tune_ev[g].second, ctx->stream));
     }
     if (e1) {
         CK(hipEventRecord(e1, ctx->stream));
@@ -539,6 +561,126 @@ static ns_status collect_events(ns_ctx *ctx)
     }
     ctx->events.clear();
     return NS_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// NS_FLAG_AUTOTUNE: chains per HRSS workgroup.  The decisions and arithmetic of a chain do not
+// depend on which workgroup runs it, so the candidates are timed on the run's own iterations
+// without changing its trajectory.
+// ------------------------------------------------------------------------------------------
+constexpr int kTuneReps = 2;   // timed iterations per candidate
+
+static std::mutex g_tune_mu;
+static std::map<std::vector<long long>, int> g_tuned;   // shape of a group -> chains per WG
+
+static std::vector<long long> tune_key(const ns_ctx *ctx, const Group &G)
+{
+    long long chains = 0;
+    for (int r : G.runs) chains += ctx->runs[r].k;
+    return {G.D, G.lik, G.mode, G.upwT, G.rw, chains};
+}
+
+// Chains per workgroup of group g's runs, on the host and in the device descriptors (slot n
+// mirrors run 0).  The caller rebuilds the launches.
+static ns_status set_group_chains(ns_ctx *ctx, size_t g, int C)
+{
+    CK(hipStreamSynchronize(ctx->stream));
+    for (int r : ctx->groups[g].runs) {
+        ctx->runs[r].R.C = C;
+        CK(hipMemcpy(ctx->dR + r, &ctx->runs[r].R, sizeof(DevRun), hipMemcpyHostToDevice));
+        if (r == 0)
+            CK(hipMemcpy(ctx->dR + ctx->n, &ctx->runs[0].R, sizeof(DevRun), hipMemcpyHostToDevice));
+    }
+    return NS_OK;
+}
+
+static bool tuning_pending(const ns_ctx *ctx)
+{
+    for (const GroupTune &t : ctx->tune)
+        if (!t.done) return true;
+    return false;
+}
+
+static void destroy_tune_events(ns_ctx *ctx)
+{
+    for (auto &pr : ctx->tune_ev) {
+        if (pr.first) (void)hipEventDestroy(pr.first);
+        if (pr.second) (void)hipEventDestroy(pr.second);
+    }
+    ctx->tune_ev.clear();
+}
+
+static ns_status enqueue_iteration(ns_ctx *ctx);
+
+// One iteration with every group still tuning on its next candidate; the group's HRSS time per
+// evaluation in that iteration is charged to the candidate.  Once every candidate has
+// kTuneReps samples the group keeps the cheapest (the earlier candidate on a tie) and the
+// choice is cached for later contexts of the same shape in this process.
+static ns_status tune_iteration(ns_ctx *ctx)
+{
+    const size_t ng = ctx->groups.size();
+    std::vector<int> used(ng, -1);
+    ns_status st;
+    for (size_t g = 0; g < ng; ++g) {
+        GroupTune &t = ctx->tune[g];
+        if (t.done) continue;
+        used[g] = t.turn % (int)t.cand.size();
+        if ((st = set_group_chains(ctx, g, t.cand[used[g]])) != NS_OK) return st;
+    }
+    if ((st = build_maps(ctx, ctx->mapped_active)) != NS_OK) return st;
+    const size_t nc = (size_t)ctx->n * 16;
+    std::vector<unsigned long long> c0(nc), c1(nc);
+    CK(hipMemcpyAsync(c0.data(), ctx->d_ctr, nc * 8, hipMemcpyDeviceToHost, ctx->stream));
+    CK(hipStreamSynchronize(ctx->stream));
+    ctx->tune_ev.assign(ng, std::make_pair((hipEvent_t) nullptr, (hipEvent_t) nullptr));
+    for (auto &pr : ctx->tune_ev) {
+        if (hipEventCreate(&pr.first) != hipSuccess || hipEventCreate(&pr.second) != hipSuccess) {
+            destroy_tune_events(ctx);
+            return fail(ctx, NS_EDEVICE, "autotune: event creation failed");
+        }
+    }
+    st = enqueue_iteration(ctx);
+    if (st == NS_OK && (hipMemcpyAsync(c1.data(), ctx->d_ctr, nc * 8, hipMemcpyDeviceToHost,
+                                       ctx->stream) != hipSuccess ||
+                        hipStreamSynchronize(ctx->stream) != hipSuccess))
+        st = fail(ctx, NS_EDEVICE, "autotune: counter read failed");
+    std::vector<float> ms(ng, 0.f);
+    for (size_t g = 0; g < ng && st == NS_OK; ++g)
+        if (used[g] >= 0 &&
+            hipEventElapsedTime(&ms[g], ctx->tune_ev[g].first, ctx->tune_ev[g].second) != hipSuccess)
+            st = fail(ctx, NS_EDEVICE, "autotune: event timing failed");
+    destroy_tune_events(ctx);
+    if (st != NS_OK) return st;
+    bool settled = false;
+    for (size_t g = 0; g < ng; ++g) {
+        if (used[g] < 0) continue;
+        GroupTune &t = ctx->tune[g];
+        unsigned long long ev = 0;
+        for (int r : ctx->groups[g].runs) ev += c1[(size_t)16 * r] - c0[(size_t)16 * r];
+        if (ev > 0) {
+            t.cost[used[g]] += (double)ms[g] / (double)ev;
+            t.samples[used[g]] += 1;
+        }
+        t.turn += 1;
+        bool all = true;
+        for (int c : t.samples) all = all && c >= kTuneReps;
+        // a group whose runs stop evaluating (all finished) keeps its heuristic choice
+        if (!all && t.turn < 4 * kTuneReps * (int)t.cand.size()) continue;
+        int best = -1;
+        for (size_t i = 0; i < t.cand.size(); ++i)
+            if (t.samples[i] > 0 &&
+                (best < 0 || t.cost[i] / t.samples[i] < t.cost[best] / t.samples[best]))
+                best = (int)i;
+        const int C = best >= 0 ? t.cand[best] : t.initial;
+        if ((st = set_group_chains(ctx, g, C)) != NS_OK) return st;
+        t.done = true;
+        settled = true;
+        if (best >= 0) {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            g_tuned[tune_key(ctx, ctx->groups[g])] = C;
+        }
+    }
+    return settled ? build_maps(ctx, ctx->mapped_active) : NS_OK;
 }
 
 // Prior draws, FP64 evaluation and first delete-k of every run; resets every run counter.
@@ -817,6 +959,7 @@ extern "C" ns_status ns_init_batch(int32_t n_runs, const ns_prior *priors,
         rh.mode = cfgs[r].precision;
         if (cfgs[r].flags & NS_FLAG_TIMING) ctx->timing = 1;
         if (cfgs[r].flags & NS_FLAG_GRAPH) ctx->use_graph = 1;
+        if (cfgs[r].flags & NS_FLAG_AUTOTUNE) ctx->autotune = 1;
         if (r == 0) ctx->smc = cfgs[r].outer == NS_OUTER_SMC;
         if ((cfgs[r].outer == NS_OUTER_SMC) != (ctx->smc != 0)) {
             ctx->err = "run " + std::to_string(r) + ": all runs of a context share the outer loop";
@@ -856,6 +999,29 @@ extern "C" ns_status ns_init_batch(int32_t n_runs, const ns_prior *priors,
         if (G.lik == LIK_GP) C = 1;   // one chain per workgroup
         for (int r : G.runs) ctx->runs[r].R.C = C;
     }
+    // NS_FLAG_AUTOTUNE: a shape tuned before in this process takes its cached value; the others
+    // time every candidate on their first iterations
+    ctx->tune.assign(ctx->groups.size(), GroupTune{});
+    for (size_t g = 0; g < ctx->groups.size() && ctx->autotune; ++g) {
+        const Group &G = ctx->groups[g];
+        if (G.lik == LIK_GP) continue;
+        int cached = 0;
+        {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            auto it = g_tuned.find(tune_key(ctx, G));
+            if (it != g_tuned.end()) cached = it->second;
+        }
+        if (cached > 0) {
+            for (int r : G.runs) ctx->runs[r].R.C = cached;
+            continue;
+        }
+        GroupTune &t = ctx->tune[g];
+        for (int c = 1; c <= kMaxChainsPerWG; ++c) t.cand.push_back(c);
+        t.cost.assign(t.cand.size(), 0.0);
+        t.samples.assign(t.cand.size(), 0);
+        t.initial = ctx->runs[G.runs[0]].R.C;
+        t.done = false;
+    }
     std::vector<DevProblem> hp(n + 1);
     std::vector<DevRun> hr(n + 1);
     std::vector<int2> m1(n + 1);
@@ -865,8 +1031,9 @@ extern "C" ns_status ns_init_batch(int32_t n_runs, const ns_prior *priors,
         hp[r] = rh.P;
         hr[r] = rh.R;
         m1[r] = make_int2(r, 0);
+        // HRSS blocks at one chain per workgroup, the most any chains-per-workgroup value needs
         cap += (size_t)init_blocks(rh) + 1 + cov_blocks(rh) + dirs_blocks(rh) + eval_blocks(rh) +
-               hrss_blocks(rh);
+               (size_t)rh.k;
     }
     hp[n] = hp[0];
     hr[n] = hr[0];
@@ -931,7 +1098,7 @@ extern "C" ns_status ns_step(ns_ctx *ctx, int32_t *done)
         if (done) *done = 1;
         return NS_DONE;
     }
-    ns_status st = enqueue_iteration(ctx);
+    ns_status st = tuning_pending(ctx) ? tune_iteration(ctx) : enqueue_iteration(ctx);
     if (st != NS_OK) return st;
     if ((st = sync_flags(ctx)) != NS_OK) return st;
     if ((st = collect_events(ctx)) != NS_OK) return st;
@@ -981,6 +1148,12 @@ extern "C" ns_status ns_run(ns_ctx *ctx, int32_t max_iter, int32_t *iters)
     std::vector<int> start(ctx->n);
     for (int r = 0; r < ctx->n; ++r) start[r] = ctx->h_iscal[8 * r + 3];
     int issued = 0;
+    while (!all_done(ctx) && issued < max_iter && tuning_pending(ctx)) {   // one at a time
+        if ((st = refresh_maps(ctx)) != NS_OK) return st;
+        if ((st = tune_iteration(ctx)) != NS_OK) return st;
+        issued += 1;
+        if ((st = sync_flags(ctx)) != NS_OK) return st;
+    }
     while (!all_done(ctx) && issued < max_iter) {
         if ((st = refresh_maps(ctx)) != NS_OK) return st;
         const int batch = (max_iter - issued) < kGraphIters ? (max_iter - issued) : kGraphIters;
@@ -1002,6 +1175,12 @@ extern "C" ns_status ns_run(ns_ctx *ctx, int32_t max_iter, int32_t *iters)
     if (iters) *iters = adv;
     if (any_error(ctx)) return fail(ctx, NS_ESTATE, state_error_text(ctx));
     return NS_OK;
+}
+
+extern "C" int32_t ns_chains_per_workgroup(const ns_ctx *ctx, int32_t run)
+{
+    if (!ctx || run < 0 || run >= ctx->n) return 0;
+    return ctx->runs[run].R.C;
 }
 
 extern "C" ns_status ns_logz_batch(ns_ctx *ctx, double *logz, double *logz_err, double *H)

@@ -28,6 +28,7 @@ REPLACEMENTS = {"hrss": NS_REPLACE_HRSS, "rw": NS_REPLACE_RW}
 NS_FP64, NS_MIXED_BF16, NS_MIXED_FP16, NS_MIXED_BF16X3, NS_MIXED_FP16X3, NS_MIXED_FP32 = 0, 1, 2, 3, 4, 5
 NS_FLAG_TRACE, NS_FLAG_TIMING, NS_FLAG_INLINE_DIRECTIONS, NS_FLAG_GRAPH = 1, 2, 4, 8
 NS_FLAG_RECORD_POINTS = 16
+NS_FLAG_AUTOTUNE = 32
 PRECISIONS = {"fp64": NS_FP64, "bf16": NS_MIXED_BF16, "fp16": NS_MIXED_FP16,
               "bf16x3": NS_MIXED_BF16X3, "fp16x3": NS_MIXED_FP16X3, "fp32": NS_MIXED_FP32}
 # guard band of each mixed mode: (rel, abs) as set by the library
@@ -135,6 +136,8 @@ def load(build_if_missing: bool = True):
                                 C.POINTER(ns_config), vp, C.POINTER(vp)]
     L.ns_num_runs.restype = C.c_int32
     L.ns_num_runs.argtypes = [vp]
+    L.ns_chains_per_workgroup.restype = C.c_int32
+    L.ns_chains_per_workgroup.argtypes = [vp, C.c_int32]
     L.ns_logz_batch.restype = C.c_int
     L.ns_logz_batch.argtypes = [vp, _d, _d, _d]
     L.ns_stats_run.restype = C.c_int
@@ -228,6 +231,10 @@ def ns_num_runs(ctx) -> int:
     return int(load().ns_num_runs(ctx))
 
 
+def ns_chains_per_workgroup(ctx, run=0) -> int:
+    return int(load().ns_chains_per_workgroup(ctx, run))
+
+
 def ns_logz_batch(ctx):
     n = ns_num_runs(ctx)
     z, e, h = np.zeros(n), np.zeros(n), np.zeros(n)
@@ -294,7 +301,7 @@ def current_stream():
 def make_config(m, k, p, width=0.0, seed=0, run_id=0, precision="fp64", term_frac=1e-3,
                 stepout_cap=10, shrink_cap=100, max_iter=100000, trace=False, timing=False,
                 inline_directions=False, graph=False, replacement="hrss", outer="ns",
-                ess_frac=0.5, record_points=False) -> ns_config:
+                ess_frac=0.5, record_points=False, autotune=False) -> ns_config:
     cfg = ns_config_default()
     cfg.n_live, cfg.k, cfg.chain_len = int(m), int(k), int(p)
     cfg.width = float(width)
@@ -306,7 +313,8 @@ def make_config(m, k, p, width=0.0, seed=0, run_id=0, precision="fp64", term_fra
     cfg.flags = ((NS_FLAG_TRACE if trace else 0) | (NS_FLAG_TIMING if timing else 0)
                  | (NS_FLAG_INLINE_DIRECTIONS if inline_directions else 0)
                  | (NS_FLAG_GRAPH if graph else 0)
-                 | (NS_FLAG_RECORD_POINTS if record_points else 0))
+                 | (NS_FLAG_RECORD_POINTS if record_points else 0)
+                 | (NS_FLAG_AUTOTUNE if autotune else 0))
     cfg.replacement = REPLACEMENTS[replacement] if isinstance(replacement, str) else int(replacement)
     cfg.outer = OUTERS[outer] if isinstance(outer, str) else int(outer)
     cfg.ess_frac = float(ess_frac)
@@ -373,7 +381,7 @@ class NSRun:
                  precision="fp64", term_frac=1e-3, stepout_cap=10, shrink_cap=100,
                  max_iter=100000, trace=False, timing=False, inline_directions=False,
                  graph=False, stream="torch", replacement="hrss", outer="ns", ess_frac=0.5,
-                 record_points=False):
+                 record_points=False, autotune=False):
         self.prob = prob
         self.d = int(prob["d"])
         self.m = int(m or prob["m"])
@@ -384,7 +392,7 @@ class NSRun:
         pr, en, self._keep = make_structs(prob)
         cfg = make_config(self.m, self.k, self.p, width, seed, run_id, precision, term_frac,
                           stepout_cap, shrink_cap, max_iter, trace, timing, inline_directions,
-                          graph, replacement, outer, ess_frac, record_points)
+                          graph, replacement, outer, ess_frac, record_points, autotune)
         self.cfg = cfg
         s = current_stream() if stream == "torch" else stream
         st, self.ctx = ns_init(pr, en, cfg, s)
@@ -400,6 +408,9 @@ class NSRun:
 
     def reset(self, seed, run_id=0):
         _check(ns_reset(self.ctx, seed, run_id), self.ctx)
+
+    def chains_per_workgroup(self) -> int:
+        return ns_chains_per_workgroup(self.ctx, 0)
 
     def step(self) -> bool:
         st, done = ns_step(self.ctx)

@@ -1,0 +1,90 @@
+"""NS_FLAG_AUTOTUNE: the chains per HRSS workgroup chosen by timing.
+
+A chain's decisions and arithmetic do not depend on the workgroup that runs it, so a tuned run
+must equal the untuned run bit for bit (points, logL, evidence, iteration count) while the
+candidates are being timed and after the choice; the choice lies in 1..4 and is reused by a
+later context of the same shape.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def N():
+    from paper_2601_23252_amd import nss
+    nss.load()
+    return nss
+
+
+def _same_state(a, b):
+    sa, sb = a.state(), b.state()
+    assert sa["iter"] == sb["iter"]
+    assert np.array_equal(sa["perm"], sb["perm"])
+    assert np.array_equal(sa["x"], sb["x"])
+    assert np.array_equal(sa["logL"], sb["logL"])
+    assert sa["logZ"] == sb["logZ"] and sa["logX"] == sb["logX"]
+
+
+def test_autotune_config1_full_run_identical(N):
+    """config 1 (k = 50): the 8 tuning iterations and the rest of the run equal the untuned
+    run; a second context of the same shape starts with the cached choice."""
+    from paper_2601_23252_amd import problems as G
+    prob = G.config1()
+    a = N.NSRun(prob, seed=5, autotune=True)
+    b = N.NSRun(prob, seed=5)
+    assert b.chains_per_workgroup() == 1   # the rule: ceil(50 / 256)
+    for _ in range(3):                     # in the middle of tuning
+        a.step()
+        b.step()
+    _same_state(a, b)
+    ia, ib = a.run(), b.run()
+    assert ia == ib
+    _same_state(a, b)
+    assert a.logz() == b.logz()
+    c = a.chains_per_workgroup()
+    assert 1 <= c <= 4
+    again = N.NSRun(prob, seed=6, autotune=True)
+    assert again.chains_per_workgroup() == c
+    for r in (a, b, again):
+        r.close()
+
+
+def test_autotune_mixture_full_size_identical(N):
+    """The d = 64 mixture (k = 1000, BF16x3, chains of 64 steps): ten iterations, eight of them
+    tuning, equal the untuned ones."""
+    from paper_2601_23252_amd import problems as G
+    prob = G.config3()
+    a = N.NSRun(prob, p=64, seed=2, precision="bf16x3", autotune=True)
+    b = N.NSRun(prob, p=64, seed=2, precision="bf16x3")
+    assert b.chains_per_workgroup() == 4
+    for _ in range(10):
+        a.step()
+        b.step()
+    _same_state(a, b)
+    assert a.stats()["evals"] == b.stats()["evals"]
+    assert 1 <= a.chains_per_workgroup() <= 4
+    a.close()
+    b.close()
+
+
+def test_autotune_batch_with_graphs_identical(N):
+    """Two kernel groups (a d = 8 Gaussian and d = 16 funnels) in one batch, with HIP graphs:
+    every run's evidence equals the untuned batch's."""
+    from paper_2601_23252_amd import problems as G
+    runs = [(G.config2(3, d=8, m=120, k=40), dict(seed=1, run_id=0)),
+            (G.funnel(16, m=100, k=30), dict(seed=1, run_id=1)),
+            (G.funnel(16, m=90, k=45), dict(seed=2, run_id=2))]
+    tuned = N.NSBatch([(p, dict(kw, autotune=True, graph=True)) for p, kw in runs])
+    plain = N.NSBatch([(p, dict(kw, graph=True)) for p, kw in runs])
+    tuned.run()
+    plain.run()
+    zt, zp = tuned.logz(), plain.logz()
+    for r in range(3):
+        assert zt[0][r] == zp[0][r] and zt[2][r] == zp[2][r]
+        st, sp = tuned.state(r), plain.state(r)
+        assert np.array_equal(st["x"], sp["x"]) and st["iter"] == sp["iter"]
+        assert 1 <= N.ns_chains_per_workgroup(tuned.ctx, r) <= 4
+    tuned.close()
+    plain.close()
