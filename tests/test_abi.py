@@ -76,6 +76,7 @@ def test_null_context_calls(N):
     assert N.ns_logz(None)[0] == N.NS_EINVAL
     assert N.ns_reset(None, 0) == N.NS_EINVAL
     assert N.ns_geom_uncertainty(None, 0, 100, 1.0, 0, 0)[0] == N.NS_EINVAL
+    assert N.ns_chains_per_workgroup(None, 0) == 0
     N.ns_free(None)
 
 
