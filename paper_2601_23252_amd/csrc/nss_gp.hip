@@ -34,6 +34,10 @@ constexpr int kGpTileWaves = 7;        // waves 0..6 hold the covariance tiles
 constexpr int kGpPivot = 7;            // wave 7 factors the diagonal tiles
 constexpr int kGpMaxTiles = 136;                                      // 16 * 17 / 2
 constexpr int kGpSlots = (kGpMaxTiles + kGpTileWaves - 1) / kGpTileWaves;  // tiles per wave
+// a wave's first kGpLdsSlots tiles (the upper block rows, final after few updates) live in its
+// own LDS area, the rest in registers: 14 register tiles keep the wave inside its 256 VGPRs
+constexpr int kGpLdsSlots = 7;
+constexpr int kGpRegSlots = kGpSlots - kGpLdsSlots;
 constexpr int kGpSpinMax = 1 << 22;    // bound on the pivot wave's wait for a diagonal tile
 constexpr int kGpLd = 17;                                             // LDS tile row stride
 constexpr int kTile = 16 * kGpLd;
@@ -49,8 +53,10 @@ constexpr int kOffT = kOffSc + 4 * kGpMaxObs * 8;
 template <typename T>
 constexpr int gp_lds_bytes()
 {
-    // 16 panel tiles, diagonal tile, inverse tile, right-hand side, z block
-    return kOffT + (int)sizeof(T) * (16 * kTile + 2 * kTile + kGpMaxObs + 32);
+    // 16 panel tiles, diagonal tile, inverse tile, right-hand side, z block, reciprocal pivots,
+    // then the tile waves' LDS-resident tiles
+    return kOffT + (int)sizeof(T) * (16 * kTile + 2 * kTile + kGpMaxObs + 32 +
+                                     kGpLdsSlots * kGpTileWaves * kTile);
 }
 
 template <typename T> struct Mf;
@@ -136,6 +142,12 @@ __device__ __forceinline__ void store_tile(const V &acc, T *p, int l)
 {
 #pragma unroll
     for (int r = 0; r < 4; ++r) p[Mf<T>::row(l, r) * kGpLd + (l & 15)] = acc[r];
+}
+template <typename T, typename V>
+__device__ __forceinline__ void load_tile(V &acc, const T *p, int l)
+{
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[r] = p[Mf<T>::row(l, r) * kGpLd + (l & 15)];
 }
 
 // Factor the diagonal tile in dg (rows of stride kGpLd) in place, write the inverse of the
@@ -239,6 +251,7 @@ __device__ __forceinline__ double gp_eval(const double *u, int n, unsigned char 
     T *yb = li + kTile;
     T *zb = yb + kGpMaxObs;
     T *dv = zb + 16;                 // reciprocal pivots of the diagonal tile
+    T *far = dv + 16;                // [kGpLdsSlots][kGpTileWaves] LDS-resident tiles
     const int tid = threadIdx.x, lane0 = tid & 63, w = uniform_i(tid >> 6);
     const int NT = (n + 15) >> 4, NTT = NT * (NT + 1) / 2;
     const GpTheta h = gp_theta(u);
@@ -279,7 +292,8 @@ __device__ __forceinline__ double gp_eval(const double *u, int n, unsigned char 
         }
     } else {
         int tI[kGpSlots], tK[kGpSlots];
-        v4 acc[kGpSlots];
+        v4 acc[kGpRegSlots];             // slot s >= kGpLdsSlots in acc[s - kGpLdsSlots]
+        T *lt[kGpLdsSlots];              // slot s < kGpLdsSlots in LDS
 #pragma unroll
         for (int s = 0; s < kGpSlots; ++s) {
             const int t = w + kGpTileWaves * s;
@@ -287,9 +301,13 @@ __device__ __forceinline__ double gp_eval(const double *u, int n, unsigned char 
             if (t < NTT) tile_ik(t, I, K);
             tI[s] = I;
             tK[s] = K;
+        }
+#pragma unroll
+        for (int s = 0; s < kGpLdsSlots; ++s) lt[s] = far + (s * kGpTileWaves + w) * kTile;
+#pragma unroll
+        for (int s = 0; s < kGpRegSlots; ++s)
 #pragma unroll
             for (int r = 0; r < 4; ++r) acc[s][r] = T(0);
-        }
         {
             // entries of the wave's tiles (a slot's four entries in a loop that is not unrolled,
             // so the exponential's code appears once per slot)
@@ -301,9 +319,17 @@ __device__ __forceinline__ double gp_eval(const double *u, int n, unsigned char 
                     int I, K;
                     tile_ik(t, I, K);
                     const int col = 16 * K + (l & 15);
+                    if (s < kGpLdsSlots) {
 #pragma unroll 1
-                    for (int r = 0; r < 4; ++r)
-                        acc[s][r] = gp_entry<T>(xs, sc, n, 16 * I + M::row(l, r), col, h);
+                        for (int r = 0; r < 4; ++r)
+                            lt[s][M::row(l, r) * kGpLd + (l & 15)] =
+                                gp_entry<T>(xs, sc, n, 16 * I + M::row(l, r), col, h);
+                    } else {
+#pragma unroll 1
+                        for (int r = 0; r < 4; ++r)
+                            acc[s - kGpLdsSlots][r] =
+                                gp_entry<T>(xs, sc, n, 16 * I + M::row(l, r), col, h);
+                    }
                 }
             }
         }
@@ -319,7 +345,10 @@ __device__ __forceinline__ double gp_eval(const double *u, int n, unsigned char 
                 for (int s = 0; s < kGpSlots; ++s) {
                     if (tK[s] == J && tI[s] > J) {
                         T *pI = pan + tI[s] * kTile;
-                        store_tile<T>(acc[s], pI, l);
+                        v4 a;
+                        if (s < kGpLdsSlots) load_tile<T>(a, lt[s], l);
+                        else a = acc[s - kGpLdsSlots];
+                        store_tile<T>(a, pI, l);
                         wave_sync();
                         v4 o;
 #pragma unroll
@@ -331,7 +360,6 @@ __device__ __forceinline__ double gp_eval(const double *u, int n, unsigned char 
                         }
                         wave_sync();
                         store_tile<T>(o, pI, l);
-                        acc[s] = o;
                         const T zc = zb[l & 15];
 #pragma unroll
                         for (int r = 0; r < 4; ++r) {
@@ -352,14 +380,17 @@ __device__ __forceinline__ double gp_eval(const double *u, int n, unsigned char 
 #pragma unroll
                 for (int s = 0; s < kGpSlots; ++s) {
                     if (w + kGpTileWaves * s == tD) {
+                        v4 a;
+                        if (s < kGpLdsSlots) load_tile<T>(a, lt[s], l);
+                        else a = acc[s - kGpLdsSlots];
                         if (J >= 0) {
 #pragma unroll
                             for (int ks = 0; ks < 4; ++ks) {
                                 const int ko = (l & 15) * kGpLd + 4 * ks + (l >> 4);
-                                acc[s] = M::mma(-pD[ko], pD[ko], acc[s]);
+                                a = M::mma(-pD[ko], pD[ko], a);
                             }
                         }
-                        store_tile<T>(acc[s], dg, l);
+                        store_tile<T>(a, dg, l);
                     }
                 }
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
@@ -370,11 +401,16 @@ __device__ __forceinline__ double gp_eval(const double *u, int n, unsigned char 
                 for (int s = 0; s < kGpSlots; ++s) {
                     if (tK[s] > J && w + kGpTileWaves * s != tD) {
                         const T *pI = pan + tI[s] * kTile, *pK = pan + tK[s] * kTile;
+                        v4 a;
+                        if (s < kGpLdsSlots) load_tile<T>(a, lt[s], l);
+                        else a = acc[s - kGpLdsSlots];
 #pragma unroll
                         for (int ks = 0; ks < 4; ++ks) {
                             const int ko = (l & 15) * kGpLd + 4 * ks + (l >> 4);
-                            acc[s] = M::mma(-pI[ko], pK[ko], acc[s]);
+                            a = M::mma(-pI[ko], pK[ko], a);
                         }
+                        if (s < kGpLdsSlots) store_tile<T>(a, lt[s], l);
+                        else acc[s - kGpLdsSlots] = a;
                     }
                     __builtin_amdgcn_sched_barrier(0);
                 }
