@@ -6,9 +6,10 @@
 // over n <= 256 observations with 2-D inputs (a squared-exponential times a periodic kernel,
 // each a product over the input dimensions).
 //
-// One workgroup of 8 waves evaluates one candidate at a time.  The kernel matrix is built
-// directly in registers as 16x16 tiles of the lower triangle, in the accumulator layout of the
-// 16x16x4 MFMA (tile t lives in wave t mod 8), and factorised by a right-looking blocked
+// One workgroup of 8 waves evaluates one candidate at a time.  The kernel matrix is built as
+// 16x16 tiles of the lower triangle in the accumulator layout of the 16x16x4 MFMA (tile t is
+// owned by tile wave t mod 7; a wave's first seven tiles sit in its own LDS area, the others in
+// its registers), and factorised by a right-looking blocked
 // Cholesky: for each block column J one wave factors the diagonal tile and inverts the factor,
 // the panel tiles are multiplied by that inverse on MFMA, and every trailing tile takes its
 // rank-16 update on MFMA with operands from LDS.  The right-hand side y rides along, so the
