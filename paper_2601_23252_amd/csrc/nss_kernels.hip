@@ -119,6 +119,15 @@ __device__ __forceinline__ void stage_problem(const DevProblem &P, const Tile &T
 // column blocks): the residual of a component is then converted once per wave and shared by its
 // blocks, and every wave still gets the same triangular work.  uu = (c - w)/4 * D/16 + jb.
 __device__ __forceinline__ bool comp_major(int K) { return K >= 4; }
+// The same for the register-fragment tiles of the mixed modes, decided at compile time where the
+// fragment capacity is only used with K >= 4 (D = 64 with 8 units per wave holds K = 5..8,
+// D = 32 with 16 units K = 9..32), so the fragments that the dealing never reads are dropped.
+template <int D, int UPW>
+__device__ __forceinline__ bool comp_major_t(int K)
+{
+    if constexpr ((D == 64 && UPW == 8) || (D == 32 && UPW == 16)) return true;
+    else return K >= 4;
+}
 
 template <int NJB>
 __device__ __forceinline__ void unit_of_cm(int w, int uu, int &c, int &jb)
@@ -324,7 +333,7 @@ __device__ int mix_eval16(const DevProblem &P, const WFrag<D, UPW, MixTraits<MOD
             cx[ks][4] = c1.x; cx[ks][5] = c1.y; cx[ks][6] = c1.z; cx[ks][7] = c1.w;
         }
     }
-    if (comp_major(P.K)) {
+    if (comp_major_t<D, UPW>(P.K)) {
         constexpr int CW = (UPW + NJB - 1) / NJB;
 #pragma unroll
         for (int cw = 0; cw < CW; ++cw) {
@@ -486,7 +495,7 @@ __device__ __forceinline__ void load_wfrag(const DevProblem &P, WFrag<D, UPW, NP
 #pragma unroll
     for (int uu = 0; uu < UPW; ++uu) {
         int c, jb;
-        if (comp_major(P.K)) unit_of_cm<NJB>(w, uu, c, jb);
+        if (comp_major_t<D, UPW>(P.K)) unit_of_cm<NJB>(w, uu, c, jb);
         else unit_of<NJB>(w, uu, c, jb);
         const int u = c * NJB + jb;
 #pragma unroll
@@ -1929,7 +1938,7 @@ int upw_for(const DevProblem &P)
 int upw_template(int D, int upw)
 {
     if (D == 32) return upw <= 4 ? 4 : (upw <= 16 ? 16 : 0);
-    if (D == 64) return upw <= 2 ? 2 : (upw <= 8 ? 8 : 0);
+    if (D == 64) return upw <= 2 ? 2 : (upw <= 4 ? 4 : (upw <= 8 ? 8 : 0));
     if (D == 128) return upw <= 4 ? 4 : 0;
     return 0;
 }
@@ -2002,6 +2011,7 @@ static hipError_t rw_t(const Launch &L, hipStream_t s)
         }                                                                                     \
         if (D == 64) {                                                                        \
             if (upw <= 2) return FN<64, MODE_, LIK_MIXTURE, 2>(__VA_ARGS__);                  \
+            if (upw <= 4) return FN<64, MODE_, LIK_MIXTURE, 4>(__VA_ARGS__);                  \
             return FN<64, MODE_, LIK_MIXTURE, 8>(__VA_ARGS__);                                \
         }                                                                                     \
         return FN<128, MODE_, LIK_MIXTURE, 4>(__VA_ARGS__);                                   \

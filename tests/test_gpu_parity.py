@@ -232,6 +232,31 @@ def test_set_state_roundtrip_and_step(N, O):
 # ------------------------------------------------------------------------------------------
 # full-size d=64 mixture (the benchmark workload): sampled chains against the oracle
 # ------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("K", [3, 4])
+def test_mixture_d48_three_and_four_components_mixed(N, O, K):
+    """d = 48 (padded to 64) with 3 and 4 components runs the 4-unit fragment kernels (3
+    components dealt by column block, 4 by component): in BF16x3 and FP16 every iteration
+    equals the oracle's."""
+    from paper_2601_23252_amd import problems as G
+    prob = G.mixture_problem(40 + K, 48, K, m=300, k=100, p=40)
+    width = _width(48)
+    _, orc = oracle_runs.run_iterations(O, prob, 300, 100, 40, width, 3, 0)
+    states = []
+    for _ in range(4):
+        orc.step()
+        states.append(orc.state())
+    for prec in ("bf16x3", "fp16"):
+        g = N.NSRun(prob, width=width, seed=3, precision=prec)
+        for it, o in enumerate(states):
+            g.step()
+            s = g.state()
+            assert np.array_equal(s["perm"], o["perm"]), (prec, it)
+            assert np.allclose(s["x"], o["x"], rtol=1e-9, atol=1e-11), (prec, it)
+            assert np.allclose(s["logL"], o["logL"], rtol=1e-10, atol=1e-10), (prec, it)
+        assert g.stats()["band_violations"] == 0
+        g.close()
+
+
 _CONFIG3_ORACLE = {}
 
 
