@@ -88,3 +88,24 @@ def test_autotune_batch_with_graphs_identical(N):
         assert 1 <= N.ns_chains_per_workgroup(tuned.ctx, r) <= 4
     tuned.close()
     plain.close()
+
+
+@pytest.mark.parametrize("kw", [dict(outer="smc", m=300, p=10), dict(replacement="rw", p=20)])
+def test_autotune_smc_and_random_walk_identical(N, kw):
+    """The tempered-SMC outer loop and the random-walk replacement under the tuner: ten
+    iterations (eight of them tuning) equal the untuned ones."""
+    from paper_2601_23252_amd import problems as G
+    prob = G.config1()
+    a = N.NSRun(prob, seed=9, autotune=True, **kw)
+    b = N.NSRun(prob, seed=9, **kw)
+    for _ in range(10):
+        da = a.step()
+        db = b.step()
+        assert da == db
+        if da:
+            break
+    _same_state(a, b)
+    assert a.stats()["evals"] == b.stats()["evals"]
+    assert 1 <= a.chains_per_workgroup() <= 4
+    a.close()
+    b.close()
