@@ -337,6 +337,19 @@ int32_t ns_num_runs(const ns_ctx *ctx);
  * index out of range. */
 int32_t ns_chains_per_workgroup(const ns_ctx *ctx, int32_t run);
 
+/* NS_FLAG_AUTOTUNE's process-wide cache of tuned launch shapes, as a JSON file:
+ * {"nss_tune": 1, "entries": [{"D", "lik", "mode", "upw", "rw", "chains", "C"}, ...]} (the
+ * shape's padded dimension, likelihood, precision, fragment capacity, replacement and total
+ * chains, and the chosen chains per workgroup).  ns_tune_save writes the cache to path;
+ * ns_tune_load merges a file in the format ns_tune_save writes (its entries replace cached
+ * ones of the same shape); contexts created afterwards with NS_FLAG_AUTOTUNE start with the
+ * cached value.  *n (may be NULL) receives the number of cached entries afterwards.  Errors:
+ * NS_EINVAL for a NULL path, a file that cannot be opened or written, or a file that is not
+ * a tuning cache or holds a malformed entry (then nothing is merged); the message is in
+ * ns_last_error(NULL).  Host only: no device is needed. */
+ns_status ns_tune_save(const char *path, int32_t *n);
+ns_status ns_tune_load(const char *path, int32_t *n);
+
 /* ns_logz for every run: logz[r], logz_err[r], H[r] (any array may be NULL). */
 ns_status ns_logz_batch(ns_ctx *ctx, double *logz, double *logz_err, double *H);
 

@@ -4,6 +4,7 @@
 #include "nss_internal.hpp"
 
 #include <math.h>
+#include <stdio.h>
 #include <string.h>
 
 #include <map>
@@ -1174,6 +1175,61 @@ extern "C" ns_status ns_run(ns_ctx *ctx, int32_t max_iter, int32_t *iters)
     }
     if (iters) *iters = adv;
     if (any_error(ctx)) return fail(ctx, NS_ESTATE, state_error_text(ctx));
+    return NS_OK;
+}
+
+// The tuning cache as JSON: {"nss_tune": 1, "entries": [{"D": .., "lik": .., "mode": ..,
+// "upw": .., "rw": .., "chains": .., "C": ..}, ...]}, one entry per line.
+extern "C" ns_status ns_tune_save(const char *path, int32_t *n)
+{
+    if (!path) return NS_EINVAL;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    FILE *f = fopen(path, "w");
+    if (!f) return fail(nullptr, NS_EINVAL, std::string("cannot open ") + path);
+    fprintf(f, "{\"nss_tune\": 1, \"entries\": [");
+    size_t i = 0;
+    for (const auto &kv : g_tuned) {
+        const std::vector<long long> &k = kv.first;
+        fprintf(f, "%s\n  {\"D\": %lld, \"lik\": %lld, \"mode\": %lld, \"upw\": %lld, "
+                   "\"rw\": %lld, \"chains\": %lld, \"C\": %d}",
+                i++ ? "," : "", k[0], k[1], k[2], k[3], k[4], k[5], kv.second);
+    }
+    fprintf(f, "\n]}\n");
+    const bool ok = fclose(f) == 0;
+    if (n) *n = (int32_t)g_tuned.size();
+    return ok ? NS_OK : fail(nullptr, NS_EINVAL, std::string("cannot write ") + path);
+}
+
+extern "C" ns_status ns_tune_load(const char *path, int32_t *n)
+{
+    if (!path) return NS_EINVAL;
+    FILE *f = fopen(path, "r");
+    if (!f) return fail(nullptr, NS_EINVAL, std::string("cannot open ") + path);
+    std::string txt;
+    char buf[4096];
+    size_t got;
+    while ((got = fread(buf, 1, sizeof(buf), f)) > 0) txt.append(buf, got);
+    fclose(f);
+    if (txt.find("\"nss_tune\": 1") == std::string::npos)
+        return fail(nullptr, NS_EINVAL, std::string(path) + ": not a tuning cache");
+    std::map<std::vector<long long>, int> add;
+    size_t pos = txt.find("\"entries\"");
+    if (pos == std::string::npos)
+        return fail(nullptr, NS_EINVAL, std::string(path) + ": not a tuning cache");
+    for (; (pos = txt.find('{', pos)) != std::string::npos; ++pos) {
+        long long D, lik, mode, upw, rw, chains;
+        int C;
+        if (sscanf(txt.c_str() + pos,
+                   "{\"D\": %lld, \"lik\": %lld, \"mode\": %lld, \"upw\": %lld, \"rw\": %lld, "
+                   "\"chains\": %lld, \"C\": %d}",
+                   &D, &lik, &mode, &upw, &rw, &chains, &C) != 7 ||
+            C < 1 || C > kMaxChainsPerWG || chains < 1 || upw < 1 || (rw != 0 && rw != 1))
+            return fail(nullptr, NS_EINVAL, std::string(path) + ": malformed entry");
+        add[{D, lik, mode, upw, rw, chains}] = C;
+    }
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (const auto &kv : add) g_tuned[kv.first] = kv.second;
+    if (n) *n = (int32_t)g_tuned.size();
     return NS_OK;
 }
 

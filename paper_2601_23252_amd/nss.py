@@ -138,6 +138,9 @@ def load(build_if_missing: bool = True):
     L.ns_num_runs.argtypes = [vp]
     L.ns_chains_per_workgroup.restype = C.c_int32
     L.ns_chains_per_workgroup.argtypes = [vp, C.c_int32]
+    for fn in (L.ns_tune_save, L.ns_tune_load):
+        fn.restype = C.c_int
+        fn.argtypes = [C.c_char_p, _i32]
     L.ns_logz_batch.restype = C.c_int
     L.ns_logz_batch.argtypes = [vp, _d, _d, _d]
     L.ns_stats_run.restype = C.c_int
@@ -233,6 +236,18 @@ def ns_num_runs(ctx) -> int:
 
 def ns_chains_per_workgroup(ctx, run=0) -> int:
     return int(load().ns_chains_per_workgroup(ctx, run))
+
+
+def ns_tune_save(path):
+    n = C.c_int32(0)
+    st = load().ns_tune_save(None if path is None else str(path).encode(), C.byref(n))
+    return st, n.value
+
+
+def ns_tune_load(path):
+    n = C.c_int32(0)
+    st = load().ns_tune_load(None if path is None else str(path).encode(), C.byref(n))
+    return st, n.value
 
 
 def ns_logz_batch(ctx):

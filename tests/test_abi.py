@@ -151,3 +151,31 @@ def test_invalid_smc_arguments(N):
     cfg.replacement = N.NS_REPLACE_HRSS
     pr, en, keep = _structs(N, G.gp_problem(4, n=20))
     assert N.ns_init(pr, en, cfg, None)[0] == N.NS_EUNSUPPORTED     # SMC: not for the GP
+
+
+def test_tune_cache_json_round_trip(N, tmp_path):
+    """The autotuner's cache file (host only): a file in the saved format merges into the
+    cache and is written back with the same entries; a malformed file is refused whole."""
+    import json
+    src = tmp_path / "tune.json"
+    entries = [dict(D=64, lik=1, mode=3, upw=8, rw=0, chains=1000, C=4),
+               dict(D=32, lik=2, mode=0, upw=1, rw=1, chains=77, C=2)]
+    body = ",".join("\n  " + json.dumps(e) for e in entries)
+    src.write_text('{"nss_tune": 1, "entries": [' + body + "\n]}\n")
+    st, n = N.ns_tune_load(src)
+    assert st == N.NS_OK and n >= 2
+    out = tmp_path / "out.json"
+    st, n2 = N.ns_tune_save(out)
+    assert st == N.NS_OK and n2 == n
+    saved = json.loads(out.read_text())
+    assert saved["nss_tune"] == 1 and len(saved["entries"]) == n
+    for e in entries:
+        assert e in saved["entries"]
+    bad = tmp_path / "bad.json"
+    bad.write_text('{"nss_tune": 1, "entries": [{"D": 64, "lik": 1, "mode": 3, "upw": 8, '
+                   '"rw": 0, "chains": 1000, "C": 9}]}')
+    assert N.ns_tune_load(bad)[0] == N.NS_EINVAL
+    assert N.ns_tune_load(tmp_path / "missing.json")[0] == N.NS_EINVAL
+    assert N.ns_tune_load(None)[0] == N.NS_EINVAL
+    st, n3 = N.ns_tune_save(tmp_path / "again.json")
+    assert st == N.NS_OK and n3 == n

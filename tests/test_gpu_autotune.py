@@ -109,3 +109,31 @@ def test_autotune_smc_and_random_walk_identical(N, kw):
     assert 1 <= a.chains_per_workgroup() <= 4
     a.close()
     b.close()
+
+
+def test_autotune_cache_file_is_used(N, tmp_path):
+    """A tuning cache written and loaded back: a context of a cached shape starts with the
+    cached chains per workgroup and runs no tuning iterations (its result equals the plain
+    run's)."""
+    import json
+    from paper_2601_23252_amd import problems as G
+    prob = G.config1()
+    path = tmp_path / "tune.json"
+    # config 1's shape in FP64: padded dimension 32, mixture, 1 fragment unit, slice sampling
+    path.write_text('{"nss_tune": 1, "entries": [\n  ' + json.dumps(
+        dict(D=32, lik=1, mode=0, upw=1, rw=0, chains=50, C=3)) + "\n]}\n")
+    assert N.ns_tune_load(path)[0] == N.NS_OK
+    a = N.NSRun(prob, seed=4, autotune=True)
+    assert a.chains_per_workgroup() == 3
+    b = N.NSRun(prob, seed=4)
+    for _ in range(3):
+        a.step()
+        b.step()
+    _same_state(a, b)
+    assert a.chains_per_workgroup() == 3
+    st, n = N.ns_tune_save(tmp_path / "saved.json")
+    assert st == N.NS_OK and n >= 1
+    saved = json.loads((tmp_path / "saved.json").read_text())
+    assert dict(D=32, lik=1, mode=0, upw=1, rw=0, chains=50, C=3) in saved["entries"]
+    a.close()
+    b.close()
