@@ -257,7 +257,10 @@ ns_status ns_logz(ns_ctx *ctx, double *logz, double *logz_err, double *H);
 ns_status ns_stats(ns_ctx *ctx, ns_stats_t *out);
 
 /* Copy the state to host arrays / overwrite it from host arrays.  ns_set_state takes x, logL,
- * logZ, logX, M and iter; it recomputes the delete-k order and L* without re-accounting. */
+ * logZ, logX, M and iter; it recomputes the delete-k order and L* without re-accounting.  A
+ * logL entry that is NaN or +inf is stored as -inf and counted in ns_stats_t.nonfinite, as a
+ * computed one would be.  If after this no live point lies strictly above L* (a total
+ * plateau), the next ns_step returns NS_ESTATE. */
 ns_status ns_get_state(ns_ctx *ctx, ns_state_view *view);
 ns_status ns_set_state(ns_ctx *ctx, const ns_state_view *view);
 
@@ -289,6 +292,7 @@ ns_status ns_get_dead(ns_ctx *ctx, double *out, int64_t cap, int64_t *n);
 ns_status ns_geom_uncertainty(ns_ctx *ctx, int32_t run, int32_t R, double beta, uint64_t seed,
                               uint32_t run_id, double *logz, double *logw_mean, int64_t cap,
                               double *ess, int64_t *n_deaths, double *device_ms);
+
 
 /* Weighted posterior samples of run `run` (App. "Estimation of prior volumes and propagation
  * of geometric uncertainty": resampling with the geometric-mean weights): the weights of

@@ -729,21 +729,24 @@ int or_init(void *rr)
 
 /* Whitening: covariance (divided by n) of the m-k survivors (SMC: of all m particles) plus
  * 1e-12 tr/d jitter, and its lower Cholesky factor; diagonal fallback if the factorisation
- * fails. */
+ * fails.  The two passes work on the points minus the first of them (the covariance does not
+ * change under a shift), so survivors that coincide give an exactly zero covariance. */
 static void whiten(orun *r)
 {
     const int d = r->p->d, m = r->m, k = r->smc ? 0 : r->k, n = m - k;
     double *mean = (double *)calloc(d, sizeof(double));
     double *C = (double *)calloc((size_t)d * d, sizeof(double));
+    const double *x0 = r->x + (size_t)r->perm[k] * d;
     for (int t = k; t < m; ++t) {
         const double *xi = r->x + (size_t)r->perm[t] * d;
-        for (int a = 0; a < d; ++a) mean[a] += xi[a];
+        for (int a = 0; a < d; ++a) mean[a] += xi[a] - x0[a];
     }
     for (int a = 0; a < d; ++a) mean[a] /= n;
     for (int t = k; t < m; ++t) {
         const double *xi = r->x + (size_t)r->perm[t] * d;
         for (int a = 0; a < d; ++a)
-            for (int b = 0; b <= a; ++b) C[a * d + b] += (xi[a] - mean[a]) * (xi[b] - mean[b]);
+            for (int b = 0; b <= a; ++b)
+                C[a * d + b] += (xi[a] - x0[a] - mean[a]) * (xi[b] - x0[b] - mean[b]);
     }
     double tr = 0.0;
     for (int a = 0; a < d; ++a) {
@@ -1001,6 +1004,9 @@ void or_set_state(void *rr, const double *x, const double *logL, const double sc
     const int d = r->p->d, m = r->m;
     memcpy(r->x, x, sizeof(double) * (size_t)m * d);
     memcpy(r->logL, logL, sizeof(double) * m);
+    /* a NaN or +inf log L is a rejected point (-inf), counted like a computed one */
+    for (int i = 0; i < m; ++i)
+        if (isnan(r->logL[i]) || r->logL[i] == INFINITY) { r->logL[i] = -INFINITY; r->counters[5]++; }
     r->logZ = scalars3[0]; r->logX = scalars3[1]; r->M = scalars3[2];
     r->iter = iter;
     for (int i = 0; i < m; ++i) r->perm[i] = i;

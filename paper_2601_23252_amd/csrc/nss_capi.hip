@@ -1362,9 +1362,21 @@ extern "C" ns_status ns_set_state(ns_ctx *ctx, const ns_state_view *v)
     std::vector<double> t((size_t)D * mp, 0.0);
     for (int i = 0; i < m; ++i)
         for (int a = 0; a < d; ++a) t[(size_t)a * mp + i] = v->x[(size_t)i * d + a];
+    // a stored log L that is NaN or +inf is taken as -inf (rejected) and counted, as for a
+    // computed one
+    std::vector<double> lg(v->logL, v->logL + m);
+    unsigned long long nf = 0;
+    for (double &l : lg)
+        if (l != l || l == INFINITY) { l = -INFINITY; ++nf; }
     CK(hipStreamSynchronize(ctx->stream));
     CK(hipMemcpy(R.X, t.data(), t.size() * 8, hipMemcpyHostToDevice));
-    CK(hipMemcpy(R.logL, v->logL, m * 8, hipMemcpyHostToDevice));
+    CK(hipMemcpy(R.logL, lg.data(), m * 8, hipMemcpyHostToDevice));
+    if (nf) {
+        unsigned long long c5 = 0;
+        CK(hipMemcpy(&c5, R.ctr + 5, sizeof(c5), hipMemcpyDeviceToHost));
+        c5 += nf;
+        CK(hipMemcpy(R.ctr + 5, &c5, sizeof(c5), hipMemcpyHostToDevice));
+    }
     double sc[4] = {0.0, v->logZ, v->logX, v->M};
     CK(hipMemcpy(R.scal, sc, sizeof(sc), hipMemcpyHostToDevice));
     int is[8];
@@ -1397,10 +1409,11 @@ extern "C" ns_status ns_get_dead(ns_ctx *ctx, double *out, int64_t cap, int64_t 
     return NS_OK;
 }
 
-// The geometric-uncertainty computation of run `run` on the context's stream, outputs left in
-// the context's buffer (extra = further bytes reserved after them, at *extra_ptr).
-static ns_status enqueue_geom(ns_ctx *ctx, int run, int R, double beta, uint64_t seed,
-                              uint32_t run_id, size_t extra, GeomLaunch &G, char **extra_ptr)
+// Checks the arguments of a geometric-uncertainty call on run `run` and fills G (sizes, keys
+// and run buffers; no output or workspace pointers).  Reads the run's death count (a copy and
+// a wait on the context's stream).
+static ns_status plan_geom(ns_ctx *ctx, int run, int R, double beta, uint64_t seed,
+                           uint32_t run_id, GeomLaunch &G)
 {
     if (ctx->smc) return fail(ctx, NS_EUNSUPPORTED, "an SMC run has no dead record");
     if (R < 1 || R > 65535) return fail(ctx, NS_EINVAL, "replicas must be in [1, 65535]");
@@ -1414,19 +1427,6 @@ static ns_status enqueue_geom(ns_ctx *ctx, int run, int R, double beta, uint64_t
         return fail(ctx, NS_ESTATE, "dead record truncated: more deaths than max_iter + 1 iterations hold");
     const long long N = (long long)nd + (rh.m - rh.k);
     if (N >= (1ll << 31)) return fail(ctx, NS_EUNSUPPORTED, "more than 2^31 - 1 deaths");
-    const int groups = geom_groups(N, R);
-    auto up = [](size_t b) { return (b + 255) / 256 * 256; };
-    const size_t out_bytes = up((size_t)R * 8) + up((size_t)N * 8) + up(8);
-    const size_t wsb = up(geom_workspace_bytes(N, R, groups));
-    const size_t need = out_bytes + wsb + extra;
-    if (need > ctx->geom_bytes) {
-        if (ctx->geom_buf) CK(hipFree(ctx->geom_buf));
-        ctx->geom_buf = nullptr;
-        ctx->geom_bytes = 0;
-        CK(hipMalloc(&ctx->geom_buf, need));
-        ctx->geom_bytes = need;
-    }
-    char *b = (char *)ctx->geom_buf;
     G = GeomLaunch{};
     G.dead = D.dead;
     G.n_dead = (long long)nd;
@@ -1436,10 +1436,33 @@ static ns_status enqueue_geom(ns_ctx *ctx, int run, int R, double beta, uint64_t
     G.m = rh.m;
     G.k = rh.k;
     G.R = R;
-    G.groups = groups;
+    G.groups = geom_groups(N, R);
     G.beta = beta;
     G.key0 = (uint32_t)seed;
     G.key1 = (uint32_t)(seed >> 32) ^ run_id;
+    return NS_OK;
+}
+
+// The geometric-uncertainty computation of run `run` on the context's stream, outputs left in
+// the context's buffer (extra = further bytes reserved after them, at *extra_ptr).
+static ns_status enqueue_geom(ns_ctx *ctx, int run, int R, double beta, uint64_t seed,
+                              uint32_t run_id, size_t extra, GeomLaunch &G, char **extra_ptr)
+{
+    ns_status st = plan_geom(ctx, run, R, beta, seed, run_id, G);
+    if (st != NS_OK) return st;
+    const long long N = G.N;
+    auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+    const size_t out_bytes = up((size_t)R * 8) + up((size_t)N * 8) + up(8);
+    const size_t wsb = up(geom_workspace_bytes(N, R, G.groups));
+    const size_t need = out_bytes + wsb + extra;
+    if (need > ctx->geom_bytes) {
+        if (ctx->geom_buf) CK(hipFree(ctx->geom_buf));
+        ctx->geom_buf = nullptr;
+        ctx->geom_bytes = 0;
+        CK(hipMalloc(&ctx->geom_buf, need));
+        ctx->geom_bytes = need;
+    }
+    char *b = (char *)ctx->geom_buf;
     G.logz = (double *)b;
     G.logw_mean = (double *)(b + up((size_t)R * 8));
     G.ess = (double *)(b + up((size_t)R * 8) + up((size_t)N * 8));
