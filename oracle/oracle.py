@@ -36,6 +36,28 @@ def build(force: bool = False) -> str:
     return LIB
 
 
+NATIVE_LIB = os.path.join(HERE, "libnss_oracle_native.so")
+NATIVE_FLAGS = ["-O3", "-march=native", "-ffp-contract=off"]
+
+
+def use_native_build() -> str:
+    """Build a copy tuned for this host (-O3 -march=native, no contraction into fused
+    multiply-adds, so every result equals the portable build's) and route later calls to it.
+    Used only to time the oracle on the host it runs on; must be called before the first call
+    into the oracle."""
+    global LIB, _lib
+    if _lib is not None and LIB == NATIVE_LIB:
+        return LIB
+    if _lib is not None:
+        raise RuntimeError("the oracle is already loaded")
+    tmp = NATIVE_LIB + f".tmp{os.getpid()}"
+    subprocess.check_call(["gcc", *NATIVE_FLAGS, "-std=c99", "-fPIC", "-shared", "-fopenmp",
+                           "-o", tmp, SRC, "-lm"])
+    os.replace(tmp, NATIVE_LIB)
+    LIB = NATIVE_LIB
+    return LIB
+
+
 _lib = None
 
 
