@@ -1,0 +1,114 @@
+"""End-to-end parity at full size through the C ABI, against stored oracle runs
+(tests/golden/oracle_*.txt, written by tests/golden/make_oracle_runs.py, which calls only the
+FP64 CPU oracle):
+
+  - the d=64, 8-component mixture (n_live=2000, k=1000, p=5d, seed 0) run to termination in
+    FP64 and in the split-BF16 mixed mode (whose decisions equal FP64 through its guard band):
+    identical iteration count and evaluation counters, |d ln Z| <= 1e-9, H within 1e-8;
+  - the GP workload (256 inputs, n_live=1000, k=500, p=30, seed 0) over its stored iterations:
+    per iteration L*, ln Z, ln X within 1e-10 relative, identical evaluation counts;
+  - a multi-seed z-test of ln Z at full size on the d=64 Gaussian built like one mixture
+    component (p=5d), where the method is accurate (the mixture itself is biased high at
+    p=5d, and the oracle run shows the same value as the GPU's).
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from tests.conftest import read_golden
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+@pytest.fixture(scope="module")
+def N():
+    from paper_2601_23252_amd import nss
+    nss.load()
+    return nss
+
+
+def _width(d):
+    from oracle import theory as T
+    return T.width_whitened(d)
+
+
+def _golden_scalars(name):
+    return {r[0]: r[1] for r in read_golden(name)}
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+def test_mixture_p5d_run_matches_oracle(N, prec):
+    from paper_2601_23252_amd import problems as G
+    g = _golden_scalars("oracle_mixture8_d64_p5d_seed0.txt")
+    prob = G.config3()
+    print(f"mixture d=64 p=320 seed 0 {prec}", flush=True)
+    per_iter = read_golden("oracle_mixture8_d64_p5d_seed0_iters.txt")
+    gpu = N.NSRun(prob, p=5 * 64, width=_width(64), seed=0, precision=prec, max_iter=2000)
+    for r in per_iter:
+        it = int(r[0])
+        if it > 0:
+            gpu.step()
+        st, s = gpu.state(), gpu.stats()
+        assert st["iter"] == it
+        assert math.isclose(st["Lstar"], float(r[1]), rel_tol=1e-10, abs_tol=1e-10), (it, st["Lstar"], r[1])
+        assert math.isclose(st["logZ"], float(r[2]), rel_tol=1e-11, abs_tol=1e-11), (it, st["logZ"], r[2])
+        assert s["evals"] == int(r[3]) and s["tests"] == int(r[4]), (it, s["evals"], r[3])
+    assert gpu.step()          # terminated: ns_step reports done
+    it = gpu.state()["iter"]
+    z, err, H = gpu.logz()
+    s = gpu.stats()
+    assert it == int(g["iterations"])
+    for key in ("evals", "tests", "prior_rejects", "stepout_caps", "shrink_caps"):
+        assert s[key] == int(g[key]), (key, s[key], g[key])
+    assert abs(z - float(g["logz"])) <= 1e-9, (z, g["logz"])
+    assert abs(H - float(g["H"])) <= 1e-8 * abs(float(g["H"]))
+    assert abs(err - float(g["sigma"])) <= 1e-10
+    assert s["band_violations"] == 0 and s["nonfinite"] == 0
+    gpu.close()
+
+
+def test_gp_iterations_match_oracle(N):
+    from paper_2601_23252_amd import problems as G
+    rows = read_golden("oracle_gp_n256_seed0.txt")
+    prob = G.config4()
+    print("gp n=256 seed 0 fp64", flush=True)
+    gpu = N.NSRun(prob, width=_width(6), seed=0, precision="fp64", max_iter=100)
+    for r in rows:
+        it = int(r[0])
+        if it > 0:
+            gpu.step()
+        st, s = gpu.state(), gpu.stats()
+        assert st["iter"] == it
+        for val, ref in ((st["Lstar"], r[1]), (st["logZ"], r[2]), (st["logX"], r[3]),
+                         (float(st["logL"].sum()), r[6])):
+            assert math.isclose(val, float(ref), rel_tol=1e-10, abs_tol=1e-10), (it, val, ref)
+        assert s["evals"] == int(r[4]) and s["tests"] == int(r[5]), (it, s["evals"], r[4])
+    gpu.close()
+
+
+def test_gauss64_full_size_multiseed_z(N):
+    """Sec. 8(c) bar for the mixed mode against a closed form: five seeds, each within 4 sigma
+    and their mean within 2 sigma (the batch deletion k/m = 0.5 widens the run-to-run spread a
+    little beyond sqrt(H/m))."""
+    from paper_2601_23252_amd import problems as G
+    rng = np.random.default_rng(1003)
+    d = 64
+    q = G.haar_orthogonal(rng, d)
+    sd = rng.uniform(0.05, 0.5, d)
+    cov = G._sym((q * (sd * sd)[None, :]) @ q.T)
+    prob = G.gaussian_problem(d, np.zeros(d), cov, "box", -10.0, 10.0, m=2000, k=1000)
+    truth = -d * math.log(20.0)
+    gpu = N.NSRun(prob, seed=0, precision="bf16x3", max_iter=2000)
+    zs = []
+    for seed in range(5):
+        gpu.reset(seed)
+        gpu.run(2000)
+        z, err, _ = gpu.logz()
+        zs.append((z - truth) / err)
+    assert np.all(np.abs(zs) < 4.0), zs
+    assert abs(np.mean(zs)) < 2.0, zs
+    gpu.close()

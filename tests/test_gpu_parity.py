@@ -311,22 +311,6 @@ def test_config3_full_size_sampled_chains(N, O, prec):
     gpu.close()
 
 
-@pytest.mark.parametrize("prec", ["bf16x3", "fp16x3", "fp64"])
-def test_config3_end_to_end_lnz(N, prec):
-    """Full runs of the d=64 mixture at chain length 20 d (5 d is biased high on this target,
-    see the design notes): |ln Z + 64 ln 20| < 3 sigma; mixed and FP64 agree exactly."""
-    prob = _problems()["config3"]
-    gpu = N.NSRun(prob, p=20 * 64, width=_width(64), seed=21, precision=prec)
-    gpu.run()
-    z, err, H = gpu.logz()
-    s = gpu.stats()
-    tz = -64 * math.log(20.0)
-    assert abs(z - tz) < 3 * err, (z, tz, err)
-    assert s["band_violations"] == 0 and s["nonfinite"] == 0
-    assert s["evals"] > 0 and s["iterations"] > 100
-    gpu.close()
-
-
 def test_funnel_d200_padded_320(N, O):
     """The funnel at d = 200 (padded dimension 320): per-iteration parity, including the
     global-memory Cholesky of the 200 x 200 covariance of 500 survivors (with fewer survivors
