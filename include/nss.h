@@ -293,6 +293,27 @@ ns_status ns_geom_uncertainty(ns_ctx *ctx, int32_t run, int32_t R, double beta, 
                               uint32_t run_id, double *logz, double *logw_mean, int64_t cap,
                               double *ess, int64_t *n_deaths, double *device_ms);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, serving loops,
+ * harnesses that forbid hipMalloc): ns_geom_uncertainty with caller-owned DEVICE outputs and
+ * the partial results in a fixed workspace compiled into the library, one copy of
+ * NS_NOALLOC_SCRATCH_BYTES per GPU, held until the process ends (its address is looked up by
+ * ns_init / ns_init_batch).  It calls no hipMalloc, hipFree or allocating library routine.
+ *   logz[R], logw_mean[cap], ess[1]: device pointers on the context's device, all required;
+ *   the values equal ns_geom_uncertainty's (logw_mean: all N of them, so cap >= N);
+ *   n_deaths: host pointer, if not NULL set to N (also when cap is too small).
+ * The work is enqueued on the context's stream after one wait for the run's death count; the
+ * outputs are ready when the stream reaches that point (the call does not wait for them).
+ * Every call on one GPU shares that GPU's workspace: calls that overlap on one GPU (other
+ * streams, other threads, other contexts) race and must be serialised by the caller.
+ * Errors: those of ns_geom_uncertainty, NS_EINVAL for a NULL output, cap < N, or a workspace
+ * needing more than NS_NOALLOC_SCRATCH_BYTES (a run with 312,000 deaths and R = 100 needs
+ * about 19 MiB; about 4 million deaths fit at R = 100), NS_EDEVICE if the workspace address
+ * could not be looked up. */
+#define NS_NOALLOC_SCRATCH_BYTES (64u << 20)
+ns_status ns_geom_uncertainty_noalloc(ns_ctx *ctx, int32_t run, int32_t R, double beta,
+                                      uint64_t seed, uint32_t run_id, double *logz,
+                                      double *logw_mean, int64_t cap, double *ess,
+                                      int64_t *n_deaths);
 
 /* Weighted posterior samples of run `run` (App. "Estimation of prior volumes and propagation
  * of geometric uncertainty": resampling with the geometric-mean weights): the weights of

@@ -87,10 +87,43 @@ struct ns_ctx {
     // ns_geom_uncertainty's device buffer (outputs and partial results), grown on demand
     void *geom_buf = nullptr;
     size_t geom_bytes = 0;
+    // this device's copy of the fixed workspace (ns_geom_uncertainty_noalloc), or null with
+    // the reason in scratch_err
+    void *scratch = nullptr;
+    std::string scratch_err;
     std::string err;
 };
 
 constexpr int kGraphIters = 16;   // iterations per host synchronisation in ns_run
+
+// Workspace of ns_geom_uncertainty_noalloc: a fixed device array, one copy per GPU, held until
+// the process ends.  Host code never passes the array's name to a kernel or a copy (on the host
+// it is only a stand-in symbol); it uses the device address that hipGetSymbolAddress returns,
+// looked up once per device by ns_init_batch with that device current.
+static __device__ __align__(256) unsigned char scratch[NS_NOALLOC_SCRATCH_BYTES];
+static std::mutex g_scratch_mu;
+static std::map<int, void *> g_scratch_addr;   // device ordinal -> its copy of scratch
+
+static void *scratch_for_current_device(std::string &err)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        err = std::string("hipGetDevice: ") + hipGetErrorString(e);
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_addr.find(dev);
+    if (it != g_scratch_addr.end()) return it->second;
+    void *ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+        err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+        return nullptr;
+    }
+    g_scratch_addr[dev] = ptr;
+    return ptr;
+}
 
 static std::string g_init_err = "";
 
@@ -935,6 +968,7 @@ extern "C" ns_status ns_init_batch(int32_t n_runs, const ns_prior *priors,
         }
         ctx->own_stream = true;
     }
+    ctx->scratch = scratch_for_current_device(ctx->scratch_err);
     const int n = n_runs;
     if ((st = dalloc(ctx, &ctx->d_iscal, (size_t)n * 8)) ||
         (st = dalloc(ctx, &ctx->d_scal, (size_t)n * 8)) ||
@@ -1508,6 +1542,35 @@ extern "C" ns_status ns_geom_uncertainty(ns_ctx *ctx, int32_t run, int32_t R, do
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
     }
+    return NS_OK;
+}
+
+extern "C" ns_status ns_geom_uncertainty_noalloc(ns_ctx *ctx, int32_t run, int32_t R,
+                                                 double beta, uint64_t seed, uint32_t run_id,
+                                                 double *logz, double *logw_mean, int64_t cap,
+                                                 double *ess, int64_t *n_deaths)
+{
+    if (!run_ok(ctx, run) || !logz || !logw_mean || !ess) return NS_EINVAL;
+    if (!ctx->scratch)
+        return fail(ctx, NS_EDEVICE, "no fixed workspace on this device: " + ctx->scratch_err);
+    GeomLaunch G;
+    ns_status st = plan_geom(ctx, run, R, beta, seed, run_id, G);
+    if (st != NS_OK) return st;
+    if (n_deaths) *n_deaths = G.N;
+    if (cap < G.N)
+        return fail(ctx, NS_EINVAL, "logw_mean holds " + std::to_string(cap) + " values, " +
+                                        std::to_string(G.N) + " deaths");
+    const size_t wsb = geom_workspace_bytes(G.N, R, G.groups);
+    if (wsb > (size_t)NS_NOALLOC_SCRATCH_BYTES)
+        return fail(ctx, NS_EINVAL, "workspace of " + std::to_string(wsb) + " bytes exceeds the " +
+                                        std::to_string((size_t)NS_NOALLOC_SCRATCH_BYTES) +
+                                        "-byte fixed workspace (fewer replicas or deaths)");
+    G.logz = logz;
+    G.logw_mean = logw_mean;
+    G.ess = ess;
+    G.ws = ctx->scratch;
+    hipError_t e = launch_geom(G, ctx->stream);
+    if (e != hipSuccess) return device_error(ctx, "geometric-uncertainty launch", e);
     return NS_OK;
 }
 

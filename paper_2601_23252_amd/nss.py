@@ -154,6 +154,10 @@ def load(build_if_missing: bool = True):
     L.ns_geom_uncertainty.argtypes = [vp, C.c_int32, C.c_int32, C.c_double, C.c_uint64,
                                       C.c_uint32, _d, _d, C.c_int64, _d, C.POINTER(C.c_int64),
                                       _d]
+    L.ns_geom_uncertainty_noalloc.restype = C.c_int
+    L.ns_geom_uncertainty_noalloc.argtypes = [vp, C.c_int32, C.c_int32, C.c_double, C.c_uint64,
+                                              C.c_uint32, vp, vp, C.c_int64, vp,
+                                              C.POINTER(C.c_int64)]
     _lib = L
     return L
 
@@ -362,6 +366,18 @@ def ns_geom_uncertainty(ctx, run, R, beta, seed, run_id, n_deaths=None, timing=F
     if lw is not None and st == NS_OK and n.value != len(lw):
         raise NSError(NS_EINVAL, f"{n.value} deaths, {len(lw)} expected")
     return st, logz[:int(R)], lw, ess.value, n.value, (ms.value if timing else None)
+
+
+def ns_geom_uncertainty_noalloc(ctx, run, R, beta, seed, run_id, logz_ptr, logw_mean_ptr, cap,
+                                ess_ptr):
+    """One call of the C function with caller-owned device outputs (integer device addresses).
+    Returns (status, N)."""
+    n = C.c_int64(0)
+    st = load().ns_geom_uncertainty_noalloc(ctx, int(run), int(R), float(beta), int(seed),
+                                            int(run_id), C.c_void_p(logz_ptr),
+                                            C.c_void_p(logw_mean_ptr), int(cap),
+                                            C.c_void_p(ess_ptr), C.byref(n))
+    return st, n.value
 
 
 def ns_posterior_samples(ctx, run, R, beta, seed, run_id, n, d):
