@@ -68,10 +68,12 @@ def algorithmic_flop_per_eval(K: int, d: int) -> int:
     return K * d * (d + 1) + 3 * K * d
 
 
-def run_gpu(N, prob, precision, seeds, p, warmup, timing=True):
-    """Runs len(seeds) full NS runs on one context; returns per-run records and totals."""
+def run_gpu(N, prob, precision, seeds, p, warmup, timing=True, autotune=True, shape_out=None):
+    """Runs len(seeds) full NS runs on one context (the launch shape tuned during the warmup
+    runs, or on the first timed run without warmup); returns per-run records and totals."""
     import torch
-    R = N.NSRun(prob, p=p, seed=seeds[0], precision=precision, timing=timing)
+    R = N.NSRun(prob, p=p, seed=seeds[0], precision=precision, timing=timing,
+                autotune=autotune)
     for w in range(warmup):
         R.reset(10_000 + w)
         R.run()
@@ -94,6 +96,10 @@ def run_gpu(N, prob, precision, seeds, p, warmup, timing=True):
                          tests=st["tests"]))
     torch.cuda.synchronize()
     total = time.perf_counter() - t_all
+    if shape_out is not None:
+        c, plan = R.launch_shape()
+        shape_out.update(chains_per_workgroup=c, tests_per_round=plan,
+                         tune_launches=R.stats()["tune_launches"])
     R.close()
     return recs, total
 
@@ -166,16 +172,21 @@ def profile_run(args):
     dst.copy_(src)
     torch.cuda.synchronize()
     prob = G.config3()
+    kw = {"tuned": dict(autotune=True), "rule": {}, "shallow": dict(shallow_plan=True),
+          "inline": dict(shallow_plan=True, inline_directions=True)}[args.profile_shape]
     R = N.NSRun(prob, p=args.chain_factor * prob["d"], seed=0, precision=args.precision,
-                timing=True)
+                timing=True, **kw)
     t0 = time.perf_counter()
     for _ in range(args.profile_iters):
         R.step()
     torch.cuda.synchronize()
     st = R.stats()
+    c, plan = R.launch_shape()
     print(json.dumps({"profile_iters": args.profile_iters, "precision": args.precision,
-                      "wall_s": time.perf_counter() - t0, "evals": st["evals"],
-                      "hrss_ms": st["hrss_ms"], "copy_bytes": 256 << 20}), flush=True)
+                      "shape": args.profile_shape, "chains_per_workgroup": c,
+                      "tests_per_round": plan, "wall_s": time.perf_counter() - t0,
+                      "evals": st["evals"], "hrss_ms": st["hrss_ms"],
+                      "copy_bytes": 256 << 20}), flush=True)
     R.close()
 
 
@@ -737,7 +748,12 @@ def main():
                     help="runs of the long-chain line (0 = skip)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
-                    help="batch256: keep the chains-per-workgroup rule instead of timing")
+                    help="keep the launch-shape rule (4 chains per workgroup, 16 planned tests "
+                         "for 16-bit mixture chains) instead of timing the candidates")
+    ap.add_argument("--profile-shape", default="tuned",
+                    choices=["tuned", "rule", "shallow", "inline"],
+                    help="profiling run: the chains' launch shape (tuned, the rule, the 4-test "
+                         "kernel, or the 4-test kernel drawing its directions inline)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--workload", default="mixture8_d64",
                     choices=["mixture8_d64", "gp_n256", "batch256", "geom", "rastrigin",
@@ -811,7 +827,9 @@ def main():
                     per_seed_evals_per_s=[r["evals"] / r["wall_s"] for r in recs])
 
     seeds = list(range(args.steps))
-    recs, total = run_gpu(N, prob, args.precision, seeds, p, args.warmup)
+    shape = {}
+    recs, total = run_gpu(N, prob, args.precision, seeds, p, args.warmup,
+                          autotune=not args.no_autotune, shape_out=shape)
     head = summary(recs, total)
     evals = sum(r["evals"] for r in recs)
     hrss_s = sum(r["hrss_ms"] for r in recs) / 1e3
@@ -840,6 +858,7 @@ def main():
                       "divided by the wall time of all timed runs",
         "runs_within_3sigma": head["runs_within_3sigma"],
         "rate_all_runs": head["rate_all_runs"],
+        "launch_shape": shape,
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / peak,
                      "traffic": kernel_traffic(args.precision, p),
@@ -863,7 +882,8 @@ def main():
                              "achieved": a / 1e12, "peak": VALU_PEAK / 1e12,
                              "unit": "T lane-instr/s", "frac": a / VALU_PEAK}
     if args.fp64_steps > 0 and mixed:
-        r64, t64 = run_gpu(N, prob, "fp64", list(range(args.fp64_steps)), p, 0)
+        r64, t64 = run_gpu(N, prob, "fp64", list(range(args.fp64_steps)), p, 1,
+                           autotune=not args.no_autotune)
         s64 = summary(r64, t64)
         ev64 = sum(r["evals"] for r in r64)
         out["fp64"] = {"value": s64["value"], "rate_all_runs": s64["rate_all_runs"],
@@ -877,7 +897,8 @@ def main():
         out["speedup_vs_fp64"] = head["rate_all_runs"] / s64["rate_all_runs"]
     if args.long_chain_steps > 0:
         pl = args.long_chain_factor * d
-        rl, tl = run_gpu(N, prob, args.precision, list(range(args.long_chain_steps)), pl, 0)
+        rl, tl = run_gpu(N, prob, args.precision, list(range(args.long_chain_steps)), pl, 0,
+                         autotune=not args.no_autotune)
         sl = summary(rl, tl)
         out["long_chain"] = {"label": f"the same workload at chain length p = "
                                       f"{args.long_chain_factor}d = {pl} (not the configured 5d)",

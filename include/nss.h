@@ -178,15 +178,27 @@ typedef enum {
                                       * it would exceed 32 GiB; not for d > 128) */
 #define NS_FLAG_RECORD_POINTS 16  /* keep the dead points' coordinates beside their logL
                                   * ((max_iter + 1) k d doubles) for ns_posterior_samples */
-#define NS_FLAG_AUTOTUNE 32  /* choose the chains per HRSS workgroup (1..4) of each compiled
-                              * kernel group by timing: the first iterations cycle through the
-                              * candidates (two timed iterations each, one host synchronisation
-                              * per iteration) and the group keeps the one with the least HRSS
-                              * time per evaluation; the choice is cached for later contexts of
-                              * the same shape (padded dimension, likelihood, precision, fragment
-                              * capacity, replacement, total chains) in this process.  Results
-                              * are identical with and without it.  Not used by NS_LIK_GP (one
-                              * chain per workgroup). */
+#define NS_FLAG_AUTOTUNE 32  /* choose the launch shape of each compiled kernel group's
+                              * chains by timing: chains per workgroup (1..4) and, for mixture
+                              * chains in a 16-bit mode, tests planned per round (4, 8 or 16).
+                              * At the group's first iteration, after whitening and directions,
+                              * the state the chains change is saved, every candidate's chain
+                              * launch is timed twice on it (the state restored each time), the
+                              * fastest is kept and the iteration completes with it.  The choice
+                              * is cached for later contexts of the same shape (padded
+                              * dimension, likelihood, precision, fragment capacity,
+                              * replacement, total chains, plan kernel allowed) in this process.
+                              * Results are identical with and without it.  Not used by
+                              * NS_LIK_GP (one chain per workgroup). */
+#define NS_FLAG_SHALLOW_PLAN 64  /* mixture chains in a 16-bit mode plan at most 4 tests per
+                                 * round (the two bracket ends, then shrink proposals) instead
+                                 * of 16 (the next two stepping-out tests of each open end and
+                                 * the shrink proposals of the likeliest expansion outcomes).
+                                 * Decisions, trajectories and counters are identical. */
+#define NS_FLAG_PLAN8 128  /* mixture chains in a 16-bit mode plan 8 tests per round (the
+                           * next two stepping-out tests of each open end and the shrink
+                           * proposals of the three likeliest expansion outcomes) instead of
+                           * 16; identical results.  NS_FLAG_SHALLOW_PLAN takes precedence. */
 #define NS_FLAG_GRAPH  8  /* ns_run captures each batch of 16 iterations as a HIP graph and
                            * replays it (re-captured when a run of the batch finishes); not
                            * used together with NS_FLAG_TIMING.  Results are identical. */
@@ -209,6 +221,8 @@ typedef struct {
     double hrss_ms;         /* NS_FLAG_TIMING: summed HRSS kernel time (HIP events) */
     int64_t hrss_launches;
     double width;           /* slice width in use */
+    int64_t tune_launches;  /* NS_FLAG_AUTOTUNE: HRSS launches the tuner timed in this context
+                             * (0 when every shape came from the cache) */
 } ns_stats_t;
 
 /* Host arrays for state access (any pointer may be NULL to skip it). */
@@ -363,17 +377,26 @@ int32_t ns_num_runs(const ns_ctx *ctx);
 int32_t ns_chains_per_workgroup(const ns_ctx *ctx, int32_t run);
 
 /* NS_FLAG_AUTOTUNE's process-wide cache of tuned launch shapes, as a JSON file:
- * {"nss_tune": 1, "entries": [{"D", "lik", "mode", "upw", "rw", "chains", "C"}, ...]} (the
- * shape's padded dimension, likelihood, precision, fragment capacity, replacement and total
- * chains, and the chosen chains per workgroup).  ns_tune_save writes the cache to path;
- * ns_tune_load merges a file in the format ns_tune_save writes (its entries replace cached
- * ones of the same shape); contexts created afterwards with NS_FLAG_AUTOTUNE start with the
- * cached value.  *n (may be NULL) receives the number of cached entries afterwards.  Errors:
- * NS_EINVAL for a NULL path, a file that cannot be opened or written, or a file that is not
- * a tuning cache or holds a malformed entry (then nothing is merged); the message is in
- * ns_last_error(NULL).  Host only: no device is needed. */
+ * {"nss_tune": 2, "entries": [{"D", "lik", "mode", "upw", "rw", "chains", "planned", "C",
+ * "plan"}, ...]} (the group shape: padded dimension, likelihood, precision, fragment capacity,
+ * replacement, total chains, whether the plan kernel is allowed; the choice: chains per
+ * workgroup and tests per round, 0 meaning the 4-test kernel).  ns_tune_save writes the cache
+ * to path; ns_tune_load merges a file in the format ns_tune_save writes (its entries replace
+ * cached ones of the same shape); ns_tune_clear empties the cache; contexts created
+ * afterwards with NS_FLAG_AUTOTUNE start with the cached value.  *n (may be NULL) receives the
+ * number of cached entries afterwards (before, for ns_tune_clear).  Errors: NS_EINVAL for a
+ * NULL path, a file that cannot be opened or written, or a file that is not a tuning cache or
+ * holds a malformed entry (unknown shape values, extra keys, non-integer values: then nothing
+ * is merged); the message is in ns_last_error(NULL).  Host only: no device is needed. */
 ns_status ns_tune_save(const char *path, int32_t *n);
 ns_status ns_tune_load(const char *path, int32_t *n);
+ns_status ns_tune_clear(int32_t *n);
+
+/* The launch shape run `run`'s chains use now: chains per workgroup and tests planned per
+ * round (4 for the k_hrss kernel, 8 or 16 for the hypothesis-plan kernel, 1 for NS_LIK_GP).
+ * Either output may be NULL.  Errors: NS_EINVAL for a NULL context or a run out of range. */
+ns_status ns_launch_shape(const ns_ctx *ctx, int32_t run, int32_t *chains_per_wg,
+                          int32_t *plan_tests);
 
 /* ns_logz for every run: logz[r], logz_err[r], H[r] (any array may be NULL). */
 ns_status ns_logz_batch(ns_ctx *ctx, double *logz, double *logz_err, double *H);

@@ -7,8 +7,8 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libnss.so")
-SOURCES = ["nss_kernels.hip", "nss_gp.hip", "nss_post.hip", "nss_capi.hip"]
-HEADERS = ["nss_internal.hpp", "nss_rng.hpp", "nss_wave.hpp"]
+SOURCES = ["nss_kernels.hip", "nss_hrss_plan.hip", "nss_gp.hip", "nss_post.hip", "nss_capi.hip"]
+HEADERS = ["nss_internal.hpp", "nss_rng.hpp", "nss_tiles.hpp", "nss_wave.hpp"]
 ARCH = os.environ.get("NSS_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

@@ -32,18 +32,20 @@ struct RunHost {
 // capacity).
 struct Group {
     int D, lik, mode, upwT, rw;
+    bool plan_ok;   // 16-bit mixture chains that may use the hypothesis-plan kernel
+    int plan;       // tests a chain plans per round: 0 = the k_hrss kernel (up to 4), or 8 / 16
     std::vector<int> runs;
 };
 
-// Autotuning state of one group: candidate chains-per-workgroup values, their summed cost
-// (HRSS milliseconds per evaluation) and sample counts, and the candidate the next tuning
-// iteration uses.
+// A launch shape of a group's HRSS kernel: chains per workgroup and planned tests per round.
+struct Shape {
+    int C, plan;
+};
+
+// Autotuning state of one group: the candidate shapes, and whether the group still has to be
+// tuned (at its next iteration).
 struct GroupTune {
-    std::vector<int> cand;
-    std::vector<double> cost;
-    std::vector<int> samples;
-    int turn = 0;
-    int initial = 1;   // the chains-per-workgroup rule's value, kept if nothing is measured
+    std::vector<Shape> cand;
     bool done = true;
 };
 
@@ -82,8 +84,12 @@ struct ns_ctx {
     // NS_FLAG_AUTOTUNE: chains per HRSS workgroup chosen per group by timing the candidates on
     // the run's own iterations (per-group events around the HRSS launch, cost per evaluation)
     int autotune = 0;
-    std::vector<GroupTune> tune;                                // per group
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> tune_ev;     // per group, tuning iterations
+    std::vector<GroupTune> tune;     // per group
+    long long tune_launches = 0;     // HRSS launches timed by the tuner
+    // per run: the state an HRSS launch changes (live points, logL, counters), saved before the
+    // tuner's candidate launches and restored after each (allocated on first use)
+    std::vector<double *> snap_x, snap_l;
+    std::vector<unsigned long long *> snap_c;
     // ns_geom_uncertainty's device buffer (outputs and partial results), grown on demand
     void *geom_buf = nullptr;
     size_t geom_bytes = 0;
@@ -95,6 +101,7 @@ struct ns_ctx {
 };
 
 constexpr int kGraphIters = 16;   // iterations per host synchronisation in ns_run
+constexpr int kDefaultPlan = 16;  // tests per round of the 16-bit mixture chains without tuning
 
 // Workspace of ns_geom_uncertainty_noalloc: a fixed device array, one copy per GPU, held until
 // the process ends.  Host code never passes the array's name to a kernel or a copy (on the host
@@ -543,7 +550,8 @@ static ns_status device_error(ns_ctx *ctx, const char *what, hipError_t e)
     return e == hipErrorNotSupported ? NS_EUNSUPPORTED : NS_EDEVICE;
 }
 
-static ns_status enqueue_iteration(ns_ctx *ctx)
+// The part of an iteration before the chains: SMC reweighting, whitening, directions.
+static ns_status enqueue_pre(ns_ctx *ctx)
 {
     hipError_t e;
     if (ctx->smc) {   // next temperature, evidence increment, resampling
@@ -556,29 +564,49 @@ static ns_status enqueue_iteration(ns_ctx *ctx)
         e = launch_dirs(ctx->L_dirs[di], kDims[di], ctx->stream);
         if (e != hipSuccess) return device_error(ctx, "direction launch", e);
     }
+    return NS_OK;
+}
+
+// The chains of group g.
+static ns_status enqueue_hrss_group(ns_ctx *ctx, size_t g)
+{
+    const Group &G = ctx->groups[g];
+    const hipError_t e =
+        G.lik == LIK_GP ? launch_hrss_gp(ctx->L_hrss[g], G.mode, ctx->stream)
+        : G.rw          ? launch_rw(ctx->L_hrss[g], G.D, G.lik, G.mode, G.upwT, ctx->stream)
+        : G.plan        ? launch_hrss_plan(ctx->L_hrss[g], G.D, G.mode, G.upwT, G.plan,
+                                           ctx->stream)
+                        : launch_hrss(ctx->L_hrss[g], G.D, G.lik, G.mode, G.upwT, ctx->stream);
+    if (e != hipSuccess) return device_error(ctx, "HRSS launch", e);
+    return NS_OK;
+}
+
+// The chains of every group (timed under NS_FLAG_TIMING), then delete-k and evidence.
+static ns_status enqueue_rest(ns_ctx *ctx)
+{
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (ctx->timing) {
         CK(hipEventCreate(&e0));
         CK(hipEventCreate(&e1));
         CK(hipEventRecord(e0, ctx->stream));
     }
-    const bool tuning = !ctx->tune_ev.empty();
-    for (size_t g = 0; g < ctx->groups.size(); ++g) {
-        const Group &G = ctx->groups[g];
-        if (tuning) CK(hipEventRecord(ctx->tune_ev[g].first, ctx->stream));
-        e = G.lik == LIK_GP ? launch_hrss_gp(ctx->L_hrss[g], G.mode, ctx->stream)
-            : G.rw          ? launch_rw(ctx->L_hrss[g], G.D, G.lik, G.mode, G.upwT, ctx->stream)
-                            : launch_hrss(ctx->L_hrss[g], G.D, G.lik, G.mode, G.upwT, ctx->stream);
-        if (e != hipSuccess) return device_error(ctx, "HRSS launch", e);
-        if (tuning) CK(hipEventRecord(ctx->tune_ev[g].second, ctx->stream));
-    }
+    ns_status st;
+    for (size_t g = 0; g < ctx->groups.size(); ++g)
+        if ((st = enqueue_hrss_group(ctx, g)) != NS_OK) return st;
     if (e1) {
         CK(hipEventRecord(e1, ctx->stream));
         ctx->events.emplace_back(e0, e1);
     }
-    e = ctx->smc ? launch_smc(ctx->L_one, 2, ctx->stream) : launch_select(ctx->L_one, 1, ctx->stream);
+    hipError_t e = ctx->smc ? launch_smc(ctx->L_one, 2, ctx->stream)
+                            : launch_select(ctx->L_one, 1, ctx->stream);
     if (e != hipSuccess) return device_error(ctx, "select launch", e);
     return NS_OK;
+}
+
+static ns_status enqueue_iteration(ns_ctx *ctx)
+{
+    ns_status st = enqueue_pre(ctx);
+    return st != NS_OK ? st : enqueue_rest(ctx);
 }
 
 static ns_status collect_events(ns_ctx *ctx)
@@ -598,29 +626,34 @@ static ns_status collect_events(ns_ctx *ctx)
 }
 
 // ------------------------------------------------------------------------------------------
-// NS_FLAG_AUTOTUNE: chains per HRSS workgroup.  The decisions and arithmetic of a chain do not
-// depend on which workgroup runs it, so the candidates are timed on the run's own iterations
-// without changing its trajectory.
+// NS_FLAG_AUTOTUNE: the launch shape of each group's HRSS kernel (chains per workgroup, and for
+// the 16-bit mixture chains the tests planned per round).  A chain's decisions and arithmetic
+// do not depend on the shape, so every candidate is timed on the same iteration: after the
+// whitening and directions, the state the chains change is saved, each candidate's HRSS
+// launch is timed and the state restored, kTuneReps times over; the group keeps the fastest
+// and the iteration then runs with it.  The choice is cached per group shape in this process.
 // ------------------------------------------------------------------------------------------
-constexpr int kTuneReps = 2;   // timed iterations per candidate
+constexpr int kTuneReps = 2;   // timed launches per candidate (the minimum counts)
 
 static std::mutex g_tune_mu;
-static std::map<std::vector<long long>, int> g_tuned;   // shape of a group -> chains per WG
+// group shape -> (chains per workgroup, planned tests per round)
+static std::map<std::vector<long long>, Shape> g_tuned;
 
 static std::vector<long long> tune_key(const ns_ctx *ctx, const Group &G)
 {
     long long chains = 0;
     for (int r : G.runs) chains += ctx->runs[r].k;
-    return {G.D, G.lik, G.mode, G.upwT, G.rw, chains};
+    return {G.D, G.lik, G.mode, G.upwT, G.rw, chains, G.plan_ok ? 1 : 0};
 }
 
-// Chains per workgroup of group g's runs, on the host and in the device descriptors (slot n
-// mirrors run 0).  The caller rebuilds the launches.
-static ns_status set_group_chains(ns_ctx *ctx, size_t g, int C)
+// Launch shape of group g's runs, on the host and in the device descriptors (slot n mirrors
+// run 0).  The caller rebuilds the launches.
+static ns_status set_group_shape(ns_ctx *ctx, size_t g, Shape sh)
 {
     CK(hipStreamSynchronize(ctx->stream));
+    ctx->groups[g].plan = sh.plan;
     for (int r : ctx->groups[g].runs) {
-        ctx->runs[r].R.C = C;
+        ctx->runs[r].R.C = sh.C;
         CK(hipMemcpy(ctx->dR + r, &ctx->runs[r].R, sizeof(DevRun), hipMemcpyHostToDevice));
         if (r == 0)
             CK(hipMemcpy(ctx->dR + ctx->n, &ctx->runs[0].R, sizeof(DevRun), hipMemcpyHostToDevice));
@@ -635,86 +668,80 @@ static bool tuning_pending(const ns_ctx *ctx)
     return false;
 }
 
-static void destroy_tune_events(ns_ctx *ctx)
+// save (dir = 0) or restore (dir = 1) the state group g's chains change
+static ns_status group_state(ns_ctx *ctx, size_t g, int dir)
 {
-    for (auto &pr : ctx->tune_ev) {
-        if (pr.first) (void)hipEventDestroy(pr.first);
-        if (pr.second) (void)hipEventDestroy(pr.second);
+    for (int r : ctx->groups[g].runs) {
+        const RunHost &rh = ctx->runs[r];
+        const size_t nx = (size_t)rh.D * rh.m_pad, nl = (size_t)rh.m;
+        ns_status st;
+        if (!ctx->snap_x[r]) {
+            if ((st = dalloc(ctx, &ctx->snap_x[r], nx)) || (st = dalloc(ctx, &ctx->snap_l[r], nl)) ||
+                (st = dalloc(ctx, &ctx->snap_c[r], 16)))
+                return st;
+        }
+        double *x = rh.R.X, *lg = rh.R.logL;
+        unsigned long long *c = rh.R.ctr;
+        if (dir == 0) {
+            CK(hipMemcpyAsync(ctx->snap_x[r], x, nx * 8, hipMemcpyDeviceToDevice, ctx->stream));
+            CK(hipMemcpyAsync(ctx->snap_l[r], lg, nl * 8, hipMemcpyDeviceToDevice, ctx->stream));
+            CK(hipMemcpyAsync(ctx->snap_c[r], c, 16 * 8, hipMemcpyDeviceToDevice, ctx->stream));
+        } else {
+            CK(hipMemcpyAsync(x, ctx->snap_x[r], nx * 8, hipMemcpyDeviceToDevice, ctx->stream));
+            CK(hipMemcpyAsync(lg, ctx->snap_l[r], nl * 8, hipMemcpyDeviceToDevice, ctx->stream));
+            CK(hipMemcpyAsync(c, ctx->snap_c[r], 16 * 8, hipMemcpyDeviceToDevice, ctx->stream));
+        }
     }
-    ctx->tune_ev.clear();
+    return NS_OK;
 }
 
-static ns_status enqueue_iteration(ns_ctx *ctx);
-
-// One iteration with every group still tuning on its next candidate; the group's HRSS time per
-// evaluation in that iteration is charged to the candidate.  Once every candidate has
-// kTuneReps samples the group keeps the cheapest (the earlier candidate on a tie) and the
-// choice is cached for later contexts of the same shape in this process.
+// One iteration in which every group still to be tuned times its candidates on the same
+// state, keeps the fastest, and the iteration completes with the chosen shapes.
 static ns_status tune_iteration(ns_ctx *ctx)
 {
-    const size_t ng = ctx->groups.size();
-    std::vector<int> used(ng, -1);
-    ns_status st;
-    for (size_t g = 0; g < ng; ++g) {
+    ns_status st = enqueue_pre(ctx);
+    if (st != NS_OK) return st;
+    for (size_t g = 0; g < ctx->groups.size(); ++g) {
         GroupTune &t = ctx->tune[g];
         if (t.done) continue;
-        used[g] = t.turn % (int)t.cand.size();
-        if ((st = set_group_chains(ctx, g, t.cand[used[g]])) != NS_OK) return st;
+        if ((st = group_state(ctx, g, 0)) != NS_OK) return st;
+        const size_t nc = t.cand.size();
+        std::vector<double> best(nc, 1e300);
+        for (int rep = 0; rep < kTuneReps; ++rep) {
+            for (size_t ci = 0; ci < nc; ++ci) {
+                if ((st = set_group_shape(ctx, g, t.cand[ci])) != NS_OK) return st;
+                if ((st = build_maps(ctx, ctx->mapped_active)) != NS_OK) return st;
+                if ((st = group_state(ctx, g, 1)) != NS_OK) return st;
+                hipEvent_t e0 = nullptr, e1 = nullptr;
+                if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+                    if (e0) (void)hipEventDestroy(e0);
+                    return fail(ctx, NS_EDEVICE, "autotune: event creation failed");
+                }
+                float ms = 0.f;
+                const bool ok = hipEventRecord(e0, ctx->stream) == hipSuccess &&
+                                (st = enqueue_hrss_group(ctx, g)) == NS_OK &&
+                                hipEventRecord(e1, ctx->stream) == hipSuccess &&
+                                hipEventSynchronize(e1) == hipSuccess &&
+                                hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+                (void)hipEventDestroy(e0);
+                (void)hipEventDestroy(e1);
+                if (st != NS_OK) return st;
+                if (!ok) return fail(ctx, NS_EDEVICE, "autotune: event timing failed");
+                ctx->tune_launches += 1;
+                if (ms < best[ci]) best[ci] = ms;
+            }
+        }
+        size_t bi = 0;
+        for (size_t ci = 1; ci < nc; ++ci)
+            if (best[ci] < best[bi]) bi = ci;
+        if ((st = set_group_shape(ctx, g, t.cand[bi])) != NS_OK) return st;
+        if ((st = group_state(ctx, g, 1)) != NS_OK) return st;
+        t.done = true;
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tuned[tune_key(ctx, ctx->groups[g])] = t.cand[bi];
     }
     if ((st = build_maps(ctx, ctx->mapped_active)) != NS_OK) return st;
-    const size_t nc = (size_t)ctx->n * 16;
-    std::vector<unsigned long long> c0(nc), c1(nc);
-    CK(hipMemcpyAsync(c0.data(), ctx->d_ctr, nc * 8, hipMemcpyDeviceToHost, ctx->stream));
-    CK(hipStreamSynchronize(ctx->stream));
-    ctx->tune_ev.assign(ng, std::make_pair((hipEvent_t) nullptr, (hipEvent_t) nullptr));
-    for (auto &pr : ctx->tune_ev) {
-        if (hipEventCreate(&pr.first) != hipSuccess || hipEventCreate(&pr.second) != hipSuccess) {
-            destroy_tune_events(ctx);
-            return fail(ctx, NS_EDEVICE, "autotune: event creation failed");
-        }
-    }
-    st = enqueue_iteration(ctx);
-    if (st == NS_OK && (hipMemcpyAsync(c1.data(), ctx->d_ctr, nc * 8, hipMemcpyDeviceToHost,
-                                       ctx->stream) != hipSuccess ||
-                        hipStreamSynchronize(ctx->stream) != hipSuccess))
-        st = fail(ctx, NS_EDEVICE, "autotune: counter read failed");
-    std::vector<float> ms(ng, 0.f);
-    for (size_t g = 0; g < ng && st == NS_OK; ++g)
-        if (used[g] >= 0 &&
-            hipEventElapsedTime(&ms[g], ctx->tune_ev[g].first, ctx->tune_ev[g].second) != hipSuccess)
-            st = fail(ctx, NS_EDEVICE, "autotune: event timing failed");
-    destroy_tune_events(ctx);
-    if (st != NS_OK) return st;
-    bool settled = false;
-    for (size_t g = 0; g < ng; ++g) {
-        if (used[g] < 0) continue;
-        GroupTune &t = ctx->tune[g];
-        unsigned long long ev = 0;
-        for (int r : ctx->groups[g].runs) ev += c1[(size_t)16 * r] - c0[(size_t)16 * r];
-        if (ev > 0) {
-            t.cost[used[g]] += (double)ms[g] / (double)ev;
-            t.samples[used[g]] += 1;
-        }
-        t.turn += 1;
-        bool all = true;
-        for (int c : t.samples) all = all && c >= kTuneReps;
-        // a group whose runs stop evaluating (all finished) keeps its heuristic choice
-        if (!all && t.turn < 4 * kTuneReps * (int)t.cand.size()) continue;
-        int best = -1;
-        for (size_t i = 0; i < t.cand.size(); ++i)
-            if (t.samples[i] > 0 &&
-                (best < 0 || t.cost[i] / t.samples[i] < t.cost[best] / t.samples[best]))
-                best = (int)i;
-        const int C = best >= 0 ? t.cand[best] : t.initial;
-        if ((st = set_group_chains(ctx, g, C)) != NS_OK) return st;
-        t.done = true;
-        settled = true;
-        if (best >= 0) {
-            std::lock_guard<std::mutex> lk(g_tune_mu);
-            g_tuned[tune_key(ctx, ctx->groups[g])] = C;
-        }
-    }
-    return settled ? build_maps(ctx, ctx->mapped_active) : NS_OK;
+    return enqueue_rest(ctx);
 }
 
 // Prior draws, FP64 evaluation and first delete-k of every run; resets every run counter.
@@ -1011,20 +1038,31 @@ extern "C" ns_status ns_init_batch(int32_t n_runs, const ns_prior *priors,
         rh.upw = (rh.mode == NS_FP64 || rh.lik == LIK_GP) ? 1 : upw_template(rh.D, upw_for(rh.P));
         rh.P = problem_for_mode(rh, rh.mode);
         if ((st = alloc_run(ctx, r)) != NS_OK) return bail(st);
-        // group by compiled HRSS kernel
+        // group by compiled HRSS kernel; the 16-bit mixture chains may plan 8 or 16 tests per
+        // round unless NS_FLAG_SHALLOW_PLAN keeps them on the 4-test kernel
+        const bool m16 = rh.mode == NS_MIXED_BF16 || rh.mode == NS_MIXED_FP16 ||
+                         rh.mode == NS_MIXED_BF16X3 || rh.mode == NS_MIXED_FP16X3;
+        const bool plan_ok = m16 && rh.lik == LIK_MIXTURE && !rh.R.rw && !rh.R.smc &&
+                             rh.D <= 128 && rh.R.dirbuf &&
+                             !(rh.cfg.flags & NS_FLAG_SHALLOW_PLAN);
+        const int plan0 = !plan_ok ? 0 : (rh.cfg.flags & NS_FLAG_PLAN8) ? 8 : kDefaultPlan;
         int g = -1;
         for (size_t i = 0; i < ctx->groups.size(); ++i) {
             const Group &G = ctx->groups[i];
             if (G.D == rh.D && G.lik == rh.lik && G.mode == rh.mode && G.upwT == rh.upw &&
-                G.rw == rh.R.rw)
+                G.rw == rh.R.rw && G.plan_ok == plan_ok && G.plan == plan0)
                 g = (int)i;
         }
         if (g < 0) {
-            ctx->groups.push_back(Group{rh.D, rh.lik, rh.mode, rh.upw, rh.R.rw, {}});
+            ctx->groups.push_back(Group{rh.D, rh.lik, rh.mode, rh.upw, rh.R.rw, plan_ok, plan0,
+                                        {}});
             g = (int)ctx->groups.size() - 1;
         }
         ctx->groups[g].runs.push_back(r);
     }
+    ctx->snap_x.assign(n, nullptr);
+    ctx->snap_l.assign(n, nullptr);
+    ctx->snap_c.assign(n, nullptr);
     // chains per HRSS workgroup: enough workgroups to cover the CUs, full 16-row tiles beyond
     for (const Group &G : ctx->groups) {
         long long chains = 0;
@@ -1040,21 +1078,22 @@ extern "C" ns_status ns_init_batch(int32_t n_runs, const ns_prior *priors,
     for (size_t g = 0; g < ctx->groups.size() && ctx->autotune; ++g) {
         const Group &G = ctx->groups[g];
         if (G.lik == LIK_GP) continue;
-        int cached = 0;
+        Shape cached{0, 0};
         {
             std::lock_guard<std::mutex> lk(g_tune_mu);
             auto it = g_tuned.find(tune_key(ctx, G));
             if (it != g_tuned.end()) cached = it->second;
         }
-        if (cached > 0) {
-            for (int r : G.runs) ctx->runs[r].R.C = cached;
+        if (cached.C > 0) {
+            for (int r : G.runs) ctx->runs[r].R.C = cached.C;
+            ctx->groups[g].plan = cached.plan;
             continue;
         }
         GroupTune &t = ctx->tune[g];
-        for (int c = 1; c <= kMaxChainsPerWG; ++c) t.cand.push_back(c);
-        t.cost.assign(t.cand.size(), 0.0);
-        t.samples.assign(t.cand.size(), 0);
-        t.initial = ctx->runs[G.runs[0]].R.C;
+        for (int plan : {0, 8, 16}) {
+            if (plan && !G.plan_ok) continue;
+            for (int c = 1; c <= kMaxChainsPerWG; ++c) t.cand.push_back(Shape{c, plan});
+        }
         t.done = false;
     }
     std::vector<DevProblem> hp(n + 1);
@@ -1212,21 +1251,23 @@ extern "C" ns_status ns_run(ns_ctx *ctx, int32_t max_iter, int32_t *iters)
     return NS_OK;
 }
 
-// The tuning cache as JSON: {"nss_tune": 1, "entries": [{"D": .., "lik": .., "mode": ..,
-// "upw": .., "rw": .., "chains": .., "C": ..}, ...]}, one entry per line.
+// The tuning cache as JSON: {"nss_tune": 2, "entries": [{"D": .., "lik": .., "mode": ..,
+// "upw": .., "rw": .., "chains": .., "planned": .., "C": .., "plan": ..}, ...]}, one entry per
+// line ("planned": whether the group may use the hypothesis-plan kernel).
 extern "C" ns_status ns_tune_save(const char *path, int32_t *n)
 {
     if (!path) return NS_EINVAL;
     std::lock_guard<std::mutex> lk(g_tune_mu);
     FILE *f = fopen(path, "w");
-    if (!f) return fail(nullptr, NS_EINVAL, std::string("cannot open ") + path);
-    fprintf(f, "{\"nss_tune\": 1, \"entries\": [");
+    if (!f) return fail(nullptr, NS_EINVAL, std::string("cannot write ") + path);
+    fprintf(f, "{\"nss_tune\": 2, \"entries\": [");
     size_t i = 0;
     for (const auto &kv : g_tuned) {
         const std::vector<long long> &k = kv.first;
         fprintf(f, "%s\n  {\"D\": %lld, \"lik\": %lld, \"mode\": %lld, \"upw\": %lld, "
-                   "\"rw\": %lld, \"chains\": %lld, \"C\": %d}",
-                i++ ? "," : "", k[0], k[1], k[2], k[3], k[4], k[5], kv.second);
+                   "\"rw\": %lld, \"chains\": %lld, \"planned\": %lld, \"C\": %d, \"plan\": %d}",
+                i++ ? "," : "", k[0], k[1], k[2], k[3], k[4], k[5], k[6], kv.second.C,
+                kv.second.plan);
     }
     fprintf(f, "\n]}\n");
     const bool ok = fclose(f) == 0;
@@ -1244,26 +1285,53 @@ extern "C" ns_status ns_tune_load(const char *path, int32_t *n)
     size_t got;
     while ((got = fread(buf, 1, sizeof(buf), f)) > 0) txt.append(buf, got);
     fclose(f);
-    if (txt.find("\"nss_tune\": 1") == std::string::npos)
+    if (txt.find("\"nss_tune\": 2") == std::string::npos)
         return fail(nullptr, NS_EINVAL, std::string(path) + ": not a tuning cache");
-    std::map<std::vector<long long>, int> add;
+    std::map<std::vector<long long>, Shape> add;
     size_t pos = txt.find("\"entries\"");
     if (pos == std::string::npos)
         return fail(nullptr, NS_EINVAL, std::string(path) + ": not a tuning cache");
     for (; (pos = txt.find('{', pos)) != std::string::npos; ++pos) {
-        long long D, lik, mode, upw, rw, chains;
-        int C;
+        long long D, lik, mode, upw, rw, chains, planned;
+        int C, plan, end = -1;
         if (sscanf(txt.c_str() + pos,
                    "{\"D\": %lld, \"lik\": %lld, \"mode\": %lld, \"upw\": %lld, \"rw\": %lld, "
-                   "\"chains\": %lld, \"C\": %d}",
-                   &D, &lik, &mode, &upw, &rw, &chains, &C) != 7 ||
-            C < 1 || C > kMaxChainsPerWG || chains < 1 || upw < 1 || (rw != 0 && rw != 1))
+                   "\"chains\": %lld, \"planned\": %lld, \"C\": %d, \"plan\": %d}%n",
+                   &D, &lik, &mode, &upw, &rw, &chains, &planned, &C, &plan, &end) != 9 ||
+            end < 0 || C < 1 || C > kMaxChainsPerWG || chains < 1 || (rw != 0 && rw != 1) ||
+            (D != 32 && D != 64 && D != 128 && D != 320) || lik < LIK_MIXTURE || lik > LIK_RG ||
+            mode < NS_FP64 || mode > NS_MIXED_FP32 ||
+            ((mode == NS_FP64 || lik == LIK_GP) ? upw != 1
+                                                : upw_template((int)D, (int)upw) != upw) ||
+            (planned != 0 && planned != 1) || (plan != 0 && plan != 8 && plan != 16) ||
+            (plan != 0 && !planned))
             return fail(nullptr, NS_EINVAL, std::string(path) + ": malformed entry");
-        add[{D, lik, mode, upw, rw, chains}] = C;
+        add[{D, lik, mode, upw, rw, chains, planned}] = Shape{C, plan};
     }
     std::lock_guard<std::mutex> lk(g_tune_mu);
     for (const auto &kv : add) g_tuned[kv.first] = kv.second;
     if (n) *n = (int32_t)g_tuned.size();
+    return NS_OK;
+}
+
+extern "C" ns_status ns_tune_clear(int32_t *n)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (n) *n = (int32_t)g_tuned.size();
+    g_tuned.clear();
+    return NS_OK;
+}
+
+extern "C" ns_status ns_launch_shape(const ns_ctx *ctx, int32_t run, int32_t *chains_per_wg,
+                                     int32_t *plan_tests)
+{
+    if (!ctx || run < 0 || run >= ctx->n) return NS_EINVAL;
+    int plan = 0;
+    for (const Group &G : ctx->groups)
+        for (int r : G.runs)
+            if (r == run) plan = G.plan;
+    if (chains_per_wg) *chains_per_wg = ctx->runs[run].R.C;
+    if (plan_tests) *plan_tests = plan ? plan : (ctx->runs[run].lik == LIK_GP ? 1 : kSlots);
     return NS_OK;
 }
 
@@ -1344,6 +1412,7 @@ extern "C" ns_status ns_stats_run(ns_ctx *ctx, int32_t run, ns_stats_t *o)
     o->hrss_ms = ctx->hrss_ms;
     o->hrss_launches = ctx->hrss_launches;
     o->width = ctx->runs[run].R.width;
+    o->tune_launches = ctx->tune_launches;
     return NS_OK;
 }
 

@@ -10,6 +10,8 @@ constexpr int kWG = 256;         // threads per chain workgroup (4 waves of 64)
 constexpr int kRows = 16;        // candidate rows per evaluation tile (one 16-row MFMA block)
 constexpr int kSlots = 4;        // candidate rows per chain per round (4 chains x 4 = 16 rows)
 constexpr int kMaxChainsPerWG = 4;
+constexpr int kStepU = 8;        // per chain step in the uniform buffer: tL0, uh, shrink uniforms
+constexpr int kStepShrinkU = kStepU - 2;
 constexpr int kSelectThreads = 1024;
 constexpr int kMaxLive = 8192;
 
@@ -110,6 +112,10 @@ hipError_t launch_smc(const Launch &L, int op, hipStream_t s);
 hipError_t launch_cov(const Launch &cov, const Launch &one, int D, hipStream_t s);
 hipError_t launch_dirs(const Launch &L, int D, hipStream_t s);
 hipError_t launch_hrss(const Launch &L, int D, int lik, int mode, int upw, hipStream_t s);
+// the mixture chains in a 16-bit mode with S-test hypothesis plans (nss_hrss_plan.hip),
+// S = 8 or 16; needs the direction buffer
+hipError_t launch_hrss_plan(const Launch &L, int D, int mode, int upw, int S, hipStream_t s);
+size_t hrss_plan_lds_bytes(int D, int K, int S);
 // the random-walk replacement kernel (same grid and tile evaluators as the HRSS kernel)
 hipError_t launch_rw(const Launch &L, int D, int lik, int mode, int upw, hipStream_t s);
 hipError_t launch_logz(const Launch &L, hipStream_t s);

@@ -29,6 +29,8 @@ NS_FP64, NS_MIXED_BF16, NS_MIXED_FP16, NS_MIXED_BF16X3, NS_MIXED_FP16X3, NS_MIXE
 NS_FLAG_TRACE, NS_FLAG_TIMING, NS_FLAG_INLINE_DIRECTIONS, NS_FLAG_GRAPH = 1, 2, 4, 8
 NS_FLAG_RECORD_POINTS = 16
 NS_FLAG_AUTOTUNE = 32
+NS_FLAG_SHALLOW_PLAN = 64
+NS_FLAG_PLAN8 = 128
 PRECISIONS = {"fp64": NS_FP64, "bf16": NS_MIXED_BF16, "fp16": NS_MIXED_FP16,
               "bf16x3": NS_MIXED_BF16X3, "fp16x3": NS_MIXED_FP16X3, "fp32": NS_MIXED_FP32}
 # guard band of each mixed mode: (rel, abs) as set by the library
@@ -65,7 +67,7 @@ class ns_stats_t(C.Structure):
                 ("shrink_caps", C.c_int64), ("nonfinite", C.c_int64), ("rechecks", C.c_int64),
                 ("band_violations", C.c_int64), ("whiten_fallbacks", C.c_int64),
                 ("n_dead", C.c_int64), ("hrss_ms", C.c_double), ("hrss_launches", C.c_int64),
-                ("width", C.c_double)]
+                ("width", C.c_double), ("tune_launches", C.c_int64)]
 
 
 class ns_state_view(C.Structure):
@@ -141,6 +143,10 @@ def load(build_if_missing: bool = True):
     for fn in (L.ns_tune_save, L.ns_tune_load):
         fn.restype = C.c_int
         fn.argtypes = [C.c_char_p, _i32]
+    L.ns_tune_clear.restype = C.c_int
+    L.ns_tune_clear.argtypes = [_i32]
+    L.ns_launch_shape.restype = C.c_int
+    L.ns_launch_shape.argtypes = [vp, C.c_int32, _i32, _i32]
     L.ns_logz_batch.restype = C.c_int
     L.ns_logz_batch.argtypes = [vp, _d, _d, _d]
     L.ns_stats_run.restype = C.c_int
@@ -254,6 +260,19 @@ def ns_tune_load(path):
     return st, n.value
 
 
+def ns_tune_clear():
+    n = C.c_int32(0)
+    st = load().ns_tune_clear(C.byref(n))
+    return st, n.value
+
+
+def ns_launch_shape(ctx, run=0):
+    """Returns (status, chains per workgroup, tests planned per round)."""
+    c, p = C.c_int32(0), C.c_int32(0)
+    st = load().ns_launch_shape(ctx, int(run), C.byref(c), C.byref(p))
+    return st, c.value, p.value
+
+
 def ns_logz_batch(ctx):
     n = ns_num_runs(ctx)
     z, e, h = np.zeros(n), np.zeros(n), np.zeros(n)
@@ -320,7 +339,8 @@ def current_stream():
 def make_config(m, k, p, width=0.0, seed=0, run_id=0, precision="fp64", term_frac=1e-3,
                 stepout_cap=10, shrink_cap=100, max_iter=100000, trace=False, timing=False,
                 inline_directions=False, graph=False, replacement="hrss", outer="ns",
-                ess_frac=0.5, record_points=False, autotune=False) -> ns_config:
+                ess_frac=0.5, record_points=False, autotune=False,
+                shallow_plan=False, plan8=False) -> ns_config:
     cfg = ns_config_default()
     cfg.n_live, cfg.k, cfg.chain_len = int(m), int(k), int(p)
     cfg.width = float(width)
@@ -333,7 +353,9 @@ def make_config(m, k, p, width=0.0, seed=0, run_id=0, precision="fp64", term_fra
                  | (NS_FLAG_INLINE_DIRECTIONS if inline_directions else 0)
                  | (NS_FLAG_GRAPH if graph else 0)
                  | (NS_FLAG_RECORD_POINTS if record_points else 0)
-                 | (NS_FLAG_AUTOTUNE if autotune else 0))
+                 | (NS_FLAG_AUTOTUNE if autotune else 0)
+                 | (NS_FLAG_SHALLOW_PLAN if shallow_plan else 0)
+                 | (NS_FLAG_PLAN8 if plan8 else 0))
     cfg.replacement = REPLACEMENTS[replacement] if isinstance(replacement, str) else int(replacement)
     cfg.outer = OUTERS[outer] if isinstance(outer, str) else int(outer)
     cfg.ess_frac = float(ess_frac)
@@ -412,7 +434,7 @@ class NSRun:
                  precision="fp64", term_frac=1e-3, stepout_cap=10, shrink_cap=100,
                  max_iter=100000, trace=False, timing=False, inline_directions=False,
                  graph=False, stream="torch", replacement="hrss", outer="ns", ess_frac=0.5,
-                 record_points=False, autotune=False):
+                 record_points=False, autotune=False, shallow_plan=False, plan8=False):
         self.prob = prob
         self.d = int(prob["d"])
         self.m = int(m or prob["m"])
@@ -423,7 +445,8 @@ class NSRun:
         pr, en, self._keep = make_structs(prob)
         cfg = make_config(self.m, self.k, self.p, width, seed, run_id, precision, term_frac,
                           stepout_cap, shrink_cap, max_iter, trace, timing, inline_directions,
-                          graph, replacement, outer, ess_frac, record_points, autotune)
+                          graph, replacement, outer, ess_frac, record_points, autotune,
+                          shallow_plan, plan8)
         self.cfg = cfg
         s = current_stream() if stream == "torch" else stream
         st, self.ctx = ns_init(pr, en, cfg, s)
@@ -442,6 +465,12 @@ class NSRun:
 
     def chains_per_workgroup(self) -> int:
         return ns_chains_per_workgroup(self.ctx, 0)
+
+    def launch_shape(self):
+        """(chains per workgroup, tests planned per round) of the run's chains."""
+        st, c, p = ns_launch_shape(self.ctx, 0)
+        _check(st, self.ctx)
+        return c, p
 
     def step(self) -> bool:
         st, done = ns_step(self.ctx)

@@ -155,27 +155,35 @@ def test_invalid_smc_arguments(N):
 
 def test_tune_cache_json_round_trip(N, tmp_path):
     """The autotuner's cache file (host only): a file in the saved format merges into the
-    cache and is written back with the same entries; a malformed file is refused whole."""
+    cache and is written back with the same entries; a malformed file is refused whole; the
+    cache can be emptied."""
     import json
+    assert N.ns_tune_clear()[0] == N.NS_OK
     src = tmp_path / "tune.json"
-    entries = [dict(D=64, lik=1, mode=3, upw=8, rw=0, chains=1000, C=4),
-               dict(D=32, lik=2, mode=0, upw=1, rw=1, chains=77, C=2)]
+    entries = [dict(D=64, lik=1, mode=3, upw=8, rw=0, chains=1000, planned=1, C=4, plan=16),
+               dict(D=32, lik=2, mode=0, upw=1, rw=1, chains=77, planned=0, C=2, plan=0)]
     body = ",".join("\n  " + json.dumps(e) for e in entries)
-    src.write_text('{"nss_tune": 1, "entries": [' + body + "\n]}\n")
+    src.write_text('{"nss_tune": 2, "entries": [' + body + "\n]}\n")
     st, n = N.ns_tune_load(src)
-    assert st == N.NS_OK and n >= 2
+    assert st == N.NS_OK and n == 2
     out = tmp_path / "out.json"
     st, n2 = N.ns_tune_save(out)
     assert st == N.NS_OK and n2 == n
     saved = json.loads(out.read_text())
-    assert saved["nss_tune"] == 1 and len(saved["entries"]) == n
+    assert saved["nss_tune"] == 2 and len(saved["entries"]) == n
     for e in entries:
         assert e in saved["entries"]
     bad = tmp_path / "bad.json"
-    bad.write_text('{"nss_tune": 1, "entries": [{"D": 64, "lik": 1, "mode": 3, "upw": 8, '
-                   '"rw": 0, "chains": 1000, "C": 9}]}')
-    assert N.ns_tune_load(bad)[0] == N.NS_EINVAL
+    good = entries[0]
+    for e in (dict(good, C=9), dict(good, C=3.7), dict(good, extra=1), dict(good, D=48),
+              dict(good, upw=5), dict(good, plan=12), dict(good, mode=9),
+              dict(good, planned=0, plan=16), dict(good, lik=7)):
+        bad.write_text('{"nss_tune": 2, "entries": [' + json.dumps(e) + "]}")
+        assert N.ns_tune_load(bad)[0] == N.NS_EINVAL, e
     assert N.ns_tune_load(tmp_path / "missing.json")[0] == N.NS_EINVAL
     assert N.ns_tune_load(None)[0] == N.NS_EINVAL
     st, n3 = N.ns_tune_save(tmp_path / "again.json")
     assert st == N.NS_OK and n3 == n
+    st, n4 = N.ns_tune_clear()
+    assert st == N.NS_OK and n4 == n
+    assert N.ns_tune_save(tmp_path / "empty.json") == (N.NS_OK, 0)

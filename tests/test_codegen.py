@@ -51,7 +51,8 @@ def test_scanner_flags_the_pattern():
     assert suspicious_selects(good) == []
 
 
-@pytest.mark.parametrize("src", ["nss_kernels.hip", "nss_gp.hip", "nss_post.hip"])
+@pytest.mark.parametrize("src", ["nss_kernels.hip", "nss_hrss_plan.hip", "nss_gp.hip",
+                                 "nss_post.hip"])
 def test_no_select_on_stale_condition_code(src, tmp_path):
     out = tmp_path / "k.s"
     cmd = ["hipcc", "-O3", "-std=c++17", "--offload-arch=gfx950", "-Xclang", "-target-feature",

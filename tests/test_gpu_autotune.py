@@ -1,9 +1,12 @@
-"""NS_FLAG_AUTOTUNE: the chains per HRSS workgroup chosen by timing.
+"""NS_FLAG_AUTOTUNE: the launch shape of each kernel group's chains chosen by timing (chains
+per workgroup 1..4, and for mixture chains in a 16-bit mode the tests planned per round:
+4, 8 or 16).
 
-A chain's decisions and arithmetic do not depend on the workgroup that runs it, so a tuned run
-must equal the untuned run bit for bit (points, logL, evidence, iteration count) while the
-candidates are being timed and after the choice; the choice lies in 1..4 and is reused by a
-later context of the same shape.
+Every candidate is timed on the same iteration (the state the chains change is saved and
+restored around each timed launch), and a chain's decisions and arithmetic do not depend on
+the launch shape, so a tuned run must equal the untuned run bit for bit (points, logL,
+evidence, iteration count); the tuner must actually time its candidates (counted launches) and
+a later context of the same shape must reuse the choice without timing anything.
 """
 import numpy as np
 import pytest
@@ -18,6 +21,14 @@ def N():
     return nss
 
 
+@pytest.fixture(autouse=True)
+def empty_cache(N):
+    """Every test starts with an empty process-wide tuning cache."""
+    assert N.ns_tune_clear()[0] == N.NS_OK
+    yield
+    N.ns_tune_clear()
+
+
 def _same_state(a, b):
     sa, sb = a.state(), b.state()
     assert sa["iter"] == sb["iter"]
@@ -28,43 +39,48 @@ def _same_state(a, b):
 
 
 def test_autotune_config1_full_run_identical(N):
-    """config 1 (k = 50): the 8 tuning iterations and the rest of the run equal the untuned
-    run; a second context of the same shape starts with the cached choice."""
+    """config 1 (k = 50, FP64: 4 candidates, 2 timed launches each): the tuned run equals the
+    untuned one; a second context of the same shape starts with the cached choice and times
+    nothing."""
     from paper_2601_23252_amd import problems as G
     prob = G.config1()
     a = N.NSRun(prob, seed=5, autotune=True)
     b = N.NSRun(prob, seed=5)
     assert b.chains_per_workgroup() == 1   # the rule: ceil(50 / 256)
-    for _ in range(3):                     # in the middle of tuning
-        a.step()
-        b.step()
+    a.step()
+    b.step()
+    assert a.stats()["tune_launches"] == 8
     _same_state(a, b)
     ia, ib = a.run(), b.run()
     assert ia == ib
     _same_state(a, b)
     assert a.logz() == b.logz()
-    c = a.chains_per_workgroup()
-    assert 1 <= c <= 4
+    c, plan = a.launch_shape()
+    assert 1 <= c <= 4 and plan == 4
     again = N.NSRun(prob, seed=6, autotune=True)
-    assert again.chains_per_workgroup() == c
+    assert again.launch_shape() == (c, plan)
+    again.step()
+    assert again.stats()["tune_launches"] == 0
     for r in (a, b, again):
         r.close()
 
 
 def test_autotune_mixture_full_size_identical(N):
-    """The d = 64 mixture (k = 1000, BF16x3, chains of 64 steps): ten iterations, eight of them
-    tuning, equal the untuned ones."""
+    """The d = 64 mixture (k = 1000, BF16x3, chains of 64 steps): 12 candidates (chains per
+    workgroup x 4, 8 or 16 planned tests), ten iterations equal to the untuned ones."""
     from paper_2601_23252_amd import problems as G
     prob = G.config3()
     a = N.NSRun(prob, p=64, seed=2, precision="bf16x3", autotune=True)
     b = N.NSRun(prob, p=64, seed=2, precision="bf16x3")
-    assert b.chains_per_workgroup() == 4
+    assert b.launch_shape() == (4, 16)
     for _ in range(10):
         a.step()
         b.step()
     _same_state(a, b)
     assert a.stats()["evals"] == b.stats()["evals"]
-    assert 1 <= a.chains_per_workgroup() <= 4
+    assert a.stats()["tune_launches"] == 24
+    c, plan = a.launch_shape()
+    assert 1 <= c <= 4 and plan in (4, 8, 16)
     a.close()
     b.close()
 
@@ -86,6 +102,7 @@ def test_autotune_batch_with_graphs_identical(N):
         st, sp = tuned.state(r), plain.state(r)
         assert np.array_equal(st["x"], sp["x"]) and st["iter"] == sp["iter"]
         assert 1 <= N.ns_chains_per_workgroup(tuned.ctx, r) <= 4
+    assert tuned.stats(0)["tune_launches"] == 16   # two groups, 4 candidates, 2 launches each
     tuned.close()
     plain.close()
 
@@ -93,7 +110,7 @@ def test_autotune_batch_with_graphs_identical(N):
 @pytest.mark.parametrize("kw", [dict(outer="smc", m=300, p=10), dict(replacement="rw", p=20)])
 def test_autotune_smc_and_random_walk_identical(N, kw):
     """The tempered-SMC outer loop and the random-walk replacement under the tuner: ten
-    iterations (eight of them tuning) equal the untuned ones."""
+    iterations (the first one tuning) equal the untuned ones."""
     from paper_2601_23252_amd import problems as G
     prob = G.config1()
     a = N.NSRun(prob, seed=9, autotune=True, **kw)
@@ -106,6 +123,7 @@ def test_autotune_smc_and_random_walk_identical(N, kw):
             break
     _same_state(a, b)
     assert a.stats()["evals"] == b.stats()["evals"]
+    assert a.stats()["tune_launches"] == 8
     assert 1 <= a.chains_per_workgroup() <= 4
     a.close()
     b.close()
@@ -113,15 +131,14 @@ def test_autotune_smc_and_random_walk_identical(N, kw):
 
 def test_autotune_cache_file_is_used(N, tmp_path):
     """A tuning cache written and loaded back: a context of a cached shape starts with the
-    cached chains per workgroup and runs no tuning iterations (its result equals the plain
-    run's)."""
+    cached launch shape and times nothing (its result equals the plain run's)."""
     import json
     from paper_2601_23252_amd import problems as G
     prob = G.config1()
     path = tmp_path / "tune.json"
     # config 1's shape in FP64: padded dimension 32, mixture, 1 fragment unit, slice sampling
-    path.write_text('{"nss_tune": 1, "entries": [\n  ' + json.dumps(
-        dict(D=32, lik=1, mode=0, upw=1, rw=0, chains=50, C=3)) + "\n]}\n")
+    entry = dict(D=32, lik=1, mode=0, upw=1, rw=0, chains=50, planned=0, C=3, plan=0)
+    path.write_text('{"nss_tune": 2, "entries": [\n  ' + json.dumps(entry) + "\n]}\n")
     assert N.ns_tune_load(path)[0] == N.NS_OK
     a = N.NSRun(prob, seed=4, autotune=True)
     assert a.chains_per_workgroup() == 3
@@ -131,9 +148,10 @@ def test_autotune_cache_file_is_used(N, tmp_path):
         b.step()
     _same_state(a, b)
     assert a.chains_per_workgroup() == 3
+    assert a.stats()["tune_launches"] == 0
     st, n = N.ns_tune_save(tmp_path / "saved.json")
     assert st == N.NS_OK and n >= 1
     saved = json.loads((tmp_path / "saved.json").read_text())
-    assert dict(D=32, lik=1, mode=0, upw=1, rw=0, chains=50, C=3) in saved["entries"]
+    assert entry in saved["entries"]
     a.close()
     b.close()
