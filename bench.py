@@ -220,6 +220,14 @@ def bench_gp(args):
     N.load()
     prob = G.config4()
     n = len(prob["gp_y"])
+    # FP32 leg first: FP32 MFMA Cholesky, FP64 refinement of the quadratic form, FP64
+    # log-determinant sum; decisions near L* (and beyond n s = 2e6) in FP64
+    R32 = N.NSRun(prob, seed=0, precision="fp32", timing=True)
+    it32, dt32 = run_until(R32, args.max_seconds)
+    st32 = R32.stats()
+    z32 = R32.logz()[0]
+    s32 = R32.state()
+    R32.close()
     R = N.NSRun(prob, seed=0, precision="fp64", timing=True)
     it, dt = run_until(R, args.max_seconds)
     st = R.stats()
@@ -240,6 +248,14 @@ def bench_gp(args):
                      "kernel": "k_hrss_gp", "flop_per_eval": fpe,
                      "avg_launch_ms": st["hrss_ms"] / max(1, st["hrss_launches"])},
         "lnz": {"logz": z, "sigma": err, "H": H},
+        "fp32": {"value": st32["evals"] / dt32, "unit": "evals/s", "iterations": it32,
+                 "speedup_vs_fp64": (st32["evals"] / dt32) / (st["evals"] / dt),
+                 "rechecks_per_eval": st32["rechecks"] / max(1, st32["evals"]),
+                 "band_violations": st32["band_violations"],
+                 "same_trajectory_as_fp64": bool(it32 == it and st32["evals"] == st["evals"]
+                                                 and abs(z32 - z) < 1e-9),
+                 "avg_launch_ms": st32["hrss_ms"] / max(1, st32["hrss_launches"]),
+                 "done": s32["done"]},
     }
     if not args.no_cpu:
         # the oracle's GP likelihood (one host thread) on prior draws for the time budget

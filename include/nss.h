@@ -199,6 +199,11 @@ typedef enum {
                            * next two stepping-out tests of each open end and the shrink
                            * proposals of the three likeliest expansion outcomes) instead of
                            * 16; identical results.  NS_FLAG_SHALLOW_PLAN takes precedence. */
+#define NS_FLAG_GP_NO_WAIT 256  /* testing the failure path of NS_LIK_GP chains: the
+                                * factorisation's bounded wait for each diagonal tile gives up
+                                * at once, so every chain evaluation fails (log L = -inf, a
+                                * rejection) and is counted in gp_wait_timeouts; every kernel
+                                * still exits normally.  The initial evaluation is unaffected. */
 #define NS_FLAG_GRAPH  8  /* ns_run captures each batch of 16 iterations as a HIP graph and
                            * replays it (re-captured when a run of the batch finishes); not
                            * used together with NS_FLAG_TIMING.  Results are identical. */
@@ -223,6 +228,9 @@ typedef struct {
     double width;           /* slice width in use */
     int64_t tune_launches;  /* NS_FLAG_AUTOTUNE: HRSS launches the tuner timed in this context
                              * (0 when every shape came from the cache) */
+    int64_t gp_wait_timeouts; /* NS_LIK_GP: chain evaluations whose factorisation gave up a
+                               * bounded wait for a diagonal tile (the candidate then counts as
+                               * log L = -inf); never expected outside NS_FLAG_GP_NO_WAIT */
 } ns_stats_t;
 
 /* Host arrays for state access (any pointer may be NULL to skip it). */

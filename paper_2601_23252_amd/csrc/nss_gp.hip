@@ -55,9 +55,11 @@ template <typename T>
 constexpr int gp_lds_bytes()
 {
     // 16 panel tiles, diagonal tile, inverse tile, right-hand side, z block, reciprocal pivots,
-    // then the tile waves' LDS-resident tiles
+    // then the tile waves' LDS-resident tiles; the FP32 refinement adds the inverse factors of
+    // all diagonal tiles, z, alpha, the partial products of a block step and one 16-vector
     return kOffT + (int)sizeof(T) * (16 * kTile + 2 * kTile + kGpMaxObs + 32 +
-                                     kGpLdsSlots * kGpTileWaves * kTile);
+                                     kGpLdsSlots * kGpTileWaves * kTile) +
+           (sizeof(T) == 4 ? 4 * (16 * kTile + 2 * kGpMaxObs + 16 * 16 + 16) : 0);
 }
 
 template <typename T> struct Mf;
@@ -236,7 +238,8 @@ __device__ __forceinline__ void diag_block(T *dg, T *li, T *zb, T *dv, const T *
 // step J).  The two roles run separate loops with the same barrier count, so the pivot wave's
 // code holds none of the tile registers.
 template <typename T>
-__device__ __forceinline__ double gp_eval(const double *u, int n, unsigned char *smem, bool &failed)
+__device__ __forceinline__ double gp_eval(const double *u, int n, unsigned char *smem, bool &failed,
+                                          bool &timed_out, int spin_max = kGpSpinMax)
 {
     typedef Mf<T> M;
     typedef typename M::v4 v4;
@@ -245,6 +248,7 @@ __device__ __forceinline__ double gp_eval(const double *u, int n, unsigned char 
     double *red = (double *)(smem + kOffMisc);
     int *flag = (int *)(red + 16);
     int *dflag = flag + 1;           // index of the last diagonal tile published to dg
+    int *tflag = flag + 2;           // the pivot wave's bounded wait gave up
     double *sc = (double *)(smem + kOffSc);
     T *pan = (T *)(smem + kOffT);
     T *dg = pan + 16 * kTile;
@@ -253,6 +257,14 @@ __device__ __forceinline__ double gp_eval(const double *u, int n, unsigned char 
     T *zb = yb + kGpMaxObs;
     T *dv = zb + 16;                 // reciprocal pivots of the diagonal tile
     T *far = dv + 16;                // [kGpLdsSlots][kGpTileWaves] LDS-resident tiles
+    constexpr bool refine = sizeof(T) == 4;
+    // FP32 refinement: L_JJ^{-1} of every block (the factor's inverse diagonal tiles), z,
+    // alpha = L^{-T} z, partial products of one block step, one 16-vector
+    float *linv = (float *)(far + kGpLdsSlots * kGpTileWaves * kTile);
+    float *zall = linv + 16 * kTile;
+    float *alpha = zall + kGpMaxObs;
+    float *part = alpha + kGpMaxObs;
+    float *wv = part + 16 * 16;
     const int tid = threadIdx.x, lane0 = tid & 63, w = uniform_i(tid >> 6);
     const int NT = (n + 15) >> 4, NTT = NT * (NT + 1) / 2;
     const GpTheta h = gp_theta(u);
@@ -264,7 +276,7 @@ __device__ __forceinline__ double gp_eval(const double *u, int n, unsigned char 
         sincospi(xs[2 * i + 1] * h.iper, &s1, &c1);
         sc[4 * i] = s0; sc[4 * i + 1] = c0; sc[4 * i + 2] = s1; sc[4 * i + 3] = c1;
     }
-    if (tid == 0) { *flag = 0; *dflag = -1; }
+    if (tid == 0) { *flag = 0; *dflag = -1; *tflag = 0; }
     __syncthreads();
 
     if (w == kGpPivot) {
@@ -275,21 +287,48 @@ __device__ __forceinline__ double gp_eval(const double *u, int n, unsigned char 
             if (J >= 0) __syncthreads();   // the panel step of the tile waves
             const int J1 = J + 1;
             if (J1 < NT) {
+                // bounded wait for the diagonal tile; giving up fails this evaluation (log L =
+                // -inf) and is reported (spin_max < 0: give up at once, a host-set test mode)
                 int spins = 0;
-                while (__hip_atomic_load(dflag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) != J1) {
-                    if (++spins > kGpSpinMax) {   // never expected: give up on this evaluation
-                        if (l == 0) *flag = 1;
+                while (spin_max < 0 ||
+                       __hip_atomic_load(dflag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) != J1) {
+                    if (++spins > spin_max) {
+                        if (l == 0) { *flag = 1; *tflag = 1; }
                         break;
                     }
                     __builtin_amdgcn_s_sleep(1);
                 }
                 diag_block<T>(dg, li, zb, dv, yb + 16 * J1, flag, l, ldet, quad);
+                if constexpr (refine) {
+                    for (int e = l; e < kTile; e += 64) linv[J1 * kTile + e] = (float)li[e];
+                    if (l < 16) zall[16 * J1 + l] = (float)zb[l];
+                }
             }
             __syncthreads();
         }
         if (lane0 == 0) {
             red[0] = ldet;
             red[1] = quad;
+        }
+        if constexpr (refine) {
+            // alpha = L^{-T} z, block rows from the last: alpha_J = L_JJ^{-T} (z_J - sum_{I > J}
+            // L_IJ^T alpha_I), the products L_IJ^T alpha_I from the tiles' owners
+            for (int J = NT - 1; J >= 0; --J) {
+                __syncthreads();   // the owners' partial products of step J
+                const int l = lane0;
+                if (l < 16) {
+                    float w = zall[16 * J + l];
+                    for (int I = J + 1; I < NT; ++I) w -= part[16 * I + l];
+                    wv[l] = w;
+                }
+                wave_sync();
+                if (l < 16) {
+                    float a = 0.f;
+                    for (int r = l; r < 16; ++r) a += linv[J * kTile + r * kGpLd + l] * wv[r];
+                    alpha[16 * J + l] = a;
+                }
+                __syncthreads();
+            }
         }
     } else {
         int tI[kGpSlots], tK[kGpSlots];
@@ -361,6 +400,10 @@ __device__ __forceinline__ double gp_eval(const double *u, int n, unsigned char 
                         }
                         wave_sync();
                         store_tile<T>(o, pI, l);
+                        if constexpr (refine) {   // the factor's tile, kept for the solve
+                            if (s < kGpLdsSlots) store_tile<T>(o, lt[s], l);
+                            else acc[s - kGpLdsSlots] = o;
+                        }
                         const T zc = zb[l & 15];
 #pragma unroll
                         for (int r = 0; r < 4; ++r) {
@@ -418,10 +461,61 @@ __device__ __forceinline__ double gp_eval(const double *u, int n, unsigned char 
             }
             __syncthreads();
         }
+        if constexpr (refine) {
+            for (int J = NT - 1; J >= 0; --J) {
+                int l = lane0;
+                asm volatile("" : "+v"(l));
+                // the partial products L_IJ^T alpha_I of this wave's tiles (I, J), I > J
+#pragma unroll
+                for (int s = 0; s < kGpSlots; ++s) {
+                    if (tK[s] == J && tI[s] > J) {
+                        v4 a;
+                        if (s < kGpLdsSlots) load_tile<T>(a, lt[s], l);
+                        else a = acc[s - kGpLdsSlots];
+                        float v = 0.f;
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) v += (float)a[r] * alpha[16 * tI[s] + M::row(l, r)];
+                        v += __shfl_xor(v, 16, 64);
+                        v += __shfl_xor(v, 32, 64);
+                        if (l < 16) part[16 * tI[s] + l] = v;
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+                __syncthreads();
+                __syncthreads();   // alpha_J from the pivot wave
+            }
+        }
     }
     __syncthreads();
-    const double ld = red[0], q = red[1];
+    const double ld = red[0];
+    double q = red[1];
     failed = (*flag != 0);
+    timed_out = (*tflag != 0);
+    if constexpr (refine) {
+        // y^T K^{-1} y from the FP32 solve alpha, with the entries in FP64:
+        // 2 y^T alpha - alpha^T K alpha = y^T K^{-1} y - |alpha - K^{-1} y|_K^2, exact up to a
+        // term of second order in the solve's error
+        double s2 = 0.0;
+        const int ne = n * (n + 1) / 2;
+        for (int e = tid; e < ne; e += kGpThreads) {
+            int i = (int)((sqrt(8.0 * (double)e + 1.0) - 1.0) * 0.5);
+            while (i * (i + 1) / 2 > e) --i;
+            while ((i + 1) * (i + 2) / 2 <= e) ++i;
+            const int jj = e - i * (i + 1) / 2;
+            const double kij = gp_entry<double>(xs, sc, n, i, jj, h);
+            const double t = (double)alpha[i] * (double)alpha[jj] * kij;
+            s2 += (i == jj) ? t : 2.0 * t;
+        }
+        for (int i = tid; i < n; i += kGpThreads) s2 -= 2.0 * ys[i] * (double)alpha[i];
+        s2 = wave_sum(s2);
+        __syncthreads();
+        if ((tid & 63) == 0) red[2 + w] = s2;
+        __syncthreads();
+        double qv = 0.0;
+#pragma unroll
+        for (int v = 0; v < kGpWaves; ++v) qv -= red[2 + v];
+        q = qv;
+    }
     __syncthreads();   // the LDS slots are reused by the next evaluation
     return -0.5 * q - ld - 0.5 * (double)n * LOG_2PI;
 }
@@ -435,16 +529,29 @@ __device__ __forceinline__ void gp_stage(const DevProblem &P, unsigned char *sme
 }
 
 // Mixed precision: the FP32 estimate decides unless it lies within this band of L*; then (and
-// when the FP32 factorisation breaks down) the FP64 value decides.  The FP32 error grows with
-// the signal-to-noise ratio s = (sigma_f^2 + sigma_n^2) / sigma_n^2 (the noise floor bounds
-// the smallest eigenvalue of the covariance, its trace the largest) and with sqrt(n).
+// when the FP32 factorisation breaks down) the FP64 value decides.  After the refinement the
+// error is that of the FP32 log-determinant, which grows with the condition number, bounded
+// by n s with s = (sigma_f^2 + sigma_n^2) / sigma_n^2 (the noise floor bounds the smallest
+// eigenvalue of the covariance, its trace the largest).  Beyond n s = kGpMaxCond the FP32
+// factor is not trusted and the FP64 value decides.
+constexpr double kGpMaxCond = 1e5;
+__device__ __forceinline__ double gp_cond(const DevProblem &P, const double *u)
+{
+    const double sf2 = exp(2.0 * u[0]), sn2 = exp(2.0 * u[5]);
+    return (sf2 + sn2) / sn2 * (double)P.gp_n;
+}
+// beyond the bound the candidate is evaluated in FP64 only (no FP32 attempt)
+__device__ __forceinline__ bool gp_illcond(const DevProblem &P, const double *u)
+{
+    return !(gp_cond(P, u) <= kGpMaxCond);
+}
 __device__ __forceinline__ bool gp_near(double L32, double Lstar, const DevProblem &P,
                                         const double *u)
 {
-    const double sf2 = exp(2.0 * u[0]), sn2 = exp(2.0 * u[5]);
-    const double snr = (sf2 + sn2) / sn2;
+    const double cond = gp_cond(P, u);
+    if (!(cond <= kGpMaxCond)) return true;
     const double band = (double)P.guard_rel * fabs(L32) + (double)P.guard_abs +
-                        (double)P.guard_kappa * snr * sqrt((double)P.gp_n);
+                        (double)P.guard_kappa * cond;
     return !(fabs(L32 - Lstar) > band);
 }
 
@@ -467,10 +574,11 @@ __global__ __launch_bounds__(kGpThreads) void k_eval_gp(Launch Lc, const double 
 #pragma unroll
     for (int a = 0; a < kGpD; ++a) u[a] = X[(size_t)a * ld + i];
     __syncthreads();
-    bool failed = false;
+    bool failed = false, timed_out = false;
     double L;
-    if constexpr (MODE == MODE_FP64) L = gp_eval<double>(u, P.gp_n, smem, failed);
-    else L = gp_eval<float>(u, P.gp_n, smem, failed);
+    if constexpr (MODE == MODE_FP64) L = gp_eval<double>(u, P.gp_n, smem, failed, timed_out);
+    else L = gp_eval<float>(u, P.gp_n, smem, failed, timed_out);
+    if (timed_out && from_run && threadIdx.x == 0) atomicAdd(&R.ctr[10], 1ull);
     if (threadIdx.x == 0) {
         unsigned long long nf = 0;
         out[i] = failed ? -INFINITY : sanitize(L, nf);
@@ -510,7 +618,8 @@ __global__ __launch_bounds__(kGpThreads) void k_hrss_gp(Launch Lc)
     bool exact0 = true;
     // counters (every thread keeps identical copies; thread 0 publishes them)
     unsigned long long c_evals = 0, c_tests = 0, c_prej = 0, c_outcap = 0, c_shcap = 0,
-                       c_nonfin = 0, c_rc = 0, c_viol = 0;
+                       c_nonfin = 0, c_rc = 0, c_viol = 0, c_wait = 0;
+    const int spin_max = P.gp_spin_max;
     __syncthreads();
 
     // log prior density (Gaussian prior; the box prior is uniform on its support)
@@ -610,17 +719,25 @@ __global__ __launch_bounds__(kGpThreads) void k_hrss_gp(Launch Lc)
             ++c_prej;
         } else {
             // the single evaluation site
-            bool failed = false;
+            bool failed = false, tout = false;
             if constexpr (MODE == MODE_FP64) {
-                L = gp_eval<double>(y, n, smem, failed);
+                L = gp_eval<double>(y, n, smem, failed, tout, spin_max);
+                c_wait += tout;
             } else {
                 bool need64 = (phase == PH_FINAL);
-                if (!need64) {
-                    L = gp_eval<float>(y, n, smem, failed);
-                    need64 = failed || !(L == L) || gp_near(L, Lstar, P, y);
+                if (!need64 && gp_illcond(P, y)) {   // FP64 only, no FP32 attempt
+                    need64 = true;
+                    ++c_rc;
+                } else if (!need64) {
+                    L = gp_eval<float>(y, n, smem, failed, tout, spin_max);
+                    c_wait += tout;
+                    need64 = (failed && !tout) || !(L == L) || gp_near(L, Lstar, P, y);
                     if (need64) ++c_rc; else exact = false;
                 }
-                if (need64) L = gp_eval<double>(y, n, smem, failed);
+                if (need64) {
+                    L = gp_eval<double>(y, n, smem, failed, tout, spin_max);
+                    c_wait += tout;
+                }
             }
             if (failed) L = -INFINITY;
             if (phase == PH_FINAL) {
@@ -670,6 +787,7 @@ __global__ __launch_bounds__(kGpThreads) void k_hrss_gp(Launch Lc)
         atomicAdd(&R.ctr[5], c_nonfin);
         atomicAdd(&R.ctr[6], c_rc);
         atomicAdd(&R.ctr[7], c_viol);
+        if (c_wait) atomicAdd(&R.ctr[10], c_wait);
     }
 }
 

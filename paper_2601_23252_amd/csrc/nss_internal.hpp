@@ -44,6 +44,8 @@ struct DevProblem {
     float guard_abs;       //   (GP: rel |L| + abs + kappa_coef kappa n / 256)
     float guard_kappa;
     int gp_n;              // GP: observations
+    int gp_spin_max;       // GP: bound on the pivot wave's wait per diagonal tile (< 0: give
+                           //     up at once, a test mode)
     const double *gp_x;    // GP: [n][2] inputs
     const double *gp_y;    // GP: [n] targets
     double rg_la, rg_l1a;  // Gaussian-Rastrigin: log alpha, log(1 - alpha) (-inf at 0 / 1)
@@ -65,7 +67,7 @@ struct DevRun {
     int *iscal;            // [0] done, [1] t0, [2] n_s, [3] iter, [4] state error
     unsigned long long *ctr;  // [0] evals [1] tests [2] prior_rejects [3] stepout_caps
                               // [4] shrink_caps [5] nonfinite [6] rechecks [7] band_violations
-                              // [8] whiten_fallbacks [9] n_dead
+                              // [8] whiten_fallbacks [9] n_dead [10] GP wait time-outs
     double *Lsig;          // [D][D] lower factor (row-major, zero above the diagonal)
     double *Lpk;           // packed lower factor, D(D+1)/2
     int *parents;          // [k]

@@ -31,13 +31,15 @@ NS_FLAG_RECORD_POINTS = 16
 NS_FLAG_AUTOTUNE = 32
 NS_FLAG_SHALLOW_PLAN = 64
 NS_FLAG_PLAN8 = 128
+NS_FLAG_GP_NO_WAIT = 256
 PRECISIONS = {"fp64": NS_FP64, "bf16": NS_MIXED_BF16, "fp16": NS_MIXED_FP16,
               "bf16x3": NS_MIXED_BF16X3, "fp16x3": NS_MIXED_FP16X3, "fp32": NS_MIXED_FP32}
 # guard band of each mixed mode: (rel, abs) as set by the library
 GUARD = {"bf16": (0.025, 2e-3), "fp16": (0.0032, 2e-3), "bf16x3": (4e-5, 2e-4),
          "fp16x3": (6e-6, 2e-4)}
-# GP FP32 mode: rel |L| + abs + c * s * sqrt(n), s = (sf^2 + sn^2) / sn^2
-GP_GUARD = (5e-5, 1.25, 5.2e-2)
+# GP FP32 mode: rel |L| + abs + c * n * s, s = (sf^2 + sn^2) / sn^2; FP64 beyond n s = 1e5
+GP_GUARD = (1e-6, 4e-3, 1e-6)
+GP_MAX_COND = 1e5
 
 _d = C.POINTER(C.c_double)
 _i32 = C.POINTER(C.c_int32)
@@ -67,7 +69,8 @@ class ns_stats_t(C.Structure):
                 ("shrink_caps", C.c_int64), ("nonfinite", C.c_int64), ("rechecks", C.c_int64),
                 ("band_violations", C.c_int64), ("whiten_fallbacks", C.c_int64),
                 ("n_dead", C.c_int64), ("hrss_ms", C.c_double), ("hrss_launches", C.c_int64),
-                ("width", C.c_double), ("tune_launches", C.c_int64)]
+                ("width", C.c_double), ("tune_launches", C.c_int64),
+                ("gp_wait_timeouts", C.c_int64)]
 
 
 class ns_state_view(C.Structure):
@@ -340,7 +343,7 @@ def make_config(m, k, p, width=0.0, seed=0, run_id=0, precision="fp64", term_fra
                 stepout_cap=10, shrink_cap=100, max_iter=100000, trace=False, timing=False,
                 inline_directions=False, graph=False, replacement="hrss", outer="ns",
                 ess_frac=0.5, record_points=False, autotune=False,
-                shallow_plan=False, plan8=False) -> ns_config:
+                shallow_plan=False, plan8=False, gp_no_wait=False) -> ns_config:
     cfg = ns_config_default()
     cfg.n_live, cfg.k, cfg.chain_len = int(m), int(k), int(p)
     cfg.width = float(width)
@@ -355,7 +358,8 @@ def make_config(m, k, p, width=0.0, seed=0, run_id=0, precision="fp64", term_fra
                  | (NS_FLAG_RECORD_POINTS if record_points else 0)
                  | (NS_FLAG_AUTOTUNE if autotune else 0)
                  | (NS_FLAG_SHALLOW_PLAN if shallow_plan else 0)
-                 | (NS_FLAG_PLAN8 if plan8 else 0))
+                 | (NS_FLAG_PLAN8 if plan8 else 0)
+                 | (NS_FLAG_GP_NO_WAIT if gp_no_wait else 0))
     cfg.replacement = REPLACEMENTS[replacement] if isinstance(replacement, str) else int(replacement)
     cfg.outer = OUTERS[outer] if isinstance(outer, str) else int(outer)
     cfg.ess_frac = float(ess_frac)
@@ -434,7 +438,8 @@ class NSRun:
                  precision="fp64", term_frac=1e-3, stepout_cap=10, shrink_cap=100,
                  max_iter=100000, trace=False, timing=False, inline_directions=False,
                  graph=False, stream="torch", replacement="hrss", outer="ns", ess_frac=0.5,
-                 record_points=False, autotune=False, shallow_plan=False, plan8=False):
+                 record_points=False, autotune=False, shallow_plan=False, plan8=False,
+                 gp_no_wait=False):
         self.prob = prob
         self.d = int(prob["d"])
         self.m = int(m or prob["m"])
@@ -446,7 +451,7 @@ class NSRun:
         cfg = make_config(self.m, self.k, self.p, width, seed, run_id, precision, term_frac,
                           stepout_cap, shrink_cap, max_iter, trace, timing, inline_directions,
                           graph, replacement, outer, ess_frac, record_points, autotune,
-                          shallow_plan, plan8)
+                          shallow_plan, plan8, gp_no_wait)
         self.cfg = cfg
         s = current_stream() if stream == "torch" else stream
         st, self.ctx = ns_init(pr, en, cfg, s)
