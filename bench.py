@@ -283,11 +283,13 @@ def bench_batch(args):
     from paper_2601_23252_amd import nss as N, problems as G
     N.load()
     probs = G.config5()
+    # HIP graphs on (16 iterations per replay), no per-launch events: the whole job is timed
+    # on the host clock; the launch shapes are tuned at each group's first iteration
     runs = [(p, dict(seed=5, run_id=r, precision="bf16x3" if p["lik"] == "mixture" else "fp64",
-                     max_iter=3000, timing=True, autotune=not args.no_autotune))
+                     max_iter=4000, graph=True, autotune=not args.no_autotune))
             for r, p in enumerate(probs)]
     B = N.NSBatch(runs)
-    it, dt = run_until(B, args.max_seconds, chunk=16)
+    it, dt = run_until(B, args.max_seconds, chunk=64)
     cpw = {}
     for r in range(len(probs)):
         c = N.ns_chains_per_workgroup(B.ctx, r)
@@ -297,21 +299,31 @@ def bench_batch(args):
     fpe = [p["d"] * (p["d"] + 1) + 3 * p["d"] if p["lik"] == "mixture" else 3 * p["d"]
            for p in probs]
     flops = sum(s["evals"] * f for s, f in zip(stats, fpe))
-    hrss_s = stats[0]["hrss_ms"] / 1e3
     done = sum(B.state(r)["done"] for r in range(len(probs)))
+    zs, errs, _ = B.logz()
+    z_of = []
+    for r, pr in enumerate(probs):
+        if pr["lik"] == "mixture":
+            from tests import truth as TR
+            tz = TR.lnz_gauss_gauss(pr["mu"][0], pr["cov"][0], 0.0, 2.0)
+        else:
+            from tests import truth as TR
+            tz = TR.lnz_funnel_box(pr["d"], 20.0)
+        z_of.append((zs[r] - tz) / errs[r])
     out = {
         "metric": "slice-step likelihood evals/s (256 batched runs, d in {8..128})",
         "value": evals / dt, "unit": "evals/s", "n_gpus": 1, "steps": 1, "warmup": 0,
         "ms_per_step": 1e3 * dt, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
         "config": {"workload": "batch256_gauss_funnel_nlive500_k250_p5d", "runs": len(probs),
-                   "runs_done": done, "max_iterations": it,
+                   "runs_done": done, "max_iterations": it, "graphs": True,
                    "autotune": not args.no_autotune, "runs_by_chains_per_workgroup": cpw},
-        "roofline": {"bound": "mfma", "achieved": flops / hrss_s / 1e12 if hrss_s else 0.0,
-                     "peak": 2500.0, "unit": "TFLOP/s",
-                     "frac": flops / hrss_s / 2.5e15 if hrss_s else 0.0, "traffic": None,
-                     "kernel": "k_hrss", "flop_per_eval": "d(d+1)+3d (Gaussian), 3d (funnel)",
-                     "avg_launch_ms": stats[0]["hrss_ms"] / max(1, stats[0]["hrss_launches"])},
+        "roofline": {"bound": "mfma", "achieved": flops / dt / 1e12, "peak": 2500.0,
+                     "unit": "TFLOP/s", "frac": flops / dt / 2.5e15, "traffic": None,
+                     "kernel": "whole job (host clock; no per-kernel events with graphs)",
+                     "flop_per_eval": "d(d+1)+3d (Gaussian), 3d (funnel)"},
+        "lnz": {"runs_within_3sigma": f"{sum(abs(z) < 3 for z in z_of)}/{len(z_of)}",
+                "z_by_run": z_of},
     }
     if not args.no_cpu:
         # the oracle on a stratified subset: every 16th run, each for an equal share of the
@@ -460,6 +472,44 @@ RG_VALU_PER_EVAL = 54595.0
 RG_SOURCE_SHA = "3f0ca1613b567c08"
 
 
+def _rastrigin_table(args):
+    """Untimed full runs per (d, alpha, seed) of the table options; ln Z against the
+    semi-analytic evidence."""
+    from paper_2601_23252_amd import nss as N, problems as G
+    table = []
+    for dd in [int(v) for v in args.table_dims.split(",") if v]:
+        for a in [float(v) for v in args.table_alphas.split(",") if v]:
+            for sd in range(1, 1 + args.table_seeds):
+                Q = N.NSRun(G.rastrigin_gauss(dd, a, k=args.table_k), seed=sd)
+                t0 = time.perf_counter()
+                Q.run()
+                z, err, _ = Q.logz()
+                t = lnz_rastrigin_gauss(dd, a)
+                table.append({"d": dd, "alpha": a, "k": args.table_k, "seed": sd, "logz": z,
+                              "sigma": err, "truth": t, "z": (z - t) / err,
+                              "seconds": time.perf_counter() - t0,
+                              "evals": Q.stats()["evals"],
+                              "iterations": Q.stats()["iterations"]})
+                print(f"[bench] table d={dd} alpha={a} k={args.table_k} seed={sd}: "
+                      f"z {(z - t) / err:.2f} ({time.perf_counter() - t0:.0f} s)",
+                      file=sys.stderr, flush=True)
+                Q.close()
+    print(f"[bench] ln Z table done", file=sys.stderr, flush=True)
+    return table
+
+
+def _rastrigin_table_only(args):
+    """--steps 0: the ln Z table alone (no timed runs, no throughput figure)."""
+    table = _rastrigin_table(args)
+    print(json.dumps({"metric": "Gaussian-Rastrigin ln Z against the semi-analytic evidence",
+                      "value": None, "unit": "z-score", "n_gpus": 1, "steps": 0,
+                      "warmup": 0, "higher_is_better": False, "dtype": "f64",
+                      "data": "synthetic",
+                      "config": {"workload": f"rastrigin_gauss_table_nlive1000_k{args.table_k}"
+                                             "_p25d"},
+                      "lnz": {"table": table}}), flush=True)
+
+
 def bench_rastrigin(args):
     """The Gaussian-Rastrigin evidence workload: full runs at d = 100, alpha = 0.5 (n_live 1000,
     k 500, p = 25d, FP64), timed; then one untimed run per (d, alpha) in
@@ -472,6 +522,9 @@ def bench_rastrigin(args):
     N.load()
     d, alpha = 100, 0.5
     prob = G.rastrigin_gauss(d, alpha)
+    if args.steps == 0:
+        _rastrigin_table_only(args)
+        return
     R = N.NSRun(prob, seed=0, timing=True)
     for w in range(args.warmup):
         R.reset(10_000 + w)
@@ -493,21 +546,7 @@ def bench_rastrigin(args):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     print(f"[bench] timed runs done in {dt:.1f} s", file=sys.stderr, flush=True)
-    table = []
-    for dd in (() if args.no_table else (2, 4, 10, 30, 100, 300)):
-        for a in (0.0, 0.5, 1.0):
-            Q = N.NSRun(G.rastrigin_gauss(dd, a), seed=1)
-            t0 = time.perf_counter()
-            Q.run()
-            z, err, _ = Q.logz()
-            t = lnz_rastrigin_gauss(dd, a)
-            table.append({"d": dd, "alpha": a, "logz": z, "sigma": err, "truth": t,
-                          "z": (z - t) / err, "seconds": time.perf_counter() - t0,
-                          "evals": Q.stats()["evals"]})
-            print(f"[bench] table d={dd} alpha={a}: z {(z - t) / err:.2f}", file=sys.stderr,
-                  flush=True)
-            Q.close()
-    print(f"[bench] ln Z table done", file=sys.stderr, flush=True)
+    table = [] if args.no_table else _rastrigin_table(args)
     src = os.path.join(ROOT, "paper_2601_23252_amd", "csrc", "nss_kernels.hip")
     with open(src, "rb") as f:
         sha = hashlib.sha256(f.read()).hexdigest()[:16]
@@ -544,6 +583,8 @@ def _step_costs(tr, rw):
         return (2 + tr[:, :, 0] + tr[:, :, 1] + tr[:, :, 2]).ravel().astype(float)
     cs = np.cumsum(tr[:, :, 2], axis=1)
     rows, cols = np.nonzero(tr[:, :, 3])
+    if rows.size == 0:
+        return np.zeros(0)
     vals = cs[rows, cols]
     prev = np.zeros_like(vals)
     same = np.r_[False, rows[1:] == rows[:-1]]
@@ -551,53 +592,96 @@ def _step_costs(tr, rw):
     return (vals - prev).astype(float)
 
 
+def _rw_costs(R, kind):
+    """Run R to the end with traces; per-step costs (see _step_costs), and for the random walk
+    its acceptance rate and the fraction of chains that never moved in their iteration."""
+    import numpy as np
+    from paper_2601_23252_amd import nss as N
+    costs, acc, steps, stuck, chains = [], 0, 0, 0, 0
+    done = False
+    while not done:
+        try:
+            done = R.step()
+        except N.NSError:   # the live set collapsed onto one point (plateau): stop there
+            done = True
+        tr = R.trace()
+        costs.append(_step_costs(tr, kind == "rw"))
+        if kind == "rw":
+            acc += int(tr[:, :, 3].sum())
+            steps += tr.shape[0] * tr.shape[1]
+            stuck += int((tr[:, :, 3].sum(axis=1) == 0).sum())
+            chains += tr.shape[0]
+    c = np.concatenate(costs)
+    if c.size == 0:       # no move accepted in the whole run
+        c = np.array([np.nan])
+    extra = {"acceptance": acc / steps, "chains_never_moved": stuck / chains} if steps else {}
+    return c, extra
+
+
 def bench_rw(args):
     """Slice (HRSS) against the constrained random walk on the condition-100 Gaussian at
     d = 10, 50, 100 (n_live 1000, k 500, FP64): HRSS with p = d steps, the random walk with
-    p = 5d proposals at scale 2.38 / sqrt(d) of the live-set covariance.  Whole runs: per-step
-    evaluation counts over every iteration (the paper's table of evaluations per step), ln Z
-    against the closed form -d ln 40, and the random-walk kernel's throughput at d = 100 with
-    its FP64 MFMA roofline."""
+    p = 5d proposals at scale 2.38 / sqrt(d) of a proposal covariance that is (a) the live
+    set's, recomputed every iteration, (b) the first iteration's live set's, kept for the run
+    (a fixed scale), or (c) the target's own covariance, kept for the run.  Whole runs:
+    per-step evaluation counts over every iteration (the paper's table of evaluations per
+    step), the random walk's acceptance rate, ln Z against the closed form -d ln 40, and the
+    adaptive random-walk kernel's throughput at d = 100 with its FP64 MFMA roofline."""
     import numpy as np
     import torch
     from paper_2601_23252_amd import nss as N, problems as G
     N.load()
     table = []
     timed = None
+    variants = (("hrss", "hrss", None), ("rw", "rw", None), ("rw_fixed_first", "rw", "first"),
+                ("rw_target_cov", "rw", "target"))
     for d in (10, 50, 100):
         prob = G.illcond_gaussian(d)
         tz = -d * math.log(40.0)
+        Lt = np.linalg.cholesky(prob["cov"][0])
         row = {"d": d}
-        for kind, p in (("hrss", d), ("rw", 5 * d)):
+        for name, kind, fixed in variants:
+            p = d if kind == "hrss" else 5 * d
+            kw = dict(p=p, seed=0, replacement=kind, freeze_whitening=fixed is not None)
+
+            def start(R):
+                if fixed == "target":
+                    s0 = R.state()
+                    R.set_state(s0["x"], s0["logL"], s0["logZ"], s0["logX"], s0["M"],
+                                s0["iter"], Lsig=Lt)
             # timed run (no trace), then the same trajectory again with traces for the costs
-            R = N.NSRun(prob, p=p, seed=0, timing=True, replacement=kind)
+            R = N.NSRun(prob, timing=True, **kw)
+            start(R)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            R.run()
+            collapsed = False
+            try:
+                R.run()
+            except N.NSError:   # every survivor a copy of one point: no strict survivor left
+                collapsed = True
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             st = R.stats()
             z, err, _ = R.logz()
             R.close()
-            R = N.NSRun(prob, p=p, seed=0, trace=True, replacement=kind)
-            costs = []
-            done = False
-            while not done:
-                done = R.step()
-                costs.append(_step_costs(R.trace(), kind == "rw"))
-            c = np.concatenate(costs)
-            row[kind] = {"mean": float(c.mean()), "std": float(c.std()), "max": float(c.max()),
-                         "p": p, "iterations": st["iterations"], "evals": st["evals"],
+            R = N.NSRun(prob, trace=True, **kw)
+            start(R)
+            c, extra = _rw_costs(R, kind)
+            row[name] = {"mean": float(c.mean()), "std": float(c.std()), "max": float(c.max()),
+                         "p99": float(np.percentile(c, 99)), "p": p,
+                         "iterations": st["iterations"], "evals": st["evals"],
                          "tests": st["tests"], "evals_per_s": st["evals"] / dt,
                          "kernel_ms": st["hrss_ms"] / max(1, st["hrss_launches"]),
-                         "logz": z, "z": (z - tz) / err}
-            if d == 100 and kind == "rw":
+                         "logz": z, "z": (z - tz) / err, "collapsed": collapsed, **extra}
+            if d == 100 and name == "rw":
                 timed = (st, dt)
             R.close()
+            print(f"[bench] d={d} {name}: {row[name]['mean']:.2f} +- {row[name]['std']:.2f} "
+                  f"(max {row[name]['max']:.0f}, z {row[name]['z']:.2f}, "
+                  f"{st['iterations']} iterations{', collapsed' if collapsed else ''}"
+                  + (f", acceptance {extra['acceptance']:.3f}" if extra else "") + ")",
+                  file=sys.stderr, flush=True)
         table.append(row)
-        print(f"[bench] d={d}: slice {row['hrss']['mean']:.2f} +- {row['hrss']['std']:.2f} "
-              f"(z {row['hrss']['z']:.2f}), rw {row['rw']['mean']:.2f} +- "
-              f"{row['rw']['std']:.2f} (z {row['rw']['z']:.2f})", file=sys.stderr, flush=True)
     st, dt = timed
     fpe = algorithmic_flop_per_eval(1, 100)
     hrss_s = st["hrss_ms"] / 1e3
@@ -785,6 +869,13 @@ def main():
     ap.add_argument("--replicas", type=int, default=100, help="geom: shrinkage replicas")
     ap.add_argument("--no-table", action="store_true",
                     help="rastrigin: skip the untimed ln Z table over (d, alpha)")
+    ap.add_argument("--table-k", type=int, default=500,
+                    help="rastrigin: deletions per iteration of the table's runs (n_live 1000)")
+    ap.add_argument("--table-dims", default="2,4,10,30,100,300",
+                    help="rastrigin: the table's dimensions")
+    ap.add_argument("--table-alphas", default="0,0.5,1", help="rastrigin: the table's alphas")
+    ap.add_argument("--table-seeds", type=int, default=1,
+                    help="rastrigin: runs per table cell (seeds 1..)")
     ap.add_argument("--max-seconds", type=float, default=120.0,
                     help="gp_n256 / batch256: stop the timed run after about this long")
     ap.add_argument("--profile-iters", type=int, default=0,

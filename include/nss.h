@@ -204,6 +204,12 @@ typedef enum {
                                 * at once, so every chain evaluation fails (log L = -inf, a
                                 * rejection) and is counted in gp_wait_timeouts; every kernel
                                 * still exits normally.  The initial evaluation is unaffected. */
+#define NS_FLAG_FREEZE_WHITENING 512  /* the whitening factor (and with it the direction
+                                      * metric, and the random walk's proposal covariance) is
+                                      * computed at the first iteration only and kept for the
+                                      * run: a proposal scale fixed over the run, the variant
+                                      * the slice-versus-random-walk comparison contrasts with
+                                      * the adaptive default.  Not for NS_OUTER_SMC. */
 #define NS_FLAG_GRAPH  8  /* ns_run captures each batch of 16 iterations as a HIP graph and
                            * replays it (re-captured when a run of the batch finishes); not
                            * used together with NS_FLAG_TIMING.  Results are identical. */
@@ -282,7 +288,11 @@ ns_status ns_stats(ns_ctx *ctx, ns_stats_t *out);
  * logZ, logX, M and iter; it recomputes the delete-k order and L* without re-accounting.  A
  * logL entry that is NaN or +inf is stored as -inf and counted in ns_stats_t.nonfinite, as a
  * computed one would be.  If after this no live point lies strictly above L* (a total
- * plateau), the next ns_step returns NS_ESTATE. */
+ * plateau), the next ns_step returns NS_ESTATE.  On a run with NS_FLAG_FREEZE_WHITENING a
+ * non-null Lsig (d x d row-major, lower triangle read) becomes the whitening factor kept for
+ * the rest of the run (until ns_reset) in place of any computed one, e.g. the Cholesky
+ * factor of the target's covariance; a non-finite entry is NS_EINVAL.  Without that flag Lsig
+ * is ignored. */
 ns_status ns_get_state(ns_ctx *ctx, ns_state_view *view);
 ns_status ns_set_state(ns_ctx *ctx, const ns_state_view *view);
 

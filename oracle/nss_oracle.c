@@ -597,6 +597,8 @@ typedef struct {
     int64_t n_dead, cap_dead;
     int whiten_fallbacks;
     int replacement;  /* 0: HRSS (width = slice width); 1: random walk (width = step scale) */
+    int freeze;       /* 1: the whitening factor of the first iteration is kept for the run */
+    int held;         /* 1: a caller-supplied factor is kept (freeze only; no whitening at all) */
     /* adaptive tempered SMC (or_smc_*): all m particles move each step */
     int smc;
     double beta, ess_frac;
@@ -771,7 +773,7 @@ int or_step(void *rr, int n_threads)
     const int d = p->d, m = r->m, k = r->k;
     const uint32_t it = (uint32_t)(r->iter + 1);
     okey key = { { (uint32_t)r->seed, (uint32_t)(r->seed >> 32) ^ r->run_id } };
-    whiten(r);
+    if (!r->freeze || (r->iter == 0 && !r->held)) whiten(r);
     /* resample: uniform over survivors with logL > L*, in ascending (logL, index) order */
     int t0 = k;
     while (t0 < m && !(r->logL[r->perm[t0]] > r->Lstar)) ++t0;
@@ -954,6 +956,30 @@ int or_run_set_replacement(void *rr, int kind)
     orun *r = (orun *)rr;
     if (!r || (kind != 0 && kind != 1)) return -1;
     r->replacement = kind;
+    return 0;
+}
+
+/* Whitening kept from the first iteration on (1) or recomputed every iteration (0, the
+ * default): the fixed-scale proposal variant of the random-walk comparison. */
+int or_run_set_freeze(void *rr, int on)
+{
+    orun *r = (orun *)rr;
+    if (!r || (on != 0 && on != 1)) return -1;
+    r->freeze = on;
+    return 0;
+}
+
+/* With the whitening frozen: keep the caller's lower-triangular factor L (d x d, row-major;
+ * entries above the diagonal are ignored) for the whole run instead of computing one, e.g. the
+ * Cholesky factor of the target's covariance for a proposal matched to the target. */
+int or_run_set_factor(void *rr, const double *L)
+{
+    orun *r = (orun *)rr;
+    if (!r || !L || !r->freeze) return -1;
+    const int d = r->p->d;
+    for (int a = 0; a < d; ++a)
+        for (int b = 0; b < d; ++b) r->Lsig[a * d + b] = b <= a ? L[a * d + b] : 0.0;
+    r->held = 1;
     return 0;
 }
 

@@ -113,6 +113,10 @@ def lib():
                                            C.c_void_p, C.c_void_p]
         L.or_run_set_replacement.restype = C.c_int
         L.or_run_set_replacement.argtypes = [C.c_void_p, C.c_int]
+        L.or_run_set_freeze.restype = C.c_int
+        L.or_run_set_freeze.argtypes = [C.c_void_p, C.c_int]
+        L.or_run_set_factor.restype = C.c_int
+        L.or_run_set_factor.argtypes = [C.c_void_p, _dp]
         L.or_rw_chain.restype = None
         L.or_rw_chain.argtypes = [C.c_void_p, _dp, _dp, C.c_double, _dp, C.c_double, C.c_int,
                                   C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, _lp,
@@ -235,8 +239,10 @@ class Run:
     """One NS run of the oracle: init, step until done, logz."""
 
     def __init__(self, problem: Problem, m, k, p, width, seed, run_id=0, term_frac=1e-3,
-                 stepout_cap=10, shrink_cap=100, threads=1, replacement="hrss"):
-        """replacement "hrss" (width = slice width) or "rw" (width = random-walk scale)."""
+                 stepout_cap=10, shrink_cap=100, threads=1, replacement="hrss",
+                 freeze_whitening=False):
+        """replacement "hrss" (width = slice width) or "rw" (width = random-walk scale);
+        freeze_whitening keeps the first iteration's whitening factor for the whole run."""
         self.P = problem
         self.m, self.k, self.p, self.d = m, k, p, problem.d
         self.threads = threads
@@ -246,7 +252,16 @@ class Run:
             raise ValueError("oracle rejected the run configuration")
         if lib().or_run_set_replacement(self.h, {"hrss": 0, "rw": 1}[replacement]) != 0:
             raise ValueError(replacement)
+        if lib().or_run_set_freeze(self.h, 1 if freeze_whitening else 0) != 0:
+            raise ValueError(freeze_whitening)
         self.done = False
+
+    def set_factor(self, L):
+        """Keep the lower-triangular factor L (d x d) as the whitening for the whole run
+        (runs with freeze_whitening only)."""
+        L = np.ascontiguousarray(L, np.float64)
+        if L.shape != (self.d, self.d) or lib().or_run_set_factor(self.h, L) != 0:
+            raise ValueError("a d x d factor on a run with frozen whitening")
 
     def __del__(self):
         if getattr(self, "h", None):

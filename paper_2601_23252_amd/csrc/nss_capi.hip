@@ -4,6 +4,7 @@
 #include "nss_internal.hpp"
 
 #include <math.h>
+#include <cmath>
 #include <stdio.h>
 #include <string.h>
 
@@ -922,6 +923,7 @@ static ns_status alloc_run(ns_ctx *ctx, int r)
     R.log_term = cfg->term_frac > 0.0 ? log(cfg->term_frac) : 0.0;
     set_key(R, cfg->seed, cfg->run_id);
     R.smc = cfg->outer == NS_OUTER_SMC;
+    R.freeze = (cfg->flags & NS_FLAG_FREEZE_WHITENING) && !R.smc;
     R.ess_frac = cfg->ess_frac;
     R.dead_cap = R.smc ? 1 : (long long)(cfg->max_iter + 1) * k;
     R.iscal = ctx->d_iscal + 8 * r;
@@ -1489,6 +1491,20 @@ extern "C" ns_status ns_set_state(ns_ctx *ctx, const ns_state_view *v)
     int is[8];
     CK(hipMemcpy(is, R.iscal, sizeof(is), hipMemcpyDeviceToHost));
     is[0] = 0; is[3] = (int)v->iter; is[4] = 0;
+    if (R.freeze && v->Lsig) {
+        // the caller's factor is kept for the run: both the row-major and the packed copy
+        std::vector<double> Ls((size_t)D * D, 0.0), pk((size_t)D * (D + 1) / 2, 0.0);
+        for (int a = 0; a < d; ++a)
+            for (int b = 0; b <= a; ++b) {
+                const double e = v->Lsig[(size_t)a * d + b];
+                if (!std::isfinite(e)) return fail(ctx, NS_EINVAL, "non-finite factor entry");
+                Ls[(size_t)a * D + b] = e;
+                pk[(size_t)a * (a + 1) / 2 + b] = e;
+            }
+        CK(hipMemcpy(R.Lsig, Ls.data(), Ls.size() * 8, hipMemcpyHostToDevice));
+        CK(hipMemcpy(R.Lpk, pk.data(), pk.size() * 8, hipMemcpyHostToDevice));
+        is[6] = 1;
+    }
     CK(hipMemcpy(R.iscal, is, sizeof(is), hipMemcpyHostToDevice));
     hipError_t e = launch_select(launch_one(ctx, 0), 2, ctx->stream);
     if (e != hipSuccess) return device_error(ctx, "select launch", e);

@@ -79,6 +79,7 @@ struct DevRun {
     double *dirbuf;        // [k][p][D] directions of the current iteration, or null (inline)
     double *ubuf;          // [k][p][8] per-step default plan (tL0, uh, 6 shrink), with dirbuf
     int rw;                // replacement by constrained random walk (width = its scale)
+    int freeze;            // whitening factor of the first iteration kept for the run
     int smc;               // adaptive tempered SMC outer loop (k = m chains, no hard constraint)
     double ess_frac;       // SMC: ESS target rho of the next temperature
     double *Xtmp, *Ltmp;   // SMC: gather buffers [D][m_pad], [m]

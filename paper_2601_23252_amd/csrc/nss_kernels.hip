@@ -281,6 +281,8 @@ __global__ __launch_bounds__(256) void k_cov(Launch Lc)
     const DevProblem P = Lc.P[bm.x];
     const DevRun R = Lc.R[bm.x];
     if (R.iscal[0]) return;
+    // frozen whitening: the first iteration's factor, or one the caller supplied, is kept
+    if (R.freeze && (R.iscal[3] > 0 || R.iscal[6])) return;
     const int d = P.d;
     const int nt = P.D / 16, ntile = nt * (nt + 1) / 2;
     const int G = R.covG;
@@ -332,6 +334,7 @@ __global__ __launch_bounds__(1024) void k_chol(Launch Lc)
     const DevProblem P = Lc.P[bm.x];
     const DevRun R = Lc.R[bm.x];
     if (R.iscal[0]) return;
+    if (R.freeze && (R.iscal[3] > 0 || R.iscal[6])) return;
     const int G = R.covG, ntile = (P.D / 16) * (P.D / 16 + 1) / 2;
     const double *part1 = R.part1, *part2 = R.part2;
     const int D = P.D, d = P.d, tid = threadIdx.x;

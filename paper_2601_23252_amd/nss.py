@@ -32,6 +32,7 @@ NS_FLAG_AUTOTUNE = 32
 NS_FLAG_SHALLOW_PLAN = 64
 NS_FLAG_PLAN8 = 128
 NS_FLAG_GP_NO_WAIT = 256
+NS_FLAG_FREEZE_WHITENING = 512
 PRECISIONS = {"fp64": NS_FP64, "bf16": NS_MIXED_BF16, "fp16": NS_MIXED_FP16,
               "bf16x3": NS_MIXED_BF16X3, "fp16x3": NS_MIXED_FP16X3, "fp32": NS_MIXED_FP32}
 # guard band of each mixed mode: (rel, abs) as set by the library
@@ -343,7 +344,8 @@ def make_config(m, k, p, width=0.0, seed=0, run_id=0, precision="fp64", term_fra
                 stepout_cap=10, shrink_cap=100, max_iter=100000, trace=False, timing=False,
                 inline_directions=False, graph=False, replacement="hrss", outer="ns",
                 ess_frac=0.5, record_points=False, autotune=False,
-                shallow_plan=False, plan8=False, gp_no_wait=False) -> ns_config:
+                shallow_plan=False, plan8=False, gp_no_wait=False,
+                freeze_whitening=False) -> ns_config:
     cfg = ns_config_default()
     cfg.n_live, cfg.k, cfg.chain_len = int(m), int(k), int(p)
     cfg.width = float(width)
@@ -359,7 +361,8 @@ def make_config(m, k, p, width=0.0, seed=0, run_id=0, precision="fp64", term_fra
                  | (NS_FLAG_AUTOTUNE if autotune else 0)
                  | (NS_FLAG_SHALLOW_PLAN if shallow_plan else 0)
                  | (NS_FLAG_PLAN8 if plan8 else 0)
-                 | (NS_FLAG_GP_NO_WAIT if gp_no_wait else 0))
+                 | (NS_FLAG_GP_NO_WAIT if gp_no_wait else 0)
+                 | (NS_FLAG_FREEZE_WHITENING if freeze_whitening else 0))
     cfg.replacement = REPLACEMENTS[replacement] if isinstance(replacement, str) else int(replacement)
     cfg.outer = OUTERS[outer] if isinstance(outer, str) else int(outer)
     cfg.ess_frac = float(ess_frac)
@@ -439,7 +442,7 @@ class NSRun:
                  max_iter=100000, trace=False, timing=False, inline_directions=False,
                  graph=False, stream="torch", replacement="hrss", outer="ns", ess_frac=0.5,
                  record_points=False, autotune=False, shallow_plan=False, plan8=False,
-                 gp_no_wait=False):
+                 gp_no_wait=False, freeze_whitening=False):
         self.prob = prob
         self.d = int(prob["d"])
         self.m = int(m or prob["m"])
@@ -451,7 +454,7 @@ class NSRun:
         cfg = make_config(self.m, self.k, self.p, width, seed, run_id, precision, term_frac,
                           stepout_cap, shrink_cap, max_iter, trace, timing, inline_directions,
                           graph, replacement, outer, ess_frac, record_points, autotune,
-                          shallow_plan, plan8, gp_no_wait)
+                          shallow_plan, plan8, gp_no_wait, freeze_whitening)
         self.cfg = cfg
         s = current_stream() if stream == "torch" else stream
         st, self.ctx = ns_init(pr, en, cfg, s)
@@ -500,11 +503,16 @@ class NSRun:
     def state(self) -> dict:
         return _state_of(self.ctx, 0, self.m, self.d, self.k)
 
-    def set_state(self, x, logL, logZ, logX, M, iter_, done=0):
+    def set_state(self, x, logL, logZ, logX, M, iter_, done=0, Lsig=None):
+        """ns_set_state; Lsig (d x d lower-triangular) is the factor kept by a run with
+        freeze_whitening=True."""
         x = np.ascontiguousarray(x, np.float64)
         logL = np.ascontiguousarray(logL, np.float64)
-        v = ns_state_view(_ptr(x), _ptr(logL), None, None, None, 0.0, float(logZ), float(logX),
-                          float(M), int(iter_), int(done))
+        Ls = None if Lsig is None else np.ascontiguousarray(Lsig, np.float64)
+        if Ls is not None and Ls.shape != (self.d, self.d):
+            raise ValueError("Lsig must be d x d")
+        v = ns_state_view(_ptr(x), _ptr(logL), None, None if Ls is None else _ptr(Ls), None,
+                          0.0, float(logZ), float(logX), float(M), int(iter_), int(done))
         _check(load().ns_set_state(self.ctx, C.byref(v)), self.ctx)
 
     def dead(self) -> np.ndarray:

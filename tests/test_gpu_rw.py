@@ -147,3 +147,85 @@ def test_rw_needs_the_direction_buffer(N):
     cfg = N.make_config(200, 50, 10, replacement="rw", inline_directions=True)
     st, ctx = N.ns_init(pr, en, cfg, None)
     assert st == N.NS_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("replacement", ["rw", "hrss"])
+def test_frozen_whitening_matches_oracle(N, oracle_lib, replacement):
+    """NS_FLAG_FREEZE_WHITENING (the first iteration's whitening kept for the run, a fixed
+    proposal scale): config 1 against the oracle with the same option, per iteration (the
+    factor stays that of iteration 1); the slice run to the end (identical ln Z).  The random
+    walk at the prior's scale stops moving as the contour contracts, its live set collapses to
+    copies of one point and the run ends in the plateau error; both sides stop there at the
+    same iteration."""
+    from oracle import theory as T
+    from paper_2601_23252_amd import problems as G
+    O = oracle_lib
+    prob = G.config1()
+    w = T.width_whitened(5) if replacement == "hrss" else 2.38 / math.sqrt(5)
+    orc = O.Run(O.Problem(prob), 200, 50, 25, w, 4, threads=8, replacement=replacement,
+                freeze_whitening=True)
+    orc.init()
+    gpu = N.NSRun(prob, p=25, width=w, seed=4, replacement=replacement, freeze_whitening=True)
+    L1 = None
+    for it in range(5):
+        orc.step()
+        gpu.step()
+        g, o = gpu.state(), orc.state()
+        Ls_o, par_o = orc.aux()
+        if L1 is None:
+            L1 = Ls_o.copy()
+        assert np.array_equal(Ls_o, L1)
+        assert np.allclose(g["Lsig"], L1, rtol=1e-9, atol=1e-12)
+        assert np.array_equal(g["parents"], par_o)
+        assert np.array_equal(g["perm"], o["perm"])
+        assert np.allclose(g["x"], o["x"], rtol=1e-10, atol=1e-12)
+    if replacement == "hrss":
+        orc.run()
+        gpu.run()
+        assert gpu.state()["iter"] == orc.state()["iter"]
+        assert abs(gpu.logz()[0] - orc.logz()[0]) <= 1e-9
+    else:
+        with pytest.raises(RuntimeError):
+            orc.run()
+        with pytest.raises(N.NSError):
+            gpu.run()
+        g, o = gpu.state(), orc.state()
+        assert g["iter"] == o["iter"]
+        assert np.allclose(g["x"], o["x"], rtol=1e-10, atol=1e-12)
+    gpu.close()
+
+
+def test_supplied_factor_matches_oracle(N, oracle_lib):
+    """A random walk whose proposal covariance is the target's (config 1: 0.01 I, so the
+    factor 0.1 I, kept for the run through ns_set_state on a frozen run) against the oracle
+    given the same factor: identical trajectory and ln Z; the factor never changes."""
+    from paper_2601_23252_amd import problems as G
+    O = oracle_lib
+    prob = G.config1()
+    L = 0.1 * np.eye(5)
+    s = 2.38 / math.sqrt(5)
+    orc = O.Run(O.Problem(prob), 200, 50, 25, s, 7, threads=8, replacement="rw",
+                freeze_whitening=True)
+    orc.init()
+    orc.set_factor(L)
+    gpu = N.NSRun(prob, p=25, width=s, seed=7, replacement="rw", freeze_whitening=True)
+    s0 = gpu.state()
+    assert np.array_equal(s0["x"], orc.state()["x"])
+    gpu.set_state(s0["x"], s0["logL"], s0["logZ"], s0["logX"], s0["M"], s0["iter"], Lsig=L)
+    for it in range(4):
+        orc.step()
+        gpu.step()
+        g, o = gpu.state(), orc.state()
+        assert np.array_equal(g["Lsig"], L) and np.array_equal(orc.aux()[0], L)
+        assert np.array_equal(g["perm"], o["perm"]), f"iter {it}"
+        assert np.allclose(g["x"], o["x"], rtol=1e-10, atol=1e-12), f"iter {it}"
+    orc.run()
+    gpu.run()
+    assert gpu.state()["iter"] == orc.state()["iter"]
+    assert abs(gpu.logz()[0] - orc.logz()[0]) <= 1e-9
+    bad = L.copy()
+    bad[1, 0] = np.nan
+    with pytest.raises(Exception):
+        gpu.set_state(s0["x"], s0["logL"], s0["logZ"], s0["logX"], s0["M"], s0["iter"],
+                      Lsig=bad)
+    gpu.close()

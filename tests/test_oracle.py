@@ -241,6 +241,28 @@ def test_whitening_factor_is_survivor_covariance(oracle_lib):
     assert set(par.tolist()) <= set(st["perm"][100:].tolist())
 
 
+def test_frozen_whitening_keeps_the_first_survivor_covariance(oracle_lib):
+    """With the whitening frozen, the factor stays the Cholesky factor of the first iteration's
+    survivor covariance (checked against numpy as above) while the live set contracts; the
+    adaptive run's factor shrinks with it."""
+    from paper_2601_23252_amd import problems as G
+    prob = G.config2(d=8, m=300, k=100)
+    P = oracle_lib.Problem(prob)
+    fz = oracle_lib.Run(P, 300, 100, 10, 4.0, 2, freeze_whitening=True)
+    ad = oracle_lib.Run(P, 300, 100, 10, 4.0, 2)
+    fz.init(); ad.init()
+    st = fz.state()
+    surv = st["x"][st["perm"][100:]]
+    C = np.cov(surv.T, bias=True)
+    C += 1e-12 * np.trace(C) / 8 * np.eye(8)
+    for _ in range(12):
+        fz.step(); ad.step()
+        Lf, _ = fz.aux()
+        assert np.allclose(Lf @ Lf.T, C, rtol=1e-10, atol=1e-13)
+    La, _ = ad.aux()
+    assert np.trace(La @ La.T) < 0.5 * np.trace(C)
+
+
 def _z_scores(oracle_lib, prob, truth_lnz, seeds, m=None, k=None, p=None, threads=8):
     from oracle import theory as T
     P = oracle_lib.Problem(prob)
@@ -898,3 +920,26 @@ def test_tied_survivors_get_no_parent_weight_and_plateau_is_an_error(oracle_lib)
     R.set_state(x, flat, -5.0, -1.0, 0.0, 1)
     with pytest.raises(RuntimeError):
         R.step()
+
+
+def test_supplied_factor_random_walk_lnz(oracle_lib):
+    """The random walk with a proposal matched to the target (config 1: covariance 0.01 I,
+    scale 2.38 / sqrt(d), the factor kept for the run): ln Z within 3.5 sigma of the closed
+    form on four seeds, and the factor is the one supplied throughout."""
+    from paper_2601_23252_amd import problems as G
+    prob = G.config1()
+    tz = truth.lnz_gauss_box_isotropic(5, 0.1, 1.0)
+    zs = []
+    for s in range(4):
+        R = oracle_lib.Run(oracle_lib.Problem(prob), 200, 50, 125, 2.38 / math.sqrt(5), s,
+                           threads=8, replacement="rw", freeze_whitening=True)
+        R.init()
+        R.set_factor(0.1 * np.eye(5))
+        R.run()
+        assert np.array_equal(R.aux()[0], 0.1 * np.eye(5))
+        lz, err, _ = R.logz()
+        zs.append((lz - tz) / err)
+    assert np.all(np.abs(zs) < 3.5), zs
+    plain = oracle_lib.Run(oracle_lib.Problem(prob), 200, 50, 5, 1.0, 0, replacement="rw")
+    with pytest.raises(ValueError):
+        plain.set_factor(np.eye(5))
