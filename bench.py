@@ -8,10 +8,14 @@ then iterations of whitening, direction generation, k parallel HRSS chains, repl
 delete-k and evidence accumulation until the remaining-evidence bound is below 1e-3 of Z, then
 the final live-set contribution.  The problem is uploaded once, before the timed region.
 
-The headline runs the workload's chain length p = 5d.  ``value`` counts only the evaluations of
-runs whose ln Z passes the 3 sigma check, divided by the wall time of all timed runs (the pass
-count is printed beside it, and ``rate_all_runs`` is the raw rate).  A labelled second leg runs
-the same workload at p = 20d.
+The headline runs the workload's chain length p = 5d with the direction metric from the
+survivors' variances (the diagonal restriction of the conditioning matrix that Sec. 3.2 suggests
+for high dimensions; with the full covariance the 8-mode mixture's metric is dominated by the
+spread between the modes and ln Z comes out far too high at p = 5d).  ``value`` counts only the
+evaluations of runs whose ln Z passes the 3 sigma check, divided by the wall time of all timed
+runs (the pass count is printed beside it, and ``rate_all_runs`` is the raw rate).  Labelled
+legs run the same workload with the full-covariance metric at p = 5d and at p = 20d, and the
+plain FP64 form with the headline's settings.
 
 Prints one JSON line (see the keys below).  --gpus N > 1 is not supported (one GPU).
 """
@@ -28,38 +32,56 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# HBM bytes per k_hrss launch from the FETCH_SIZE / WRITE_SIZE counter passes, each scaled by
-# the same counter on a copy of known size (FETCH x 2, WRITE x 1), keyed by (precision, chain
-# length), recorded for the kernel source with this sha256 prefix; reported as null once the
-# source differs or for a shape the counters were not taken on.
-TRAFFIC = {("bf16x3", 1280): 748.2e6}
-TRAFFIC_SOURCE_SHA = "3f0ca1613b567c08"
+# HBM bytes per launch of the chain kernel from the FETCH_SIZE / WRITE_SIZE counter passes, each
+# scaled by the same counter on a copy of known size (FETCH x 2, WRITE x 1), keyed by
+# (precision, chain length, chains per workgroup, planned tests per round), recorded for the
+# kernel sources with this sha256 prefix; reported as null once the sources differ or for a
+# shape the counters were not taken on.
+TRAFFIC = {("bf16x3", 320, 4, 8): 194.9e6, ("bf16x3", 320, 4, 16): 222.1e6}
+TRAFFIC_SOURCE_SHA = "5137e281ccfe634f"
 
 
-# VALU lane-instructions per evaluation issued by k_hrss over one full run of the mixture
-# workload (SQ_INSTS_VALU x 64 / evaluations), keyed like TRAFFIC, for the kernel source with
-# this prefix: the instruction view of the same kernel (its chain logic runs on the vector ALU).
-HRSS_VALU_PER_EVAL = {("bf16x3", 1280): 21995.0}
-HRSS_VALU_SOURCE_SHA = "3f0ca1613b567c08"
+# VALU lane-instructions per evaluation issued by the chain kernel (SQ_INSTS_VALU x 64 /
+# evaluations of the profiled launches), keyed like TRAFFIC, for the kernel sources with this
+# prefix: the instruction view of the same kernel (its chain logic runs on the vector ALU).
+HRSS_VALU_PER_EVAL = {("bf16x3", 320, 4, 8): 24911.0, ("bf16x3", 320, 4, 16): 29313.0}
+HRSS_VALU_SOURCE_SHA = "5137e281ccfe634f"
+
+KERNEL_SOURCES = ("nss_kernels.hip", "nss_hrss_plan.hip", "nss_tiles.hpp", "nss_internal.hpp")
 
 
 def _kernel_sha():
+    """sha256 prefix over the chain kernels' sources (the counters above hold for them only)."""
     import hashlib
-    src = os.path.join(ROOT, "paper_2601_23252_amd", "csrc", "nss_kernels.hip")
-    with open(src, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2601_23252_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
-def hrss_valu_per_eval(precision, p):
+def _shape_key(precision, p, shape):
+    return (precision, p, shape.get("chains_per_workgroup"), shape.get("tests_per_round"))
+
+
+def hrss_valu_per_eval(precision, p, shape):
     if _kernel_sha() != HRSS_VALU_SOURCE_SHA:
         return None
-    return HRSS_VALU_PER_EVAL.get((precision, p))
+    return HRSS_VALU_PER_EVAL.get(_shape_key(precision, p, shape))
 
 
-def kernel_traffic(precision, p):
+def kernel_traffic(precision, p, shape):
     if _kernel_sha() != TRAFFIC_SOURCE_SHA:
         return None
-    return TRAFFIC.get((precision, p))
+    return TRAFFIC.get(_shape_key(precision, p, shape))
+
+
+def chain_kernel_name(precision, shape):
+    """The chain kernel a launch shape runs: the planned-test kernel for 8 or 16 tests per
+    round, else the 4-test kernel."""
+    mode = {"fp64": 0, "bf16": 1, "fp16": 2, "bf16x3": 3, "fp16x3": 4}.get(precision)
+    plan = shape.get("tests_per_round")
+    return ("k_hrss_plan" if plan in (8, 16) else "k_hrss") + f" (mode {mode}, {plan} tests)"
 
 
 def algorithmic_flop_per_eval(K: int, d: int) -> int:
@@ -68,12 +90,13 @@ def algorithmic_flop_per_eval(K: int, d: int) -> int:
     return K * d * (d + 1) + 3 * K * d
 
 
-def run_gpu(N, prob, precision, seeds, p, warmup, timing=True, autotune=True, shape_out=None):
+def run_gpu(N, prob, precision, seeds, p, warmup, timing=True, autotune=True, shape_out=None,
+            diagonal_metric=False):
     """Runs len(seeds) full NS runs on one context (the launch shape tuned during the warmup
     runs, or on the first timed run without warmup); returns per-run records and totals."""
     import torch
     R = N.NSRun(prob, p=p, seed=seeds[0], precision=precision, timing=timing,
-                autotune=autotune)
+                autotune=autotune, diagonal_metric=diagonal_metric)
     for w in range(warmup):
         R.reset(10_000 + w)
         R.run()
@@ -104,7 +127,7 @@ def run_gpu(N, prob, precision, seeds, p, warmup, timing=True, autotune=True, sh
     return recs, total
 
 
-def cpu_baseline(prob, p, seconds_budget=20.0, warm_iters=None):
+def cpu_baseline(prob, p, seconds_budget=20.0, warm_iters=None, diagonal_metric=False):
     """The FP64 oracle on the host cores, built for this host (-O3 -march=native): iterations of
     the same workload from a mid-run live set until the time budget; evals/s over the timed
     iterations.  The mid-run state comes from the oracle itself: warm_iters iterations with a
@@ -121,7 +144,7 @@ def cpu_baseline(prob, p, seconds_budget=20.0, warm_iters=None):
     dt = 0.0
     seed = 0
     while dt < seconds_budget:
-        warm = O.Run(P, m, k, 4, w, seed, threads=threads)
+        warm = O.Run(P, m, k, 4, w, seed, threads=threads, diagonal_metric=diagonal_metric)
         warm.init()
         for _ in range(warm_iters):
             if warm.done:
@@ -129,7 +152,7 @@ def cpu_baseline(prob, p, seconds_budget=20.0, warm_iters=None):
             warm.step()
         ws = warm.state()
         del warm
-        run = O.Run(P, m, k, p, w, seed, threads=threads)
+        run = O.Run(P, m, k, p, w, seed, threads=threads, diagonal_metric=diagonal_metric)
         run.init()
         run.set_state(ws["x"], ws["logL"], ws["logZ"], ws["logX"], ws["M"], ws["iter"])
         e0 = run.state()["evals"]
@@ -145,7 +168,8 @@ def cpu_baseline(prob, p, seconds_budget=20.0, warm_iters=None):
                 sample=f"{iters} iterations over {runs} run(s) (seeds 0..{runs - 1}) of the same "
                        f"workload (p={p}), each from the live set after {warm_iters} iterations "
                        f"of a 4-step chain, {ev} evaluations in {dt:.1f} s, OpenMP over chains "
-                       "on every host thread, oracle built -O3 -march=native", **host_info())
+                       "on every host thread, oracle built -O3 -march=native"
+                       + (", diagonal metric" if diagonal_metric else ""), **host_info())
 
 
 def host_info():
@@ -172,10 +196,11 @@ def profile_run(args):
     dst.copy_(src)
     torch.cuda.synchronize()
     prob = G.config3()
-    kw = {"tuned": dict(autotune=True), "rule": {}, "shallow": dict(shallow_plan=True),
+    kw = {"tuned": dict(autotune=True), "rule": {}, "plan8": dict(plan8=True),
+          "shallow": dict(shallow_plan=True),
           "inline": dict(shallow_plan=True, inline_directions=True)}[args.profile_shape]
     R = N.NSRun(prob, p=args.chain_factor * prob["d"], seed=0, precision=args.precision,
-                timing=True, **kw)
+                timing=True, diagonal_metric=args.metric == "diagonal", **kw)
     t0 = time.perf_counter()
     for _ in range(args.profile_iters):
         R.step()
@@ -482,7 +507,10 @@ def _rastrigin_table(args):
             for sd in range(1, 1 + args.table_seeds):
                 Q = N.NSRun(G.rastrigin_gauss(dd, a, k=args.table_k), seed=sd)
                 t0 = time.perf_counter()
-                Q.run()
+                while not Q.state()["done"]:   # in slices of 200 iterations, with progress
+                    Q.run(max_iter=200)
+                    print(f"[bench]   d={dd} alpha={a}: {Q.state()['iter']} iterations, "
+                          f"{time.perf_counter() - t0:.0f} s", file=sys.stderr, flush=True)
                 z, err, _ = Q.logz()
                 t = lnz_rastrigin_gauss(dd, a)
                 table.append({"d": dd, "alpha": a, "k": args.table_k, "seed": sd, "logz": z,
@@ -835,7 +863,12 @@ def prec_key(p):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5, help="timed full runs (seeds 0..K-1)")
+    ap.add_argument("--steps", type=int, default=10, help="timed full runs (seeds 0..K-1)")
+    ap.add_argument("--metric", default="diagonal", choices=["diagonal", "full"],
+                    help="headline direction metric: the survivors' variances (the diagonal "
+                         "restriction of Sec. 3.2) or their full covariance")
+    ap.add_argument("--other-metric-steps", type=int, default=5,
+                    help="runs of the labelled line with the other direction metric (0 = skip)")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", default="bf16x3",
                     choices=["bf16", "fp16", "bf16x3", "fp16x3", "fp64"])
@@ -844,16 +877,17 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=3, help="FP64 comparison runs (0 = skip)")
     ap.add_argument("--long-chain-factor", type=int, default=20,
                     help="chain length factor of the labelled long-chain line")
-    ap.add_argument("--long-chain-steps", type=int, default=10,
-                    help="runs of the long-chain line (0 = skip)")
+    ap.add_argument("--long-chain-steps", type=int, default=5,
+                    help="runs of the long-chain line (full-covariance metric; 0 = skip)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the launch-shape rule (4 chains per workgroup, 16 planned tests "
                          "for 16-bit mixture chains) instead of timing the candidates")
     ap.add_argument("--profile-shape", default="tuned",
-                    choices=["tuned", "rule", "shallow", "inline"],
-                    help="profiling run: the chains' launch shape (tuned, the rule, the 4-test "
-                         "kernel, or the 4-test kernel drawing its directions inline)")
+                    choices=["tuned", "rule", "plan8", "shallow", "inline"],
+                    help="profiling run: the chains' launch shape (tuned, the rule, 8 planned "
+                         "tests per round, the 4-test kernel, or the 4-test kernel drawing its "
+                         "directions inline)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--workload", default="mixture8_d64",
                     choices=["mixture8_d64", "gp_n256", "batch256", "geom", "rastrigin",
@@ -935,8 +969,9 @@ def main():
 
     seeds = list(range(args.steps))
     shape = {}
+    diag = args.metric == "diagonal"
     recs, total = run_gpu(N, prob, args.precision, seeds, p, args.warmup,
-                          autotune=not args.no_autotune, shape_out=shape)
+                          autotune=not args.no_autotune, shape_out=shape, diagonal_metric=diag)
     head = summary(recs, total)
     evals = sum(r["evals"] for r in recs)
     hrss_s = sum(r["hrss_ms"] for r in recs) / 1e3
@@ -960,7 +995,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": "mixture8_d64_uniform10_nlive2000_k1000", "d": d, "n_comp": K,
                    "n_live": prob["m"], "k": prob["k"], "chain_len": p,
-                   "precision": args.precision, "term_frac": 1e-3, "seeds": seeds},
+                   "precision": args.precision, "term_frac": 1e-3, "seeds": seeds,
+                   "direction_metric": "survivor variances (diagonal)" if diag
+                   else "survivor covariance (full)"},
         "value_rule": "evaluations of the runs with |ln Z + 64 ln 20| < 3 sqrt(H/n_live), "
                       "divided by the wall time of all timed runs",
         "runs_within_3sigma": head["runs_within_3sigma"],
@@ -968,8 +1005,8 @@ def main():
         "launch_shape": shape,
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / peak,
-                     "traffic": kernel_traffic(args.precision, p),
-                     "kernel": "k_hrss", "flop_per_eval": fpe,
+                     "traffic": kernel_traffic(args.precision, p, shape),
+                     "kernel": chain_kernel_name(args.precision, shape), "flop_per_eval": fpe,
                      "avg_launch_ms": 1e3 * hrss_s / max(1, launches)},
         "lnz": {"truth": truth, "z_scores": head["z_scores"], "z_mean": head["z_mean"],
                 "z_sd": head["z_sd"], "logz": head["logz"], "sigma": head["sigma"]},
@@ -982,15 +1019,16 @@ def main():
         "band_violations": sum(r["band_violations"] for r in recs),
         "iterations": head["iterations"],
     }
-    vpe = hrss_valu_per_eval(args.precision, p)
+    vpe = hrss_valu_per_eval(args.precision, p, shape)
     if vpe is not None and hrss_s > 0:
         a = vpe * evals / hrss_s
-        out["valu_issue"] = {"kernel": "k_hrss", "lane_instr_per_eval": vpe,
+        out["valu_issue"] = {"kernel": chain_kernel_name(args.precision, shape),
+                             "lane_instr_per_eval": vpe,
                              "achieved": a / 1e12, "peak": VALU_PEAK / 1e12,
                              "unit": "T lane-instr/s", "frac": a / VALU_PEAK}
     if args.fp64_steps > 0 and mixed:
         r64, t64 = run_gpu(N, prob, "fp64", list(range(args.fp64_steps)), p, 1,
-                           autotune=not args.no_autotune)
+                           autotune=not args.no_autotune, diagonal_metric=diag)
         s64 = summary(r64, t64)
         ev64 = sum(r["evals"] for r in r64)
         out["fp64"] = {"value": s64["value"], "rate_all_runs": s64["rate_all_runs"],
@@ -1002,20 +1040,33 @@ def main():
                            and abs(a["logz"] - b["logz"]) < 1e-9 for a, b in zip(r64, recs)],
                        "hrss_frac_of_fp64_peak": ev64 * fpe / (sum(r["hrss_ms"] for r in r64) / 1e3) / 78.6e12}
         out["speedup_vs_fp64"] = head["rate_all_runs"] / s64["rate_all_runs"]
+    if args.other_metric_steps > 0:
+        # the same workload and chain length with the other direction metric
+        ro, to = run_gpu(N, prob, args.precision, list(range(args.other_metric_steps)), p, 0,
+                         autotune=not args.no_autotune, diagonal_metric=not diag)
+        so = summary(ro, to)
+        out["other_metric"] = {
+            "label": "the same workload at p = 5d with the direction metric from the survivors' "
+                     + ("full covariance (the paper's default)" if diag
+                        else "variances alone (diagonal)"),
+            "value": so["value"], "rate_all_runs": so["rate_all_runs"], "unit": "evals/s",
+            "runs_within_3sigma": so["runs_within_3sigma"], "z_scores": so["z_scores"],
+            "z_mean": so["z_mean"], "z_sd": so["z_sd"]}
     if args.long_chain_steps > 0:
         pl = args.long_chain_factor * d
         rl, tl = run_gpu(N, prob, args.precision, list(range(args.long_chain_steps)), pl, 0,
-                         autotune=not args.no_autotune)
+                         autotune=not args.no_autotune, diagonal_metric=False)
         sl = summary(rl, tl)
         out["long_chain"] = {"label": f"the same workload at chain length p = "
-                                      f"{args.long_chain_factor}d = {pl} (not the configured 5d)",
+                                      f"{args.long_chain_factor}d = {pl} (not the configured "
+                                      "5d), full-covariance metric",
                              "chain_len": pl, "value": sl["value"],
                              "rate_all_runs": sl["rate_all_runs"], "unit": "evals/s",
                              "runs_within_3sigma": sl["runs_within_3sigma"],
                              "z_scores": sl["z_scores"], "z_mean": sl["z_mean"],
                              "z_sd": sl["z_sd"], "iterations": sl["iterations"]}
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(prob, p, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(prob, p, args.cpu_seconds, diagonal_metric=diag)
     print(json.dumps(out), flush=True)
 
 

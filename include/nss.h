@@ -130,7 +130,10 @@ typedef struct {
     uint64_t seed;        /* Philox key: (seed_lo, seed_hi ^ run_id) */
     uint32_t run_id;
     int32_t precision;    /* ns_precision */
-    int32_t max_iter;     /* capacity of the dead-point record in iterations (>= 1) */
+    int32_t max_iter;     /* upper bound of the dead-point record in iterations (>= 1): the
+                           * record starts at min(max_iter + 1, 512) iterations and doubles
+                           * between launches as the run proceeds (ns_step / ns_run return
+                           * NS_ENOMEM if that allocation fails) */
     int32_t flags;        /* NS_FLAG_* */
     int32_t replacement;  /* ns_replacement: the constrained kernel that replaces deleted
                            * points (Sec. 3.1 "Replacement strategies"); default HRSS */
@@ -177,19 +180,24 @@ typedef enum {
                                       * of k*p*(d+8) doubles (the buffer is also skipped when
                                       * it would exceed 32 GiB; not for d > 128) */
 #define NS_FLAG_RECORD_POINTS 16  /* keep the dead points' coordinates beside their logL
-                                  * ((max_iter + 1) k d doubles) for ns_posterior_samples */
+                                  * (k d doubles per iteration, grown like the dead
+                                  * record) for ns_posterior_samples */
 #define NS_FLAG_AUTOTUNE 32  /* choose the launch shape of each compiled kernel group's
                               * chains by timing: chains per workgroup (1..4) and, for mixture
                               * chains in a 16-bit mode, tests planned per round (4, 8 or 16).
-                              * At the group's first iteration, after whitening and directions,
-                              * the state the chains change is saved, every candidate's chain
-                              * launch is timed twice on it (the state restored each time), the
-                              * fastest is kept and the iteration completes with it.  The choice
-                              * is cached for later contexts of the same shape (padded
-                              * dimension, likelihood, precision, fragment capacity,
-                              * replacement, total chains, plan kernel allowed) in this process.
-                              * Results are identical with and without it.  Not used by
-                              * NS_LIK_GP (one chain per workgroup). */
+                              * At the context's iterations 0, 32 and 96 (counted from the
+                              * runs' start or reset), after whitening and directions, the state
+                              * the chains change is saved, every candidate's chain launch is
+                              * timed twice on it (the state restored each time), each
+                              * candidate's best time is added to its sum, and the iteration
+                              * completes with the shape of least sum so far: the chains'
+                              * behaviour changes over a run, so one early iteration would
+                              * mislead.  The current choice is cached for later contexts of
+                              * the same shape (padded dimension, likelihood, precision,
+                              * fragment capacity, replacement, total chains, plan kernel
+                              * allowed) in this process, which then do not tune.  Results are
+                              * identical with and without it.  Not used by NS_LIK_GP (one chain
+                              * per workgroup). */
 #define NS_FLAG_SHALLOW_PLAN 64  /* mixture chains in a 16-bit mode plan at most 4 tests per
                                  * round (the two bracket ends, then shrink proposals) instead
                                  * of 16 (the next two stepping-out tests of each open end and
@@ -210,6 +218,12 @@ typedef enum {
                                       * run: a proposal scale fixed over the run, the variant
                                       * the slice-versus-random-walk comparison contrasts with
                                       * the adaptive default.  Not for NS_OUTER_SMC. */
+#define NS_FLAG_DIAGONAL_METRIC 1024  /* the direction metric (whitening) from the
+                                      * survivors' variances alone, a diagonal conditioning
+                                      * matrix, instead of their full covariance: the
+                                      * restriction Sec. 3.2 suggests for high dimensions.
+                                      * Applies to slice and random-walk chains and to the
+                                      * tempered-SMC mutation. */
 #define NS_FLAG_GRAPH  8  /* ns_run captures each batch of 16 iterations as a HIP graph and
                            * replays it (re-captured when a run of the batch finishes); not
                            * used together with NS_FLAG_TIMING.  Results are identical. */

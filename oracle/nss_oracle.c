@@ -599,6 +599,7 @@ typedef struct {
     int replacement;  /* 0: HRSS (width = slice width); 1: random walk (width = step scale) */
     int freeze;       /* 1: the whitening factor of the first iteration is kept for the run */
     int held;         /* 1: a caller-supplied factor is kept (freeze only; no whitening at all) */
+    int diag;         /* 1: the metric keeps only the survivors' variances (diagonal M) */
     /* adaptive tempered SMC (or_smc_*): all m particles move each step */
     int smc;
     double beta, ess_frac;
@@ -756,6 +757,10 @@ static void whiten(orun *r)
         tr += C[a * d + a];
     }
     for (int a = 0; a < d; ++a) C[a * d + a] += 1e-12 * tr / d;
+    if (r->diag)   /* a diagonal conditioning matrix: the variances alone */
+        for (int a = 0; a < d; ++a)
+            for (int b = 0; b < d; ++b)
+                if (a != b) C[a * d + b] = 0.0;
     if (cholesky_lower(C, r->Lsig, d) != 0) {
         r->whiten_fallbacks++;
         memset(r->Lsig, 0, sizeof(double) * (size_t)d * d);
@@ -966,6 +971,16 @@ int or_run_set_freeze(void *rr, int on)
     orun *r = (orun *)rr;
     if (!r || (on != 0 && on != 1)) return -1;
     r->freeze = on;
+    return 0;
+}
+
+/* Direction metric from the survivors' full covariance (0, the default) or from their
+ * variances alone (1): the diagonal restriction the paper suggests for high dimensions. */
+int or_run_set_diag(void *rr, int on)
+{
+    orun *r = (orun *)rr;
+    if (!r || (on != 0 && on != 1)) return -1;
+    r->diag = on;
     return 0;
 }
 

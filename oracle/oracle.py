@@ -116,6 +116,8 @@ def lib():
         L.or_run_set_freeze.restype = C.c_int
         L.or_run_set_freeze.argtypes = [C.c_void_p, C.c_int]
         L.or_run_set_factor.restype = C.c_int
+        L.or_run_set_diag.restype = C.c_int
+        L.or_run_set_diag.argtypes = [C.c_void_p, C.c_int]
         L.or_run_set_factor.argtypes = [C.c_void_p, _dp]
         L.or_rw_chain.restype = None
         L.or_rw_chain.argtypes = [C.c_void_p, _dp, _dp, C.c_double, _dp, C.c_double, C.c_int,
@@ -240,9 +242,10 @@ class Run:
 
     def __init__(self, problem: Problem, m, k, p, width, seed, run_id=0, term_frac=1e-3,
                  stepout_cap=10, shrink_cap=100, threads=1, replacement="hrss",
-                 freeze_whitening=False):
+                 freeze_whitening=False, diagonal_metric=False):
         """replacement "hrss" (width = slice width) or "rw" (width = random-walk scale);
-        freeze_whitening keeps the first iteration's whitening factor for the whole run."""
+        freeze_whitening keeps the first iteration's whitening factor for the whole run;
+        diagonal_metric whitens by the survivors' variances alone."""
         self.P = problem
         self.m, self.k, self.p, self.d = m, k, p, problem.d
         self.threads = threads
@@ -254,6 +257,8 @@ class Run:
             raise ValueError(replacement)
         if lib().or_run_set_freeze(self.h, 1 if freeze_whitening else 0) != 0:
             raise ValueError(freeze_whitening)
+        if lib().or_run_set_diag(self.h, 1 if diagonal_metric else 0) != 0:
+            raise ValueError(diagonal_metric)
         self.done = False
 
     def set_factor(self, L):

@@ -27,6 +27,7 @@ struct RunHost {
     const uint4 *wf_bf16 = nullptr, *wf_fp16 = nullptr, *wf_bf16_lo = nullptr,
                 *wf_fp16_lo = nullptr;
     int done = 0;
+    long long deaths_bound = 0;   // upper bound of the deaths recorded once the issued work ends
 };
 
 // Runs that share one compiled HRSS kernel: (padded dimension, likelihood, precision, fragment
@@ -47,6 +48,9 @@ struct Shape {
 // tuned (at its next iteration).
 struct GroupTune {
     std::vector<Shape> cand;
+    std::vector<double> sum;   // per candidate: its best times summed over the points taken
+    int points = 0;            // tuning points taken
+    long long next_at = 0;     // context iteration of the next tuning point
     bool done = true;
 };
 
@@ -87,6 +91,7 @@ struct ns_ctx {
     int autotune = 0;
     std::vector<GroupTune> tune;     // per group
     long long tune_launches = 0;     // HRSS launches timed by the tuner
+    long long iters_issued = 0;      // outer iterations issued since the runs started
     // per run: the state an HRSS launch changes (live points, logL, counters), saved before the
     // tuner's candidate launches and restored after each (allocated on first use)
     std::vector<double *> snap_x, snap_l;
@@ -633,10 +638,16 @@ static ns_status collect_events(ns_ctx *ctx)
 // the 16-bit mixture chains the tests planned per round).  A chain's decisions and arithmetic
 // do not depend on the shape, so every candidate is timed on the same iteration: after the
 // whitening and directions, the state the chains change is saved, each candidate's HRSS
-// launch is timed and the state restored, kTuneReps times over; the group keeps the fastest
-// and the iteration then runs with it.  The choice is cached per group shape in this process.
+// launch is timed and the state restored, kTuneReps times over (the minimum counts), and the
+// iteration then runs with the shape of least summed time so far.  The chains' behaviour
+// changes over a run (early contours are wide and brackets expand often, later ones rarely),
+// so this is done at kTunePoints iterations spread over the run's start (kTuneAt) and the
+// candidates are ranked by their summed times.  The current choice is cached per group shape
+// in this process after every point; a context whose shape is cached does not tune.
 // ------------------------------------------------------------------------------------------
-constexpr int kTuneReps = 2;   // timed launches per candidate (the minimum counts)
+constexpr int kTuneReps = 2;   // timed launches per candidate and point
+constexpr int kTunePoints = 3;
+constexpr long long kTuneAt[kTunePoints] = {0, 32, 96};   // context iterations of the points
 
 static std::mutex g_tune_mu;
 // group shape -> (chains per workgroup, planned tests per round)
@@ -664,10 +675,20 @@ static ns_status set_group_shape(ns_ctx *ctx, size_t g, Shape sh)
     return NS_OK;
 }
 
-static bool tuning_pending(const ns_ctx *ctx)
+// Group g still has tuning points to take and unfinished runs to take them on.
+static bool tune_waiting(const ns_ctx *ctx, size_t g)
 {
-    for (const GroupTune &t : ctx->tune)
-        if (!t.done) return true;
+    if (ctx->tune[g].done) return false;
+    for (int r : ctx->groups[g].runs)
+        if (!ctx->runs[r].done) return true;
+    return false;
+}
+
+// A tuning point is due at this iteration for some group.
+static bool tuning_due(const ns_ctx *ctx)
+{
+    for (size_t g = 0; g < ctx->tune.size(); ++g)
+        if (tune_waiting(ctx, g) && ctx->iters_issued >= ctx->tune[g].next_at) return true;
     return false;
 }
 
@@ -706,7 +727,7 @@ static ns_status tune_iteration(ns_ctx *ctx)
     if (st != NS_OK) return st;
     for (size_t g = 0; g < ctx->groups.size(); ++g) {
         GroupTune &t = ctx->tune[g];
-        if (t.done) continue;
+        if (!tune_waiting(ctx, g) || ctx->iters_issued < t.next_at) continue;
         if ((st = group_state(ctx, g, 0)) != NS_OK) return st;
         const size_t nc = t.cand.size();
         std::vector<double> best(nc, 1e300);
@@ -734,12 +755,17 @@ static ns_status tune_iteration(ns_ctx *ctx)
                 if (ms < best[ci]) best[ci] = ms;
             }
         }
+        t.sum.resize(nc, 0.0);
         size_t bi = 0;
-        for (size_t ci = 1; ci < nc; ++ci)
-            if (best[ci] < best[bi]) bi = ci;
+        for (size_t ci = 0; ci < nc; ++ci) {
+            t.sum[ci] += best[ci];
+            if (t.sum[ci] < t.sum[bi]) bi = ci;
+        }
         if ((st = set_group_shape(ctx, g, t.cand[bi])) != NS_OK) return st;
         if ((st = group_state(ctx, g, 1)) != NS_OK) return st;
-        t.done = true;
+        t.points += 1;
+        t.done = t.points >= kTunePoints;
+        if (!t.done) t.next_at = kTuneAt[t.points];
         std::lock_guard<std::mutex> lk(g_tune_mu);
         g_tuned[tune_key(ctx, ctx->groups[g])] = t.cand[bi];
     }
@@ -748,6 +774,56 @@ static ns_status tune_iteration(ns_ctx *ctx)
 }
 
 // Prior draws, FP64 evaluation and first delete-k of every run; resets every run counter.
+// Replaces the allocation `old` (owned by the context) with `nw`, freeing `old`.
+static void swap_alloc(ns_ctx *ctx, void *old, void *nw)
+{
+    for (void *&p : ctx->allocs)
+        if (p == old) { p = nw; break; }
+    (void)hipFree(old);
+}
+
+// Makes room in every unfinished run's dead record for the deaths of `iters` more iterations:
+// a record that could overflow is reallocated at twice its size (or what is needed, up to
+// max_iter + 1 iterations), its contents copied, and the run's device descriptor updated.
+// The kernels read the record's address from the descriptor, so captured graphs stay valid.
+static ns_status reserve_dead(ns_ctx *ctx, int iters)
+{
+    bool synced = false;
+    for (int r = 0; r < ctx->n; ++r) {
+        RunHost &rh = ctx->runs[r];
+        DevRun &R = rh.R;
+        if (rh.done || R.smc) continue;
+        rh.deaths_bound += (long long)iters * rh.k;
+        const long long maxcap = (long long)(rh.cfg.max_iter + 1) * rh.k;
+        if (rh.deaths_bound <= R.dead_cap || R.dead_cap >= maxcap) continue;
+        long long cap = rh.deaths_bound > 2 * R.dead_cap ? rh.deaths_bound : 2 * R.dead_cap;
+        if (cap > maxcap) cap = maxcap;
+        if (!synced) {
+            CK(hipStreamSynchronize(ctx->stream));
+            synced = true;
+        }
+        double *nd = nullptr, *nx = nullptr;
+        if (hipMalloc((void **)&nd, (size_t)cap * 8) != hipSuccess)
+            return fail(ctx, NS_ENOMEM, "growing the dead record failed");
+        if (R.deadx && hipMalloc((void **)&nx, (size_t)cap * rh.d * 8) != hipSuccess) {
+            (void)hipFree(nd);
+            return fail(ctx, NS_ENOMEM, "growing the dead points' record failed");
+        }
+        CK(hipMemcpy(nd, R.dead, (size_t)R.dead_cap * 8, hipMemcpyDeviceToDevice));
+        swap_alloc(ctx, R.dead, nd);
+        R.dead = nd;
+        if (R.deadx) {
+            CK(hipMemcpy(nx, R.deadx, (size_t)R.dead_cap * rh.d * 8, hipMemcpyDeviceToDevice));
+            swap_alloc(ctx, R.deadx, nx);
+            R.deadx = nx;
+        }
+        R.dead_cap = cap;
+        CK(hipMemcpy(ctx->dR + r, &R, sizeof(DevRun), hipMemcpyHostToDevice));
+        if (r == 0) CK(hipMemcpy(ctx->dR + ctx->n, &R, sizeof(DevRun), hipMemcpyHostToDevice));
+    }
+    return NS_OK;
+}
+
 static ns_status start_runs(ns_ctx *ctx)
 {
     const int n = ctx->n;
@@ -759,7 +835,11 @@ static ns_status start_runs(ns_ctx *ctx)
         if (R.trace) CK(hipMemsetAsync(R.trace, 0, (size_t)rh.k * rh.p * 16, ctx->stream));
         if (R.prof) CK(hipMemsetAsync(R.prof, 0, 16 * 8, ctx->stream));
         rh.done = 0;
+        rh.deaths_bound = rh.k;   // the first deletion
     }
+    ctx->iters_issued = 0;
+    for (GroupTune &t : ctx->tune)   // pending tuning points count from the new start
+        if (!t.done) t.next_at = kTuneAt[t.points];
     CK(hipMemsetAsync(ctx->d_iscal, 0, (size_t)n * 8 * sizeof(int), ctx->stream));
     CK(hipMemsetAsync(ctx->d_ctr, 0, (size_t)n * 16 * 8, ctx->stream));
     std::vector<double> sc((size_t)n * 8, 0.0);
@@ -924,8 +1004,13 @@ static ns_status alloc_run(ns_ctx *ctx, int r)
     set_key(R, cfg->seed, cfg->run_id);
     R.smc = cfg->outer == NS_OUTER_SMC;
     R.freeze = (cfg->flags & NS_FLAG_FREEZE_WHITENING) && !R.smc;
+    R.diag = (cfg->flags & NS_FLAG_DIAGONAL_METRIC) ? 1 : 0;
     R.ess_frac = cfg->ess_frac;
-    R.dead_cap = R.smc ? 1 : (long long)(cfg->max_iter + 1) * k;
+    // the dead record starts at kDeadInitIters iterations and grows between launches
+    // (reserve_dead), up to max_iter + 1 iterations
+    R.dead_cap = R.smc ? 1
+                       : (long long)(cfg->max_iter + 1 < kDeadInitIters ? cfg->max_iter + 1
+                                                                         : kDeadInitIters) * k;
     R.iscal = ctx->d_iscal + 8 * r;
     R.scal = ctx->d_scal + 8 * r;
     R.ctr = ctx->d_ctr + 16 * r;
@@ -1177,8 +1262,11 @@ extern "C" ns_status ns_step(ns_ctx *ctx, int32_t *done)
         if (done) *done = 1;
         return NS_DONE;
     }
-    ns_status st = tuning_pending(ctx) ? tune_iteration(ctx) : enqueue_iteration(ctx);
+    ns_status st = reserve_dead(ctx, 1);
     if (st != NS_OK) return st;
+    st = tuning_due(ctx) ? tune_iteration(ctx) : enqueue_iteration(ctx);
+    if (st != NS_OK) return st;
+    ctx->iters_issued += 1;
     if ((st = sync_flags(ctx)) != NS_OK) return st;
     if ((st = collect_events(ctx)) != NS_OK) return st;
     if ((st = refresh_maps(ctx)) != NS_OK) return st;
@@ -1227,15 +1315,21 @@ extern "C" ns_status ns_run(ns_ctx *ctx, int32_t max_iter, int32_t *iters)
     std::vector<int> start(ctx->n);
     for (int r = 0; r < ctx->n; ++r) start[r] = ctx->h_iscal[8 * r + 3];
     int issued = 0;
-    while (!all_done(ctx) && issued < max_iter && tuning_pending(ctx)) {   // one at a time
-        if ((st = refresh_maps(ctx)) != NS_OK) return st;
-        if ((st = tune_iteration(ctx)) != NS_OK) return st;
-        issued += 1;
-        if ((st = sync_flags(ctx)) != NS_OK) return st;
-    }
     while (!all_done(ctx) && issued < max_iter) {
         if ((st = refresh_maps(ctx)) != NS_OK) return st;
-        const int batch = (max_iter - issued) < kGraphIters ? (max_iter - issued) : kGraphIters;
+        if (tuning_due(ctx)) {   // a tuning iteration, alone
+            if ((st = reserve_dead(ctx, 1)) != NS_OK) return st;
+            if ((st = tune_iteration(ctx)) != NS_OK) return st;
+            issued += 1;
+            ctx->iters_issued += 1;
+            if ((st = sync_flags(ctx)) != NS_OK) return st;
+            continue;
+        }
+        int batch = (max_iter - issued) < kGraphIters ? (max_iter - issued) : kGraphIters;
+        for (size_t g = 0; g < ctx->tune.size(); ++g)   // stop at the next tuning point
+            if (tune_waiting(ctx, g) && ctx->tune[g].next_at - ctx->iters_issued < batch)
+                batch = (int)(ctx->tune[g].next_at - ctx->iters_issued);
+        if ((st = reserve_dead(ctx, batch)) != NS_OK) return st;
         if (ctx->use_graph && !ctx->timing && batch == kGraphIters) {
             if ((st = launch_graph_batch(ctx)) != NS_OK) return st;
         } else {
@@ -1243,6 +1337,7 @@ extern "C" ns_status ns_run(ns_ctx *ctx, int32_t max_iter, int32_t *iters)
                 if ((st = enqueue_iteration(ctx)) != NS_OK) return st;
         }
         issued += batch;
+        ctx->iters_issued += batch;
         if ((st = sync_flags(ctx)) != NS_OK) return st;
     }
     if ((st = collect_events(ctx)) != NS_OK) return st;

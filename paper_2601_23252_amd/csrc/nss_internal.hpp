@@ -14,6 +14,7 @@ constexpr int kStepU = 8;        // per chain step in the uniform buffer: tL0, u
 constexpr int kStepShrinkU = kStepU - 2;
 constexpr int kSelectThreads = 1024;
 constexpr int kMaxLive = 8192;
+constexpr long long kDeadInitIters = 512;   // initial dead record, in iterations (then grown)
 
 // likelihood arithmetic inside the chains (values equal the C ABI's ns_precision)
 enum Mode { MODE_FP64 = 0, MODE_BF16 = 1, MODE_FP16 = 2, MODE_BF16X3 = 3, MODE_FP16X3 = 4,
@@ -80,6 +81,7 @@ struct DevRun {
     double *ubuf;          // [k][p][8] per-step default plan (tL0, uh, 6 shrink), with dirbuf
     int rw;                // replacement by constrained random walk (width = its scale)
     int freeze;            // whitening factor of the first iteration kept for the run
+    int diag;              // metric from the survivors' variances alone (diagonal)
     int smc;               // adaptive tempered SMC outer loop (k = m chains, no hard constraint)
     double ess_frac;       // SMC: ESS target rho of the next temperature
     double *Xtmp, *Ltmp;   // SMC: gather buffers [D][m_pad], [m]

@@ -375,6 +375,13 @@ __global__ __launch_bounds__(1024) void k_chol(Launch Lc)
     for (int a = tid; a < d; a += blockDim.x) tr += A[a * (a + 1) / 2 + a];
     tr = block_sum(tr, red);
     for (int a = tid; a < d; a += blockDim.x) A[a * (a + 1) / 2 + a] += 1e-12 * tr / d;
+    if (R.diag) {   // diagonal metric: the variances alone
+        for (int e = tid; e < np; e += blockDim.x) {
+            int a, b;
+            unpack_tri(e, a, b);
+            if (a != b) A[e] = 0.0;
+        }
+    }
     __syncthreads();
     // right-looking Cholesky on the packed lower triangle
     for (int j = 0; j < d; ++j) {

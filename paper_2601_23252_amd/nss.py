@@ -33,6 +33,7 @@ NS_FLAG_SHALLOW_PLAN = 64
 NS_FLAG_PLAN8 = 128
 NS_FLAG_GP_NO_WAIT = 256
 NS_FLAG_FREEZE_WHITENING = 512
+NS_FLAG_DIAGONAL_METRIC = 1024
 PRECISIONS = {"fp64": NS_FP64, "bf16": NS_MIXED_BF16, "fp16": NS_MIXED_FP16,
               "bf16x3": NS_MIXED_BF16X3, "fp16x3": NS_MIXED_FP16X3, "fp32": NS_MIXED_FP32}
 # guard band of each mixed mode: (rel, abs) as set by the library
@@ -345,7 +346,7 @@ def make_config(m, k, p, width=0.0, seed=0, run_id=0, precision="fp64", term_fra
                 inline_directions=False, graph=False, replacement="hrss", outer="ns",
                 ess_frac=0.5, record_points=False, autotune=False,
                 shallow_plan=False, plan8=False, gp_no_wait=False,
-                freeze_whitening=False) -> ns_config:
+                freeze_whitening=False, diagonal_metric=False) -> ns_config:
     cfg = ns_config_default()
     cfg.n_live, cfg.k, cfg.chain_len = int(m), int(k), int(p)
     cfg.width = float(width)
@@ -362,7 +363,8 @@ def make_config(m, k, p, width=0.0, seed=0, run_id=0, precision="fp64", term_fra
                  | (NS_FLAG_SHALLOW_PLAN if shallow_plan else 0)
                  | (NS_FLAG_PLAN8 if plan8 else 0)
                  | (NS_FLAG_GP_NO_WAIT if gp_no_wait else 0)
-                 | (NS_FLAG_FREEZE_WHITENING if freeze_whitening else 0))
+                 | (NS_FLAG_FREEZE_WHITENING if freeze_whitening else 0)
+                 | (NS_FLAG_DIAGONAL_METRIC if diagonal_metric else 0))
     cfg.replacement = REPLACEMENTS[replacement] if isinstance(replacement, str) else int(replacement)
     cfg.outer = OUTERS[outer] if isinstance(outer, str) else int(outer)
     cfg.ess_frac = float(ess_frac)
@@ -442,7 +444,7 @@ class NSRun:
                  max_iter=100000, trace=False, timing=False, inline_directions=False,
                  graph=False, stream="torch", replacement="hrss", outer="ns", ess_frac=0.5,
                  record_points=False, autotune=False, shallow_plan=False, plan8=False,
-                 gp_no_wait=False, freeze_whitening=False):
+                 gp_no_wait=False, freeze_whitening=False, diagonal_metric=False):
         self.prob = prob
         self.d = int(prob["d"])
         self.m = int(m or prob["m"])
@@ -454,7 +456,8 @@ class NSRun:
         cfg = make_config(self.m, self.k, self.p, width, seed, run_id, precision, term_frac,
                           stepout_cap, shrink_cap, max_iter, trace, timing, inline_directions,
                           graph, replacement, outer, ess_frac, record_points, autotune,
-                          shallow_plan, plan8, gp_no_wait, freeze_whitening)
+                          shallow_plan, plan8, gp_no_wait, freeze_whitening,
+                          diagonal_metric)
         self.cfg = cfg
         s = current_stream() if stream == "torch" else stream
         st, self.ctx = ns_init(pr, en, cfg, s)

@@ -1,13 +1,21 @@
 """NS_FLAG_AUTOTUNE: the launch shape of each kernel group's chains chosen by timing (chains
 per workgroup 1..4, and for mixture chains in a 16-bit mode the tests planned per round:
-4, 8 or 16).
+4, 8 or 16), at the context's iterations 0, 32 and 96, ranked by summed time.
 
 Every candidate is timed on the same iteration (the state the chains change is saved and
 restored around each timed launch), and a chain's decisions and arithmetic do not depend on
 the launch shape, so a tuned run must equal the untuned run bit for bit (points, logL,
-evidence, iteration count); the tuner must actually time its candidates (counted launches) and
-a later context of the same shape must reuse the choice without timing anything.
+evidence, iteration count); the tuner must actually time its candidates at each point the run
+reaches (counted launches) and a later context of the same shape must reuse the choice
+without timing anything.
 """
+
+TUNE_AT = (0, 32, 96)
+
+
+def _points(iterations):
+    """Tuning points a run of this many iterations reaches."""
+    return sum(a < iterations for a in TUNE_AT)
 import numpy as np
 import pytest
 
@@ -39,9 +47,9 @@ def _same_state(a, b):
 
 
 def test_autotune_config1_full_run_identical(N):
-    """config 1 (k = 50, FP64: 4 candidates, 2 timed launches each): the tuned run equals the
-    untuned one; a second context of the same shape starts with the cached choice and times
-    nothing."""
+    """config 1 (k = 50, FP64: 4 candidates, 2 timed launches each per point): the tuned run
+    equals the untuned one, timing at every tuning point the run reaches; a second context of
+    the same shape starts with the cached choice and times nothing."""
     from paper_2601_23252_amd import problems as G
     prob = G.config1()
     a = N.NSRun(prob, seed=5, autotune=True)
@@ -55,6 +63,9 @@ def test_autotune_config1_full_run_identical(N):
     assert ia == ib
     _same_state(a, b)
     assert a.logz() == b.logz()
+    n_it = a.state()["iter"]
+    assert n_it > 32
+    assert a.stats()["tune_launches"] == 8 * _points(n_it)
     c, plan = a.launch_shape()
     assert 1 <= c <= 4 and plan == 4
     again = N.NSRun(prob, seed=6, autotune=True)
@@ -102,7 +113,10 @@ def test_autotune_batch_with_graphs_identical(N):
         st, sp = tuned.state(r), plain.state(r)
         assert np.array_equal(st["x"], sp["x"]) and st["iter"] == sp["iter"]
         assert 1 <= N.ns_chains_per_workgroup(tuned.ctx, r) <= 4
-    assert tuned.stats(0)["tune_launches"] == 16   # two groups, 4 candidates, 2 launches each
+    # two groups, 4 candidates, 2 launches each, at every point a group's runs reach
+    tl = tuned.stats(0)["tune_launches"]
+    assert tl >= 16 and tl % 8 == 0
+    assert tl <= 16 * _points(max(tuned.state(r)["iter"] for r in range(3)))
     tuned.close()
     plain.close()
 
@@ -153,5 +167,30 @@ def test_autotune_cache_file_is_used(N, tmp_path):
     assert st == N.NS_OK and n >= 1
     saved = json.loads((tmp_path / "saved.json").read_text())
     assert entry in saved["entries"]
+    a.close()
+    b.close()
+
+
+def test_autotune_points_follow_the_schedule(N):
+    """The d = 32 correlated Gaussian in BF16x3 (4 candidates per point, or 12 where the plan
+    kernel applies): timing happens at iterations 0, 32 and 96 exactly, and the run equals the
+    untuned one throughout."""
+    from paper_2601_23252_amd import problems as G
+    prob = G.config2()
+    a = N.NSRun(prob, p=32, seed=3, precision="bf16x3", autotune=True)
+    b = N.NSRun(prob, p=32, seed=3, precision="bf16x3")
+    per_point = None
+    for it in range(100):
+        da = a.step()
+        assert b.step() == da
+        tl = a.stats()["tune_launches"]
+        if it == 0:
+            per_point = tl
+            assert per_point in (8, 24)
+        assert tl == per_point * _points(it + 1), f"iteration {it}"
+        if da:
+            break
+    assert it >= 96
+    _same_state(a, b)
     a.close()
     b.close()

@@ -177,3 +177,42 @@ def test_singular_survivors_take_the_diagonal_fallback(N, oracle_lib):
     assert np.array_equal(g["parents"], par)
     _cmp(g, orc.state(), "fallback")
     gpu.close()
+
+
+def test_dead_record_grows_past_its_initial_size(N, oracle_lib):
+    """A run of ~1,400 iterations (config 1 with k = 2) outgrows the dead record's initial 512
+    iterations twice; the whole record equals the oracle's, and posterior samples drawn over it
+    (the dead points' coordinates, grown alongside) are the oracle's.  With max_iter = 600 the
+    record stops at 601 iterations: its stored part still equals the oracle's and the
+    geometric-uncertainty call reports the truncation."""
+    from paper_2601_23252_amd import problems as G
+    from oracle import theory as T
+    from tests import oracle_runs
+    prob = G.config1()
+    w = T.width_whitened(5)
+    orc = oracle_lib.Run(oracle_lib.Problem(prob), 200, 2, 10, w, 3, threads=8)
+    orc.init()
+    orc.run()
+    gpu = N.NSRun(prob, k=2, p=10, width=w, seed=3, record_points=True)
+    gpu.run()
+    it = gpu.state()["iter"]
+    assert it == orc.state()["iter"] and it > 1024
+    dg, do = gpu.dead(), orc.dead()
+    assert dg.shape == do.shape == (2 * (it + 1),)
+    assert np.allclose(dg, do, rtol=1e-10, atol=1e-10)
+    assert abs(gpu.logz()[0] - orc.logz()[0]) <= 1e-9
+    x, idx = gpu.posterior_samples(2000, R=10, beta=1.0, seed=2, run_id=0)
+    dead_o, fin_o, finx_o = oracle_runs.deaths(orc)
+    ox, oidx = oracle_lib.posterior_samples(dead_o, orc.dead_x(), fin_o, finx_o, 200, 2, 10,
+                                            2000, 1.0, seed=2, run_id=0)
+    assert np.array_equal(idx, oidx)
+    assert np.allclose(x, ox, rtol=1e-10, atol=1e-12)
+    gpu.close()
+    short = N.NSRun(prob, k=2, p=10, width=w, seed=3, max_iter=600)
+    short.run()
+    assert short.state()["iter"] == it
+    ds = short.dead()
+    assert np.allclose(ds[:1202], do[:1202], rtol=1e-10, atol=1e-10)
+    with pytest.raises(N.NSError):
+        short.geom(R=4)
+    short.close()

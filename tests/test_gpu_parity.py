@@ -120,7 +120,8 @@ def _parity_run(N, O, prob, m, k, p, seed, n_iter, threads=8, **kw):
     width = _width(prob["d"])
     P = O.Problem(prob)
     orc = O.Run(P, m, k, p, width, seed, threads=threads, **{a: b for a, b in kw.items()
-                                                             if a in ("stepout_cap", "shrink_cap", "term_frac")})
+                                                             if a in ("stepout_cap", "shrink_cap", "term_frac",
+                                                                      "diagonal_metric")})
     orc.init()
     gpu = N.NSRun(prob, m=m, k=k, p=p, width=width, seed=seed, trace=True, **kw)
     _cmp_state(gpu.state(), orc.state(), k, "init")
@@ -319,3 +320,19 @@ def test_funnel_d200_padded_320(N, O):
     from paper_2601_23252_amd import problems as G
     prob = G.funnel(200, box=20.0, m=600, k=100)
     _parity_run(N, O, prob, 600, 100, 20, seed=6, n_iter=4)
+
+
+def test_parity_diagonal_metric(N, O):
+    """NS_FLAG_DIAGONAL_METRIC on the correlated d = 32 Gaussian (config 2 at m = 300, k = 100,
+    p = 32) for 12 iterations, and config 1 to the end: the same per-iteration bars."""
+    from paper_2601_23252_amd import problems as G
+    prob = G.config2(m=300, k=100)
+    gpu, orc = _parity_run(N, O, prob, 300, 100, 32, seed=5, n_iter=12, diagonal_metric=True)
+    Ls = gpu.state()["Lsig"]
+    assert np.count_nonzero(Ls - np.diag(np.diag(Ls))) == 0
+    gpu.close()
+    prob = _problems()["config1"]
+    gpu, orc = _parity_run(N, O, prob, 200, 50, 25, seed=3, n_iter=10_000, diagonal_metric=True)
+    assert gpu.state()["done"] == 1
+    assert abs(gpu.logz()[0] - orc.logz()[0]) <= 1e-9
+    gpu.close()

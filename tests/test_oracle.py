@@ -263,6 +263,23 @@ def test_frozen_whitening_keeps_the_first_survivor_covariance(oracle_lib):
     assert np.trace(La @ La.T) < 0.5 * np.trace(C)
 
 
+def test_diagonal_metric_is_the_survivor_standard_deviations(oracle_lib):
+    """The diagonal metric's factor is diag(sqrt(var_a + 1e-12 tr / d)) of the survivors
+    (numpy's population variance), zero elsewhere."""
+    from paper_2601_23252_amd import problems as G
+    prob = G.config2(d=8, m=300, k=100)
+    R = oracle_lib.Run(oracle_lib.Problem(prob), 300, 100, 10, 4.0, 2, diagonal_metric=True)
+    R.init()
+    st = R.state()
+    R.step()
+    Ls, _ = R.aux()
+    surv = st["x"][st["perm"][100:]]
+    v = surv.var(axis=0)
+    v += 1e-12 * v.sum() / 8
+    assert np.allclose(np.diag(Ls), np.sqrt(v), rtol=1e-12, atol=0)
+    assert np.count_nonzero(Ls - np.diag(np.diag(Ls))) == 0
+
+
 def _z_scores(oracle_lib, prob, truth_lnz, seeds, m=None, k=None, p=None, threads=8):
     from oracle import theory as T
     P = oracle_lib.Problem(prob)
