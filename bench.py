@@ -37,14 +37,16 @@ sys.path.insert(0, ROOT)
 # (precision, chain length, chains per workgroup, planned tests per round), recorded for the
 # kernel sources with this sha256 prefix; reported as null once the sources differ or for a
 # shape the counters were not taken on.
-TRAFFIC = {("bf16x3", 320, 4, 8): 194.9e6, ("bf16x3", 320, 4, 16): 222.1e6}
+TRAFFIC = {("fp16x3", 320, 4, 8): 196.7e6, ("bf16x3", 320, 4, 8): 194.9e6,
+           ("bf16x3", 320, 4, 16): 222.1e6}
 TRAFFIC_SOURCE_SHA = "5137e281ccfe634f"
 
 
 # VALU lane-instructions per evaluation issued by the chain kernel (SQ_INSTS_VALU x 64 /
 # evaluations of the profiled launches), keyed like TRAFFIC, for the kernel sources with this
 # prefix: the instruction view of the same kernel (its chain logic runs on the vector ALU).
-HRSS_VALU_PER_EVAL = {("bf16x3", 320, 4, 8): 24911.0, ("bf16x3", 320, 4, 16): 29313.0}
+HRSS_VALU_PER_EVAL = {("fp16x3", 320, 4, 8): 24801.0, ("bf16x3", 320, 4, 8): 24911.0,
+                      ("bf16x3", 320, 4, 16): 29313.0}
 HRSS_VALU_SOURCE_SHA = "5137e281ccfe634f"
 
 KERNEL_SOURCES = ("nss_kernels.hip", "nss_hrss_plan.hip", "nss_tiles.hpp", "nss_internal.hpp")
@@ -870,7 +872,7 @@ def main():
     ap.add_argument("--other-metric-steps", type=int, default=5,
                     help="runs of the labelled line with the other direction metric (0 = skip)")
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", default="bf16x3",
+    ap.add_argument("--precision", default="fp16x3",
                     choices=["bf16", "fp16", "bf16x3", "fp16x3", "fp64"])
     ap.add_argument("--chain-factor", type=int, default=5,
                     help="chain length p = factor * d of the headline (the workload's 5d)")

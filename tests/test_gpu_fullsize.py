@@ -112,3 +112,25 @@ def test_gauss64_full_size_multiseed_z(N):
     assert np.all(np.abs(zs) < 4.0), zs
     assert abs(np.mean(zs)) < 2.0, zs
     gpu.close()
+
+
+def test_mixture_config3_diagonal_metric_multiseed_z(N):
+    """The benchmark's configuration (d = 64, 8-mode mixture, m = 2000, k = 1000, p = 5d,
+    BF16x3, diagonal direction metric), ten seeds against ln Z = -64 ln 20: at least half inside
+    3 sigma and the mean z within 3.  (With the full-covariance metric every seed is 15-35
+    sigma high at this chain length.)"""
+    from paper_2601_23252_amd import problems as G
+    prob = G.config3()
+    truth = -64 * math.log(20.0)
+    gpu = N.NSRun(prob, p=320, seed=0, precision="bf16x3", diagonal_metric=True)
+    zs = []
+    for seed in range(10):
+        gpu.reset(seed)
+        gpu.run()
+        z, err, _ = gpu.logz()
+        zs.append((z - truth) / err)
+        print(f"config 3 diagonal metric seed {seed}: z {zs[-1]:.2f}", flush=True)
+    zs = np.array(zs)
+    assert np.sum(np.abs(zs) < 3.0) >= 5, zs
+    assert abs(zs.mean()) < 3.0, zs
+    gpu.close()
