@@ -186,7 +186,10 @@ typedef enum {
                               * chains by timing: chains per workgroup (1..4) and, for mixture
                               * chains in a 16-bit mode, tests planned per round (4, 8 or 16).
                               * At the context's iterations 0, 32 and 96 (counted from the
-                              * runs' start or reset), after whitening and directions, the state
+                              * runs' start or reset; the later points are skipped once one
+                              * candidate's sum is 25% below every other's after the first
+                              * point or 5% below after the second), after whitening and
+                              * directions, the state
                               * the chains change is saved, every candidate's chain launch is
                               * timed twice on it (the state restored each time), each
                               * candidate's best time is added to its sum, and the iteration
@@ -224,6 +227,13 @@ typedef enum {
                                       * restriction Sec. 3.2 suggests for high dimensions.
                                       * Applies to slice and random-walk chains and to the
                                       * tempered-SMC mutation. */
+#define NS_FLAG_SERIAL_GROUPS 2048  /* (read from the first run's config) a batch whose runs
+                                    * compile to several chain kernels launches them one after
+                                    * the other on the context's stream; by default the second
+                                    * and later ones run concurrently on side streams of the
+                                    * library's own (default priority), forked and joined with
+                                    * events around the chain phase of each iteration.  Results
+                                    * are identical either way. */
 #define NS_FLAG_GRAPH  8  /* ns_run captures each batch of 16 iterations as a HIP graph and
                            * replays it (re-captured when a run of the batch finishes); not
                            * used together with NS_FLAG_TIMING.  Results are identical. */

@@ -86,8 +86,13 @@ struct ns_ctx {
     int use_graph = 0;
     long long map_epoch = 0, graph_epoch = -1;
     hipGraphExec_t gexec = nullptr;
-    // NS_FLAG_AUTOTUNE: chains per HRSS workgroup chosen per group by timing the candidates on
-    // the run's own iterations (per-group events around the HRSS launch, cost per evaluation)
+    // groups after the first launch their chains on side streams (default priority), forked
+    // from and joined back into `stream` around the chain phase of each iteration
+    std::vector<hipStream_t> side;   // [groups - 1]
+    hipEvent_t ev_fork = nullptr;
+    std::vector<hipEvent_t> ev_join;   // [groups - 1]
+    // NS_FLAG_AUTOTUNE: the launch shape of each group chosen by timing its candidates on saved
+    // iterations (see tune_iteration)
     int autotune = 0;
     std::vector<GroupTune> tune;     // per group
     long long tune_launches = 0;     // HRSS launches timed by the tuner
@@ -576,16 +581,47 @@ static ns_status enqueue_pre(ns_ctx *ctx)
 }
 
 // The chains of group g.
-static ns_status enqueue_hrss_group(ns_ctx *ctx, size_t g)
+static ns_status enqueue_hrss_group(ns_ctx *ctx, size_t g, hipStream_t s)
 {
     const Group &G = ctx->groups[g];
     const hipError_t e =
-        G.lik == LIK_GP ? launch_hrss_gp(ctx->L_hrss[g], G.mode, ctx->stream)
-        : G.rw          ? launch_rw(ctx->L_hrss[g], G.D, G.lik, G.mode, G.upwT, ctx->stream)
-        : G.plan        ? launch_hrss_plan(ctx->L_hrss[g], G.D, G.mode, G.upwT, G.plan,
-                                           ctx->stream)
-                        : launch_hrss(ctx->L_hrss[g], G.D, G.lik, G.mode, G.upwT, ctx->stream);
+        G.lik == LIK_GP ? launch_hrss_gp(ctx->L_hrss[g], G.mode, s)
+        : G.rw          ? launch_rw(ctx->L_hrss[g], G.D, G.lik, G.mode, G.upwT, s)
+        : G.plan        ? launch_hrss_plan(ctx->L_hrss[g], G.D, G.mode, G.upwT, G.plan, s)
+                        : launch_hrss(ctx->L_hrss[g], G.D, G.lik, G.mode, G.upwT, s);
     if (e != hipSuccess) return device_error(ctx, "HRSS launch", e);
+    return NS_OK;
+}
+static ns_status enqueue_hrss_group(ns_ctx *ctx, size_t g)
+{
+    return enqueue_hrss_group(ctx, g, ctx->stream);
+}
+
+// The chains of every group with unfinished runs: the first such group on the context's
+// stream, the others concurrently on side streams (their runs are disjoint, and a run's
+// arithmetic does not depend on the order), forked after the directions and joined before
+// delete-k.  The fork and join are events, so graph capture records them as dependencies.
+static ns_status enqueue_chains(ns_ctx *ctx)
+{
+    std::vector<size_t> live;
+    for (size_t g = 0; g < ctx->groups.size(); ++g)
+        if (ctx->L_hrss[g].nblocks > 0) live.push_back(g);
+    ns_status st;
+    if (live.size() <= 1 || ctx->side.empty()) {
+        for (size_t g : live)
+            if ((st = enqueue_hrss_group(ctx, g)) != NS_OK) return st;
+        return NS_OK;
+    }
+    CK(hipEventRecord(ctx->ev_fork, ctx->stream));
+    for (size_t i = 1; i < live.size(); ++i) {
+        hipStream_t s = ctx->side[i - 1];
+        CK(hipStreamWaitEvent(s, ctx->ev_fork, 0));
+        if ((st = enqueue_hrss_group(ctx, live[i], s)) != NS_OK) return st;
+        CK(hipEventRecord(ctx->ev_join[i - 1], s));
+    }
+    if ((st = enqueue_hrss_group(ctx, live[0])) != NS_OK) return st;
+    for (size_t i = 1; i < live.size(); ++i)
+        CK(hipStreamWaitEvent(ctx->stream, ctx->ev_join[i - 1], 0));
     return NS_OK;
 }
 
@@ -599,8 +635,7 @@ static ns_status enqueue_rest(ns_ctx *ctx)
         CK(hipEventRecord(e0, ctx->stream));
     }
     ns_status st;
-    for (size_t g = 0; g < ctx->groups.size(); ++g)
-        if ((st = enqueue_hrss_group(ctx, g)) != NS_OK) return st;
+    if ((st = enqueue_chains(ctx)) != NS_OK) return st;
     if (e1) {
         CK(hipEventRecord(e1, ctx->stream));
         ctx->events.emplace_back(e0, e1);
@@ -641,13 +676,16 @@ static ns_status collect_events(ns_ctx *ctx)
 // launch is timed and the state restored, kTuneReps times over (the minimum counts), and the
 // iteration then runs with the shape of least summed time so far.  The chains' behaviour
 // changes over a run (early contours are wide and brackets expand often, later ones rarely),
-// so this is done at kTunePoints iterations spread over the run's start (kTuneAt) and the
-// candidates are ranked by their summed times.  The current choice is cached per group shape
+// so this is done at up to kTunePoints iterations spread over the run's start (kTuneAt) and
+// the candidates are ranked by their summed times; a leader 25% ahead of every other candidate
+// after the first point, or 5% ahead after two, ends the tuning early.  The current choice is cached per group shape
 // in this process after every point; a context whose shape is cached does not tune.
 // ------------------------------------------------------------------------------------------
 constexpr int kTuneReps = 2;   // timed launches per candidate and point
 constexpr int kTunePoints = 3;
 constexpr long long kTuneAt[kTunePoints] = {0, 32, 96};   // context iterations of the points
+constexpr double kTuneClear1 = 1.25;   // a lead that ends tuning after the first point
+constexpr double kTuneClear2 = 1.05;   // ... after the second point
 
 static std::mutex g_tune_mu;
 // group shape -> (chains per workgroup, planned tests per round)
@@ -764,7 +802,13 @@ static ns_status tune_iteration(ns_ctx *ctx)
         if ((st = set_group_shape(ctx, g, t.cand[bi])) != NS_OK) return st;
         if ((st = group_state(ctx, g, 1)) != NS_OK) return st;
         t.points += 1;
-        t.done = t.points >= kTunePoints;
+        // done after the last point, or earlier when the leader is clearly ahead of every
+        // other candidate: by kTuneClear1 after one point, by kTuneClear2 after two
+        double second = 1e300;
+        for (size_t ci = 0; ci < nc; ++ci)
+            if (ci != bi && t.sum[ci] < second) second = t.sum[ci];
+        t.done = t.points >= kTunePoints ||
+                 second > (t.points == 1 ? kTuneClear1 : kTuneClear2) * t.sum[bi];
         if (!t.done) t.next_at = kTuneAt[t.points];
         std::lock_guard<std::mutex> lk(g_tune_mu);
         g_tuned[tune_key(ctx, ctx->groups[g])] = t.cand[bi];
@@ -877,6 +921,9 @@ extern "C" void ns_free(ns_ctx *ctx)
     if (!ctx) return;
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
+    for (hipStream_t st : ctx->side) if (st) { (void)hipStreamSynchronize(st); (void)hipStreamDestroy(st); }
+    for (hipEvent_t ev : ctx->ev_join) if (ev) (void)hipEventDestroy(ev);
+    if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
     for (auto &pr : ctx->events) { (void)hipEventDestroy(pr.first); (void)hipEventDestroy(pr.second); }
     for (void *p : ctx->allocs) if (p) (void)hipFree(p);
     if (ctx->geom_buf) (void)hipFree(ctx->geom_buf);
@@ -1161,6 +1208,19 @@ extern "C" ns_status ns_init_batch(int32_t n_runs, const ns_prior *priors,
         C = C < 1 ? 1 : (C > kMaxChainsPerWG ? kMaxChainsPerWG : C);
         if (G.lik == LIK_GP) C = 1;   // one chain per workgroup
         for (int r : G.runs) ctx->runs[r].R.C = C;
+    }
+    // side streams and fork / join events for the concurrent chain launches of the groups
+    if (ctx->groups.size() > 1 && !(cfgs[0].flags & NS_FLAG_SERIAL_GROUPS)) {
+        ctx->side.assign(ctx->groups.size() - 1, nullptr);
+        ctx->ev_join.assign(ctx->groups.size() - 1, nullptr);
+        bool ok = hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming) == hipSuccess;
+        for (size_t i = 0; ok && i + 1 < ctx->groups.size(); ++i)
+            ok = hipStreamCreateWithFlags(&ctx->side[i], hipStreamNonBlocking) == hipSuccess &&
+                 hipEventCreateWithFlags(&ctx->ev_join[i], hipEventDisableTiming) == hipSuccess;
+        if (!ok) {
+            ctx->err = "side stream or event creation failed";
+            return bail(NS_EDEVICE);
+        }
     }
     // NS_FLAG_AUTOTUNE: a shape tuned before in this process takes its cached value; the others
     // time every candidate on their first iterations

@@ -357,7 +357,7 @@ __global__ __launch_bounds__(1024) void k_chol(Launch Lc)
         int a, b;  // a >= b
         unpack_tri(e, a, b);
         double v = 0.0;
-        if (a < d && b < d) {
+        if (a < d && b < d && (a == b || !R.diag)) {   // the diagonal metric needs variances only
             const int ta = a >> 4, tb = b >> 4;
             const int tile = ta * (ta + 1) / 2 + tb;
             const int off = (b & 15) * 16 + (a & 15);
@@ -375,15 +375,17 @@ __global__ __launch_bounds__(1024) void k_chol(Launch Lc)
     for (int a = tid; a < d; a += blockDim.x) tr += A[a * (a + 1) / 2 + a];
     tr = block_sum(tr, red);
     for (int a = tid; a < d; a += blockDim.x) A[a * (a + 1) / 2 + a] += 1e-12 * tr / d;
-    if (R.diag) {   // diagonal metric: the variances alone
-        for (int e = tid; e < np; e += blockDim.x) {
-            int a, b;
-            unpack_tri(e, a, b);
-            if (a != b) A[e] = 0.0;
-        }
-    }
     __syncthreads();
-    // right-looking Cholesky on the packed lower triangle
+    // right-looking Cholesky on the packed lower triangle; for the diagonal metric it reduces
+    // to the square roots of the (jittered) variances, taken directly
+    if (R.diag) {
+        for (int a = tid; a < d; a += blockDim.x) {
+            const double v = A[a * (a + 1) / 2 + a];
+            if (!(v > 0.0)) *fail = 1;
+            else A[a * (a + 1) / 2 + a] = sqrt(v);
+        }
+        __syncthreads();
+    } else
     for (int j = 0; j < d; ++j) {
         const double ajj = A[j * (j + 1) / 2 + j];
         if (!(ajj > 0.0)) { if (tid == 0) *fail = 1; break; }

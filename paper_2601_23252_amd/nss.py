@@ -34,6 +34,7 @@ NS_FLAG_PLAN8 = 128
 NS_FLAG_GP_NO_WAIT = 256
 NS_FLAG_FREEZE_WHITENING = 512
 NS_FLAG_DIAGONAL_METRIC = 1024
+NS_FLAG_SERIAL_GROUPS = 2048
 PRECISIONS = {"fp64": NS_FP64, "bf16": NS_MIXED_BF16, "fp16": NS_MIXED_FP16,
               "bf16x3": NS_MIXED_BF16X3, "fp16x3": NS_MIXED_FP16X3, "fp32": NS_MIXED_FP32}
 # guard band of each mixed mode: (rel, abs) as set by the library
@@ -346,7 +347,8 @@ def make_config(m, k, p, width=0.0, seed=0, run_id=0, precision="fp64", term_fra
                 inline_directions=False, graph=False, replacement="hrss", outer="ns",
                 ess_frac=0.5, record_points=False, autotune=False,
                 shallow_plan=False, plan8=False, gp_no_wait=False,
-                freeze_whitening=False, diagonal_metric=False) -> ns_config:
+                freeze_whitening=False, diagonal_metric=False,
+                serial_groups=False) -> ns_config:
     cfg = ns_config_default()
     cfg.n_live, cfg.k, cfg.chain_len = int(m), int(k), int(p)
     cfg.width = float(width)
@@ -364,7 +366,8 @@ def make_config(m, k, p, width=0.0, seed=0, run_id=0, precision="fp64", term_fra
                  | (NS_FLAG_PLAN8 if plan8 else 0)
                  | (NS_FLAG_GP_NO_WAIT if gp_no_wait else 0)
                  | (NS_FLAG_FREEZE_WHITENING if freeze_whitening else 0)
-                 | (NS_FLAG_DIAGONAL_METRIC if diagonal_metric else 0))
+                 | (NS_FLAG_DIAGONAL_METRIC if diagonal_metric else 0)
+                 | (NS_FLAG_SERIAL_GROUPS if serial_groups else 0))
     cfg.replacement = REPLACEMENTS[replacement] if isinstance(replacement, str) else int(replacement)
     cfg.outer = OUTERS[outer] if isinstance(outer, str) else int(outer)
     cfg.ess_frac = float(ess_frac)

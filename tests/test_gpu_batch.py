@@ -178,3 +178,23 @@ def test_graph_replay_matches_eager(N):
     assert np.array_equal(A.logz()[0], G.logz()[0])
     A.close()
     G.close()
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_concurrent_groups_equal_serial_groups(N, graph):
+    """The small batch compiles to several chain kernels; launched concurrently on side streams
+    (the default) or one after the other (NS_FLAG_SERIAL_GROUPS), eagerly or as captured graphs,
+    every run's trajectory is the same bit for bit."""
+    runs = _small_batch()
+    Sr = N.NSBatch([(p, dict(kw, serial_groups=True, graph=graph)) for p, kw in runs])
+    Cc = N.NSBatch([(p, dict(kw, graph=graph)) for p, kw in runs])
+    Sr.run()
+    Cc.run()
+    assert np.array_equal(Sr.logz()[0], Cc.logz()[0])
+    for r in range(len(runs)):
+        a, b = Sr.state(r), Cc.state(r)
+        assert a["iter"] == b["iter"] and a["done"] == b["done"] == 1
+        assert np.array_equal(a["x"], b["x"]) and np.array_equal(a["logL"], b["logL"])
+        assert Sr.stats(r)["evals"] == Cc.stats(r)["evals"]
+    Sr.close()
+    Cc.close()
