@@ -545,7 +545,7 @@ __global__ __launch_bounds__(256) void k_hrss_plan(Launch Lc)
         const int fslot = (force == PF_RIGHT) ? 2 : 0;
         unsigned okm = 0;
         if (act) {
-            unsigned oob = 0;   // slots with a coordinate of this lane outside the box
+            unsigned oob = 0;   // slots with a coordinate outside the box
 #pragma unroll
             for (int s = 0; s < S; ++s) {   // every slot (unplanned ones are never consumed)
                 double y[NA];
@@ -557,14 +557,11 @@ __global__ __launch_bounds__(256) void k_hrss_plan(Launch Lc)
                     if (a < D) crow[s * LDC32 + a] = (float)y[i];
                     if (a < d) inb = inb && (y[i] >= par[i] && y[i] <= pbr[i]);
                 }
-                if (box) oob |= (inb ? 0u : 1u) << s;
+                // a slot is in the box when every lane's coordinates are (a wave vote)
+                if (box) oob |= (__all(inb) != 0 ? 0u : 1u) << s;
                 else if ((vm >> s) & 1u) okm |= (logprior_at(y) > logy ? 1u : 0u) << s;
             }
-            if (box) {
-#pragma unroll
-                for (int o = 1; o < 64; o <<= 1) oob |= (unsigned)__shfl_xor((int)oob, o, 64);
-                okm = vm & ~oob;
-            }
+            if (box) okm = vm & ~oob;
             if (force != PF_NONE) {
                 const double tf = (force == PF_RIGHT) ? tv[2] : tv[0];
 #pragma unroll
