@@ -198,3 +198,29 @@ def test_concurrent_groups_equal_serial_groups(N, graph):
         assert Sr.stats(r)["evals"] == Cc.stats(r)["evals"]
     Sr.close()
     Cc.close()
+
+
+def test_dead_record_growth_in_a_graph_batch(N):
+    """A batch with graphs in which one run (config 1 at k = 2, ~1,700 iterations) outgrows its
+    dead record's initial 512 iterations while another finishes early: every run's evidence,
+    death count and post-hoc replicas over the whole dead record equal its single run's (the
+    growth replaces the record between graph replays; the kernels read its address from the
+    run's descriptor)."""
+    from paper_2601_23252_amd import problems as G
+    from oracle import theory as T
+    w = T.width_whitened(5)
+    runs = [(G.config1(), dict(k=2, p=10, width=w, seed=3, run_id=0, graph=True)),
+            (G.funnel(8, m=100, k=50), dict(seed=4, run_id=1, graph=True))]
+    B = N.NSBatch(runs)
+    B.run()
+    for r, (prob, kw) in enumerate(runs):
+        S = N.NSRun(prob, **{a: b for a, b in kw.items() if a != "graph"})
+        S.run()
+        assert B.state(r)["iter"] == S.state()["iter"]
+        assert B.logz()[0][r] == S.logz()[0]
+        assert B.stats(r)["n_dead"] == S.stats()["n_dead"]
+        gb, gs = B.geom(r, R=8, seed=2, run_id=0), S.geom(R=8, seed=2, run_id=0)
+        assert np.array_equal(gb["logz"], gs["logz"])   # over the whole dead record
+        S.close()
+    assert B.state(0)["iter"] > 1024
+    B.close()
