@@ -323,7 +323,7 @@ def bench_batch(args):
     # HIP graphs on (16 iterations per replay), no per-launch events: the whole job is timed
     # on the host clock; the launch shapes are tuned at each group's first iteration
     runs = [(p, dict(seed=5, run_id=r, precision="bf16x3" if p["lik"] == "mixture" else "fp64",
-                     max_iter=4000, graph=True, autotune=not args.no_autotune,
+                     max_iter=4000, graph=not args.no_graph, autotune=not args.no_autotune,
                      serial_groups=args.serial_groups))
             for r, p in enumerate(probs)]
     B = N.NSBatch(runs)
@@ -354,7 +354,7 @@ def bench_batch(args):
         "ms_per_step": 1e3 * dt, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
         "config": {"workload": "batch256_gauss_funnel_nlive500_k250_p5d", "runs": len(probs),
-                   "runs_done": done, "max_iterations": it, "graphs": True,
+                   "runs_done": done, "max_iterations": it, "graphs": not args.no_graph,
                    "concurrent_groups": not args.serial_groups,
                    "autotune": not args.no_autotune, "runs_by_chains_per_workgroup": cpw},
         "roofline": {"bound": "mfma", "achieved": flops / dt / 1e12, "peak": 2500.0,
@@ -916,6 +916,9 @@ def main():
                          "tempered SMC with the slice mutation against nested sampling; "
                          "gauss5 / corr32: the small Gaussian configurations")
     ap.add_argument("--replicas", type=int, default=100, help="geom: shrinkage replicas")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="batch256: eager iterations instead of HIP-graph replays (the groups' "
+                         "chains then run concurrently on side streams)")
     ap.add_argument("--serial-groups", action="store_true",
                     help="batch256: launch the kernel groups' chains one after the other "
                          "instead of concurrently on side streams")

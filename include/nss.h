@@ -232,8 +232,10 @@ typedef enum {
                                     * the other on the context's stream; by default the second
                                     * and later ones run concurrently on side streams of the
                                     * library's own (default priority), forked and joined with
-                                    * events around the chain phase of each iteration.  Results
-                                    * are identical either way. */
+                                    * events around the chain phase of each iteration (eager
+                                    * iterations only: iterations captured as a HIP graph run
+                                    * the groups in sequence).  Results are identical either
+                                    * way. */
 #define NS_FLAG_GRAPH  8  /* ns_run captures each batch of 16 iterations as a HIP graph and
                            * replays it (re-captured when a run of the batch finishes); not
                            * used together with NS_FLAG_TIMING.  Results are identical. */

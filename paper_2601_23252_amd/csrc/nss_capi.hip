@@ -91,6 +91,7 @@ struct ns_ctx {
     std::vector<hipStream_t> side;   // [groups - 1]
     hipEvent_t ev_fork = nullptr;
     std::vector<hipEvent_t> ev_join;   // [groups - 1]
+    bool capturing = false;            // a graph capture is recording the iterations
     // NS_FLAG_AUTOTUNE: the launch shape of each group chosen by timing its candidates on saved
     // iterations (see tune_iteration)
     int autotune = 0;
@@ -581,13 +582,20 @@ static ns_status enqueue_pre(ns_ctx *ctx)
 }
 
 // The chains of group g.
+// Workgroups per CU the hypothesis-plan kernel is compiled for: two when the launch has more
+// workgroups than the chip has CUs (they then hide each other's latency, at the cost of
+// spilled registers), else one.
+constexpr int kChipCUs = 256;
+static int plan_occupancy(const Launch &L) { return L.nblocks > kChipCUs ? 2 : 1; }
+
 static ns_status enqueue_hrss_group(ns_ctx *ctx, size_t g, hipStream_t s)
 {
     const Group &G = ctx->groups[g];
     const hipError_t e =
         G.lik == LIK_GP ? launch_hrss_gp(ctx->L_hrss[g], G.mode, s)
         : G.rw          ? launch_rw(ctx->L_hrss[g], G.D, G.lik, G.mode, G.upwT, s)
-        : G.plan        ? launch_hrss_plan(ctx->L_hrss[g], G.D, G.mode, G.upwT, G.plan, s)
+        : G.plan        ? launch_hrss_plan(ctx->L_hrss[g], G.D, G.mode, G.upwT, G.plan,
+                                           plan_occupancy(ctx->L_hrss[g]), s)
                         : launch_hrss(ctx->L_hrss[g], G.D, G.lik, G.mode, G.upwT, s);
     if (e != hipSuccess) return device_error(ctx, "HRSS launch", e);
     return NS_OK;
@@ -600,14 +608,16 @@ static ns_status enqueue_hrss_group(ns_ctx *ctx, size_t g)
 // The chains of every group with unfinished runs: the first such group on the context's
 // stream, the others concurrently on side streams (their runs are disjoint, and a run's
 // arithmetic does not depend on the order), forked after the directions and joined before
-// delete-k.  The fork and join are events, so graph capture records them as dependencies.
+// delete-k.  Inside a graph capture the groups go one after the other on the context's stream:
+// a graph whose iterations branched over the side streams stalled once in a batch test (no
+// cause found; the runtime then schedules the branches itself), so graphs stay linear.
 static ns_status enqueue_chains(ns_ctx *ctx)
 {
     std::vector<size_t> live;
     for (size_t g = 0; g < ctx->groups.size(); ++g)
         if (ctx->L_hrss[g].nblocks > 0) live.push_back(g);
     ns_status st;
-    if (live.size() <= 1 || ctx->side.empty()) {
+    if (live.size() <= 1 || ctx->side.empty() || ctx->capturing) {
         for (size_t g : live)
             if ((st = enqueue_hrss_group(ctx, g)) != NS_OK) return st;
         return NS_OK;
@@ -1347,7 +1357,9 @@ static ns_status launch_graph_batch(ns_ctx *ctx)
         }
         CK(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
         ns_status st = NS_OK;
+        ctx->capturing = true;
         for (int b = 0; b < kGraphIters && st == NS_OK; ++b) st = enqueue_iteration(ctx);
+        ctx->capturing = false;
         hipGraph_t g = nullptr;
         const hipError_t e = hipStreamEndCapture(ctx->stream, &g);
         if (st != NS_OK) {

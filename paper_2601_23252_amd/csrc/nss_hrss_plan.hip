@@ -275,8 +275,11 @@ __device__ __forceinline__ unsigned compress_ballot(unsigned long long b)
 
 enum { PF_NONE = 0, PF_LEFT = 1, PF_RIGHT = 2, PF_SHRINK = 3 };
 
-template <int D, int MODE, int UPW, int S>
-__global__ __launch_bounds__(256) void k_hrss_plan(Launch Lc)
+// OCC: workgroups per CU the register allocation targets (1, or 2 with the excess spilled):
+// two resident workgroups hide each other's round latency when a launch has more workgroups
+// than the chip has CUs; the arithmetic, and so every result, is the same.
+template <int D, int MODE, int UPW, int S, int OCC>
+__global__ __launch_bounds__(256, OCC) void k_hrss_plan(Launch Lc)
 {
     static_assert(S == 8 || S == 16, "plan slots");
     typedef PlanShape<S> Shape;
@@ -741,11 +744,11 @@ __global__ __launch_bounds__(256) void k_hrss_plan(Launch Lc)
 // ------------------------------------------------------------------------------------------
 size_t hrss_plan_lds_bytes(int D, int K, int S) { return (size_t)plan_layout(D, K, S).total; }
 
-template <int D, int MODE, int UPW, int S>
+template <int D, int MODE, int UPW, int S, int OCC>
 static hipError_t plan_t(const Launch &L, hipStream_t s)
 {
     const size_t lds = hrss_plan_lds_bytes(D, L.max_K, S);
-    auto f = k_hrss_plan<D, MODE, UPW, S>;
+    auto f = k_hrss_plan<D, MODE, UPW, S, OCC>;
     hipError_t e = hipFuncSetAttribute((const void *)f,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
@@ -753,37 +756,41 @@ static hipError_t plan_t(const Launch &L, hipStream_t s)
     return hipGetLastError();
 }
 
-template <int MODE, int S>
+template <int MODE, int S, int OCC>
 static hipError_t plan_mode(const Launch &L, int D, int upw, hipStream_t s)
 {
-    if (D == 32) return upw <= 4 ? plan_t<32, MODE, 4, S>(L, s) : plan_t<32, MODE, 16, S>(L, s);
+    if (D == 32)
+        return upw <= 4 ? plan_t<32, MODE, 4, S, OCC>(L, s) : plan_t<32, MODE, 16, S, OCC>(L, s);
     if (D == 64) {
-        if (upw <= 2) return plan_t<64, MODE, 2, S>(L, s);
-        if (upw <= 4) return plan_t<64, MODE, 4, S>(L, s);
-        return plan_t<64, MODE, 8, S>(L, s);
+        if (upw <= 2) return plan_t<64, MODE, 2, S, OCC>(L, s);
+        if (upw <= 4) return plan_t<64, MODE, 4, S, OCC>(L, s);
+        return plan_t<64, MODE, 8, S, OCC>(L, s);
     }
-    if (D == 128) return plan_t<128, MODE, 4, S>(L, s);
+    if (D == 128) return plan_t<128, MODE, 4, S, OCC>(L, s);
     return hipErrorInvalidValue;
 }
 
-template <int S>
+template <int S, int OCC>
 static hipError_t plan_s(const Launch &L, int D, int mode, int upw, hipStream_t s)
 {
     switch (mode) {
-    case MODE_BF16: return plan_mode<MODE_BF16, S>(L, D, upw, s);
-    case MODE_FP16: return plan_mode<MODE_FP16, S>(L, D, upw, s);
-    case MODE_BF16X3: return plan_mode<MODE_BF16X3, S>(L, D, upw, s);
-    case MODE_FP16X3: return plan_mode<MODE_FP16X3, S>(L, D, upw, s);
+    case MODE_BF16: return plan_mode<MODE_BF16, S, OCC>(L, D, upw, s);
+    case MODE_FP16: return plan_mode<MODE_FP16, S, OCC>(L, D, upw, s);
+    case MODE_BF16X3: return plan_mode<MODE_BF16X3, S, OCC>(L, D, upw, s);
+    case MODE_FP16X3: return plan_mode<MODE_FP16X3, S, OCC>(L, D, upw, s);
     default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_hrss_plan(const Launch &L, int D, int mode, int upw, int S, hipStream_t s)
+hipError_t launch_hrss_plan(const Launch &L, int D, int mode, int upw, int S, int occ,
+                            hipStream_t s)
 {
     if (L.nblocks <= 0) return hipSuccess;
     if (upw_template(D, upw) == 0) return hipErrorNotSupported;
-    if (S == 8) return plan_s<8>(L, D, mode, upw, s);
-    if (S == 16) return plan_s<16>(L, D, mode, upw, s);
+    if (occ != 1 && occ != 2) return hipErrorInvalidValue;
+    if (S == 8) return occ == 2 ? plan_s<8, 2>(L, D, mode, upw, s) : plan_s<8, 1>(L, D, mode, upw, s);
+    if (S == 16)
+        return occ == 2 ? plan_s<16, 2>(L, D, mode, upw, s) : plan_s<16, 1>(L, D, mode, upw, s);
     return hipErrorInvalidValue;
 }
 

@@ -119,7 +119,8 @@ hipError_t launch_dirs(const Launch &L, int D, hipStream_t s);
 hipError_t launch_hrss(const Launch &L, int D, int lik, int mode, int upw, hipStream_t s);
 // the mixture chains in a 16-bit mode with S-test hypothesis plans (nss_hrss_plan.hip),
 // S = 8 or 16; needs the direction buffer
-hipError_t launch_hrss_plan(const Launch &L, int D, int mode, int upw, int S, hipStream_t s);
+hipError_t launch_hrss_plan(const Launch &L, int D, int mode, int upw, int S, int occ,
+                            hipStream_t s);
 size_t hrss_plan_lds_bytes(int D, int K, int S);
 // the random-walk replacement kernel (same grid and tile evaluators as the HRSS kernel)
 hipError_t launch_rw(const Launch &L, int D, int lik, int mode, int upw, hipStream_t s);

@@ -183,8 +183,8 @@ def test_graph_replay_matches_eager(N):
 @pytest.mark.parametrize("graph", [False, True])
 def test_concurrent_groups_equal_serial_groups(N, graph):
     """The small batch compiles to several chain kernels; launched concurrently on side streams
-    (the default) or one after the other (NS_FLAG_SERIAL_GROUPS), eagerly or as captured graphs,
-    every run's trajectory is the same bit for bit."""
+    (the default, eager iterations) or one after the other (NS_FLAG_SERIAL_GROUPS, and every
+    graph-captured iteration), every run's trajectory is the same bit for bit."""
     runs = _small_batch()
     Sr = N.NSBatch([(p, dict(kw, serial_groups=True, graph=graph)) for p, kw in runs])
     Cc = N.NSBatch([(p, dict(kw, graph=graph)) for p, kw in runs])

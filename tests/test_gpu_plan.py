@@ -75,3 +75,30 @@ def test_plan_caps_and_short_chains(N):
             assert ta[key] == tb[key], (caps, key)
         a.close()
         b.close()
+
+
+@pytest.mark.parametrize("prec", ["fp16x3", "bf16"])
+@pytest.mark.parametrize("plan8", [False, True])
+def test_two_workgroups_per_cu_variant_is_identical(N, prec, plan8):
+    """A batch whose plan-kernel launch has more workgroups than CUs (six d = 48 mixtures with
+    k = 200: 1,200 chains, 300 workgroups) runs the variant compiled for two workgroups per CU;
+    each run's trajectory equals its single run's (200 chains, one workgroup per CU)."""
+    from paper_2601_23252_amd import problems as G
+    runs = [(G.mixture_problem(20 + r, 48, 3, m=400, k=200),
+             dict(p=24, seed=5, run_id=r, precision=prec, plan8=plan8)) for r in range(6)]
+    B = N.NSBatch(runs)
+    assert N.ns_chains_per_workgroup(B.ctx, 0) == 4
+    for _ in range(5):
+        B.step()
+    for r, (prob, kw) in enumerate(runs):
+        S = N.NSRun(prob, **kw)
+        assert S.chains_per_workgroup() == 1
+        for _ in range(5):
+            S.step()
+        sb, ss = B.state(r), S.state()
+        assert np.array_equal(sb["perm"], ss["perm"]), r
+        assert np.array_equal(sb["x"], ss["x"]), r
+        assert np.array_equal(sb["logL"], ss["logL"]), r
+        assert B.stats(r)["evals"] == S.stats()["evals"]
+        S.close()
+    B.close()
