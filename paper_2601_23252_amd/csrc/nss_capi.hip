@@ -92,6 +92,7 @@ struct ns_ctx {
     hipEvent_t ev_fork = nullptr;
     std::vector<hipEvent_t> ev_join;   // [groups - 1]
     bool capturing = false;            // a graph capture is recording the iterations
+    bool forked = false;               // the chain launches being issued run concurrently
     // NS_FLAG_AUTOTUNE: the launch shape of each group chosen by timing its candidates on saved
     // iterations (see tune_iteration)
     int autotune = 0;
@@ -583,10 +584,14 @@ static ns_status enqueue_pre(ns_ctx *ctx)
 
 // The chains of group g.
 // Workgroups per CU the hypothesis-plan kernel is compiled for: two when the launch has more
-// workgroups than the chip has CUs (they then hide each other's latency, at the cost of
-// spilled registers), else one.
+// workgroups than the chip has CUs, or runs beside other groups' chains on side streams (two
+// resident workgroups then hide each other's latency, at the cost of spilled registers), else
+// one.
 constexpr int kChipCUs = 256;
-static int plan_occupancy(const Launch &L) { return L.nblocks > kChipCUs ? 2 : 1; }
+static int plan_occupancy(const ns_ctx *ctx, const Launch &L)
+{
+    return (L.nblocks > kChipCUs || ctx->forked) ? 2 : 1;
+}
 
 static ns_status enqueue_hrss_group(ns_ctx *ctx, size_t g, hipStream_t s)
 {
@@ -595,7 +600,7 @@ static ns_status enqueue_hrss_group(ns_ctx *ctx, size_t g, hipStream_t s)
         G.lik == LIK_GP ? launch_hrss_gp(ctx->L_hrss[g], G.mode, s)
         : G.rw          ? launch_rw(ctx->L_hrss[g], G.D, G.lik, G.mode, G.upwT, s)
         : G.plan        ? launch_hrss_plan(ctx->L_hrss[g], G.D, G.mode, G.upwT, G.plan,
-                                           plan_occupancy(ctx->L_hrss[g]), s)
+                                           plan_occupancy(ctx, ctx->L_hrss[g]), s)
                         : launch_hrss(ctx->L_hrss[g], G.D, G.lik, G.mode, G.upwT, s);
     if (e != hipSuccess) return device_error(ctx, "HRSS launch", e);
     return NS_OK;
@@ -623,13 +628,16 @@ static ns_status enqueue_chains(ns_ctx *ctx)
         return NS_OK;
     }
     CK(hipEventRecord(ctx->ev_fork, ctx->stream));
+    ctx->forked = true;
     for (size_t i = 1; i < live.size(); ++i) {
         hipStream_t s = ctx->side[i - 1];
         CK(hipStreamWaitEvent(s, ctx->ev_fork, 0));
-        if ((st = enqueue_hrss_group(ctx, live[i], s)) != NS_OK) return st;
+        if ((st = enqueue_hrss_group(ctx, live[i], s)) != NS_OK) { ctx->forked = false; return st; }
         CK(hipEventRecord(ctx->ev_join[i - 1], s));
     }
-    if ((st = enqueue_hrss_group(ctx, live[0])) != NS_OK) return st;
+    st = enqueue_hrss_group(ctx, live[0]);
+    ctx->forked = false;
+    if (st != NS_OK) return st;
     for (size_t i = 1; i < live.size(); ++i)
         CK(hipStreamWaitEvent(ctx->stream, ctx->ev_join[i - 1], 0));
     return NS_OK;
