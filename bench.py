@@ -38,14 +38,14 @@ sys.path.insert(0, ROOT)
 # kernel sources with this sha256 prefix; reported as null once the sources differ or for a
 # shape the counters were not taken on.
 TRAFFIC = {("fp16x3", 320, 4, 8): 196.7e6}
-TRAFFIC_SOURCE_SHA = "06249d20ac27f2ae"
+TRAFFIC_SOURCE_SHA = "fd6c2f8f156d9218"
 
 
 # VALU lane-instructions per evaluation issued by the chain kernel (SQ_INSTS_VALU x 64 /
 # evaluations of the profiled launches), keyed like TRAFFIC, for the kernel sources with this
 # prefix: the instruction view of the same kernel (its chain logic runs on the vector ALU).
 HRSS_VALU_PER_EVAL = {("fp16x3", 320, 4, 8): 24544.0}
-HRSS_VALU_SOURCE_SHA = "06249d20ac27f2ae"
+HRSS_VALU_SOURCE_SHA = "fd6c2f8f156d9218"
 
 KERNEL_SOURCES = ("nss_kernels.hip", "nss_hrss_plan.hip", "nss_tiles.hpp", "nss_internal.hpp")
 
