@@ -628,16 +628,18 @@ static ns_status enqueue_chains(ns_ctx *ctx)
         return NS_OK;
     }
     CK(hipEventRecord(ctx->ev_fork, ctx->stream));
-    ctx->forked = true;
+    struct Forked {   // the launches below run concurrently (read by plan_occupancy)
+        ns_ctx *c;
+        explicit Forked(ns_ctx *x) : c(x) { c->forked = true; }
+        ~Forked() { c->forked = false; }
+    } forked(ctx);
     for (size_t i = 1; i < live.size(); ++i) {
         hipStream_t s = ctx->side[i - 1];
         CK(hipStreamWaitEvent(s, ctx->ev_fork, 0));
-        if ((st = enqueue_hrss_group(ctx, live[i], s)) != NS_OK) { ctx->forked = false; return st; }
+        if ((st = enqueue_hrss_group(ctx, live[i], s)) != NS_OK) return st;
         CK(hipEventRecord(ctx->ev_join[i - 1], s));
     }
-    st = enqueue_hrss_group(ctx, live[0]);
-    ctx->forked = false;
-    if (st != NS_OK) return st;
+    if ((st = enqueue_hrss_group(ctx, live[0])) != NS_OK) return st;
     for (size_t i = 1; i < live.size(); ++i)
         CK(hipStreamWaitEvent(ctx->stream, ctx->ev_join[i - 1], 0));
     return NS_OK;
