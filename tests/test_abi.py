@@ -187,3 +187,21 @@ def test_tune_cache_json_round_trip(N, tmp_path):
     st, n4 = N.ns_tune_clear()
     assert st == N.NS_OK and n4 == n
     assert N.ns_tune_save(tmp_path / "empty.json") == (N.NS_OK, 0)
+
+
+def test_binding_constants_match_the_header(N):
+    """Every NS_FLAG_* / NS_* integer constant the binding defines has the value the header
+    #defines or enumerates, and the flags are distinct single bits."""
+    import re
+    txt = open(N.HEADER).read()
+    defined = {m.group(1): int(m.group(2))
+               for m in re.finditer(r"#define\s+(NS_FLAG_\w+)\s+(\d+)", txt)}
+    assert len(defined) >= 12
+    for name, val in defined.items():
+        assert getattr(N, name) == val, name
+        assert val & (val - 1) == 0, name
+    assert len(set(defined.values())) == len(defined)
+    enums = {m.group(1): int(m.group(2)) for m in re.finditer(r"\b(NS_\w+)\s*=\s*(-?\d+)", txt)}
+    for name, val in enums.items():
+        if hasattr(N, name):
+            assert getattr(N, name) == val, name
