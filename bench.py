@@ -943,7 +943,7 @@ def main():
                          "this many outer iterations of one run; prints their timing only")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "this library runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
     if args.profile_iters > 0:
         profile_run(args)

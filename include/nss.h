@@ -45,7 +45,7 @@ typedef enum {
     NS_ENOMEM = -2,         /* device or host allocation failed */
     NS_EDEVICE = -3,        /* a HIP call failed; the context should be freed */
     NS_ESTATE = -4,         /* no survivor lies strictly above L* (likelihood plateau) */
-    NS_EUNSUPPORTED = -5    /* valid but outside what this build supports (sizes, kinds) */
+    NS_EUNSUPPORTED = -5    /* valid but outside what this library supports (sizes, kinds) */
 } ns_status;
 
 /* Prior Pi, one factor per coordinate (Sec. 1, the reference density). */
@@ -283,7 +283,7 @@ typedef struct {
 /* Create a run: copy the problem to the device, draw m points from the prior (Philox purpose
  * INIT), evaluate them in FP64, delete the k worst and account their evidence (Alg. outer
  * kernel, first evaluate-sort-record).  Returns NS_EINVAL for inconsistent arguments,
- * NS_EUNSUPPORTED for sizes beyond this build. */
+ * NS_EUNSUPPORTED for sizes beyond this library. */
 ns_status ns_init(const ns_prior *prior, const ns_energy *energy, const ns_config *cfg,
                   void *hip_stream, ns_ctx **out);
 
@@ -408,7 +408,7 @@ ns_status ns_eval_loglik(ns_ctx *ctx, const double *x, int32_t n, int32_t precis
  * ns_get_state, ns_set_state, ns_get_dead, ns_get_trace and ns_eval_loglik address run 0.
  * Arrays have n_runs entries; all pointers are host pointers copied as by ns_init.
  * Errors: NS_EINVAL if n_runs < 1 or any run's arguments are invalid (ns_last_error(NULL)
- * names the run), NS_EUNSUPPORTED for n_runs > 65536 or a run beyond this build. */
+ * names the run), NS_EUNSUPPORTED for n_runs > 65536 or a run beyond this library. */
 ns_status ns_init_batch(int32_t n_runs, const ns_prior *priors, const ns_energy *energies,
                         const ns_config *cfgs, void *hip_stream, ns_ctx **out);
 
